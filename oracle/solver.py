@@ -1,0 +1,125 @@
+"""The three-dimensional tensor-product--Thomas solve (oracle; test
+infrastructure only).
+
+Solution steps of the procedure of §2.2.2 (also Algorithm 1, solution part,
+without the transposes, which only redistribute data):
+
+2.1  f^(x)  = (Q_x^{-1} (x) I_y (x) I_z) f                    (Eq. forward-xy)
+2.2  f^(xy) = (I_x (x) Q_y^{-1} (x) I_z) f^(x)
+2.3  (lambda_ij I_z + T_z) phi^(xy)_ij = f^(xy)_ij, lambda_ij = lambda_x,i + lambda_y,j,
+     one Thomas solve per (i, j) line
+2.4  phi^(x) = (I_x (x) Q_y (x) I_z) phi^(xy)                  (Eq. inverse-xy)
+2.5  phi     = (Q_x (x) I_y (x) I_z) phi^(x)
+
+Helmholtz (I - alpha T) u = f uses the same eigenvectors with a constant
+modal shift (end of §2.2.2): line (i, j) solves
+(sigma + tau (lambda_ij + T_z)) u^ = f^ with sigma = 1, tau = -alpha;
+Poisson is sigma = 0, tau = 1.
+
+Gauge (§3): for a Poisson problem with a constant null mode, the line whose
+shift is lambda_x = lambda_y = 0 has a vanishing final pivot; its last modal
+unknown is set to zero and back substitution proceeds from there.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .eig import eig_direction
+from .operator import operator_1d, has_null
+
+
+def thomas_lines(az, bz, cz, lam, sigma, tau, rhs, pin=None):
+    """Solve (sigma + tau (lam + T_z)) x = rhs for every line at once.
+
+    rhs has shape (Nz,) + lam.shape; T_z has sub-diagonal az, diagonal bz,
+    super-diagonal cz (az[0] and cz[-1] unused).  Plain Thomas algorithm:
+    forward elimination then back substitution.  `pin` is the index tuple of
+    the line whose final pivot vanishes; its last unknown is set to zero.
+    Returns (x, last_pivot).
+    """
+    nz = len(bz)
+    cp = np.empty_like(rhs)
+    dp = np.empty_like(rhs)
+    x = np.empty_like(rhs)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        den = sigma + tau * (lam + bz[0])
+        cp[0] = tau * cz[0] / den if nz > 1 else 0.0
+        dp[0] = rhs[0] / den
+        for k in range(1, nz):
+            den = sigma + tau * (lam + bz[k]) - tau * az[k] * cp[k - 1]
+            cp[k] = (tau * cz[k] / den) if k < nz - 1 else 0.0
+            dp[k] = (rhs[k] - tau * az[k] * dp[k - 1]) / den
+    last_pivot = np.array(den, copy=True)
+    x[nz - 1] = dp[nz - 1]
+    if pin is not None:
+        x[(nz - 1,) + tuple(pin)] = 0.0
+    for k in range(nz - 2, -1, -1):
+        x[k] = dp[k] - cp[k] * x[k + 1]
+    return x, last_pivot
+
+
+def _coeffs(p):
+    if p.kind == "poisson":
+        return 0.0, 1.0
+    if p.kind == "helmholtz":
+        return 1.0, -p.alpha
+    raise ValueError(p.kind)
+
+
+class Plan:
+    """Initialization steps 1.1-1.3 for x and y, and T_z, for one problem."""
+
+    def __init__(self, p):
+        if p.bc[2][0] == "P":
+            raise ValueError("periodic z (cyclic Thomas) is not part of this solver")
+        self.p = p
+        self.ex = eig_direction(p.faces[0], p.bc[0], p.loc[0])
+        self.ey = eig_direction(p.faces[1], p.bc[1], p.loc[1])
+        self.az, self.bz, self.cz, _ = operator_1d(p.faces[2], p.bc[2], p.loc[2])
+        self.sigma, self.tau = _coeffs(p)
+        self.pin = None
+        if (self.sigma == 0.0 and self.ex.null_index >= 0 and self.ey.null_index >= 0
+                and has_null(p.bc[2], p.loc[2])):
+            self.pin = (self.ey.null_index, self.ex.null_index)
+
+    def forward(self, f):
+        fx = f @ self.ex.Qinv.T            # 2.1: sum_i Qx^{-1}[p, i] f[k, j, i]
+        return np.matmul(self.ey.Qinv, fx)  # 2.2: sum_j Qy^{-1}[q, j] fx[k, j, p]
+
+    def modal(self, fxy):
+        lam = self.ey.lam[:, None] + self.ex.lam[None, :]
+        x, piv = thomas_lines(self.az, self.bz, self.cz, lam, self.sigma, self.tau, fxy, self.pin)
+        self.last_pivot = piv
+        return x
+
+    def inverse(self, phixy):
+        phix = np.matmul(self.ey.Q, phixy)  # 2.4
+        return phix @ self.ex.Q.T           # 2.5: sum_p Qx[i, p] phix[k, j, p]
+
+    def solve(self, f):
+        f = np.asarray(f, dtype=np.float64)
+        if f.shape != self.p.shape:
+            raise ValueError(f"rhs shape {f.shape} != {self.p.shape}")
+        return self.inverse(self.modal(self.forward(f)))
+
+
+def solve(p, f, plan: Plan | None = None):
+    """phi for problem p and right-hand side f (shape p.shape)."""
+    return (plan or Plan(p)).solve(f)
+
+
+def gauge_normalise(p, x):
+    """Subtract the volume-weighted mean for a singular problem (solutions are
+    defined up to a constant); identity otherwise."""
+    if not p.singular:
+        return x
+    dv = p.volumes()
+    return x - (dv * x).sum() / dv.sum()
+
+
+def relative_error(p, x, ref, norm="2"):
+    """||g(x) - g(ref)|| / ||g(ref)|| with g = gauge_normalise."""
+    gx, gr = gauge_normalise(p, np.asarray(x, dtype=np.float64)), gauge_normalise(p, ref)
+    if norm == "2":
+        return float(np.linalg.norm((gx - gr).ravel()) / np.linalg.norm(gr.ravel()))
+    return float(np.abs(gx - gr).max() / np.abs(gr).max())
