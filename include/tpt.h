@@ -1,0 +1,240 @@
+/*
+ * tpt — tensor-product–Thomas direct solver for constant-coefficient
+ * Poisson and Helmholtz equations on staggered, non-uniform 3-D Cartesian
+ * grids, for one AMD Instinct MI355X (gfx950).
+ *
+ * Method (arXiv 2603.09528, §2.2): the 1-D second-order operators along x and
+ * y (Eq. poisson-fd2 / tridiagonal-coefficients) are symmetrised by the
+ * diagonal similarity T~ = D^{1/2} T D^{-1/2} (Eq. reverse-similarity-
+ * transform), eigendecomposed once per grid (T~ = Q~ Λ Q~^T), and applied as
+ * dense transforms Q^{-1} = Q~^T D^{1/2}, Q = D^{-1/2} Q~ (Eq. q-from-tildeq)
+ * over all grid lines at once (one GEMM per direction, end of §2.2.2).  The
+ * remaining z direction is solved line by line with the Thomas algorithm,
+ * shifted by λ_x,i + λ_y,j (§2.2.2, solution steps 2.1–2.5).  Helmholtz uses
+ * the same eigenvectors with a constant modal shift.  The pressure gauge of a
+ * singular Poisson problem follows §3: the modal unknown whose final pivot
+ * vanishes is set to zero.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Fields are contiguous row-major arrays u[k][j][i] (x fastest) of
+ *   Nz*Ny*Nx elements, where N_d is the unknown count of direction d: the
+ *   cell count n[d], or n[d]-1 for a face-located direction between two
+ *   Dirichlet walls.  Several right-hand sides are stored back to back.
+ * - Device pointers are HIP device memory on the current device.  The
+ *   library never frees memory it did not allocate.
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   Solve calls are stream-ordered and return before the GPU finishes,
+ *   except where stated.
+ * - Every function returns an int: TPT_OK (0) on success, TPT_PENDING (1)
+ *   for a server request still running, or a negative TPT_ERR_* code.
+ *   Nothing is thrown across the ABI.  tpt_last_error() returns a message
+ *   for the last failing call of the calling thread.  A device fault raised
+ *   by an earlier asynchronous launch surfaces as TPT_ERR_HIP on a later call.
+ */
+#ifndef TPT_H
+#define TPT_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    TPT_OK = 0,
+    TPT_PENDING = 1,
+    TPT_ERR_INVALID = -1,       /* bad argument (sizes, faces, BC pairing, NULL) */
+    TPT_ERR_UNSUPPORTED = -2,   /* valid but not supported combination */
+    TPT_ERR_OOM = -3,           /* device allocation failed / over budget */
+    TPT_ERR_ALIAS = -4,         /* rhs and out overlap */
+    TPT_ERR_NOT_CONVERGED = -5, /* refinement stopped above its tolerance */
+    TPT_ERR_HIP = -6,           /* a HIP runtime call failed */
+    TPT_ERR_WORKSPACE = -7      /* workspace too small */
+};
+
+/* Homogeneous boundary conditions, per direction and side (§2.2.1: the first
+ * and last rows of T are modified by the boundary conditions; periodic
+ * boundaries add cyclic corners).  Periodic must be set on both sides. */
+enum { TPT_BC_PERIODIC = 0, TPT_BC_NEUMANN = 1, TPT_BC_DIRICHLET = 2 };
+/* Location of the unknowns along a direction on the staggered grid (§2.1):
+ * cell centres (pressure) or faces (the velocity component normal to them). */
+enum { TPT_LOC_CENTER = 0, TPT_LOC_FACE = 1 };
+/* Poisson: L phi = f (Eq. poi_ns).  Helmholtz: (I - alpha L) u = f
+ * (Eq. helmholtz_ns with alpha = gamma nu dt / 2, implicit in x, y and z). */
+enum { TPT_POISSON = 0, TPT_HELMHOLTZ = 1 };
+/* Arithmetic of the transforms.  FP64: everything in double precision.
+ * MIXED_FP32: transforms in FP32 MFMA; MIXED_BF16X3: transforms as three
+ * BF16 MFMA products (hi*hi + hi*lo + lo*hi) with FP32 accumulation.  Both
+ * mixed modes refine in FP64 (residual, update, Thomas and the null-line pin
+ * in double precision).  Input and output are FP64 in every mode. */
+enum { TPT_FP64 = 0, TPT_MIXED_FP32 = 1, TPT_MIXED_BF16X3 = 2 };
+
+/* Plan flags. */
+enum {
+    TPT_FLAG_HOST_ONLY = 1  /* build the host-side operators and eigenbases
+                               only (no device memory, no GPU needed); such a
+                               plan can be inspected but not solved */
+};
+
+typedef struct tpt_plan_s *tpt_plan;
+typedef struct tpt_batch_s *tpt_batch;
+typedef struct tpt_server_s *tpt_server;
+
+typedef struct {
+    int n[3];               /* cells per direction x, y, z (>= 2) */
+    const double *faces[3]; /* host arrays of n[d]+1 strictly increasing face
+                               coordinates (copied; caller keeps ownership).
+                               A periodic direction must be uniform only if
+                               its analytic basis is wanted; any spacing works */
+    int bc[3][2];           /* [direction][lower, upper], TPT_BC_*; z may not be periodic */
+    int loc[3];             /* TPT_LOC_*; FACE needs periodic or Dirichlet-Dirichlet */
+    int kind;               /* TPT_POISSON or TPT_HELMHOLTZ */
+    double alpha;           /* Helmholtz coefficient (> 0), ignored for Poisson */
+    int precision;          /* TPT_FP64, TPT_MIXED_FP32, TPT_MIXED_BF16X3 */
+    double rtol;            /* mixed modes: stop when ||e||_2/||x||_2 <= rtol (default 1e-12 if <= 0) */
+    int max_refine;         /* mixed modes: cap on corrections (default 8 if <= 0) */
+    int fixed_refine;       /* mixed modes: >= 0 runs exactly this many corrections with
+                               no host synchronisation (stream-ordered, capturable);
+                               -1 = adaptive, which synchronises the stream once per correction */
+    int nrhs;               /* right-hand sides per solve call (>= 1), stored back to back */
+    int flags;              /* TPT_FLAG_* */
+} tpt_plan_desc;
+
+/* Result of the last solve of a plan (valid after the stream has been
+ * synchronised). */
+typedef struct {
+    int iters;              /* corrections applied (0 for FP64) */
+    double rel_correction;  /* ||e_last||_2 / ||x||_2 (mixed modes), 0 for FP64 */
+    double rel_residual;    /* ||f - A x||_2 / ||f||_2 at the last refinement residual (mixed), or -1 */
+    int null_line;          /* index i + Nx*j of the pinned modal line, or -1 */
+} tpt_info;
+
+/* Fill a descriptor with defaults (FP64 Poisson, centre-located, Neumann, nrhs 1). */
+void tpt_plan_desc_init(tpt_plan_desc *desc);
+
+/* Build a plan: 1-D operators with their boundary rows (§2.2.1), eigenbases
+ * of x and y (analytic on uniform periodic / Neumann / Dirichlet directions,
+ * otherwise the library's own symmetric tridiagonal QL, with a dense
+ * Householder reduction for cyclic operators; initialization steps 1.1–1.3 of
+ * §2.2.2) and their device copies.  Eigenbases are cached on the device and
+ * shared by plans with identical (faces, BC, location).  Synchronous.
+ * Errors: TPT_ERR_INVALID, TPT_ERR_UNSUPPORTED, TPT_ERR_OOM, TPT_ERR_HIP. */
+int tpt_plan_create(const tpt_plan_desc *desc, tpt_plan *out);
+int tpt_plan_destroy(tpt_plan plan);
+
+/* Unknown counts {Nx, Ny, Nz} of a plan. */
+int tpt_plan_shape(tpt_plan plan, int shape[3]);
+
+/* Bytes of device workspace one tpt_solve call needs (all nrhs included). */
+int tpt_plan_workspace_bytes(tpt_plan plan, size_t *bytes);
+
+/* Host copy of the eigen data of direction dir (0 = x, 1 = y): lam[N] (Λ)
+ * and, if Qt is not NULL, Q~ as an N x N row-major array (Qt[i*N + p] is
+ * component i of eigenvector p).  Works on host-only plans. */
+int tpt_plan_eigen(tpt_plan plan, int dir, double *lam, double *Qt);
+
+/* Host copy of the 1-D operator of direction dir (0, 1, 2): sub-diagonal a,
+ * diagonal b, super-diagonal c and control volumes vol, N entries each (for a
+ * periodic direction a[0] and c[N-1] are the cyclic corners). */
+int tpt_plan_operator(tpt_plan plan, int dir, double *a, double *b, double *c, double *vol);
+
+/* Solve A x = rhs for the plan's nrhs right-hand sides.  rhs, out: device
+ * FP64 fields (nrhs * Nz*Ny*Nx each); rhs is read only and must not overlap
+ * out (TPT_ERR_ALIAS).  workspace: device memory of at least
+ * tpt_plan_workspace_bytes, or NULL to use a buffer owned by the plan
+ * (allocated on first use).  Stream-ordered; the adaptive mixed mode
+ * (fixed_refine = -1) synchronises `stream` once per correction.  A singular
+ * Poisson right-hand side is solved with the gauge of §3 (pinned final
+ * modal unknown); an incompatible component is absorbed by that pin. */
+int tpt_solve(tpt_plan plan, const double *rhs, double *out, void *workspace,
+              size_t workspace_bytes, void *stream);
+
+/* Info of the plan's last solve (call after synchronising its stream). */
+int tpt_solve_info(tpt_plan plan, tpt_info *info);
+
+/* ---- multi-problem batches (independent problems, uneven sizes) ---------- */
+
+/* Group `count` plans (any sizes, same precision) into a batch whose solve
+ * issues one launch per stage for all problems (a work list of tiles from
+ * every problem), with GEMM tiles chosen by the autotuning table.  Plans must
+ * outlive the batch.  Plans with nrhs > 1 are rejected. */
+int tpt_batch_create(int count, const tpt_plan *plans, tpt_batch *out);
+int tpt_batch_destroy(tpt_batch batch);
+int tpt_batch_workspace_bytes(tpt_batch batch, size_t *bytes);
+/* rhs[i], out[i]: device FP64 fields of plan i.  use_graph != 0 captures the
+ * batch's launches once (per stream and pointer set) in a hipGraph and
+ * replays it.  Stream-ordered; fixed-refinement mixed plans only
+ * (adaptive ones are rejected with TPT_ERR_UNSUPPORTED). */
+int tpt_batch_solve(tpt_batch batch, const double *const *rhs, double *const *out,
+                    void *workspace, size_t workspace_bytes, void *stream, int use_graph);
+
+/* ---- autotuning of GEMM tiles --------------------------------------------- */
+
+/* Time every compiled tile variant for the GEMM shapes of the given plans and
+ * record the fastest per (shape class, precision) in the process-wide table.
+ * Needs the GPU; synchronous. */
+int tpt_autotune(int count, const tpt_plan *plans, void *stream);
+/* Save / load the table as text (one "kind prec M N K variant" line per entry). */
+int tpt_autotune_save(const char *path);
+int tpt_autotune_load(const char *path);
+
+/* ---- serving loop ---------------------------------------------------------- */
+
+/* A server admits solve requests while others run: a request waits until a
+ * slot is free and its workspace fits in the HBM budget, then its stages are
+ * launched on that slot's stream (requests admitted together share one
+ * multi-problem launch per stage).  Eigenbases stay device-resident in the
+ * plan cache.  max_slots concurrent requests, hbm_budget_bytes for request
+ * workspaces (0 = 3/4 of the free memory at creation). */
+int tpt_server_create(size_t hbm_budget_bytes, int max_slots, tpt_server *out);
+/* Queue a request; rhs/out are device FP64 fields owned by the caller and
+ * must stay valid until the request completes.  Returns at once. */
+int tpt_server_submit(tpt_server server, tpt_plan plan, const double *rhs, double *out,
+                      unsigned long long *ticket);
+/* TPT_OK when done (times in seconds on a process-wide monotonic clock:
+ * submit, admitted to a slot, finished on the GPU), TPT_PENDING if not yet. */
+int tpt_server_poll(tpt_server server, unsigned long long ticket, tpt_info *info,
+                    double *t_submit, double *t_start, double *t_done);
+/* Block until every submitted request has finished. */
+int tpt_server_drain(tpt_server server);
+int tpt_server_destroy(tpt_server server);
+
+/* ---- kernel-level entry points (testing and measurement) ------------------ */
+
+/* Batched Thomas solve (§2.2.2 step 2.3) on explicit inputs: for every line
+ * l = i + nx*j of each of nsys systems,
+ *   (sigma + tau*(lamx[i] + lamy[j] + T_z)) x = f,
+ * T_z with sub-diagonal az, diagonal bz, super-diagonal cz (device, nz each);
+ * f, x: device FP64 [nsys][nz][ny][nx]; scratch: device FP64 of the same
+ * size.  pin_line >= 0 sets the last unknown of that line to zero (§3 gauge).
+ * f may equal x. */
+int tpt_thomas(int nx, int ny, int nz, int nsys, const double *lamx, const double *lamy,
+               const double *az, const double *bz, const double *cz, double sigma,
+               double tau, int pin_line, const double *f, double *x, double *scratch,
+               void *stream);
+
+/* Strided-batched row-major GEMM C_b = A_b B_b (M x K times K x N) with the
+ * library's MFMA kernels.  prec: TPT_FP64 (double operands), TPT_MIXED_FP32
+ * (float operands) or TPT_MIXED_BF16X3 (float operands split to bf16 pairs).
+ * Leading dimensions are K, N, N; batch strides in elements (0 = shared). */
+int tpt_gemm(int prec, int M, int N, int K, int batch, const void *A, long long strideA,
+             const void *B, long long strideB, void *C, long long strideC, void *stream);
+
+/* Per-kernel timing with HIP events recorded on the launch stream around
+ * every library kernel while enabled (process-wide). */
+int tpt_timing_enable(int enable);
+/* Synchronises the recorded events, then for each kernel kind k < *count
+ * fills names (NUL-separated, up to names_len bytes), total_ms[k] and
+ * launches[k]; *count becomes the number of kinds.  Clears the log. */
+int tpt_timing_collect(int *count, char *names, size_t names_len, double *total_ms,
+                       long long *launches);
+
+const char *tpt_last_error(void);
+const char *tpt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TPT_H */

@@ -1,0 +1,119 @@
+// Internal types of the tpt library (plans, eigenbasis cache, workspace
+// layout, error reporting, kernel timing).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/tpt.h"
+#include "host_ops.h"
+#include "kernels.h"
+
+namespace tpt {
+
+// ---- errors ---------------------------------------------------------------
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+const char* last_error_cstr();
+#define TPT_HIP(call)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return ::tpt::fail(TPT_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// ---- device eigenbasis of one direction (shared through the cache) --------
+// Orientation: Qinv[p][i] = Q~[i][p] s_i (forward, Q^{-1} = Q~^T D^{1/2}) and
+// Q[i][p] = Q~[i][p] / s_i (inverse, Q = D^{-1/2} Q~), both row-major
+// [out][in] (Eq. q-from-tildeq).
+struct DirBasis {
+    int device = 0;
+    int n = 0;
+    Eig1D eig;                       // host eigen data
+    double* d_lam = nullptr;         // device eigenvalues
+    double* d_qinv = nullptr;        // FP64
+    double* d_q = nullptr;
+    float* s_qinv = nullptr;         // FP32 copies
+    float* s_q = nullptr;
+    uint16_t* h_qinv = nullptr;      // bf16 hi / lo planes
+    uint16_t* l_qinv = nullptr;
+    uint16_t* h_q = nullptr;
+    uint16_t* l_q = nullptr;
+    void* block = nullptr;           // single allocation holding all of the above
+    size_t bytes = 0;
+    ~DirBasis();
+};
+
+// Device-resident cache of eigenbases keyed by (device, faces, BC, location).
+std::shared_ptr<DirBasis> basis_cache_get(int ncells, const double* faces, int bc_lo, int bc_hi, int loc,
+                                          bool host_only, std::string& err);
+size_t basis_cache_bytes();   // device bytes held by live cached bases
+
+// ---- plans ------------------------------------------------------------------
+struct PlanBuffers {  // per-plan small device arrays
+    double* ax = nullptr; double* bx = nullptr; double* cx = nullptr;
+    double* ay = nullptr; double* by = nullptr; double* cy = nullptr;
+    double* az = nullptr; double* bz = nullptr; double* cz = nullptr;
+    double* norms = nullptr;     // device scratch for reduced sums
+    void* block = nullptr;
+};
+
+}  // namespace tpt
+
+struct tpt_plan_s {
+    tpt_plan_desc desc{};
+    std::vector<double> faces[3];
+    tpt::Op1D op[3];
+    std::shared_ptr<tpt::DirBasis> bx, by;
+    int N[3] = {0, 0, 0};            // unknowns x, y, z
+    long long dof = 0;               // per right-hand side
+    double sigma = 0.0, tau = 1.0;   // line operator sigma + tau (lambda + T_z)
+    int null_line = -1;
+    bool host_only = false;
+    int device = 0;
+    tpt::PlanBuffers buf;
+    void* own_ws = nullptr;
+    size_t own_ws_bytes = 0;
+    double* h_norms = nullptr;       // pinned host copy of norms (adaptive mode)
+    tpt_info info{};
+    int gemm_variant[4] = {-1, -1, -1, -1};  // per stage (x fwd, y fwd, y inv, x inv); -1 = table
+    ~tpt_plan_s();
+};
+
+namespace tpt {
+
+// Workspace layout of one solve (bytes per unknown * dof * nrhs).
+size_t plan_workspace_bytes(const tpt_plan_s* p);
+
+// GEMM descriptors for the four transform stages of a plan.
+enum Stage { ST_XF = 0, ST_YF = 1, ST_YI = 2, ST_XI = 3 };
+GemmDesc stage_gemm(const tpt_plan_s* p, int stage, int prec, const void* in, int tin, void* out, int tout,
+                    int epi, double* partials, int nrhs);
+ThomasDesc plan_thomas(const tpt_plan_s* p, const void* f, int tf, void* x, int tx, double* scratch, int nrhs);
+StencilDesc plan_stencil(const tpt_plan_s* p, const double* x, const double* f, float* r, double* partials);
+int plan_gemm_prec(const tpt_plan_s* p);
+
+// Tile selection: autotuned table lookup (falls back to a size heuristic).
+int choose_variant(int prec, int stage_kind, int M, int N, int K);
+void autotune_record(int prec, int stage_kind, int M, int N, int K, int variant);
+// stage_kind: 0 = x pass (B = basis), 1 = y pass (A = basis)
+
+// ---- kernel timing ------------------------------------------------------------
+bool timing_enabled();
+// Launch wrapper: records events around f() on stream s when timing is on.
+struct TimedScope {
+    TimedScope(const char* name, hipStream_t s);
+    ~TimedScope();
+    const char* name;
+    hipStream_t s;
+    hipEvent_t e0 = nullptr;
+    bool on = false;
+};
+
+int solve_one(tpt_plan_s* p, const double* rhs, double* out, void* ws, size_t ws_bytes, hipStream_t s);
+
+}  // namespace tpt

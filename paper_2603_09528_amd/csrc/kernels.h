@@ -1,0 +1,109 @@
+// Device kernels of the tensor-product–Thomas solve and their launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace tpt {
+
+// Element types of GEMM operands/results in global memory.
+enum DType { DT_F64 = 0, DT_F32 = 1 };
+// MFMA arithmetic of a GEMM.
+enum GemmPrec { GP_F64 = 0, GP_F32 = 1, GP_BF16X3 = 2 };
+// What the epilogue does with the accumulated tile.
+enum Epilogue {
+    EPI_STORE = 0,      // C = acc (converted to C's type)
+    EPI_ACCUM_F64 = 1   // C (double) += acc; per-block partial sums of acc^2 and C^2
+};
+
+// Tile shapes (BM x BN) compiled for every precision; the autotuner picks.
+enum TileVariant { TV_128x128 = 0, TV_64x128 = 1, TV_128x64 = 2, TV_64x64 = 3, TV_32x64 = 4, TV_COUNT = 5 };
+const char* tile_variant_name(int v);
+void tile_variant_shape(int v, int* bm, int* bn);
+
+// One strided-batched GEMM C_b = A_b op(B_b), A row-major M x K (lda),
+// C row-major M x N (ldc).  b_nk = 0: B stored K x N row-major (ldb);
+// b_nk = 1: B stored N x K row-major (ldb), i.e. C = A B^T.
+// For GP_BF16X3 the basis operand (A when basis_is_A, else B) is given as
+// pre-split bf16 planes basis_hi / basis_lo in the same layout; the other
+// operand is split on the fly.
+struct GemmDesc {
+    const void* A;
+    const void* B;
+    void* C;
+    int M, N, K;
+    int lda, ldb, ldc;
+    long long sA, sB, sC;   // batch strides in elements (0 = shared)
+    int batch;
+    int b_nk;
+    int tA, tB, tC;         // DType of A, B, C in global memory (basis planes ignore tA/tB)
+    const uint16_t* basis_hi;
+    const uint16_t* basis_lo;
+    int basis_is_A;
+    int epi;                // Epilogue
+    double* partials;       // EPI_ACCUM_F64: 2 doubles per block
+    // filled by the launcher / work-list builder
+    int tiles_m, tiles_n;
+    long long block_begin;
+};
+
+long long gemm_blocks(const GemmDesc& g, int variant);
+// One launch for one descriptor.
+hipError_t launch_gemm(GemmDesc g, int prec, int variant, hipStream_t s);
+// One launch over a device array of descriptors (block_begin, tiles_m/n set
+// by the caller, sorted by block_begin, all with the same prec/variant/b_nk).
+hipError_t launch_gemm_multi(const GemmDesc* d_work, int nwork, long long total_blocks, int prec,
+                             int variant, int b_nk, hipStream_t s);
+
+// Thomas solve along z (§2.2.2 step 2.3) for nsys systems of nx*ny lines.
+struct ThomasDesc {
+    int nx, ny, nz, nsys;
+    const double* lamx;
+    const double* lamy;
+    const double* az;
+    const double* bz;
+    const double* cz;
+    double sigma, tau;
+    int pin_line;
+    const void* f;
+    void* x;
+    double* scratch;       // 2 doubles per unknown
+    int tf, tx;            // DType of f and x
+    long long line_begin;  // multi-problem: first global line
+};
+hipError_t launch_thomas(const ThomasDesc& t, hipStream_t s);
+hipError_t launch_thomas_multi(const ThomasDesc* d_work, int nwork, long long total_lines, hipStream_t s);
+
+// Residual r = f - A x of the 7-point operator in FP64, r stored as float,
+// with per-block partial sums (r^2, f^2).
+struct StencilDesc {
+    int nx, ny, nz;
+    const double* ax; const double* bx; const double* cx;
+    const double* ay; const double* by; const double* cy;
+    const double* az; const double* bz; const double* cz;
+    int perx, pery;
+    int helmholtz;
+    double alpha;
+    const double* x;
+    const double* f;
+    float* r;
+    double* partials;
+    long long block_begin;  // multi-problem
+};
+int residual_blocks(const StencilDesc& st);
+hipError_t launch_residual(const StencilDesc& st, hipStream_t s);
+hipError_t launch_residual_multi(const StencilDesc* d_work, int nwork, long long total_blocks, hipStream_t s);
+
+// Deterministic sum of n (a, b) pairs into out[0], out[1].
+hipError_t launch_reduce_pairs(const double* partials, int n, double* out, hipStream_t s);
+struct ReduceDesc {
+    const double* partials;
+    int n;
+    double* out;
+};
+hipError_t launch_reduce_pairs_multi(const ReduceDesc* d_work, int nwork, hipStream_t s);
+
+// Split float -> bf16 hi/lo planes (round to nearest even), n elements.
+hipError_t launch_split_bf16(const float* x, uint16_t* hi, uint16_t* lo, long long n, hipStream_t s);
+hipError_t launch_convert_f64_f32(const double* x, float* y, long long n, hipStream_t s);
+
+}  // namespace tpt

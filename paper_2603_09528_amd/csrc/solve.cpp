@@ -1,0 +1,555 @@
+// Solve sequencing (§2.2.2 solution steps 2.1–2.5 on one GPU, no transposes),
+// mixed-precision refinement, GEMM tile selection and kernel timing.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+
+#include "internal.h"
+
+namespace tpt {
+
+// ---- kernel timing ------------------------------------------------------------
+namespace {
+struct TimingRec {
+    std::string name;
+    hipEvent_t e0, e1;
+};
+std::mutex g_timing_mu;
+bool g_timing = false;
+std::vector<TimingRec> g_recs;
+std::vector<hipEvent_t> g_pool;
+
+hipEvent_t get_event() {
+    if (!g_pool.empty()) {
+        hipEvent_t e = g_pool.back();
+        g_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+}  // namespace
+
+bool timing_enabled() { return g_timing; }
+
+TimedScope::TimedScope(const char* n, hipStream_t st) : name(n), s(st) {
+    if (!g_timing) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+    std::lock_guard<std::mutex> lock(g_timing_mu);
+    e0 = get_event();
+    if (!e0) return;
+    if (hipEventRecord(e0, s) != hipSuccess) return;
+    on = true;
+}
+
+TimedScope::~TimedScope() {
+    if (!on) return;
+    std::lock_guard<std::mutex> lock(g_timing_mu);
+    hipEvent_t e1 = get_event();
+    if (!e1) return;
+    if (hipEventRecord(e1, s) != hipSuccess) return;
+    g_recs.push_back({name, e0, e1});
+}
+
+// ---- GEMM tile selection ---------------------------------------------------------
+namespace {
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune;
+
+std::string tune_key(int prec, int kind, int M, int N, int K) {
+    // the x pass has M = N_y N_z rows (large): its tile choice depends on N, K only
+    if (kind == 0) M = 0;
+    std::ostringstream os;
+    os << prec << ' ' << kind << ' ' << M << ' ' << N << ' ' << K;
+    return os.str();
+}
+}  // namespace
+
+void autotune_record(int prec, int kind, int M, int N, int K, int variant) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune[tune_key(prec, kind, M, N, K)] = variant;
+}
+
+int choose_variant(int prec, int kind, int M, int N, int K) {
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        auto it = g_tune.find(tune_key(prec, kind, M, N, K));
+        if (it != g_tune.end()) return it->second;
+    }
+    // heuristic: least padded area, then the larger tile
+    int best = TV_128x128;
+    double best_cost = 1e300;
+    for (int v = 0; v < TV_COUNT; ++v) {
+        int bm, bn;
+        tile_variant_shape(v, &bm, &bn);
+        const double pm = std::ceil((double)M / bm) * bm, pn = std::ceil((double)N / bn) * bn;
+        const double waste = pm * pn / ((double)M * N);
+        const double small = 1.0 + 0.08 * (128.0 * 128.0 / (bm * bn));  // smaller tiles reuse less
+        const double cost = waste * small;
+        if (cost < best_cost - 1e-12) {
+            best_cost = cost;
+            best = v;
+        }
+    }
+    return best;
+}
+
+// ---- stage descriptors ---------------------------------------------------------------
+GemmDesc stage_gemm(const tpt_plan_s* p, int stage, int prec, const void* in, int tin, void* out, int tout, int epi,
+                    double* partials, int nrhs) {
+    GemmDesc g{};
+    const int nx = p->N[0], ny = p->N[1], nz = p->N[2];
+    const DirBasis* b = (stage == ST_XF || stage == ST_XI) ? p->bx.get() : p->by.get();
+    const bool fwd = stage == ST_XF || stage == ST_YF;
+    const void* basis = nullptr;
+    const uint16_t *bh = nullptr, *bl = nullptr;
+    int tbasis = DT_F64;
+    if (prec == GP_F64) {
+        basis = fwd ? b->d_qinv : b->d_q;
+    } else if (prec == GP_F32) {
+        basis = fwd ? b->s_qinv : b->s_q;
+        tbasis = DT_F32;
+    } else {
+        bh = fwd ? b->h_qinv : b->h_q;
+        bl = fwd ? b->l_qinv : b->l_q;
+        tbasis = DT_F32;
+    }
+    g.basis_hi = bh;
+    g.basis_lo = bl;
+    g.epi = epi;
+    g.partials = partials;
+    g.tC = tout;
+    if (stage == ST_XF || stage == ST_XI) {
+        // C[m][p] = sum_i F[m][i] Qinv[p][i]  /  Phi[m][i] = sum_p S[m][p] Q[i][p]
+        g.A = in;
+        g.tA = tin;
+        g.B = basis;
+        g.tB = tbasis;
+        g.basis_is_A = 0;
+        g.b_nk = 1;
+        g.M = ny * nz * nrhs;
+        g.N = nx;
+        g.K = nx;
+        g.lda = nx;
+        g.ldb = nx;
+        g.ldc = nx;
+        g.batch = 1;
+    } else {
+        // per z slab: C[q][p] = sum_j Qinv_y[q][j] S[j][p]  /  C[j][p] = sum_q Q_y[j][q] S[q][p]
+        g.A = basis;
+        g.tA = tbasis;
+        g.B = in;
+        g.tB = tin;
+        g.basis_is_A = 1;
+        g.b_nk = 0;
+        g.M = ny;
+        g.N = nx;
+        g.K = ny;
+        g.lda = ny;
+        g.ldb = nx;
+        g.ldc = nx;
+        g.sA = 0;
+        g.sB = (long long)nx * ny;
+        g.sC = (long long)nx * ny;
+        g.batch = nz * nrhs;
+    }
+    g.C = out;
+    return g;
+}
+
+ThomasDesc plan_thomas(const tpt_plan_s* p, const void* f, int tf, void* x, int tx, double* scratch, int nrhs) {
+    ThomasDesc t{};
+    t.nx = p->N[0];
+    t.ny = p->N[1];
+    t.nz = p->N[2];
+    t.nsys = nrhs;
+    t.lamx = p->bx->d_lam;
+    t.lamy = p->by->d_lam;
+    t.az = p->buf.az;
+    t.bz = p->buf.bz;
+    t.cz = p->buf.cz;
+    t.sigma = p->sigma;
+    t.tau = p->tau;
+    t.pin_line = p->null_line;
+    t.f = f;
+    t.tf = tf;
+    t.x = x;
+    t.tx = tx;
+    t.scratch = scratch;
+    return t;
+}
+
+StencilDesc plan_stencil(const tpt_plan_s* p, const double* x, const double* f, float* r, double* partials) {
+    StencilDesc st{};
+    st.nx = p->N[0];
+    st.ny = p->N[1];
+    st.nz = p->N[2];
+    st.ax = p->buf.ax; st.bx = p->buf.bx; st.cx = p->buf.cx;
+    st.ay = p->buf.ay; st.by = p->buf.by; st.cy = p->buf.cy;
+    st.az = p->buf.az; st.bz = p->buf.bz; st.cz = p->buf.cz;
+    st.perx = p->op[0].periodic ? 1 : 0;
+    st.pery = p->op[1].periodic ? 1 : 0;
+    st.helmholtz = p->desc.kind == TPT_HELMHOLTZ ? 1 : 0;
+    st.alpha = p->desc.alpha;
+    st.x = x;
+    st.f = f;
+    st.r = r;
+    st.partials = partials;
+    return st;
+}
+
+static int stage_variant(const tpt_plan_s* p, int stage, const GemmDesc& g, int prec) {
+    if (p->gemm_variant[stage] >= 0) return p->gemm_variant[stage];
+    const int kind = (stage == ST_XF || stage == ST_XI) ? 0 : 1;
+    return choose_variant(prec, kind, g.M, g.N, g.K);
+}
+
+static const char* stage_name(int stage, int prec) {
+    static const char* n[3][4] = {
+        {"gemm_x_fwd_f64", "gemm_y_fwd_f64", "gemm_y_inv_f64", "gemm_x_inv_f64"},
+        {"gemm_x_fwd_f32", "gemm_y_fwd_f32", "gemm_y_inv_f32", "gemm_x_inv_f32"},
+        {"gemm_x_fwd_bf16x3", "gemm_y_fwd_bf16x3", "gemm_y_inv_bf16x3", "gemm_x_inv_bf16x3"}};
+    return n[prec][stage];
+}
+
+static int run_gemm(const tpt_plan_s* p, int stage, int prec, const void* in, int tin, void* out, int tout, int epi,
+                    double* partials, int nrhs, hipStream_t s, long long* nblocks = nullptr) {
+    GemmDesc g = stage_gemm(p, stage, prec, in, tin, out, tout, epi, partials, nrhs);
+    const int v = stage_variant(p, stage, g, prec);
+    if (nblocks) *nblocks = gemm_blocks(g, v);
+    TimedScope ts(stage_name(stage, prec), s);
+    hipError_t e = launch_gemm(g, prec, v, s);
+    if (e != hipSuccess) return fail(TPT_ERR_HIP, std::string("GEMM launch: ") + hipGetErrorString(e));
+    return TPT_OK;
+}
+
+static int run_thomas(const tpt_plan_s* p, const void* f, int tf, void* x, int tx, double* scratch, int nrhs,
+                      hipStream_t s) {
+    ThomasDesc t = plan_thomas(p, f, tf, x, tx, scratch, nrhs);
+    TimedScope ts(tf == DT_F64 ? "thomas_f64" : "thomas_f32io", s);
+    hipError_t e = launch_thomas(t, s);
+    if (e != hipSuccess) return fail(TPT_ERR_HIP, std::string("Thomas launch: ") + hipGetErrorString(e));
+    return TPT_OK;
+}
+
+// Workspace carve-up (see plan_workspace_bytes).
+struct Ws {
+    char* base;
+    size_t n;  // unknowns over all rhs
+    void* w1;
+    void* w2;
+    float* r;
+    double* scratch;
+    double* partials;
+};
+
+static inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static Ws carve(const tpt_plan_s* p, void* ws) {
+    Ws w{};
+    w.base = (char*)ws;
+    w.n = (size_t)p->dof * p->desc.nrhs;
+    const size_t n = w.n;
+    size_t o = 0;
+    if (p->desc.precision == TPT_FP64) {
+        w.w1 = w.base + o; o += al256(8 * n);
+        w.w2 = w.base + o; o += al256(8 * n);
+        w.scratch = (double*)(w.base + o); o += al256(16 * n);
+        w.r = nullptr;
+    } else {
+        w.scratch = (double*)(w.base + o); o += al256(16 * n);
+        w.w1 = w.base + o; o += al256(4 * n);
+        w.w2 = w.base + o; o += al256(4 * n);
+        w.r = (float*)(w.base + o); o += al256(4 * n);
+    }
+    w.partials = (double*)(w.base + o);
+    return w;
+}
+
+// FP64 path: 2.1 x forward, 2.2 y forward, 2.3 Thomas, 2.4 y inverse, 2.5 x inverse.
+static int solve_fp64(tpt_plan_s* p, const double* rhs, double* out, const Ws& w, hipStream_t s) {
+    const int R = p->desc.nrhs;
+    int rc;
+    if ((rc = run_gemm(p, ST_XF, GP_F64, rhs, DT_F64, w.w1, DT_F64, EPI_STORE, nullptr, R, s))) return rc;
+    if ((rc = run_gemm(p, ST_YF, GP_F64, w.w1, DT_F64, w.w2, DT_F64, EPI_STORE, nullptr, R, s))) return rc;
+    if ((rc = run_thomas(p, w.w2, DT_F64, w.w2, DT_F64, w.scratch, R, s))) return rc;
+    if ((rc = run_gemm(p, ST_YI, GP_F64, w.w2, DT_F64, w.w1, DT_F64, EPI_STORE, nullptr, R, s))) return rc;
+    if ((rc = run_gemm(p, ST_XI, GP_F64, w.w1, DT_F64, out, DT_F64, EPI_STORE, nullptr, R, s))) return rc;
+    p->info.iters = 0;
+    p->info.rel_correction = 0.0;
+    p->info.rel_residual = -1.0;
+    return TPT_OK;
+}
+
+// Low-precision application of M^{-1} to `in` (FP64 rhs or FP32 residual):
+// result stored into out (epi STORE) or added to out (epi ACCUM, with norm
+// partials of the correction and the updated iterate).
+static int apply_minv(tpt_plan_s* p, int prec, const void* in, int tin, double* out, int epi, const Ws& w,
+                      hipStream_t s, long long* xi_blocks) {
+    const int R = p->desc.nrhs;
+    int rc;
+    if ((rc = run_gemm(p, ST_XF, prec, in, tin, w.w1, DT_F32, EPI_STORE, nullptr, R, s))) return rc;
+    if ((rc = run_gemm(p, ST_YF, prec, w.w1, DT_F32, w.w2, DT_F32, EPI_STORE, nullptr, R, s))) return rc;
+    if ((rc = run_thomas(p, w.w2, DT_F32, w.w2, DT_F32, w.scratch, R, s))) return rc;
+    if ((rc = run_gemm(p, ST_YI, prec, w.w2, DT_F32, w.w1, DT_F32, EPI_STORE, nullptr, R, s))) return rc;
+    if ((rc = run_gemm(p, ST_XI, prec, w.w1, DT_F32, out, DT_F64, epi, w.partials, R, s, xi_blocks))) return rc;
+    return TPT_OK;
+}
+
+// Mixed path: x0 = M^{-1} f; then repeat r = f - A x (FP64), x += M^{-1} r.
+static int solve_mixed(tpt_plan_s* p, const double* rhs, double* out, const Ws& w, hipStream_t s) {
+    const int prec = plan_gemm_prec(p);
+    const int R = p->desc.nrhs;
+    int rc;
+    long long xi_blocks = 0;
+    if ((rc = apply_minv(p, prec, rhs, DT_F64, out, EPI_STORE, w, s, &xi_blocks))) return rc;
+    const bool adaptive = p->desc.fixed_refine < 0;
+    const int max_it = adaptive ? p->desc.max_refine : p->desc.fixed_refine;
+    double* dn = p->buf.norms;  // [0,1] = (r^2, f^2), [2,3] = (e^2, x^2)
+    int it = 0;
+    double rel_e = 0.0, rel_r = -1.0;
+    for (it = 0; it < max_it;) {
+        // residual of every rhs, partials packed back to back
+        long long pb = 0;
+        for (int r = 0; r < R; ++r) {
+            StencilDesc st = plan_stencil(p, out + (size_t)r * p->dof, rhs + (size_t)r * p->dof,
+                                          w.r + (size_t)r * p->dof, w.partials + 2 * pb);
+            TimedScope ts("residual_f64", s);
+            hipError_t e = launch_residual(st, s);
+            if (e != hipSuccess) return fail(TPT_ERR_HIP, std::string("residual launch: ") + hipGetErrorString(e));
+            pb += residual_blocks(st);
+        }
+        {
+            TimedScope ts("reduce", s);
+            hipError_t e = launch_reduce_pairs(w.partials, (int)pb, dn, s);
+            if (e != hipSuccess) return fail(TPT_ERR_HIP, hipGetErrorString(e));
+        }
+        if ((rc = apply_minv(p, prec, w.r, DT_F32, out, EPI_ACCUM_F64, w, s, &xi_blocks))) return rc;
+        {
+            TimedScope ts("reduce", s);
+            hipError_t e = launch_reduce_pairs(w.partials, (int)xi_blocks, dn + 2, s);
+            if (e != hipSuccess) return fail(TPT_ERR_HIP, hipGetErrorString(e));
+        }
+        ++it;
+        if (adaptive) {
+            TPT_HIP(hipMemcpyAsync(p->h_norms, dn, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+            TPT_HIP(hipStreamSynchronize(s));
+            const double* h = p->h_norms;
+            rel_r = h[1] > 0 ? std::sqrt(h[0] / h[1]) : 0.0;
+            rel_e = h[3] > 0 ? std::sqrt(h[2] / h[3]) : 0.0;
+            if (!(rel_e == rel_e)) return fail(TPT_ERR_NOT_CONVERGED, "non-finite correction");
+            if (rel_e <= p->desc.rtol) break;
+        }
+    }
+    p->info.iters = it;
+    if (!adaptive) {
+        // norms are read back lazily by tpt_solve_info
+        p->info.rel_correction = -2.0;
+        p->info.rel_residual = -2.0;
+    } else {
+        p->info.rel_correction = rel_e;
+        p->info.rel_residual = rel_r;
+        if (rel_e > p->desc.rtol && it >= max_it)
+            return fail(TPT_ERR_NOT_CONVERGED, "refinement stopped at ||e||/||x|| = " + std::to_string(rel_e));
+    }
+    return TPT_OK;
+}
+
+int solve_one(tpt_plan_s* p, const double* rhs, double* out, void* ws, size_t ws_bytes, hipStream_t s) {
+    if (p->host_only) return fail(TPT_ERR_INVALID, "host-only plan cannot solve");
+    if (!rhs || !out) return fail(TPT_ERR_INVALID, "NULL rhs or out");
+    const size_t bytes = (size_t)p->dof * p->desc.nrhs * sizeof(double);
+    const char* a0 = (const char*)rhs;
+    const char* b0 = (const char*)out;
+    if (a0 < b0 + bytes && b0 < a0 + bytes) return fail(TPT_ERR_ALIAS, "rhs and out overlap");
+    const size_t need = plan_workspace_bytes(p);
+    if (!ws) {
+        if (p->own_ws_bytes < need) {
+            if (p->own_ws) TPT_HIP(hipFree(p->own_ws));
+            p->own_ws = nullptr;
+            p->own_ws_bytes = 0;
+            if (hipMalloc(&p->own_ws, need) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(TPT_ERR_OOM, "cannot allocate the plan workspace");
+            }
+            p->own_ws_bytes = need;
+        }
+        ws = p->own_ws;
+        ws_bytes = p->own_ws_bytes;
+    }
+    if (ws_bytes < need) return fail(TPT_ERR_WORKSPACE, "workspace too small: need " + std::to_string(need));
+    Ws w = carve(p, ws);
+    if (p->desc.precision == TPT_FP64) return solve_fp64(p, rhs, out, w, s);
+    return solve_mixed(p, rhs, out, w, s);
+}
+
+}  // namespace tpt
+
+using namespace tpt;
+
+extern "C" {
+
+int tpt_solve(tpt_plan plan, const double* rhs, double* out, void* workspace, size_t workspace_bytes, void* stream) {
+    if (!plan) return fail(TPT_ERR_INVALID, "NULL plan");
+    int cur = 0;
+    if (hipGetDevice(&cur) == hipSuccess && cur != plan->device) TPT_HIP(hipSetDevice(plan->device));
+    return solve_one(plan, rhs, out, workspace, workspace_bytes, (hipStream_t)stream);
+}
+
+int tpt_solve_info(tpt_plan plan, tpt_info* info) {
+    if (!plan || !info) return fail(TPT_ERR_INVALID, "NULL argument");
+    if (plan->info.rel_correction == -2.0) {
+        // fixed-refinement mode: the norms of the last correction are on the device
+        double h[4];
+        TPT_HIP(hipMemcpy(h, plan->buf.norms, sizeof(h), hipMemcpyDeviceToHost));
+        plan->info.rel_residual = h[1] > 0 ? std::sqrt(h[0] / h[1]) : 0.0;
+        plan->info.rel_correction = h[3] > 0 ? std::sqrt(h[2] / h[3]) : 0.0;
+        if (plan->info.iters == 0) {
+            plan->info.rel_residual = -1.0;
+            plan->info.rel_correction = 0.0;
+        }
+    }
+    *info = plan->info;
+    return TPT_OK;
+}
+
+int tpt_thomas(int nx, int ny, int nz, int nsys, const double* lamx, const double* lamy, const double* az,
+               const double* bz, const double* cz, double sigma, double tau, int pin_line, const double* f, double* x,
+               double* scratch, void* stream) {
+    if (nx < 1 || ny < 1 || nz < 1 || nsys < 1) return fail(TPT_ERR_INVALID, "bad sizes");
+    if (!lamx || !lamy || !az || !bz || !cz || !f || !x || !scratch) return fail(TPT_ERR_INVALID, "NULL pointer");
+    if (pin_line >= nx * ny) return fail(TPT_ERR_INVALID, "pin_line out of range");
+    ThomasDesc t{};
+    t.nx = nx; t.ny = ny; t.nz = nz; t.nsys = nsys;
+    t.lamx = lamx; t.lamy = lamy; t.az = az; t.bz = bz; t.cz = cz;
+    t.sigma = sigma; t.tau = tau; t.pin_line = pin_line;
+    t.f = f; t.tf = DT_F64; t.x = x; t.tx = DT_F64; t.scratch = scratch;
+    TimedScope ts("thomas_f64", (hipStream_t)stream);
+    hipError_t e = launch_thomas(t, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(TPT_ERR_HIP, hipGetErrorString(e));
+    return TPT_OK;
+}
+
+int tpt_gemm(int prec, int M, int N, int K, int batch, const void* A, long long strideA, const void* B,
+             long long strideB, void* C, long long strideC, void* stream) {
+    if (M < 1 || N < 1 || K < 1 || batch < 1 || !A || !B || !C) return fail(TPT_ERR_INVALID, "bad GEMM arguments");
+    if (prec < TPT_FP64 || prec > TPT_MIXED_BF16X3) return fail(TPT_ERR_INVALID, "bad precision");
+    GemmDesc g{};
+    g.A = A; g.B = B; g.C = C;
+    g.M = M; g.N = N; g.K = K; g.lda = K; g.ldb = N; g.ldc = N;
+    g.sA = strideA; g.sB = strideB; g.sC = strideC; g.batch = batch;
+    g.b_nk = 0;
+    const int t = prec == TPT_FP64 ? DT_F64 : DT_F32;
+    g.tA = g.tB = g.tC = t;
+    g.epi = EPI_STORE;
+    const int gp = prec == TPT_FP64 ? GP_F64 : (prec == TPT_MIXED_FP32 ? GP_F32 : GP_BF16X3);
+    std::vector<uint16_t> dummy;
+    void* planes = nullptr;
+    if (gp == GP_BF16X3) {
+        // split the shared-or-batched A operand into bf16 planes on the device
+        const long long na = strideA ? strideA * batch : (long long)M * K;
+        if (hipMalloc(&planes, 2 * sizeof(uint16_t) * na) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(TPT_ERR_OOM, "GEMM planes");
+        }
+        uint16_t* hi = (uint16_t*)planes;
+        uint16_t* lo = hi + na;
+        hipError_t e = launch_split_bf16((const float*)A, hi, lo, na, (hipStream_t)stream);
+        if (e != hipSuccess) {
+            (void)hipFree(planes);
+            return fail(TPT_ERR_HIP, hipGetErrorString(e));
+        }
+        g.basis_hi = hi;
+        g.basis_lo = lo;
+        g.basis_is_A = 1;
+    }
+    const int v = choose_variant(gp, 1, M, N, K);
+    hipError_t e;
+    {
+        TimedScope ts("gemm_test", (hipStream_t)stream);
+        e = launch_gemm(g, gp, v, (hipStream_t)stream);
+    }
+    if (planes) {
+        (void)hipStreamSynchronize((hipStream_t)stream);
+        (void)hipFree(planes);
+    }
+    if (e != hipSuccess) return fail(TPT_ERR_HIP, hipGetErrorString(e));
+    return TPT_OK;
+}
+
+int tpt_timing_enable(int enable) {
+    std::lock_guard<std::mutex> lock(g_timing_mu);
+    g_timing = enable != 0;
+    return TPT_OK;
+}
+
+int tpt_timing_collect(int* count, char* names, size_t names_len, double* total_ms, long long* launches) {
+    if (!count) return fail(TPT_ERR_INVALID, "NULL count");
+    std::lock_guard<std::mutex> lock(g_timing_mu);
+    std::vector<std::string> kinds;
+    std::vector<double> ms;
+    std::vector<long long> cnt;
+    for (auto& r : g_recs) {
+        if (hipEventSynchronize(r.e1) != hipSuccess) return fail(TPT_ERR_HIP, "event sync failed");
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, r.e0, r.e1) != hipSuccess) t = 0.f;
+        size_t k = 0;
+        for (; k < kinds.size(); ++k)
+            if (kinds[k] == r.name) break;
+        if (k == kinds.size()) {
+            kinds.push_back(r.name);
+            ms.push_back(0.0);
+            cnt.push_back(0);
+        }
+        ms[k] += t;
+        cnt[k] += 1;
+        g_pool.push_back(r.e0);
+        g_pool.push_back(r.e1);
+    }
+    g_recs.clear();
+    const int cap = *count;
+    size_t pos = 0;
+    for (int k = 0; k < (int)kinds.size() && k < cap; ++k) {
+        if (total_ms) total_ms[k] = ms[k];
+        if (launches) launches[k] = cnt[k];
+        if (names && pos + kinds[k].size() + 1 <= names_len) {
+            std::memcpy(names + pos, kinds[k].c_str(), kinds[k].size() + 1);
+            pos += kinds[k].size() + 1;
+        }
+    }
+    *count = (int)kinds.size();
+    return TPT_OK;
+}
+
+int tpt_autotune_save(const char* path) {
+    if (!path) return fail(TPT_ERR_INVALID, "NULL path");
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    std::ofstream f(path);
+    if (!f) return fail(TPT_ERR_INVALID, "cannot open " + std::string(path));
+    f << "# prec kind M N K variant\n";
+    for (auto& kv : g_tune) f << kv.first << ' ' << kv.second << '\n';
+    return TPT_OK;
+}
+
+int tpt_autotune_load(const char* path) {
+    if (!path) return fail(TPT_ERR_INVALID, "NULL path");
+    std::ifstream f(path);
+    if (!f) return fail(TPT_ERR_INVALID, "cannot open " + std::string(path));
+    std::string line;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    while (std::getline(f, line)) {
+        if (line.empty() || line[0] == '#') continue;
+        std::istringstream is(line);
+        int prec, kind, M, N, K, v;
+        if (!(is >> prec >> kind >> M >> N >> K >> v)) continue;
+        if (v < 0 || v >= TV_COUNT) continue;
+        g_tune[tune_key(prec, kind, M, N, K)] = v;
+    }
+    return TPT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,100 @@
+"""Kernel-level parity on the GPU: the batched Thomas kernel and the MFMA
+GEMM kernels, called through the C-ABI on explicit seeded inputs, against
+the oracle's Thomas lines and numpy products."""
+import numpy as np
+import pytest
+
+import oracle as O
+from tests.gpu_util import cuda, host, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _T():
+    import paper_2603_09528_amd as T
+    return T
+
+
+@pytest.mark.parametrize("nx,ny,nz,nsys", [(37, 5, 11, 1), (64, 64, 33, 2), (3, 2, 2, 1), (1, 1, 1, 1), (130, 7, 64, 1)])
+@pytest.mark.parametrize("sigma,tau", [(0.0, 1.0), (1.0, -3e-3)])
+def test_thomas_matches_oracle(nx, ny, nz, nsys, sigma, tau):
+    import torch
+    T = _T()
+    say("thomas", nx, ny, nz, nsys, sigma, tau)
+    rng = np.random.default_rng(nx * 1000 + ny * 10 + nz)
+    w = rng.uniform(0.5, 2.0, nz)
+    az = rng.uniform(0.5, 2.0, nz)
+    cz = rng.uniform(0.5, 2.0, nz)
+    az[0] = 0.0
+    cz[-1] = 0.0
+    bz = -(az + cz) - rng.uniform(0.0, 0.3, nz)
+    lamx = -rng.uniform(0.0, 50.0, nx)
+    lamy = -rng.uniform(0.0, 50.0, ny)
+    f = rng.standard_normal((nsys, nz, ny, nx))
+    lam = lamy[:, None] + lamx[None, :]
+    ref = np.stack([O.thomas_lines(az, bz, cz, lam, sigma, tau, f[s])[0] for s in range(nsys)])
+    x = torch.empty(f.shape, dtype=torch.float64, device="cuda")
+    scratch = torch.empty((2,) + f.shape, dtype=torch.float64, device="cuda")
+    T.thomas(nx, ny, nz, nsys, cuda(lamx), cuda(lamy), cuda(az), cuda(bz), cuda(cz), sigma, tau, -1,
+             cuda(f), x, scratch)
+    torch.cuda.synchronize()
+    got = host(x)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+    del w
+
+
+def test_thomas_pinned_line_in_place():
+    import torch
+    T = _T()
+    nx, ny, nz = 9, 4, 17
+    rng = np.random.default_rng(5)
+    faces = np.cumsum(np.concatenate([[0.0], rng.uniform(0.5, 1.5, nz)]))
+    az, bz, cz, _ = O.operator_1d(faces, ("N", "N"), "C")
+    lamx = -rng.uniform(1.0, 20.0, nx)
+    lamy = -rng.uniform(1.0, 20.0, ny)
+    lamx[3] = 0.0
+    lamy[2] = 0.0
+    f = rng.standard_normal((nz, ny, nx))
+    lam = lamy[:, None] + lamx[None, :]
+    ref, _ = O.thomas_lines(az, bz, cz, lam, 0.0, 1.0, f, pin=(2, 3))
+    xf = cuda(f)
+    scratch = torch.empty((2, nz, ny, nx), dtype=torch.float64, device="cuda")
+    T.thomas(nx, ny, nz, 1, cuda(lamx), cuda(lamy), cuda(az), cuda(bz), cuda(cz), 0.0, 1.0, 3 + nx * 2,
+             xf, xf, scratch)
+    torch.cuda.synchronize()
+    got = host(xf)
+    assert got[-1, 2, 3] == 0.0
+    assert np.isfinite(got).all()
+    assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+GEMM_SHAPES = [(1, 1, 1, 1), (16, 16, 16, 1), (37, 53, 29, 3), (128, 128, 128, 1), (200, 131, 77, 2),
+               (256, 64, 256, 1), (33, 300, 17, 1)]
+
+
+@pytest.mark.parametrize("M,N,K,batch", GEMM_SHAPES)
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_gemm_matches_numpy(prec, M, N, K, batch):
+    import torch
+    T = _T()
+    say("gemm", prec, M, N, K, batch)
+    rng = np.random.default_rng(M + 7 * N + 13 * K)
+    A = rng.standard_normal((batch, M, K))
+    B = rng.standard_normal((batch, K, N))
+    if prec == "fp64":
+        dt, tol = torch.float64, 1e-14
+    else:
+        dt = torch.float32
+        A = A.astype(np.float32).astype(np.float64)
+        B = B.astype(np.float32).astype(np.float64)
+        tol = 2e-6 if prec == "fp32" else 2e-5
+    ref = A @ B
+    Ad = torch.from_numpy(A).to("cuda", dt)
+    Bd = torch.from_numpy(B).to("cuda", dt)
+    C = torch.empty((batch, M, N), dtype=dt, device="cuda")
+    T.gemm(prec, Ad, Bd, C, M, N, K, batch, M * K, K * N, M * N)
+    torch.cuda.synchronize()
+    got = host(C).astype(np.float64)
+    scale = np.abs(A).max() * np.abs(B).max() * K
+    err = np.abs(got - ref).max() / scale
+    assert err <= tol, err

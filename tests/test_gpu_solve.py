@@ -1,0 +1,142 @@
+"""Solve parity on the GPU: the HIP path (through the C-ABI) against the CPU
+oracle on the same seeded inputs, FP64 at <= 1e-12 and the mixed-precision
+refined modes at <= 1e-10 (relative 2-norm after gauge normalisation)."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from tests.gpu_util import cuda, host, say
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+MIXED_TOL = 1e-10
+
+
+def _T():
+    import paper_2603_09528_amd as T
+    return T
+
+
+def _solve(p, f, **kw):
+    import torch
+    T = _T()
+    plan = T.Plan.from_problem(p, **kw)
+    out = plan.solve(cuda(f))
+    torch.cuda.synchronize()
+    return host(out), plan
+
+
+def test_cavity32_fp64_matches_oracle():
+    p = W.cavity32()
+    f = W.rhs(p, 1, "uniform")
+    say("cavity32", p.shape)
+    got, plan = _solve(p, f)
+    ref = O.solve(p, f)
+    assert O.relative_error(p, got, ref) <= FP64_TOL
+    r = O.residual(p, f, got)
+    assert np.linalg.norm(r) / np.linalg.norm(f) <= 1e-12
+    assert plan.info().null_line >= 0
+
+
+def test_cavity32_mms():
+    p, f, u = W.cavity32_mms()
+    got, _ = _solve(p, f)
+    ref = O.solve(p, f)
+    assert O.relative_error(p, got, ref) <= FP64_TOL
+    # discretisation error of the manufactured case, as the oracle's
+    assert abs(O.relative_error(p, got, u) - O.relative_error(p, ref, u)) <= 1e-9
+
+
+SMALL = [
+    ((37, 29, 23), (1.5, 2.0, 1.0), (W.NN, W.NN, W.NN), ("C", "C", "C"), "poisson"),
+    ((48, 31, 17), (0.0, 2.0, 2.0), (W.PP, W.NN, W.NN), ("C", "C", "C"), "poisson"),
+    ((33, 40, 19), (2.5, 0.0, 1.5), (("N", "D"), W.PP, W.DD), ("C", "C", "C"), "poisson"),
+    ((65, 18, 21), (1.0, 2.0, 2.0), (W.DD, W.DD, ("D", "N")), ("C", "F", "C"), "helmholtz"),
+    ((32, 24, 16), (0.0, 2.0, 2.0), (W.PP, W.DD, W.DD), ("F", "C", "F"), "helmholtz"),
+    ((130, 70, 9), (2.0, 1.0, 0.5), (W.PP, ("D", "N"), W.NN), ("C", "C", "C"), "poisson"),
+    ((2, 2, 2), (1.0, 1.0, 1.0), (W.NN, W.NN, W.NN), ("C", "C", "C"), "poisson"),
+    ((3, 2, 5), (1.0, 1.0, 1.0), (W.PP, W.DD, W.NN), ("C", "C", "C"), "helmholtz"),
+]
+
+
+def _small_problem(case):
+    n, beta, bc, loc, kind = case
+    return W.make_problem(n, beta, bc, loc=loc, kind=kind, alpha=1e-3 if kind == "helmholtz" else 0.0)
+
+
+@pytest.mark.parametrize("case", SMALL, ids=lambda c: f"{c[0][0]}x{c[0][1]}x{c[0][2]}-{c[4]}")
+def test_small_fp64_matches_oracle(case):
+    p = _small_problem(case)
+    f = W.rhs(p, 11)
+    say("small fp64", p.n, p.bc, p.loc, p.kind)
+    got, _ = _solve(p, f)
+    ref = O.solve(p, f)
+    assert O.relative_error(p, got, ref) <= FP64_TOL
+
+
+@pytest.mark.parametrize("case", SMALL, ids=lambda c: f"{c[0][0]}x{c[0][1]}x{c[0][2]}-{c[4]}")
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_small_mixed_matches_oracle(case, prec):
+    p = _small_problem(case)
+    f = W.rhs(p, 12)
+    say("small mixed", prec, p.n, p.bc, p.loc, p.kind)
+    got, plan = _solve(p, f, precision=prec, rtol=1e-13, max_refine=12)
+    ref = O.solve(p, f)
+    err = O.relative_error(p, got, ref)
+    say("  iters", plan.info().iters, "err", err)
+    assert err <= MIXED_TOL
+
+
+def test_nrhs_batch_equals_single():
+    import torch
+    T = _T()
+    p = _small_problem(SMALL[3])
+    fs = np.stack([W.rhs(p, 21), W.rhs(p, 22), W.rhs(p, 23)])
+    plan3 = T.Plan.from_problem(p, nrhs=3)
+    out3 = host(plan3.solve(cuda(fs)))
+    plan1 = T.Plan.from_problem(p)
+    for i in range(3):
+        o1 = host(plan1.solve(cuda(fs[i])))
+        ref = O.solve(p, fs[i])
+        assert O.relative_error(p, out3[i], ref) <= FP64_TOL
+        assert O.relative_error(p, o1, ref) <= FP64_TOL
+    torch.cuda.synchronize()
+
+
+def test_rhs_out_alias_rejected():
+    import torch
+    T = _T()
+    p = _small_problem(SMALL[0])
+    plan = T.Plan.from_problem(p)
+    x = cuda(W.rhs(p, 1))
+    with pytest.raises(T.TptError) as ei:
+        plan.solve(x, x)
+    assert ei.value.code == -4
+    torch.cuda.synchronize()
+
+
+def test_repeatable_bitwise():
+    p = _small_problem(SMALL[1])
+    f = W.rhs(p, 5)
+    a, _ = _solve(p, f)
+    b, _ = _solve(p, f)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.slow
+def test_channel256_fp64_and_mixed_match_oracle():
+    p = W.channel256()
+    f = W.rhs(p, 2)
+    say("channel256 oracle")
+    ref = O.solve(p, f)
+    say("channel256 fp64")
+    got, _ = _solve(p, f)
+    assert O.relative_error(p, got, ref) <= FP64_TOL
+    for prec in ("fp32", "bf16x3"):
+        say("channel256", prec)
+        got, plan = _solve(p, f, precision=prec, rtol=1e-12, max_refine=12)
+        err = O.relative_error(p, got, ref)
+        say("  iters", plan.info().iters, "err", err)
+        assert err <= MIXED_TOL
