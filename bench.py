@@ -1,0 +1,233 @@
+#!/usr/bin/env python3
+"""Benchmark: GDOF/s per Poisson solve on one MI355X, mixed precision vs FP64
+at <= 1e-10 relative error, with per-solve p50/p99 latency.
+
+Workload: the 256^3 channel-like Poisson problem (x uniform periodic with the
+Fourier eigenbasis applied by GEMM, y tanh-stretched Neumann beta = 2 by GEMM,
+z tanh-stretched Neumann beta = 2 by Thomas), seeded Gaussian right-hand side
+with its volume-weighted mean removed.  A step is one complete solve (x and y
+forward transforms, Thomas, inverse transforms, and for the mixed modes the
+FP64 residual/refinement loop) with the input already resident in HBM; the
+eigendecomposition (plan) is one-time initialization and is not timed.
+
+Prints one JSON line.  ``--gpus`` above 1 is refused: this build measures one
+GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
+TOL = 1e-10
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--modes", default="fp64,fp32,bf16x3")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--n", type=int, default=256, help="cells per direction (default: the 256^3 workload)")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2603_09528_amd", "csrc", "kernels.hip"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel_name):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernels_hip_sha256_16") != kernel_hash():
+        return None
+    ent = d.get("kernels", {}).get(kernel_name)
+    return None if ent is None else ent.get("hbm_bytes_per_launch")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only (--gpus 1); "
+                          "multi-GPU sharding is a design in DESIGN.md, not part of this build"}))
+        sys.exit(2)
+    import torch
+    import paper_2603_09528_amd as T
+    import workloads as W
+
+    if not torch.cuda.is_available():
+        raise SystemExit("no GPU visible")
+    torch.cuda.set_device(0)
+    n = args.n
+    prob = W.make_problem((n, n, n), (0.0, 2.0, 2.0), (W.PP, W.NN, W.NN), name=f"channel{n}_pnn_b2")
+    f_host = W.rhs(prob, 2)
+    f = torch.from_numpy(f_host).to("cuda")
+    dof = prob.dof
+    stream = torch.cuda.current_stream()
+    modes = [m for m in args.modes.split(",") if m]
+
+    results = {}
+    outs = {}
+    for mode in modes:
+        t0 = time.time()
+        if mode == "fp64":
+            plan = T.Plan.from_problem(prob)
+            iters = 0
+        else:
+            # calibrate the number of corrections with the adaptive stop rule
+            # (||e||/||x|| <= 1e-11), then time that count with no host syncs
+            cal = T.Plan.from_problem(prob, precision=mode, rtol=1e-11, max_refine=12)
+            try:
+                cal.solve(f)
+                iters = cal.info().iters
+            except T.TptError as e:
+                log(f"{mode}: refinement did not converge ({e}); skipped")
+                continue
+            plan = T.Plan.from_problem(prob, precision=mode, fixed_refine=iters)
+        log(f"{mode}: plan {time.time() - t0:.2f}s, corrections {iters}")
+        out = torch.empty_like(f)
+        ws = plan.workspace()
+        for _ in range(args.warmup):
+            plan.solve(f, out, ws)
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        T.timing_collect()
+        T.timing_enable(True)
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for k in range(args.steps):
+            evs[k][0].record(stream)
+            plan.solve(f, out, ws)
+            evs[k][1].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_start
+        T.timing_enable(False)
+        kern = T.timing_collect()
+        lat = np.array([a.elapsed_time(b) for a, b in evs])
+        ms = wall * 1e3 / args.steps
+        results[mode] = {
+            "ms_per_solve": ms,
+            "gdofs": dof / (ms * 1e-3) / 1e9,
+            "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)),
+            "corrections": iters,
+            "kernels_ms_per_solve": {k: v[0] / args.steps for k, v in kern.items()},
+            "kernel_launches": {k: int(v[1]) for k, v in kern.items()},
+        }
+        outs[mode] = out.detach().cpu().numpy()
+        log(f"{mode}: {ms:.3f} ms/solve, {results[mode]['gdofs']:.2f} GDOF/s")
+        del plan
+
+    # ---- CPU oracle: baseline timing on a bounded sample, and the error check ----
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle as O
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+        except Exception:
+            cores = os.cpu_count()
+        t0 = time.time()
+        oplan = O.solver.Plan(prob)
+        t_plan = time.time() - t0
+        solves = 0
+        t0 = time.time()
+        ref = None
+        while True:
+            ref = oplan.solve(f_host)
+            solves += 1
+            if time.time() - t0 >= args.cpu_seconds or solves >= 50:
+                break
+        t_cpu = (time.time() - t0) / solves
+        cpu = {"value": dof / t_cpu / 1e9, "unit": "GDOF/s", "cores": int(cores), "kind": "oracle",
+               "sample": f"{solves} full {n}^3 FP64 oracle solves ({t_cpu:.2f} s each; "
+                         f"Jacobi eigendecomposition {t_plan:.1f} s, untimed)"}
+        for mode, out in outs.items():
+            results[mode]["rel_err_vs_oracle"] = O.relative_error(prob, out, ref)
+            log(f"{mode}: rel err vs oracle {results[mode]['rel_err_vs_oracle']:.3e}")
+
+    # ---- headline: fastest mode that meets the 1e-10 bar -------------------------
+    ok = [m for m in results if results[m].get("rel_err_vs_oracle", 0.0) <= TOL]
+    best = max(ok or list(results), key=lambda m: results[m]["gdofs"])
+    r = results[best]
+    # dominant kernel of the headline mode and its roofline
+    kname, kms = max(r["kernels_ms_per_solve"].items(), key=lambda kv: kv[1])
+    launches = r["kernel_launches"][kname] / args.steps
+    per_launch_ms = kms / launches
+    nalpha = n
+    if kname.startswith("gemm"):
+        dt = kname.rsplit("_", 1)[1]
+        mult = 3 if dt == "bf16x3" else 1
+        flops = 2.0 * nalpha * dof * mult
+        peak = PEAK_TFLOPS["bf16" if dt == "bf16x3" else dt]
+        elem = 8 if dt == "f64" else 4
+        ai = flops / (2 * elem * dof)
+        ridge = peak * 1e12 / (HBM_PEAK_GBS * 1e9)
+        if ai >= ridge:
+            achieved = flops / (per_launch_ms * 1e-3) / 1e12
+            roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s"}
+        else:
+            achieved = 2 * elem * dof / (per_launch_ms * 1e-3) / 1e9
+            roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    else:
+        byt = 16.0 * dof if "f64" in kname else 8.0 * dof
+        achieved = byt / (per_launch_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["kernel"] = kname
+    roof["ms_per_launch"] = per_launch_ms
+    roof["traffic"] = load_traffic(kname)
+
+    dtype = {"fp64": "f64", "fp32": "f32 transforms, f64 refinement",
+             "bf16x3": "bf16x3 transforms (f32 accumulate), f64 refinement"}[best]
+    line = {
+        "metric": "GDOF/s per Poisson solve, mixed vs FP64 at <=1e-10 rel err; p99 solve latency",
+        "value": r["gdofs"],
+        "unit": "GDOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_solve"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic (seeded Gaussian RHS, volume-weighted mean removed)",
+        "config": {"workload": f"channel{n}: {n}^3 Poisson, x periodic uniform (Fourier basis by GEMM), "
+                               f"y,z Neumann tanh beta=2 (y by GEMM, z by Thomas)",
+                   "dof": dof, "mode": best},
+        "p50_ms": r["p50_ms"],
+        "p99_ms": r["p99_ms"],
+        "modes": results,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -10,28 +10,25 @@
  * Schur decomposition), swept over all off-diagonal pairs in the round-robin
  * ("parallel") ordering of §8.5.5: each of the n'-1 rounds of a sweep applies
  * n'/2 disjoint rotations, which commute, so a round is one orthogonal
- * similarity A <- J^T A J, V <- V J.  Sweeps repeat until the off-diagonal
- * Frobenius norm is below tol * ||A||_F.
+ * similarity A <- J^T A J, V <- V J.  Sweeps repeat until one sweep finds
+ * every off-diagonal entry negligible (|a_pq| <= tol sqrt(|a_pp a_qq|), the
+ * relative criterion of Demmel & Veselic, or |a_pq| <= tol^2 max|a|).
  *
  * Plain C, no BLAS/LAPACK.  OpenMP only splits the independent row/column
  * updates of a round across threads.
+ *
+ * Precision: the rotations are accumulated in 80-bit extended precision
+ * (C long double, 64-bit significand) and rounded to double at the end.  A
+ * double-precision eigensolver determines an eigenvector only to about
+ * eps ||T|| / gap; on a stretched grid with N ~ 10^2-10^3 that is 10^-12 to
+ * 10^-11 for the smooth low modes that carry the solution of a Poisson
+ * problem, which would make the oracle itself miss a 10^-12 comparison.
  */
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
-static double off_norm2(int n, const double *A, double *fro2)
-{
-    double off = 0.0, all = 0.0;
-    for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) {
-            double v = A[(size_t)i * n + j];
-            all += v * v;
-            if (i != j) off += v * v;
-        }
-    *fro2 = all;
-    return off;
-}
+typedef long double real;
 
 /* Round-robin schedule: m players (m even), round r in [0, m-1).  Player m-1
  * is fixed; the others rotate.  Fills pairs[2*i], pairs[2*i+1]. */
@@ -46,26 +43,32 @@ static void round_pairs(int m, int r, int *pairs)
 }
 
 /*
- * A: n*n row-major symmetric, overwritten (ends nearly diagonal).
- * V: n*n row-major output, columns are the eigenvectors.
+ * Ad: n*n row-major symmetric, overwritten (ends nearly diagonal).
+ * Vd: n*n row-major output, columns are the eigenvectors.
  * w: n output eigenvalues (unsorted, w[i] belongs to column i of V).
  * Returns the number of sweeps used, or -1 if max_sweeps was reached.
  */
-int oracle_jacobi(int n, double *A, double *V, double *w, double tol, int max_sweeps)
+int oracle_jacobi(int n, double *Ad, double *Vd, double *w, double tol, int max_sweeps)
 {
     for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) V[(size_t)i * n + j] = (i == j) ? 1.0 : 0.0;
-    if (n == 1) { w[0] = A[0]; return 0; }
+        for (int j = 0; j < n; ++j) Vd[(size_t)i * n + j] = (i == j) ? 1.0 : 0.0;
+    if (n == 1) { w[0] = Ad[0]; return 0; }
+    real *A = (real *)malloc(sizeof(real) * (size_t)n * n);
+    real *V = (real *)malloc(sizeof(real) * (size_t)n * n);
+    for (size_t e = 0; e < (size_t)n * n; ++e) { A[e] = Ad[e]; V[e] = Vd[e]; }
     int m = (n % 2) ? n + 1 : n;
     int *pairs = (int *)malloc(sizeof(int) * m);
-    double *cs = (double *)malloc(sizeof(double) * m);   /* c, s per pair */
+    real *cs = (real *)malloc(sizeof(real) * m);   /* c, s per pair */
     int *pq = (int *)malloc(sizeof(int) * m);           /* active p, q per pair */
+    /* A rotation is skipped (and a_pq treated as zero) when
+     * |a_pq| <= tol * sqrt(|a_pp a_qq|) or |a_pq| <= tol^2 max|a_ij|; the
+     * iteration stops after a sweep with no rotation. */
+    real amax = 0.0L;
+    for (size_t e = 0; e < (size_t)n * n; ++e) amax = fmaxl(amax, fabsl(A[e]));
+    const real rtol = (real)tol, atol = (real)tol * (real)tol * amax;
     int sweeps = -1;
     for (int sweep = 0; sweep <= max_sweeps; ++sweep) {
-        double fro2;
-        double off2 = off_norm2(n, A, &fro2);
-        if (off2 <= tol * tol * fro2) { sweeps = sweep; break; }
-        if (sweep == max_sweeps) break;
+        int rotations = 0;
         for (int r = 0; r < m - 1; ++r) {
             round_pairs(m, r, pairs);
             int np = 0;
@@ -73,26 +76,27 @@ int oracle_jacobi(int n, double *A, double *V, double *w, double tol, int max_sw
                 int p = pairs[2 * i], q = pairs[2 * i + 1];
                 if (p >= n || q >= n) continue;        /* dummy player for odd n */
                 if (p > q) { int t = p; p = q; q = t; }
-                double apq = A[(size_t)p * n + q];
-                if (apq == 0.0) continue;
-                double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
-                double tau = (aqq - app) / (2.0 * apq);
-                double t = (tau >= 0.0) ? 1.0 / (tau + sqrt(1.0 + tau * tau))
-                                        : -1.0 / (-tau + sqrt(1.0 + tau * tau));
-                double c = 1.0 / sqrt(1.0 + t * t);
+                real apq = A[(size_t)p * n + q];
+                real app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
+                if (fabsl(apq) <= rtol * sqrtl(fabsl(app * aqq)) || fabsl(apq) <= atol) continue;
+                real tau = (aqq - app) / (2.0L * apq);
+                real t = (tau >= 0.0L) ? 1.0L / (tau + sqrtl(1.0L + tau * tau))
+                                       : -1.0L / (-tau + sqrtl(1.0L + tau * tau));
+                real c = 1.0L / sqrtl(1.0L + t * t);
                 pq[2 * np] = p; pq[2 * np + 1] = q;
                 cs[2 * np] = c; cs[2 * np + 1] = t * c;
                 ++np;
             }
+            rotations += np;
             if (np == 0) continue;
             /* rows: A <- J^T A  (row p <- c row_p - s row_q, row q <- s row_p + c row_q) */
             #pragma omp parallel for schedule(static)
             for (int k = 0; k < np; ++k) {
                 int p = pq[2 * k], q = pq[2 * k + 1];
-                double c = cs[2 * k], s = cs[2 * k + 1];
-                double *rp = A + (size_t)p * n, *rq = A + (size_t)q * n;
+                real c = cs[2 * k], s = cs[2 * k + 1];
+                real *rp = A + (size_t)p * n, *rq = A + (size_t)q * n;
                 for (int j = 0; j < n; ++j) {
-                    double x = rp[j], y = rq[j];
+                    real x = rp[j], y = rq[j];
                     rp[j] = c * x - s * y;
                     rq[j] = s * x + c * y;
                 }
@@ -100,11 +104,11 @@ int oracle_jacobi(int n, double *A, double *V, double *w, double tol, int max_sw
             /* columns: A <- A J and V <- V J (col p <- c col_p - s col_q, col q <- s col_p + c col_q) */
             #pragma omp parallel for schedule(static)
             for (int i = 0; i < n; ++i) {
-                double *ra = A + (size_t)i * n, *rv = V + (size_t)i * n;
+                real *ra = A + (size_t)i * n, *rv = V + (size_t)i * n;
                 for (int k = 0; k < np; ++k) {
                     int p = pq[2 * k], q = pq[2 * k + 1];
-                    double c = cs[2 * k], s = cs[2 * k + 1];
-                    double x = ra[p], y = ra[q];
+                    real c = cs[2 * k], s = cs[2 * k + 1];
+                    real x = ra[p], y = ra[q];
                     ra[p] = c * x - s * y;
                     ra[q] = s * x + c * y;
                     x = rv[p]; y = rv[q];
@@ -113,8 +117,10 @@ int oracle_jacobi(int n, double *A, double *V, double *w, double tol, int max_sw
                 }
             }
         }
+        if (rotations == 0) { sweeps = sweep; break; }
     }
-    for (int i = 0; i < n; ++i) w[i] = A[(size_t)i * n + i];
-    free(pairs); free(cs); free(pq);
+    for (int i = 0; i < n; ++i) w[i] = (double)A[(size_t)i * n + i];
+    for (size_t e = 0; e < (size_t)n * n; ++e) { Ad[e] = (double)A[e]; Vd[e] = (double)V[e]; }
+    free(pairs); free(cs); free(pq); free(A); free(V);
     return sweeps;
 }

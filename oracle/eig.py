@@ -8,7 +8,10 @@ Q = D^{-1/2} Q~ and Q^{-1} = Q~^T D^{1/2} (Eq. q-from-tildeq).  Steps 1.1-1.3
 of the initialization of the three-dimensional procedure (§2.2.2).
 
 The eigensolver is the cyclic Jacobi method (``csrc/jacobi.c``), not the
-divide-and-conquer / dense LAPACK routines of §3.
+divide-and-conquer / dense LAPACK routines of §3.  Its rotations run in 80-bit
+extended precision: in double precision the smooth low modes of a stretched
+operator, which carry the solution, are only determined to eps ||T|| / gap
+(about 1e-12 at N = 256).
 
 Null mode (periodic or Neumann-Neumann): T 1 = 0, so T~ has the exact null
 vector D^{1/2} 1 / ||D^{1/2} 1||.  The eigenvalue of smallest magnitude is set
@@ -45,9 +48,10 @@ def _lib():
     return _LIB
 
 
-def jacobi_eigh(S: np.ndarray, tol: float = 1e-15, max_sweeps: int = 60):
+def jacobi_eigh(S: np.ndarray, tol: float = 2.0 ** -63, max_sweeps: int = 60):
     """Eigenvalues w and orthonormal eigenvectors V (columns) of a dense
-    symmetric matrix by cyclic Jacobi; S V = V diag(w)."""
+    symmetric matrix by cyclic Jacobi (rotations in extended precision, see
+    csrc/jacobi.c); S V = V diag(w)."""
     S = np.ascontiguousarray(S, dtype=np.float64)
     n = S.shape[0]
     A = S.copy()

@@ -14,9 +14,12 @@
 
 #include <algorithm>
 #include <cmath>
+#include <limits>
 #include <numeric>
 
 namespace tpt {
+
+typedef long double real;
 
 static bool nearly_equal(double x, double y, double tol) { return std::fabs(x - y) <= tol * std::fabs(y); }
 
@@ -122,35 +125,35 @@ std::string build_op1d(int ncells, const double* faces, int bc_lo, int bc_hi, in
 static bool analytic_basis(const Op1D& op, Eig1D& e) {
     if (!op.uniform) return false;
     const int n = op.n;
-    const double h = op.vol[0];
-    const double s4 = 4.0 / (h * h);
+    const real h = op.vol[0];
+    const real s4 = 4.0L / (h * h);
     e.n = n;
     e.lam.assign(n, 0.0);
     e.Qt.assign((size_t)n * n, 0.0);
     auto Q = [&](int i, int p) -> double& { return e.Qt[(size_t)i * n + p]; };
-    const double pi = 3.14159265358979323846;
+    const real pi = 3.14159265358979323846264338327950288L;
     if (op.periodic) {
         // real Fourier basis: p = 0 constant; pairs (cos, sin) of wavenumber m;
         // for even n the alternating vector.
         int p = 0;
-        for (int i = 0; i < n; ++i) Q(i, 0) = 1.0 / std::sqrt((double)n);
+        for (int i = 0; i < n; ++i) Q(i, 0) = (double)(1.0L / std::sqrt((real)n));
         e.lam[0] = 0.0;
         p = 1;
         for (int m = 1; 2 * m < n; ++m) {
-            double th = pi * m / n;
-            double lam = -s4 * std::sin(th) * std::sin(th);
-            double nc = std::sqrt(2.0 / n);
+            real th = pi * m / n;
+            real lam = -s4 * std::sin(th) * std::sin(th);
+            real nc = std::sqrt(2.0L / n);
             for (int i = 0; i < n; ++i) {
-                double ang = 2.0 * pi * (double)m * (double)i / (double)n;
-                Q(i, p) = nc * std::cos(ang);
-                Q(i, p + 1) = nc * std::sin(ang);
+                real ang = 2.0L * pi * (real)(((long long)m * i) % n) / (real)n;
+                Q(i, p) = (double)(nc * std::cos(ang));
+                Q(i, p + 1) = (double)(nc * std::sin(ang));
             }
-            e.lam[p] = e.lam[p + 1] = lam;
+            e.lam[p] = e.lam[p + 1] = (double)lam;
             p += 2;
         }
         if (n % 2 == 0) {
-            for (int i = 0; i < n; ++i) Q(i, p) = ((i % 2) ? -1.0 : 1.0) / std::sqrt((double)n);
-            e.lam[p] = -s4;
+            for (int i = 0; i < n; ++i) Q(i, p) = (double)(((i % 2) ? -1.0L : 1.0L) / std::sqrt((real)n));
+            e.lam[p] = (double)(-s4);
             ++p;
         }
         e.null_index = 0;
@@ -160,10 +163,10 @@ static bool analytic_basis(const Op1D& op, Eig1D& e) {
     if (op.loc == LOC_C && op.bc_lo == BC_N && op.bc_hi == BC_N) {
         // cosine basis cos(pi k (i + 1/2) / n)
         for (int k = 0; k < n; ++k) {
-            double nc = (k == 0) ? std::sqrt(1.0 / n) : std::sqrt(2.0 / n);
-            for (int i = 0; i < n; ++i) Q(i, k) = nc * std::cos(pi * k * (i + 0.5) / n);
-            double th = pi * k / (2.0 * n);
-            e.lam[k] = -s4 * std::sin(th) * std::sin(th);
+            real nc = (k == 0) ? std::sqrt(1.0L / n) : std::sqrt(2.0L / n);
+            for (int i = 0; i < n; ++i) Q(i, k) = (double)(nc * std::cos(pi * k * (i + 0.5L) / n));
+            real th = pi * k / (2.0L * n);
+            e.lam[k] = (double)(-s4 * std::sin(th) * std::sin(th));
         }
         e.lam[0] = 0.0;
         e.null_index = 0;
@@ -173,10 +176,10 @@ static bool analytic_basis(const Op1D& op, Eig1D& e) {
     if (op.loc == LOC_C && op.bc_lo == BC_D && op.bc_hi == BC_D) {
         // sine basis sin(pi k (i + 1/2) / n), k = 1..n
         for (int k = 1; k <= n; ++k) {
-            double nc = (k == n) ? std::sqrt(1.0 / n) : std::sqrt(2.0 / n);
-            for (int i = 0; i < n; ++i) Q(i, k - 1) = nc * std::sin(pi * k * (i + 0.5) / n);
-            double th = pi * k / (2.0 * n);
-            e.lam[k - 1] = -s4 * std::sin(th) * std::sin(th);
+            real nc = (k == n) ? std::sqrt(1.0L / n) : std::sqrt(2.0L / n);
+            for (int i = 0; i < n; ++i) Q(i, k - 1) = (double)(nc * std::sin(pi * k * (i + 0.5L) / n));
+            real th = pi * k / (2.0L * n);
+            e.lam[k - 1] = (double)(-s4 * std::sin(th) * std::sin(th));
         }
         e.null_index = -1;
         e.analytic = true;
@@ -186,10 +189,10 @@ static bool analytic_basis(const Op1D& op, Eig1D& e) {
         // interior faces of n+1 cells: sin(pi k (i + 1) / (n + 1)), k = 1..n
         const int m = n + 1;
         for (int k = 1; k <= n; ++k) {
-            double nc = std::sqrt(2.0 / m);
-            for (int i = 0; i < n; ++i) Q(i, k - 1) = nc * std::sin(pi * k * (i + 1.0) / m);
-            double th = pi * k / (2.0 * m);
-            e.lam[k - 1] = -s4 * std::sin(th) * std::sin(th);
+            real nc = std::sqrt(2.0L / m);
+            for (int i = 0; i < n; ++i) Q(i, k - 1) = (double)(nc * std::sin(pi * k * (i + 1.0L) / m));
+            real th = pi * k / (2.0L * m);
+            e.lam[k - 1] = (double)(-s4 * std::sin(th) * std::sin(th));
         }
         e.null_index = -1;
         e.analytic = true;
@@ -203,53 +206,59 @@ static bool analytic_basis(const Op1D& op, Eig1D& e) {
 // implicit symmetric QR step with Wilkinson shift, run bottom-up).  The
 // eigenvector matrix is kept column-major (one contiguous row per vector) so
 // that each Givens rotation updates two contiguous arrays.
+//
+// The numerical eigensolvers run in 80-bit extended precision (long double)
+// and round to double at the end: a double-precision eigensolver fixes an
+// eigenvector only to about eps ||T|| / gap, i.e. 1e-12..1e-11 for the smooth
+// low modes of a stretched operator with N ~ 10^2..10^3, and those modes carry
+// the solution of a Poisson problem.
 // ---------------------------------------------------------------------------
-bool tridiag_ql(int n, std::vector<double>& d, std::vector<double>& e, std::vector<double>& Zt) {
+static bool tridiag_ql(int n, std::vector<real>& d, std::vector<real>& e, std::vector<real>& Zt) {
     if (n <= 1) return true;
     e.resize(n);
-    e[n - 1] = 0.0;
-    const double eps = std::numeric_limits<double>::epsilon();
+    e[n - 1] = 0.0L;
+    const real eps = std::numeric_limits<real>::epsilon();
     for (int l = 0; l < n; ++l) {
         int iter = 0;
         for (;;) {
             // find the first negligible off-diagonal at or below l
             int m = l;
             for (; m < n - 1; ++m) {
-                double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
+                real dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
                 if (std::fabs(e[m]) <= eps * dd) break;
             }
             if (m == l) break;
             if (++iter > 60) return false;
             // shift from the leading 2x2 block of the unreduced part (d[l], e[l], d[l+1])
-            double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-            double r = std::hypot(g, 1.0);
+            real g = (d[l + 1] - d[l]) / (2.0L * e[l]);
+            real r = std::hypot(g, (real)1.0L);
             g = d[m] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
-            double s = 1.0, c = 1.0, p = 0.0;
+            real s = 1.0L, c = 1.0L, p = 0.0L;
             int i = m - 1;
             bool underflow = false;
             for (; i >= l; --i) {
-                double f = s * e[i];
-                double b = c * e[i];
+                real f = s * e[i];
+                real b = c * e[i];
                 r = std::hypot(f, g);
                 e[i + 1] = r;
-                if (r == 0.0) {  // deflation by underflow
+                if (r == 0.0L) {  // deflation by underflow
                     d[i + 1] -= p;
-                    e[m] = 0.0;
+                    e[m] = 0.0L;
                     underflow = true;
                     break;
                 }
                 s = f / r;
                 c = g / r;
                 g = d[i + 1] - p;
-                r = (d[i] - g) * s + 2.0 * c * b;
+                r = (d[i] - g) * s + 2.0L * c * b;
                 p = s * r;
                 d[i + 1] = g + p;
                 g = c * r - b;
                 // rotate eigenvector columns i and i+1
-                double* zi = &Zt[(size_t)i * n];
-                double* zj = &Zt[(size_t)(i + 1) * n];
+                real* zi = &Zt[(size_t)i * n];
+                real* zj = &Zt[(size_t)(i + 1) * n];
                 for (int k = 0; k < n; ++k) {
-                    double t = zj[k];
+                    real t = zj[k];
                     zj[k] = s * zi[k] + c * t;
                     zi[k] = c * zi[k] - s * t;
                 }
@@ -257,7 +266,7 @@ bool tridiag_ql(int n, std::vector<double>& d, std::vector<double>& e, std::vect
             if (underflow) continue;
             d[l] -= p;
             e[l] = g;
-            e[m] = 0.0;
+            e[m] = 0.0L;
         }
     }
     return true;
@@ -265,65 +274,66 @@ bool tridiag_ql(int n, std::vector<double>& d, std::vector<double>& e, std::vect
 
 // Householder reduction to tridiagonal form (Golub & Van Loan §8.3.1):
 // for k = 0..n-3 reflect A[k+1:, k] onto e_1, update the trailing block with
-// the symmetric rank-2 form, accumulate Z = H_0 H_1 ... .
-void householder_tridiag(int n, std::vector<double> A, std::vector<double>& d, std::vector<double>& e,
-                         std::vector<double>& Zt) {
-    auto a = [&](int i, int j) -> double& { return A[(size_t)i * n + j]; };
-    std::vector<double> Z((size_t)n * n, 0.0);
-    for (int i = 0; i < n; ++i) Z[(size_t)i * n + i] = 1.0;
-    std::vector<double> v(n), pv(n), wv(n);
+// the symmetric rank-2 form, accumulate Z = H_0 H_1 ... .  Zt is returned
+// column-major (Zt[p*n + i] = Z[i][p]).
+static void householder_tridiag(int n, std::vector<real> A, std::vector<real>& d, std::vector<real>& e,
+                                std::vector<real>& Zt) {
+    auto a = [&](int i, int j) -> real& { return A[(size_t)i * n + j]; };
+    std::vector<real> Z((size_t)n * n, 0.0L);
+    for (int i = 0; i < n; ++i) Z[(size_t)i * n + i] = 1.0L;
+    std::vector<real> v(n), pv(n), wv(n);
     for (int k = 0; k + 2 < n; ++k) {
         const int m = n - k - 1;  // length of x = A[k+1:, k]
-        double alpha = 0.0;
+        real alpha = 0.0L;
         for (int i = 0; i < m; ++i) alpha += a(k + 1 + i, k) * a(k + 1 + i, k);
         alpha = std::sqrt(alpha);
-        if (alpha == 0.0) continue;
-        double x0 = a(k + 1, k);
-        double sgn = x0 >= 0 ? 1.0 : -1.0;
+        if (alpha == 0.0L) continue;
+        real x0 = a(k + 1, k);
+        real sgn = x0 >= 0 ? 1.0L : -1.0L;
         // v = x + sgn*alpha*e1, H = I - beta v v^T, beta = 2 / v^T v
         for (int i = 0; i < m; ++i) v[i] = a(k + 1 + i, k);
         v[0] += sgn * alpha;
-        double vtv = 0.0;
+        real vtv = 0.0L;
         for (int i = 0; i < m; ++i) vtv += v[i] * v[i];
-        if (vtv == 0.0) continue;
-        double beta = 2.0 / vtv;
+        if (vtv == 0.0L) continue;
+        real beta = 2.0L / vtv;
         // p = beta * A22 v
         for (int i = 0; i < m; ++i) {
-            double s = 0.0;
-            const double* row = &A[(size_t)(k + 1 + i) * n + (k + 1)];
-            for (int j = 0; j < m; ++j) s += row[j] * v[j];
-            pv[i] = beta * s;
+            real sum = 0.0L;
+            const real* row = &A[(size_t)(k + 1 + i) * n + (k + 1)];
+            for (int j = 0; j < m; ++j) sum += row[j] * v[j];
+            pv[i] = beta * sum;
         }
-        double ptv = 0.0;
+        real ptv = 0.0L;
         for (int i = 0; i < m; ++i) ptv += pv[i] * v[i];
-        double kk = 0.5 * beta * ptv;
+        real kk = 0.5L * beta * ptv;
         for (int i = 0; i < m; ++i) wv[i] = pv[i] - kk * v[i];
         // A22 -= v w^T + w v^T
         for (int i = 0; i < m; ++i) {
-            double* row = &A[(size_t)(k + 1 + i) * n + (k + 1)];
+            real* row = &A[(size_t)(k + 1 + i) * n + (k + 1)];
             for (int j = 0; j < m; ++j) row[j] -= v[i] * wv[j] + wv[i] * v[j];
         }
         // column k / row k below the diagonal become (-sgn*alpha, 0, ...)
         a(k + 1, k) = -sgn * alpha;
         a(k, k + 1) = -sgn * alpha;
         for (int i = 1; i < m; ++i) {
-            a(k + 1 + i, k) = 0.0;
-            a(k, k + 1 + i) = 0.0;
+            a(k + 1 + i, k) = 0.0L;
+            a(k, k + 1 + i) = 0.0L;
         }
         // Z <- Z H  (columns k+1..n-1)
         for (int r = 0; r < n; ++r) {
-            double* zr = &Z[(size_t)r * n + (k + 1)];
-            double s = 0.0;
-            for (int j = 0; j < m; ++j) s += zr[j] * v[j];
-            s *= beta;
-            for (int j = 0; j < m; ++j) zr[j] -= s * v[j];
+            real* zr = &Z[(size_t)r * n + (k + 1)];
+            real sum = 0.0L;
+            for (int j = 0; j < m; ++j) sum += zr[j] * v[j];
+            sum *= beta;
+            for (int j = 0; j < m; ++j) zr[j] -= sum * v[j];
         }
     }
-    d.assign(n, 0.0);
-    e.assign(n, 0.0);
+    d.assign(n, 0.0L);
+    e.assign(n, 0.0L);
     for (int i = 0; i < n; ++i) d[i] = a(i, i);
     for (int i = 0; i + 1 < n; ++i) e[i] = a(i + 1, i);
-    Zt.assign((size_t)n * n, 0.0);
+    Zt.assign((size_t)n * n, 0.0L);
     for (int i = 0; i < n; ++i)
         for (int p = 0; p < n; ++p) Zt[(size_t)p * n + i] = Z[(size_t)i * n + p];
 }
@@ -333,19 +343,19 @@ std::string eig_op1d(const Op1D& op, Eig1D& e) {
     const int n = op.n;
     e.n = n;
     if (analytic_basis(op, e)) return "";
-    std::vector<double> s(n);
-    for (int i = 0; i < n; ++i) s[i] = std::sqrt(op.vol[i]);
-    std::vector<double> d(n), off(n, 0.0), Zt;
+    std::vector<real> s(n);
+    for (int i = 0; i < n; ++i) s[i] = std::sqrt((real)op.vol[i]);
+    std::vector<real> d(n), off(n, 0.0L), Zt;
     for (int i = 0; i < n; ++i) d[i] = op.b[i];
     if (!op.periodic) {
         // symmetric tridiagonal T~: off-diagonal sqrt(c_i a_{i+1})
-        for (int i = 0; i + 1 < n; ++i) off[i] = std::sqrt(op.c[i] * op.a[i + 1]);
-        Zt.assign((size_t)n * n, 0.0);
-        for (int i = 0; i < n; ++i) Zt[(size_t)i * n + i] = 1.0;
+        for (int i = 0; i + 1 < n; ++i) off[i] = std::sqrt((real)op.c[i] * (real)op.a[i + 1]);
+        Zt.assign((size_t)n * n, 0.0L);
+        for (int i = 0; i < n; ++i) Zt[(size_t)i * n + i] = 1.0L;
     } else {
         // cyclic: dense T~ with corners, reduced by Householder first
-        std::vector<double> A((size_t)n * n, 0.0);
-        auto put = [&](int i, int j, double v) { A[(size_t)i * n + j] += v * s[i] / s[j]; };
+        std::vector<real> A((size_t)n * n, 0.0L);
+        auto put = [&](int i, int j, double v) { A[(size_t)i * n + j] += (real)v * s[i] / s[j]; };
         for (int i = 0; i < n; ++i) {
             put(i, i, op.b[i]);
             put(i, (i + n - 1) % n, op.a[i]);
@@ -353,7 +363,7 @@ std::string eig_op1d(const Op1D& op, Eig1D& e) {
         }
         for (int i = 0; i < n; ++i)
             for (int j = i + 1; j < n; ++j) {
-                double m = 0.5 * (A[(size_t)i * n + j] + A[(size_t)j * n + i]);
+                real m = 0.5L * (A[(size_t)i * n + j] + A[(size_t)j * n + i]);
                 A[(size_t)i * n + j] = A[(size_t)j * n + i] = m;
             }
         householder_tridiag(n, A, d, off, Zt);
@@ -363,41 +373,44 @@ std::string eig_op1d(const Op1D& op, Eig1D& e) {
     std::vector<int> idx(n);
     std::iota(idx.begin(), idx.end(), 0);
     std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return d[x] > d[y]; });
-    e.lam.resize(n);
-    e.Qt.assign((size_t)n * n, 0.0);
+    std::vector<real> lam(n), Q((size_t)n * n);
     for (int p = 0; p < n; ++p) {
-        e.lam[p] = d[idx[p]];
-        const double* z = &Zt[(size_t)idx[p] * n];
-        for (int i = 0; i < n; ++i) e.Qt[(size_t)i * n + p] = z[i];
+        lam[p] = d[idx[p]];
+        const real* z = &Zt[(size_t)idx[p] * n];
+        for (int i = 0; i < n; ++i) Q[(size_t)i * n + p] = z[i];
     }
     if (op.null_mode) {
         // exact null vector D^{1/2} 1 / ||D^{1/2} 1||, eigenvalue exactly 0; the
         // other vectors are made orthogonal to it
         int k0 = 0;
         for (int p = 1; p < n; ++p)
-            if (std::fabs(e.lam[p]) < std::fabs(e.lam[k0])) k0 = p;
-        double nrm = 0.0;
-        for (int i = 0; i < n; ++i) nrm += op.vol[i];
+            if (std::fabs(lam[p]) < std::fabs(lam[k0])) k0 = p;
+        real nrm = 0.0L;
+        for (int i = 0; i < n; ++i) nrm += (real)op.vol[i];
         nrm = std::sqrt(nrm);
-        std::vector<double> v0(n);
+        std::vector<real> v0(n);
         for (int i = 0; i < n; ++i) v0[i] = s[i] / nrm;
-        e.lam[k0] = 0.0;
-        for (int i = 0; i < n; ++i) e.Qt[(size_t)i * n + k0] = v0[i];
+        lam[k0] = 0.0L;
+        for (int i = 0; i < n; ++i) Q[(size_t)i * n + k0] = v0[i];
         for (int p = 0; p < n; ++p) {
             if (p == k0) continue;
-            double dot = 0.0;
-            for (int i = 0; i < n; ++i) dot += v0[i] * e.Qt[(size_t)i * n + p];
-            double q2 = 0.0;
+            real dot = 0.0L;
+            for (int i = 0; i < n; ++i) dot += v0[i] * Q[(size_t)i * n + p];
+            real q2 = 0.0L;
             for (int i = 0; i < n; ++i) {
-                double& q = e.Qt[(size_t)i * n + p];
+                real& q = Q[(size_t)i * n + p];
                 q -= dot * v0[i];
                 q2 += q * q;
             }
-            double inv = 1.0 / std::sqrt(q2);
-            for (int i = 0; i < n; ++i) e.Qt[(size_t)i * n + p] *= inv;
+            real inv = 1.0L / std::sqrt(q2);
+            for (int i = 0; i < n; ++i) Q[(size_t)i * n + p] *= inv;
         }
         e.null_index = k0;
     }
+    e.lam.resize(n);
+    e.Qt.resize((size_t)n * n);
+    for (int p = 0; p < n; ++p) e.lam[p] = (double)lam[p];
+    for (size_t k = 0; k < (size_t)n * n; ++k) e.Qt[k] = (double)Q[k];
     return "";
 }
 

@@ -36,16 +36,4 @@ struct Eig1D {
 
 std::string eig_op1d(const Op1D& op, Eig1D& e);
 
-// Exposed for tests of the building blocks.
-// Symmetric tridiagonal eigenproblem by implicit QL with Wilkinson-type
-// shifts; d (diag, n), e (off-diagonal, e[i] couples i and i+1, n-1 used),
-// Z (n x n row-major, columns = vectors) is multiplied on the right by the
-// accumulated rotations.  Returns false if an eigenvalue needs > 60 iterations.
-bool tridiag_ql(int n, std::vector<double>& d, std::vector<double>& e, std::vector<double>& Zt_colmajor);
-// Householder reduction of a dense symmetric A (n x n row-major) to
-// tridiagonal form A = Z Tri Z^T; returns diag d, off-diagonal e, and Z
-// stored column-major (Zt[p*n + i] = Z[i][p]).
-void householder_tridiag(int n, std::vector<double> A, std::vector<double>& d,
-                         std::vector<double>& e, std::vector<double>& Zt_colmajor);
-
 }  // namespace tpt

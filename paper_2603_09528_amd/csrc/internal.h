@@ -116,4 +116,19 @@ struct TimedScope {
 
 int solve_one(tpt_plan_s* p, const double* rhs, double* out, void* ws, size_t ws_bytes, hipStream_t s);
 
+// Workspace carve-up of one plan's solve (see plan_workspace_bytes).
+struct Ws {
+    char* base;
+    size_t n;  // unknowns over all rhs
+    void* w1;
+    void* w2;
+    float* r;
+    double* scratch;
+    double* partials;
+};
+Ws carve(const tpt_plan_s* p, void* ws);
+int stage_variant(const tpt_plan_s* p, int stage, const GemmDesc& g, int prec);
+const char* stage_name(int stage, int prec);
+long long plan_residual_blocks(const tpt_plan_s* p);
+
 }  // namespace tpt

@@ -66,11 +66,14 @@ struct ThomasDesc {
     int pin_line;
     const void* f;
     void* x;
-    double* scratch;       // 2 doubles per unknown
+    double* scratch;       // thomas_scratch_doubles() doubles
     int tf, tx;            // DType of f and x
     long long line_begin;  // multi-problem: first global line
 };
 hipError_t launch_thomas(const ThomasDesc& t, hipStream_t s);
+// Scratch the Thomas kernel needs: c' checkpoints (one per line every
+// THOMAS_KC planes) and, when x is FP32, the FP64 d' of every unknown.
+long long thomas_scratch_doubles(int nx, int ny, int nz, int nsys, int tx);
 hipError_t launch_thomas_multi(const ThomasDesc* d_work, int nwork, long long total_lines, hipStream_t s);
 
 // Residual r = f - A x of the 7-point operator in FP64, r stored as float,

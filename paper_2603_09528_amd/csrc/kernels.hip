@@ -611,59 +611,139 @@ hipError_t launch_gemm_multi(const GemmDesc* d_work, int nwork, long long total_
 // ---------------------------------------------------------------------------
 // Batched Thomas along z, one lane per (i, j) line (§2.2.2 step 2.3): at each
 // k the lanes of a wave touch consecutive addresses (stride N_x N_y between k
-// planes).  Arithmetic in FP64 whatever the storage type of f and x; the
-// forward sweep keeps (c', d') per unknown in an FP64 scratch.  The line
-// pin_line is the null line of a singular Poisson problem: its final pivot
-// vanishes and its last unknown is set to zero (§3).
+// planes).  Arithmetic in FP64 whatever the storage type of f and x.
+//
+// Traffic: the forward sweep stores only d' (into x when x is FP64, else into
+// an FP64 scratch) and, every THOMAS_KC planes, a checkpoint of c'; the
+// backward sweep recomputes c' chunk by chunk from its checkpoint in
+// registers instead of reading it back.  Loads of the next chunk are issued
+// before the current chunk is computed (one lane per line leaves only one
+// wave per SIMD at the workload sizes, so latency is hidden by prefetching,
+// not by occupancy).
+//
+// The line pin_line is the null line of a singular Poisson problem: its final
+// pivot vanishes and its last unknown is set to zero (§3).
 // ---------------------------------------------------------------------------
+constexpr int THOMAS_KC = 16;
+
+long long thomas_scratch_doubles(int nx, int ny, int nz, int nsys, int tx) {
+    const long long lines = (long long)nx * ny * nsys;
+    const long long nck = (nz + THOMAS_KC - 1) / THOMAS_KC;
+    return lines * nck + (tx == DT_F64 ? 0 : lines * nz);
+}
+
+template <typename TF, typename TX>
 __device__ __forceinline__ void thomas_line(const ThomasDesc& t, long long gl) {
+    constexpr int KC = THOMAS_KC;
     const long long S = (long long)t.nx * t.ny;
     const int sys = (int)(gl / S);
     const long long line = gl - (long long)sys * S;
     const int i = (int)(line % t.nx), j = (int)(line / t.nx);
     const int nz = t.nz;
+    const int nc = (nz + KC - 1) / KC;
+    const long long lines = S * t.nsys;
     const double lam = t.lamx[i] + t.lamy[j];
     const long long base = (long long)sys * S * nz + line;
-    double2* cd = (double2*)t.scratch + base;
+    const TF* f = (const TF*)t.f + base;
+    TX* x = (TX*)t.x + base;
+    // checkpoints ck[c][gl] (c' entering chunk c), then (FP32 x) d' [sys][k][line]
+    double* ck = t.scratch + gl;
+    double* dst = sizeof(TX) == 8 ? (double*)((TX*)t.x + base) : t.scratch + lines * nc + base;
     const bool pinned = line == t.pin_line;
     const double sig = t.sigma, tau = t.tau;
+    const double* __restrict__ az = t.az;
+    const double* __restrict__ bz = t.bz;
+    const double* __restrict__ cz = t.cz;
+
+    // ---- forward elimination ----
     double cp = 0.0, dp = 0.0;
-    for (int k = 0; k < nz; ++k) {
-        const double sub = k > 0 ? tau * t.az[k] : 0.0;
-        const double den = sig + tau * (lam + t.bz[k]) - sub * cp;
-        const double inv = (pinned && k == nz - 1) ? 0.0 : 1.0 / den;
-        const double fk = t.tf == DT_F64 ? ((const double*)t.f)[base + k * S] : (double)((const float*)t.f)[base + k * S];
-        cp = k < nz - 1 ? tau * t.cz[k] * inv : 0.0;
-        dp = (fk - sub * dp) * inv;
-        if (k < nz - 1) cd[k * S] = make_double2(cp, dp);
+    double fb[KC], fn[KC];
+#pragma unroll
+    for (int e = 0; e < KC; ++e) fb[e] = e < nz ? (double)f[(long long)e * S] : 0.0;
+    for (int c = 0; c < nc; ++c) {
+        const int k0 = c * KC;
+        ck[(long long)c * lines] = cp;
+#pragma unroll
+        for (int e = 0; e < KC; ++e) {
+            const int k = k0 + KC + e;
+            fn[e] = k < nz ? (double)f[(long long)k * S] : 0.0;
+        }
+#pragma unroll
+        for (int e = 0; e < KC; ++e) {
+            const int k = k0 + e;
+            if (k < nz) {
+                const double sub = k > 0 ? tau * az[k] : 0.0;
+                const double den = sig + tau * (lam + bz[k]) - sub * cp;
+                const double inv = (pinned && k == nz - 1) ? 0.0 : 1.0 / den;
+                cp = k < nz - 1 ? tau * cz[k] * inv : 0.0;
+                dp = (fb[e] - sub * dp) * inv;
+                dst[(long long)k * S] = dp;
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < KC; ++e) fb[e] = fn[e];
     }
-    double xv = dp;
-    if (t.tx == DT_F64) {
-        double* x = (double*)t.x + base;
-        x[(long long)(nz - 1) * S] = xv;
-        for (int k = nz - 2; k >= 0; --k) {
-            const double2 v = cd[k * S];
-            xv = v.y - v.x * xv;
-            x[k * S] = xv;
+
+    // ---- back substitution, c' recomputed per chunk from its checkpoint ----
+    double xv = dp;  // x_{nz-1} (0 on the pinned line: inv = 0 there)
+    x[(long long)(nz - 1) * S] = (TX)xv;
+    double db[KC], dn[KC];
+    {
+        const int k0 = (nc - 1) * KC;
+#pragma unroll
+        for (int e = 0; e < KC; ++e) {
+            const int k = k0 + e;
+            db[e] = k < nz - 1 ? dst[(long long)k * S] : 0.0;
         }
-    } else {
-        float* x = (float*)t.x + base;
-        x[(long long)(nz - 1) * S] = (float)xv;
-        for (int k = nz - 2; k >= 0; --k) {
-            const double2 v = cd[k * S];
-            xv = v.y - v.x * xv;
-            x[k * S] = (float)xv;
+    }
+    for (int c = nc - 1; c >= 0; --c) {
+        const int k0 = c * KC;
+        if (c > 0) {
+#pragma unroll
+            for (int e = 0; e < KC; ++e) dn[e] = dst[(long long)(k0 - KC + e) * S];
         }
+        double cb[KC];
+        double cpr = ck[(long long)c * lines];
+#pragma unroll
+        for (int e = 0; e < KC; ++e) {
+            const int k = k0 + e;
+            if (k < nz) {
+                const double sub = k > 0 ? tau * az[k] : 0.0;
+                const double den = sig + tau * (lam + bz[k]) - sub * cpr;
+                const double inv = (pinned && k == nz - 1) ? 0.0 : 1.0 / den;
+                cpr = k < nz - 1 ? tau * cz[k] * inv : 0.0;
+            }
+            cb[e] = cpr;
+        }
+#pragma unroll
+        for (int e = KC - 1; e >= 0; --e) {
+            const int k = k0 + e;
+            if (k < nz - 1) {
+                xv = db[e] - cb[e] * xv;
+                x[(long long)k * S] = (TX)xv;
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < KC; ++e) db[e] = dn[e];
     }
 }
 
-__global__ __launch_bounds__(256) void thomas_kernel(ThomasDesc t, long long nlines) {
+__device__ __forceinline__ void thomas_dispatch(const ThomasDesc& t, long long gl) {
+    if (t.tf == DT_F64 && t.tx == DT_F64) thomas_line<double, double>(t, gl);
+    else if (t.tf == DT_F32 && t.tx == DT_F32) thomas_line<float, float>(t, gl);
+    else if (t.tf == DT_F64) thomas_line<double, float>(t, gl);
+    else thomas_line<float, double>(t, gl);
+}
+
+constexpr int THOMAS_NT = 64;
+
+__global__ __launch_bounds__(THOMAS_NT) void thomas_kernel(ThomasDesc t, long long nlines) {
     const long long gl = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gl < nlines) thomas_line(t, gl);
+    if (gl < nlines) thomas_dispatch(t, gl);
 }
 
-__global__ __launch_bounds__(256) void thomas_multi_kernel(const ThomasDesc* __restrict__ work, int nwork,
-                                                           long long total) {
+__global__ __launch_bounds__(THOMAS_NT) void thomas_multi_kernel(const ThomasDesc* __restrict__ work, int nwork,
+                                                                 long long total) {
     for (long long gl = (long long)blockIdx.x * blockDim.x + threadIdx.x; gl < total;
          gl += (long long)gridDim.x * blockDim.x) {
         int lo = 0, hi = nwork - 1;
@@ -674,22 +754,23 @@ __global__ __launch_bounds__(256) void thomas_multi_kernel(const ThomasDesc* __r
         }
         const ThomasDesc t = work[lo];
         const long long local = gl - t.line_begin;
-        if (local < (long long)t.nx * t.ny * t.nsys) thomas_line(t, local);
+        if (local < (long long)t.nx * t.ny * t.nsys) thomas_dispatch(t, local);
     }
 }
 
 hipError_t launch_thomas(const ThomasDesc& t, hipStream_t s) {
     const long long n = (long long)t.nx * t.ny * t.nsys;
     if (n <= 0) return hipSuccess;
-    const long long blocks = (n + 255) / 256;
-    hipLaunchKernelGGL(thomas_kernel, dim3((unsigned)blocks), dim3(256), 0, s, t, n);
+    const long long blocks = (n + THOMAS_NT - 1) / THOMAS_NT;
+    hipLaunchKernelGGL(thomas_kernel, dim3((unsigned)blocks), dim3(THOMAS_NT), 0, s, t, n);
     return hipGetLastError();
 }
 
 hipError_t launch_thomas_multi(const ThomasDesc* d_work, int nwork, long long total_lines, hipStream_t s) {
     if (total_lines <= 0) return hipSuccess;
-    const long long blocks = std::min((total_lines + 255) / 256, 8 * PERSISTENT_BLOCKS);
-    hipLaunchKernelGGL(thomas_multi_kernel, dim3((unsigned)blocks), dim3(256), 0, s, d_work, nwork, total_lines);
+    const long long blocks = std::min((total_lines + THOMAS_NT - 1) / THOMAS_NT, 32 * PERSISTENT_BLOCKS);
+    hipLaunchKernelGGL(thomas_multi_kernel, dim3((unsigned)blocks), dim3(THOMAS_NT), 0, s, d_work, nwork,
+                       total_lines);
     return hipGetLastError();
 }
 

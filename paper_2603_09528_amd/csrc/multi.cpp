@@ -1,0 +1,391 @@
+// Multi-problem execution (batches of uneven independent problems) and the
+// GEMM tile autotuner.
+#include "multi.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <tuple>
+
+namespace tpt {
+
+static inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+MultiExec::~MultiExec() {
+    if (pinned_) (void)hipHostFree(pinned_);
+}
+
+int MultiExec::init(const std::vector<tpt_plan_s*>& plans) {
+    if (plans.empty()) return fail(TPT_ERR_INVALID, "empty batch");
+    plans_ = plans;
+    const int prec = plans[0]->desc.precision;
+    for (auto* p : plans) {
+        if (!p) return fail(TPT_ERR_INVALID, "NULL plan in batch");
+        if (p->host_only) return fail(TPT_ERR_INVALID, "host-only plan in batch");
+        if (p->desc.nrhs != 1) return fail(TPT_ERR_UNSUPPORTED, "batched plans must have nrhs = 1");
+        if (p->desc.precision != prec) return fail(TPT_ERR_UNSUPPORTED, "batched plans must share a precision");
+        if (prec != TPT_FP64 && p->desc.fixed_refine < 0)
+            return fail(TPT_ERR_UNSUPPORTED, "batched mixed plans need fixed_refine >= 0");
+        if (prec != TPT_FP64 && p->desc.fixed_refine != plans[0]->desc.fixed_refine)
+            return fail(TPT_ERR_UNSUPPORTED, "batched mixed plans must share fixed_refine");
+    }
+    prec_ = plan_gemm_prec(plans[0]);
+    mixed_ = prec != TPT_FP64;
+    iters_ = mixed_ ? plans[0]->desc.fixed_refine : 0;
+    ws_off_.clear();
+    norm_off_.clear();
+    size_t off = 0;
+    for (auto* p : plans) {
+        ws_off_.push_back(off);
+        off += al256(plan_workspace_bytes(p));
+        norm_off_.push_back(off);
+        off += 256;
+    }
+    ws_total_ = off;
+    return TPT_OK;
+}
+
+template <typename T>
+static size_t append(std::vector<char>& blob, const std::vector<T>& v) {
+    size_t off = (blob.size() + 15) & ~(size_t)15;
+    blob.resize(off + sizeof(T) * v.size());
+    std::memcpy(blob.data() + off, v.data(), sizeof(T) * v.size());
+    return off;
+}
+
+int MultiExec::add_gemm_stage(int stage, int prec, const std::vector<GemmDesc>& gs) {
+    // group problems by tile variant; each group is one persistent launch
+    std::vector<int> var(gs.size());
+    for (size_t i = 0; i < gs.size(); ++i) var[i] = stage_variant(plans_[i], stage, gs[i], prec);
+    for (int v = 0; v < TV_COUNT; ++v) {
+        std::vector<GemmDesc> grp;
+        long long total = 0;
+        int bm, bn;
+        tile_variant_shape(v, &bm, &bn);
+        for (size_t i = 0; i < gs.size(); ++i) {
+            if (var[i] != v) continue;
+            GemmDesc g = gs[i];
+            g.tiles_m = (g.M + bm - 1) / bm;
+            g.tiles_n = (g.N + bn - 1) / bn;
+            g.block_begin = total;
+            total += (long long)g.tiles_m * g.tiles_n * g.batch;
+            grp.push_back(g);
+        }
+        if (grp.empty()) continue;
+        Launch L{};
+        L.kind = 0;
+        L.prec = prec;
+        L.variant = v;
+        L.b_nk = grp[0].b_nk;
+        L.off = append(blob_, grp);
+        L.nwork = (int)grp.size();
+        L.total = total;
+        seq_.push_back(L);
+    }
+    return TPT_OK;
+}
+
+int MultiExec::build(const double* const* rhs, double* const* out, void* ws) {
+    blob_.clear();
+    seq_.clear();
+    ws_ = ws;
+    const int n = (int)plans_.size();
+    std::vector<Ws> w(n);
+    for (int i = 0; i < n; ++i) {
+        if (!rhs[i] || !out[i]) return fail(TPT_ERR_INVALID, "NULL rhs/out in batch");
+        w[i] = carve(plans_[i], (char*)ws + ws_off_[i]);
+    }
+    auto minv = [&](bool from_rhs, int epi) {
+        const int tin0 = from_rhs ? DT_F64 : DT_F32;
+        const int tmid = mixed_ ? DT_F32 : DT_F64;
+        std::vector<GemmDesc> g(n);
+        for (int i = 0; i < n; ++i)
+            g[i] = stage_gemm(plans_[i], ST_XF, prec_, from_rhs ? (const void*)rhs[i] : (const void*)w[i].r, tin0,
+                              w[i].w1, tmid, EPI_STORE, nullptr, 1);
+        add_gemm_stage(ST_XF, prec_, g);
+        for (int i = 0; i < n; ++i)
+            g[i] = stage_gemm(plans_[i], ST_YF, prec_, w[i].w1, tmid, w[i].w2, tmid, EPI_STORE, nullptr, 1);
+        add_gemm_stage(ST_YF, prec_, g);
+        std::vector<ThomasDesc> t(n);
+        long long lines = 0;
+        for (int i = 0; i < n; ++i) {
+            t[i] = plan_thomas(plans_[i], w[i].w2, tmid, w[i].w2, tmid, w[i].scratch, 1);
+            t[i].line_begin = lines;
+            lines += (long long)t[i].nx * t[i].ny;
+        }
+        Launch L{};
+        L.kind = 1;
+        L.off = append(blob_, t);
+        L.nwork = n;
+        L.total = lines;
+        seq_.push_back(L);
+        for (int i = 0; i < n; ++i)
+            g[i] = stage_gemm(plans_[i], ST_YI, prec_, w[i].w2, tmid, w[i].w1, tmid, EPI_STORE, nullptr, 1);
+        add_gemm_stage(ST_YI, prec_, g);
+        for (int i = 0; i < n; ++i)
+            g[i] = stage_gemm(plans_[i], ST_XI, prec_, w[i].w1, tmid, out[i], DT_F64, epi, w[i].partials, 1);
+        add_gemm_stage(ST_XI, prec_, g);
+        return g;
+    };
+    std::vector<GemmDesc> xi = minv(true, EPI_STORE);
+    for (int it = 0; it < iters_; ++it) {
+        std::vector<StencilDesc> st(n);
+        std::vector<ReduceDesc> rd(n);
+        long long blocks = 0;
+        for (int i = 0; i < n; ++i) {
+            st[i] = plan_stencil(plans_[i], out[i], rhs[i], w[i].r, w[i].partials);
+            st[i].block_begin = blocks;
+            const int nb = residual_blocks(st[i]);
+            blocks += nb;
+            rd[i].partials = w[i].partials;
+            rd[i].n = nb;
+            rd[i].out = (double*)((char*)ws + norm_off_[i]);
+        }
+        Launch L{};
+        L.kind = 2;
+        L.off = append(blob_, st);
+        L.nwork = n;
+        L.total = blocks;
+        seq_.push_back(L);
+        Launch R{};
+        R.kind = 3;
+        R.off = append(blob_, rd);
+        R.nwork = n;
+        seq_.push_back(R);
+        xi = minv(false, EPI_ACCUM_F64);
+        for (int i = 0; i < n; ++i) {
+            const int v = stage_variant(plans_[i], ST_XI, xi[i], prec_);
+            rd[i].partials = w[i].partials;
+            rd[i].n = (int)gemm_blocks(xi[i], v);
+            rd[i].out = (double*)((char*)ws + norm_off_[i]) + 2;
+        }
+        Launch R2{};
+        R2.kind = 3;
+        R2.off = append(blob_, rd);
+        R2.nwork = n;
+        seq_.push_back(R2);
+    }
+    return TPT_OK;
+}
+
+int MultiExec::upload(void* d_desc, hipStream_t s) {
+    d_desc_ = (char*)d_desc;
+    if (blob_.empty()) return TPT_OK;
+    if (pinned_bytes_ < blob_.size()) {
+        if (pinned_) TPT_HIP(hipHostFree(pinned_));
+        pinned_ = nullptr;
+        pinned_bytes_ = 0;
+        TPT_HIP(hipHostMalloc(&pinned_, blob_.size(), hipHostMallocDefault));
+        pinned_bytes_ = blob_.size();
+    }
+    std::memcpy(pinned_, blob_.data(), blob_.size());
+    TPT_HIP(hipMemcpyAsync(d_desc, pinned_, blob_.size(), hipMemcpyHostToDevice, s));
+    TPT_HIP(hipStreamSynchronize(s));
+    return TPT_OK;
+}
+
+int MultiExec::enqueue(hipStream_t s) const {
+    for (const Launch& L : seq_) {
+        hipError_t e = hipSuccess;
+        switch (L.kind) {
+            case 0: {
+                TimedScope ts("multi_gemm", s);
+                e = launch_gemm_multi((const GemmDesc*)(d_desc_ + L.off), L.nwork, L.total, L.prec, L.variant,
+                                      L.b_nk, s);
+                break;
+            }
+            case 1: {
+                TimedScope ts("multi_thomas", s);
+                e = launch_thomas_multi((const ThomasDesc*)(d_desc_ + L.off), L.nwork, L.total, s);
+                break;
+            }
+            case 2: {
+                TimedScope ts("multi_residual", s);
+                e = launch_residual_multi((const StencilDesc*)(d_desc_ + L.off), L.nwork, L.total, s);
+                break;
+            }
+            case 3: {
+                TimedScope ts("multi_reduce", s);
+                e = launch_reduce_pairs_multi((const ReduceDesc*)(d_desc_ + L.off), L.nwork, s);
+                break;
+            }
+        }
+        if (e != hipSuccess) return fail(TPT_ERR_HIP, std::string("multi launch: ") + hipGetErrorString(e));
+    }
+    return TPT_OK;
+}
+
+}  // namespace tpt
+
+// ---------------------------------------------------------------------------
+// Batches
+// ---------------------------------------------------------------------------
+struct tpt_batch_s {
+    tpt::MultiExec exec;
+    int device = 0;
+    void* d_desc = nullptr;
+    size_t d_desc_bytes = 0;
+    // cached work list / graph for one pointer set and stream
+    std::vector<const void*> key;
+    bool built = false;
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t gstream = nullptr;
+    ~tpt_batch_s() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (d_desc) (void)hipFree(d_desc);
+    }
+};
+
+using namespace tpt;
+
+extern "C" {
+
+int tpt_batch_create(int count, const tpt_plan* plans, tpt_batch* out) {
+    if (count < 1 || !plans || !out) return fail(TPT_ERR_INVALID, "bad batch arguments");
+    *out = nullptr;
+    std::unique_ptr<tpt_batch_s> b(new tpt_batch_s());
+    std::vector<tpt_plan_s*> v(plans, plans + count);
+    int rc = b->exec.init(v);
+    if (rc) return rc;
+    TPT_HIP(hipGetDevice(&b->device));
+    *out = b.release();
+    return TPT_OK;
+}
+
+int tpt_batch_destroy(tpt_batch b) {
+    delete b;
+    return TPT_OK;
+}
+
+int tpt_batch_workspace_bytes(tpt_batch b, size_t* bytes) {
+    if (!b || !bytes) return fail(TPT_ERR_INVALID, "NULL argument");
+    *bytes = b->exec.workspace_bytes();
+    return TPT_OK;
+}
+
+int tpt_batch_solve(tpt_batch b, const double* const* rhs, double* const* out, void* ws, size_t ws_bytes,
+                    void* stream, int use_graph) {
+    if (!b || !rhs || !out || !ws) return fail(TPT_ERR_INVALID, "NULL argument");
+    if (ws_bytes < b->exec.workspace_bytes()) return fail(TPT_ERR_WORKSPACE, "batch workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    const int n = b->exec.count();
+    std::vector<const void*> key;
+    key.reserve(2 * n + 2);
+    for (int i = 0; i < n; ++i) {
+        key.push_back(rhs[i]);
+        key.push_back(out[i]);
+    }
+    key.push_back(ws);
+    key.push_back((const void*)s);
+    if (!b->built || key != b->key) {
+        if (b->gexec) {
+            TPT_HIP(hipGraphExecDestroy(b->gexec));
+            b->gexec = nullptr;
+        }
+        int rc = b->exec.build(rhs, out, ws);
+        if (rc) return rc;
+        if (b->d_desc_bytes < b->exec.desc_bytes()) {
+            if (b->d_desc) TPT_HIP(hipFree(b->d_desc));
+            b->d_desc = nullptr;
+            b->d_desc_bytes = 0;
+            if (hipMalloc(&b->d_desc, b->exec.desc_bytes()) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(TPT_ERR_OOM, "batch descriptors");
+            }
+            b->d_desc_bytes = b->exec.desc_bytes();
+        }
+        rc = b->exec.upload(b->d_desc, s);
+        if (rc) return rc;
+        b->key = key;
+        b->built = true;
+    }
+    if (!use_graph) return b->exec.enqueue(s);
+    if (!b->gexec) {
+        hipGraph_t graph = nullptr;
+        TPT_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        int rc = b->exec.enqueue(s);
+        hipError_t e = hipStreamEndCapture(s, &graph);
+        if (rc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(TPT_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+        e = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            b->gexec = nullptr;
+            return fail(TPT_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+        }
+    }
+    TimedScope ts("batch_graph", s);
+    TPT_HIP(hipGraphLaunch(b->gexec, s));
+    return TPT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: time every tile variant on the plan's own GEMM shapes and keep
+// the fastest per (precision, pass, shape).
+// ---------------------------------------------------------------------------
+int tpt_autotune(int count, const tpt_plan* plans, void* stream) {
+    if (count < 1 || !plans) return fail(TPT_ERR_INVALID, "bad autotune arguments");
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    TPT_HIP(hipEventCreate(&e0));
+    TPT_HIP(hipEventCreate(&e1));
+    std::vector<std::tuple<int, int, int, int, int>> done;
+    int rc = TPT_OK;
+    for (int pi = 0; pi < count && rc == TPT_OK; ++pi) {
+        tpt_plan_s* p = plans[pi];
+        if (!p || p->host_only) {
+            rc = fail(TPT_ERR_INVALID, "bad plan for autotune");
+            break;
+        }
+        const int prec = plan_gemm_prec(p);
+        const size_t elem = prec == GP_F64 ? 8 : 4;
+        const size_t bytes = (size_t)p->dof * elem + 256;
+        void *in = nullptr, *outb = nullptr;
+        if (hipMalloc(&in, bytes) != hipSuccess || hipMalloc(&outb, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            if (in) (void)hipFree(in);
+            rc = fail(TPT_ERR_OOM, "autotune buffers");
+            break;
+        }
+        (void)hipMemsetAsync(in, 0, bytes, s);
+        for (int stage : {ST_XF, ST_YF}) {
+            const int dt = prec == GP_F64 ? DT_F64 : DT_F32;
+            GemmDesc g = stage_gemm(p, stage, prec, in, dt, outb, dt, EPI_STORE, nullptr, 1);
+            const int kind = stage == ST_XF ? 0 : 1;
+            auto key = std::make_tuple(prec, kind, kind == 0 ? 0 : g.M, g.N, g.K);
+            if (std::find(done.begin(), done.end(), key) != done.end()) continue;
+            done.push_back(key);
+            int best = -1;
+            float best_ms = 1e30f;
+            for (int v = 0; v < TV_COUNT; ++v) {
+                if (launch_gemm(g, prec, v, s) != hipSuccess) continue;  // warm-up
+                float ms_min = 1e30f;
+                for (int r = 0; r < 3; ++r) {
+                    (void)hipEventRecord(e0, s);
+                    (void)launch_gemm(g, prec, v, s);
+                    (void)hipEventRecord(e1, s);
+                    (void)hipEventSynchronize(e1);
+                    float ms = 0.f;
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    ms_min = std::min(ms_min, ms);
+                }
+                if (ms_min < best_ms) {
+                    best_ms = ms_min;
+                    best = v;
+                }
+            }
+            if (best >= 0) autotune_record(prec, kind, g.M, g.N, g.K, best);
+        }
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(in);
+        (void)hipFree(outb);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
+}  // extern "C"

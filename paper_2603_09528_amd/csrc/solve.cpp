@@ -202,13 +202,13 @@ StencilDesc plan_stencil(const tpt_plan_s* p, const double* x, const double* f, 
     return st;
 }
 
-static int stage_variant(const tpt_plan_s* p, int stage, const GemmDesc& g, int prec) {
+int stage_variant(const tpt_plan_s* p, int stage, const GemmDesc& g, int prec) {
     if (p->gemm_variant[stage] >= 0) return p->gemm_variant[stage];
     const int kind = (stage == ST_XF || stage == ST_XI) ? 0 : 1;
     return choose_variant(prec, kind, g.M, g.N, g.K);
 }
 
-static const char* stage_name(int stage, int prec) {
+const char* stage_name(int stage, int prec) {
     static const char* n[3][4] = {
         {"gemm_x_fwd_f64", "gemm_y_fwd_f64", "gemm_y_inv_f64", "gemm_x_inv_f64"},
         {"gemm_x_fwd_f32", "gemm_y_fwd_f32", "gemm_y_inv_f32", "gemm_x_inv_f32"},
@@ -236,20 +236,9 @@ static int run_thomas(const tpt_plan_s* p, const void* f, int tf, void* x, int t
     return TPT_OK;
 }
 
-// Workspace carve-up (see plan_workspace_bytes).
-struct Ws {
-    char* base;
-    size_t n;  // unknowns over all rhs
-    void* w1;
-    void* w2;
-    float* r;
-    double* scratch;
-    double* partials;
-};
-
 static inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static Ws carve(const tpt_plan_s* p, void* ws) {
+Ws carve(const tpt_plan_s* p, void* ws) {
     Ws w{};
     w.base = (char*)ws;
     w.n = (size_t)p->dof * p->desc.nrhs;
@@ -268,6 +257,11 @@ static Ws carve(const tpt_plan_s* p, void* ws) {
     }
     w.partials = (double*)(w.base + o);
     return w;
+}
+
+long long plan_residual_blocks(const tpt_plan_s* p) {
+    StencilDesc st = plan_stencil(p, nullptr, nullptr, nullptr, nullptr);
+    return residual_blocks(st);
 }
 
 // FP64 path: 2.1 x forward, 2.2 y forward, 2.3 Thomas, 2.4 y inverse, 2.5 x inverse.

@@ -34,7 +34,8 @@ def test_cavity32_fp64_matches_oracle():
     say("cavity32", p.shape)
     got, plan = _solve(p, f)
     ref = O.solve(p, f)
-    assert O.relative_error(p, got, ref) <= FP64_TOL
+    err = O.relative_error(p, got, ref)
+    assert err <= FP64_TOL, err
     r = O.residual(p, f, got)
     assert np.linalg.norm(r) / np.linalg.norm(f) <= 1e-12
     assert plan.info().null_line >= 0
@@ -44,7 +45,8 @@ def test_cavity32_mms():
     p, f, u = W.cavity32_mms()
     got, _ = _solve(p, f)
     ref = O.solve(p, f)
-    assert O.relative_error(p, got, ref) <= FP64_TOL
+    err = O.relative_error(p, got, ref)
+    assert err <= FP64_TOL, err
     # discretisation error of the manufactured case, as the oracle's
     assert abs(O.relative_error(p, got, u) - O.relative_error(p, ref, u)) <= 1e-9
 
@@ -73,7 +75,8 @@ def test_small_fp64_matches_oracle(case):
     say("small fp64", p.n, p.bc, p.loc, p.kind)
     got, _ = _solve(p, f)
     ref = O.solve(p, f)
-    assert O.relative_error(p, got, ref) <= FP64_TOL
+    err = O.relative_error(p, got, ref)
+    assert err <= FP64_TOL, err
 
 
 @pytest.mark.parametrize("case", SMALL, ids=lambda c: f"{c[0][0]}x{c[0][1]}x{c[0][2]}-{c[4]}")
@@ -133,7 +136,8 @@ def test_channel256_fp64_and_mixed_match_oracle():
     ref = O.solve(p, f)
     say("channel256 fp64")
     got, _ = _solve(p, f)
-    assert O.relative_error(p, got, ref) <= FP64_TOL
+    err = O.relative_error(p, got, ref)
+    assert err <= FP64_TOL, err
     for prec in ("fp32", "bf16x3"):
         say("channel256", prec)
         got, plan = _solve(p, f, precision=prec, rtol=1e-12, max_refine=12)
