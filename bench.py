@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--n", type=int, default=256, help="cells per direction (default: the 256^3 workload)")
+    ap.add_argument("--serve-requests", type=int, default=400,
+                    help="requests per serving run (0 disables the serving measurement)")
     return ap.parse_args()
 
 
@@ -67,6 +69,34 @@ def load_traffic(kernel_name):
         return None
     ent = d.get("kernels", {}).get(kernel_name)
     return None if ent is None else ent.get("hbm_bytes_per_launch")
+
+
+def run_serving(args, T, W):
+    """Serving on the ten grid families: closed-loop FP64 throughput, then open
+    loop at 0.7x that rate for FP64 and split-BF16x3 (fixed correction count,
+    the largest the adaptive rule needs over the families)."""
+    import torch
+    from paper_2603_09528_amd import loadgen
+    fams = W.serving_families()
+    rhs = [torch.from_numpy(W.rhs(p, 50 + i)).to("cuda") for i, p in enumerate(fams)]
+    t0 = time.time()
+    plans64 = [T.Plan.from_problem(p) for p in fams]
+    log(f"serving: {len(fams)} fp64 plans in {time.time() - t0:.1f}s")
+    nreq, warm = args.serve_requests, max(20, args.serve_requests // 10)
+    closed = loadgen.run(fams, rhs, plans64, n_requests=nreq, warmup=warm, rate=None)
+    rate = 0.7 * closed["solves_per_s"]
+    log(f"serving: closed loop {closed['solves_per_s']:.1f} solves/s; open loop at {rate:.1f}/s")
+    open64 = loadgen.run(fams, rhs, plans64, n_requests=nreq, warmup=warm, rate=rate)
+    iters = 0
+    for p, f in zip(fams, rhs):
+        cal = T.Plan.from_problem(p, precision="bf16x3", rtol=1e-11, max_refine=12)
+        cal.solve(f)
+        iters = max(iters, cal.info().iters)
+    plansb = [T.Plan.from_problem(p, precision="bf16x3", fixed_refine=iters) for p in fams]
+    openb = loadgen.run(fams, rhs, plansb, n_requests=nreq, warmup=warm, rate=rate)
+    openb["corrections"] = iters
+    return {"families": [p.name + f" {p.n[0]}^3 {''.join(b[0] + b[1] for b in p.bc)}" for p in fams],
+            "closed_loop_fp64": closed, "open_loop_fp64": open64, "open_loop_bf16x3": openb}
 
 
 def main():
@@ -170,6 +200,11 @@ def main():
             results[mode]["rel_err_vs_oracle"] = O.relative_error(prob, out, ref)
             log(f"{mode}: rel err vs oracle {results[mode]['rel_err_vs_oracle']:.3e}")
 
+    # ---- serving loop: 10 grid families 64^3..512^3, Poisson arrivals -------------
+    serving = None
+    if args.serve_requests > 0:
+        serving = run_serving(args, T, W)
+
     # ---- headline: fastest mode that meets the 1e-10 bar -------------------------
     ok = [m for m in results if results[m].get("rel_err_vs_oracle", 0.0) <= TOL]
     best = max(ok or list(results), key=lambda m: results[m]["gdofs"])
@@ -225,6 +260,7 @@ def main():
         "modes": results,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(line))
 

@@ -1,0 +1,72 @@
+// Device helpers shared by the kernel translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace tpt {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+
+// ---------------------------------------------------------------------------
+// Wave-level helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Sum (a, b) over the block in a fixed order; thread 0 gets the result.
+template <int NT>
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* red) {
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+    __syncthreads();
+    if (l == 0) {
+        red[2 * w] = a;
+        red[2 * w + 1] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sa = 0.0, sb = 0.0;
+        for (int i = 0; i < NT / 64; ++i) {
+            sa += red[2 * i];
+            sb += red[2 * i + 1];
+        }
+        a = sa;
+        b = sb;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T load_as(const void* p, long long i, int dtype) {
+    if (dtype == DT_F64) return (T)(((const double*)p)[i]);
+    return (T)(((const float*)p)[i]);
+}
+
+
+// Round to nearest even to bf16 (inf / nan kept), and back.
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+// x = hi + lo with hi = bf16(x), lo = bf16(x - hi)
+__device__ __forceinline__ void split_bf16(float x, uint16_t& hi, uint16_t& lo) {
+    hi = bf16_rne(x);
+    lo = bf16_rne(x - bf16_to_f(hi));
+}
+
+// Upper bound on the grid of a persistent multi-problem launch.
+constexpr long long PERSISTENT_BLOCKS = 2048;
+
+}  // namespace tpt

@@ -1,0 +1,487 @@
+// MFMA GEMM tiles for the eigenbasis transforms (x pass: C = A B^T with A the
+// field's x-lines and B the basis; y pass: C_k = A B_k with A the basis and
+// B_k one z slab).  Included by the per-precision translation units.
+#pragma once
+#include <type_traits>
+
+#include "device_common.h"
+
+namespace tpt {
+
+// ---------------------------------------------------------------------------
+// FP64 / FP32 MFMA (v_mfma_f64_16x16x4f64, v_mfma_f32_16x16x4f32).
+// Operand fragments: lane l holds A[m0 + l%16][k0 + l/16] and
+// B[k0 + l/16][n0 + l%16]; the 16x16 result of lane l is column l%16, rows
+// l/16 + 4r (f64, measured on gfx950) or 4(l/16) + r (f32), r = 0..3.
+// ---------------------------------------------------------------------------
+template <typename TM> struct Mfma;
+template <> struct Mfma<double> {
+    typedef d4 acc;
+    static __device__ __forceinline__ acc zero() { return (acc){0.0, 0.0, 0.0, 0.0}; }
+    static __device__ __forceinline__ acc mma(double a, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lg, int r) { return lg + 4 * r; }
+};
+template <> struct Mfma<float> {
+    typedef f4 acc;
+    static __device__ __forceinline__ acc zero() { return (acc){0.f, 0.f, 0.f, 0.f}; }
+    static __device__ __forceinline__ acc mma(float a, float b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lg, int r) { return 4 * lg + r; }
+};
+
+// Work decomposition of a BM x BN tile: waves of WM x WN.
+template <int BM, int BN> struct TileCfg {
+    static constexpr int WM = BM >= 64 ? 64 : 32;
+    static constexpr int WN = BN >= 64 ? 64 : BN;
+    static constexpr int WAVES_M = BM / WM;
+    static constexpr int WAVES_N = BN / WN;
+    static constexpr int NT = WAVES_M * WAVES_N * 64;
+    static constexpr int MI = WM / 16;
+    static constexpr int NI = WN / 16;
+};
+
+// LDS layout of the FP64/FP32 tile: A as [m][k], B as [n][k] (x pass) or
+// [k][n] (y pass), double-buffered, rows padded against bank conflicts.
+template <typename TM, int BM, int BN, bool BNK> struct SmemF {
+    static constexpr int BK = 16;
+    static constexpr int PA = BK + 1;
+    static constexpr int PB = BNK ? BK + 1 : BN + 2;
+    static constexpr int A_ELEMS = BM * PA;
+    static constexpr int B_ELEMS = BNK ? BN * PB : BK * PB;
+    static constexpr int TOTAL = 2 * (A_ELEMS + B_ELEMS);
+};
+
+__device__ __forceinline__ void decode_tile(const GemmDesc& g, long long lb, int& b, int& tm, int& tn) {
+    const long long per = (long long)g.tiles_m * g.tiles_n;
+    b = (int)(lb / per);
+    const int rem = (int)(lb - (long long)b * per);
+    tm = rem / g.tiles_n;
+    tn = rem - tm * g.tiles_n;
+}
+
+// Epilogue store of one result element.
+template <typename TC, int EPI>
+__device__ __forceinline__ void epi_store(TC* __restrict__ C, long long idx, double v, double& se, double& sx) {
+    if constexpr (EPI == EPI_ACCUM_F64) {
+        const double x = C[idx] + v;
+        C[idx] = x;
+        se += v * v;
+        sx += x * x;
+    } else {
+        C[idx] = (TC)v;
+    }
+}
+
+template <typename TM, typename TA, typename TB, typename TC, int EPI, int BM, int BN, bool BNK>
+__device__ __forceinline__ void gemm_tile_f(const GemmDesc& g, long long lb, TM* smem, double* red) {
+    typedef TileCfg<BM, BN> C;
+    typedef SmemF<TM, BM, BN, BNK> S;
+    typedef Mfma<TM> MM;
+    constexpr int BK = S::BK;
+    constexpr int NT = C::NT;
+    constexpr int LA = BM * BK / NT;
+    constexpr int LB = BN * BK / NT;
+    static_assert(NT % BK == 0, "thread count must be a multiple of BK");
+    TM* As = smem;
+    TM* Bs = smem + 2 * S::A_ELEMS;
+
+    int b, tm, tn;
+    decode_tile(g, lb, b, tm, tn);
+    const int m0 = tm * BM, n0 = tn * BN;
+    const int tid = threadIdx.x;
+    const int w = tid / 64, l = tid % 64, lr = l % 16, lg = l / 16;
+    const int wm = w / C::WAVES_N, wn = w % C::WAVES_N;
+    const int mrem = g.M - m0, nrem = g.N - n0, K = g.K;
+    const int lda = g.lda, ldb = g.ldb;
+    const TA* __restrict__ Ab = (const TA*)g.A + (long long)b * g.sA + (long long)m0 * lda;
+    const TB* __restrict__ Bb =
+        BNK ? (const TB*)g.B + (long long)b * g.sB + (long long)n0 * ldb : (const TB*)g.B + (long long)b * g.sB + n0;
+
+    typename MM::acc acc[C::MI][C::NI];
+#pragma unroll
+    for (int i = 0; i < C::MI; ++i)
+#pragma unroll
+        for (int j = 0; j < C::NI; ++j) acc[i][j] = MM::zero();
+
+    // fixed per-thread load geometry: A slot t covers row tid/BK + t*(NT/BK), column tid%BK
+    const int arow = tid / BK, acol = tid % BK;
+    TM ra[LA], rb[LB];
+    auto gload = [&](int k0) {
+        const bool kok = k0 + acol < K;
+#pragma unroll
+        for (int t = 0; t < LA; ++t) {
+            const int row = arow + t * (NT / BK);
+            ra[t] = (kok && row < mrem) ? (TM)Ab[row * lda + k0 + acol] : (TM)0;
+        }
+#pragma unroll
+        for (int t = 0; t < LB; ++t) {
+            if constexpr (BNK) {
+                const int row = arow + t * (NT / BK);  // over n
+                rb[t] = (kok && row < nrem) ? (TM)Bb[row * ldb + k0 + acol] : (TM)0;
+            } else {
+                const int e = tid + NT * t;
+                const int row = e / BN, col = e % BN;  // row over k, col over n
+                rb[t] = (k0 + row < K && col < nrem) ? (TM)Bb[(k0 + row) * ldb + col] : (TM)0;
+            }
+        }
+    };
+    auto sstore = [&](int buf) {
+        TM* a = As + buf * S::A_ELEMS;
+        TM* bb = Bs + buf * S::B_ELEMS;
+#pragma unroll
+        for (int t = 0; t < LA; ++t) a[(arow + t * (NT / BK)) * S::PA + acol] = ra[t];
+#pragma unroll
+        for (int t = 0; t < LB; ++t) {
+            if constexpr (BNK) {
+                bb[(arow + t * (NT / BK)) * S::PB + acol] = rb[t];
+            } else {
+                const int e = tid + NT * t;
+                bb[(e / BN) * S::PB + (e % BN)] = rb[t];
+            }
+        }
+    };
+
+    const int nk = (K + BK - 1) / BK;
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) gload((kt + 1) * BK);
+        const TM* a = As + cur * S::A_ELEMS + (wm * C::WM + lr) * S::PA + lg;
+        const TM* bb = Bs + cur * S::B_ELEMS;
+#pragma unroll
+        for (int kk = 0; kk < BK / 4; ++kk) {
+            TM fa[C::MI], fb[C::NI];
+#pragma unroll
+            for (int i = 0; i < C::MI; ++i) fa[i] = a[i * 16 * S::PA + kk * 4];
+#pragma unroll
+            for (int j = 0; j < C::NI; ++j) {
+                if constexpr (BNK) fb[j] = bb[(wn * C::WN + j * 16 + lr) * S::PB + kk * 4 + lg];
+                else fb[j] = bb[(kk * 4 + lg) * S::PB + wn * C::WN + j * 16 + lr];
+            }
+#pragma unroll
+            for (int i = 0; i < C::MI; ++i)
+#pragma unroll
+                for (int j = 0; j < C::NI; ++j) acc[i][j] = MM::mma(fa[i], fb[j], acc[i][j]);
+        }
+        if (kt + 1 < nk) sstore(cur ^ 1);
+        __syncthreads();
+    }
+
+    double se = 0.0, sx = 0.0;
+    TC* __restrict__ Cb = (TC*)g.C + (long long)b * g.sC + (long long)m0 * g.ldc + n0;
+#pragma unroll
+    for (int i = 0; i < C::MI; ++i) {
+#pragma unroll
+        for (int j = 0; j < C::NI; ++j) {
+            const int n = wn * C::WN + j * 16 + lr;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = wm * C::WM + i * 16 + MM::row(lg, r);
+                if (m < mrem && n < nrem)
+                    epi_store<TC, EPI>(Cb, (long long)m * g.ldc + n, (double)acc[i][j][r], se, sx);
+            }
+        }
+    }
+    if constexpr (EPI == EPI_ACCUM_F64) {
+        block_sum2<NT>(se, sx, red);
+        if (threadIdx.x == 0) {
+            g.partials[2 * lb] = se;
+            g.partials[2 * lb + 1] = sx;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Split-BF16 x3 (v_mfma_f32_16x16x32_bf16, FP32 accumulate): each operand is
+// x = hi + lo (hi = bf16(x), lo = bf16(x - hi), round to nearest even) and
+// C = A_lo B_hi + A_hi B_lo + A_hi B_hi, small products first.  Fragments:
+// lane l holds A[m0 + l%16][k0 + 8(l/16) .. +7] and B[k0 + 8(l/16) .. +7][n0 + l%16];
+// result rows 4(l/16) + r.  Both LDS tiles are k-contiguous (As[m][k],
+// Bs[n][k]) so each fragment is one 16-byte LDS read.  The basis operand
+// arrives pre-split (bf16 planes); the data operand is split on the fly.
+// ---------------------------------------------------------------------------
+template <int BM, int BN> struct SmemB {
+    static constexpr int BK = 32;
+    static constexpr int P = BK + 8;  // row stride in bf16 (16-byte padding)
+    static constexpr int A_ELEMS = BM * P;
+    static constexpr int B_ELEMS = BN * P;
+    static constexpr int TOTAL = 2 * 2 * (A_ELEMS + B_ELEMS);  // [buffer][hi, lo][A | B]
+};
+
+// 8 consecutive k of one row of a k-contiguous operand: pre-split planes or
+// data to split.  Returns zeros outside [0, nrows) x [0, K).
+template <typename TD>
+__device__ __forceinline__ void load8_data(const TD* __restrict__ p, bool rowok, int k, int K, u16x8& h, u16x8& lo) {
+    float v[8];
+    if constexpr (sizeof(TD) == 4) {
+        if (rowok && k + 8 <= K && ((((uintptr_t)(p + k)) & 15) == 0)) {
+            const float4 p0 = *(const float4*)(p + k);
+            const float4 p1 = *(const float4*)(p + k + 4);
+            v[0] = p0.x; v[1] = p0.y; v[2] = p0.z; v[3] = p0.w;
+            v[4] = p1.x; v[5] = p1.y; v[6] = p1.z; v[7] = p1.w;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = (rowok && k + e < K) ? (float)p[k + e] : 0.f;
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = (rowok && k + e < K) ? (float)p[k + e] : 0.f;
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        uint16_t hh, ll;
+        split_bf16(v[e], hh, ll);
+        h[e] = hh;
+        lo[e] = ll;
+    }
+}
+
+__device__ __forceinline__ void load8_planes(const uint16_t* __restrict__ ph, const uint16_t* __restrict__ pl,
+                                             bool rowok, int k, int K, u16x8& h, u16x8& lo) {
+    if (rowok && k + 8 <= K && ((((uintptr_t)(ph + k)) & 15) == 0)) {
+        h = *(const u16x8*)(ph + k);
+        lo = *(const u16x8*)(pl + k);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const bool ok = rowok && k + e < K;
+            h[e] = ok ? ph[k + e] : (uint16_t)0;
+            lo[e] = ok ? pl[k + e] : (uint16_t)0;
+        }
+    }
+}
+
+template <typename TD, typename TC, int EPI, int BM, int BN, bool BNK>
+__device__ __forceinline__ void gemm_tile_b(const GemmDesc& g, long long lb, uint16_t* smem, double* red) {
+    typedef TileCfg<BM, BN> C;
+    typedef SmemB<BM, BN> S;
+    constexpr int BK = S::BK;
+    constexpr int NT = C::NT;
+    constexpr int P = S::P;
+    constexpr int CA = BM * BK / 8 / NT;  // 8-element chunks of A per thread
+    constexpr int CB = BN * BK / 8 / NT;
+    static_assert(CA >= 1 && CB >= 1, "tile too small for the thread count");
+    uint16_t* sm_hi = smem;
+    uint16_t* sm_lo = smem + 2 * (S::A_ELEMS + S::B_ELEMS);
+
+    int b, tm, tn;
+    decode_tile(g, lb, b, tm, tn);
+    const int m0 = tm * BM, n0 = tn * BN;
+    const int tid = threadIdx.x;
+    const int w = tid / 64, l = tid % 64, lr = l % 16, lg = l / 16;
+    const int wm = w / C::WAVES_N, wn = w % C::WAVES_N;
+    const int mrem = g.M - m0, nrem = g.N - n0, K = g.K;
+    const int lda = g.lda, ldb = g.ldb;
+    // x pass (BNK): A = data [m][k], B = basis planes [n][k]
+    // y pass:       A = basis planes [m][k], B = data [k][n]
+    const long long offA = (long long)b * g.sA + (long long)m0 * lda;
+    const long long offB = BNK ? (long long)b * g.sB + (long long)n0 * ldb : (long long)b * g.sB + n0;
+
+    f4 acc[C::MI][C::NI];
+#pragma unroll
+    for (int i = 0; i < C::MI; ++i)
+#pragma unroll
+        for (int j = 0; j < C::NI; ++j) acc[i][j] = (f4){0.f, 0.f, 0.f, 0.f};
+
+    u16x8 rah[CA], ral[CA], rbh[CB], rbl[CB];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int t = 0; t < CA; ++t) {
+            const int c = tid + NT * t;
+            const int row = c / (BK / 8), kc = c % (BK / 8);
+            const bool rok = row < mrem;
+            if constexpr (BNK)
+                load8_data<TD>((const TD*)g.A + offA + (long long)row * lda, rok, k0 + kc * 8, K, rah[t], ral[t]);
+            else
+                load8_planes(g.basis_hi + offA + (long long)row * lda, g.basis_lo + offA + (long long)row * lda, rok,
+                             k0 + kc * 8, K, rah[t], ral[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < CB; ++t) {
+            const int c = tid + NT * t;
+            if constexpr (BNK) {
+                const int row = c / (BK / 8), kc = c % (BK / 8);
+                load8_planes(g.basis_hi + offB + (long long)row * ldb, g.basis_lo + offB + (long long)row * ldb,
+                             row < nrem, k0 + kc * 8, K, rbh[t], rbl[t]);
+            } else {
+                // B data stored [k][n]: chunk c covers column n = c % BN, k = 8 (c / BN) .. +7
+                const int nn = c % BN, kc = c / BN;
+                const TD* pb = (const TD*)g.B + offB + nn;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int k = k0 + kc * 8 + e;
+                    const float v = (nn < nrem && k < K) ? (float)pb[(long long)k * ldb] : 0.f;
+                    uint16_t hh, ll;
+                    split_bf16(v, hh, ll);
+                    rbh[t][e] = hh;
+                    rbl[t][e] = ll;
+                }
+            }
+        }
+    };
+    auto sstore = [&](int buf) {
+        uint16_t* ah = sm_hi + buf * (S::A_ELEMS + S::B_ELEMS);
+        uint16_t* al = sm_lo + buf * (S::A_ELEMS + S::B_ELEMS);
+#pragma unroll
+        for (int t = 0; t < CA; ++t) {
+            const int c = tid + NT * t;
+            const int row = c / (BK / 8), kc = c % (BK / 8);
+            *(u16x8*)(ah + row * P + kc * 8) = rah[t];
+            *(u16x8*)(al + row * P + kc * 8) = ral[t];
+        }
+        uint16_t* bh = ah + S::A_ELEMS;
+        uint16_t* bl = al + S::A_ELEMS;
+#pragma unroll
+        for (int t = 0; t < CB; ++t) {
+            const int c = tid + NT * t;
+            int row, kc;
+            if constexpr (BNK) {
+                row = c / (BK / 8);
+                kc = c % (BK / 8);
+            } else {
+                row = c % BN;
+                kc = c / BN;
+            }
+            *(u16x8*)(bh + row * P + kc * 8) = rbh[t];
+            *(u16x8*)(bl + row * P + kc * 8) = rbl[t];
+        }
+    };
+
+    const int nk = (K + BK - 1) / BK;
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) gload((kt + 1) * BK);
+        const uint16_t* ah = sm_hi + cur * (S::A_ELEMS + S::B_ELEMS);
+        const uint16_t* al = sm_lo + cur * (S::A_ELEMS + S::B_ELEMS);
+        const uint16_t* bh = ah + S::A_ELEMS;
+        const uint16_t* bl = al + S::A_ELEMS;
+        bf16x8 fah[C::MI], fal[C::MI], fbh[C::NI], fbl[C::NI];
+#pragma unroll
+        for (int i = 0; i < C::MI; ++i) {
+            const int row = wm * C::WM + i * 16 + lr;
+            fah[i] = __builtin_bit_cast(bf16x8, *(const u16x8*)(ah + row * P + lg * 8));
+            fal[i] = __builtin_bit_cast(bf16x8, *(const u16x8*)(al + row * P + lg * 8));
+        }
+#pragma unroll
+        for (int j = 0; j < C::NI; ++j) {
+            const int row = wn * C::WN + j * 16 + lr;
+            fbh[j] = __builtin_bit_cast(bf16x8, *(const u16x8*)(bh + row * P + lg * 8));
+            fbl[j] = __builtin_bit_cast(bf16x8, *(const u16x8*)(bl + row * P + lg * 8));
+        }
+#pragma unroll
+        for (int i = 0; i < C::MI; ++i)
+#pragma unroll
+            for (int j = 0; j < C::NI; ++j) {
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fal[i], fbh[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fah[i], fbl[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fah[i], fbh[j], acc[i][j], 0, 0, 0);
+            }
+        if (kt + 1 < nk) sstore(cur ^ 1);
+        __syncthreads();
+    }
+
+    double se = 0.0, sx = 0.0;
+    TC* __restrict__ Cb = (TC*)g.C + (long long)b * g.sC + (long long)m0 * g.ldc + n0;
+#pragma unroll
+    for (int i = 0; i < C::MI; ++i) {
+#pragma unroll
+        for (int j = 0; j < C::NI; ++j) {
+            const int n = wn * C::WN + j * 16 + lr;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = wm * C::WM + i * 16 + 4 * lg + r;
+                if (m < mrem && n < nrem)
+                    epi_store<TC, EPI>(Cb, (long long)m * g.ldc + n, (double)acc[i][j][r], se, sx);
+            }
+        }
+    }
+    if constexpr (EPI == EPI_ACCUM_F64) {
+        block_sum2<NT>(se, sx, red);
+        if (threadIdx.x == 0) {
+            g.partials[2 * lb] = se;
+            g.partials[2 * lb + 1] = sx;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Kernels: one descriptor, or a persistent loop over a work list (a block
+// finds its problem by binary search on block_begin).
+// ---------------------------------------------------------------------------
+// PREC: GP_F64 / GP_F32 / GP_BF16X3; TA: data type of the x-pass A (or of A
+// for a plain GEMM), TB: data type of the y-pass B, TC output type.
+template <int PREC, typename TA, typename TB, typename TC, int EPI, int BM, int BN, bool BNK>
+struct GemmKernel {
+    static __device__ __forceinline__ void tile(const GemmDesc& g, long long lb) {
+        if constexpr (PREC == GP_BF16X3) {
+            __shared__ __attribute__((aligned(16))) uint16_t smem[SmemB<BM, BN>::TOTAL];
+            __shared__ double red[2 * TileCfg<BM, BN>::NT / 64];
+            if constexpr (BNK) gemm_tile_b<TA, TC, EPI, BM, BN, true>(g, lb, smem, red);
+            else gemm_tile_b<TB, TC, EPI, BM, BN, false>(g, lb, smem, red);
+        } else {
+            typedef typename std::conditional<PREC == GP_F64, double, float>::type T;
+            __shared__ __attribute__((aligned(16))) T smem[SmemF<T, BM, BN, BNK>::TOTAL];
+            __shared__ double red[2 * TileCfg<BM, BN>::NT / 64];
+            gemm_tile_f<T, TA, TB, TC, EPI, BM, BN, BNK>(g, lb, smem, red);
+        }
+    }
+};
+
+template <int PREC, typename TA, typename TB, typename TC, int EPI, int BM, int BN, bool BNK>
+__global__ __launch_bounds__((TileCfg<BM, BN>::NT)) void gemm_kernel(GemmDesc g) {
+    GemmKernel<PREC, TA, TB, TC, EPI, BM, BN, BNK>::tile(g, blockIdx.x);
+}
+
+template <int PREC, typename TA, typename TB, typename TC, int EPI, int BM, int BN, bool BNK>
+__global__ __launch_bounds__((TileCfg<BM, BN>::NT)) void gemm_multi_kernel(const GemmDesc* __restrict__ work,
+                                                                            int nwork, long long total) {
+    for (long long blk = blockIdx.x; blk < total; blk += gridDim.x) {
+        int lo = 0, hi = nwork - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if (work[mid].block_begin <= blk) lo = mid;
+            else hi = mid - 1;
+        }
+        const GemmDesc g = work[lo];
+        GemmKernel<PREC, TA, TB, TC, EPI, BM, BN, BNK>::tile(g, blk - g.block_begin);
+        __syncthreads();
+    }
+}
+
+template <int PREC, typename TA, typename TB, typename TC, int EPI, bool BNK>
+hipError_t launch_gemm_typed(const GemmDesc& g, const GemmDesc* d_work, int nwork, long long blocks, int variant,
+                             hipStream_t s) {
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+#define TPT_LAUNCH(BM_, BN_)                                                                                     \
+    do {                                                                                                         \
+        constexpr int NT_ = TileCfg<BM_, BN_>::NT;                                                               \
+        if (d_work)                                                                                              \
+            hipLaunchKernelGGL((gemm_multi_kernel<PREC, TA, TB, TC, EPI, BM_, BN_, BNK>),                        \
+                               dim3((unsigned)(blocks < PERSISTENT_BLOCKS ? blocks : PERSISTENT_BLOCKS)),        \
+                               dim3(NT_), 0, s, d_work, nwork, blocks);                                          \
+        else                                                                                                     \
+            hipLaunchKernelGGL((gemm_kernel<PREC, TA, TB, TC, EPI, BM_, BN_, BNK>), dim3((unsigned)blocks),      \
+                               dim3(NT_), 0, s, g);                                                              \
+    } while (0)
+    switch (variant) {
+        case TV_128x128: TPT_LAUNCH(128, 128); break;
+        case TV_64x128: TPT_LAUNCH(64, 128); break;
+        case TV_128x64: TPT_LAUNCH(128, 64); break;
+        case TV_64x64: TPT_LAUNCH(64, 64); break;
+        case TV_32x64: TPT_LAUNCH(32, 64); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef TPT_LAUNCH
+    return hipGetLastError();
+}
+
+}  // namespace tpt

@@ -50,9 +50,17 @@ long long gemm_blocks(const GemmDesc& g, int variant);
 // One launch for one descriptor.
 hipError_t launch_gemm(GemmDesc g, int prec, int variant, hipStream_t s);
 // One launch over a device array of descriptors (block_begin, tiles_m/n set
-// by the caller, sorted by block_begin, all with the same prec/variant/b_nk).
-hipError_t launch_gemm_multi(const GemmDesc* d_work, int nwork, long long total_blocks, int prec,
-                             int variant, int b_nk, hipStream_t s);
+// by the caller, sorted by block_begin, all sharing prec, variant, b_nk, the
+// operand types and the epilogue of `rep`).
+hipError_t launch_gemm_multi(const GemmDesc& rep, const GemmDesc* d_work, int nwork, long long total_blocks,
+                             int prec, int variant, hipStream_t s);
+// Per-precision launchers (gemm_f64.hip, gemm_f32.hip, gemm_bf16.hip).
+hipError_t launch_gemm_f64(const GemmDesc& g, const GemmDesc* d_work, int nwork, long long blocks, int variant,
+                           hipStream_t s);
+hipError_t launch_gemm_f32(const GemmDesc& g, const GemmDesc* d_work, int nwork, long long blocks, int variant,
+                           hipStream_t s);
+hipError_t launch_gemm_bf16(const GemmDesc& g, const GemmDesc* d_work, int nwork, long long blocks, int variant,
+                            hipStream_t s);
 
 // Thomas solve along z (§2.2.2 step 2.3) for nsys systems of nx*ny lines.
 struct ThomasDesc {

@@ -190,8 +190,8 @@ int MultiExec::enqueue(hipStream_t s) const {
         switch (L.kind) {
             case 0: {
                 TimedScope ts("multi_gemm", s);
-                e = launch_gemm_multi((const GemmDesc*)(d_desc_ + L.off), L.nwork, L.total, L.prec, L.variant,
-                                      L.b_nk, s);
+                const GemmDesc& rep = *(const GemmDesc*)(blob_.data() + L.off);
+                e = launch_gemm_multi(rep, (const GemmDesc*)(d_desc_ + L.off), L.nwork, L.total, L.prec, L.variant, s);
                 break;
             }
             case 1: {
@@ -229,9 +229,10 @@ struct tpt_batch_s {
     std::vector<const void*> key;
     bool built = false;
     hipGraphExec_t gexec = nullptr;
-    hipStream_t gstream = nullptr;
+    hipStream_t capture = nullptr;  // private stream used only to record the graph
     ~tpt_batch_s() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (capture) (void)hipStreamDestroy(capture);
         if (d_desc) (void)hipFree(d_desc);
     }
 };
@@ -301,10 +302,13 @@ int tpt_batch_solve(tpt_batch b, const double* const* rhs, double* const* out, v
     }
     if (!use_graph) return b->exec.enqueue(s);
     if (!b->gexec) {
+        // record on a private stream (the caller's may be the legacy null
+        // stream, which cannot be captured), replay on the caller's stream
+        if (!b->capture) TPT_HIP(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
         hipGraph_t graph = nullptr;
-        TPT_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        int rc = b->exec.enqueue(s);
-        hipError_t e = hipStreamEndCapture(s, &graph);
+        TPT_HIP(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
+        int rc = b->exec.enqueue(b->capture);
+        hipError_t e = hipStreamEndCapture(b->capture, &graph);
         if (rc) {
             if (graph) (void)hipGraphDestroy(graph);
             return rc;
