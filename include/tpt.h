@@ -206,8 +206,9 @@ int tpt_server_destroy(tpt_server server);
  * l = i + nx*j of each of nsys systems,
  *   (sigma + tau*(lamx[i] + lamy[j] + T_z)) x = f,
  * T_z with sub-diagonal az, diagonal bz, super-diagonal cz (device, nz each);
- * f, x: device FP64 [nsys][nz][ny][nx]; scratch: device FP64 of the same
- * size.  pin_line >= 0 sets the last unknown of that line to zero (§3 gauge).
+ * f, x: device FP64 [nsys][nz][ny][nx]; scratch: device FP64 of at least
+ * 2 * nx * ny * nsys * ceil(nz / 16) elements (chunk checkpoints).
+ * pin_line >= 0 sets the last unknown of that line to zero (§3 gauge).
  * f may equal x. */
 int tpt_thomas(int nx, int ny, int nz, int nsys, const double *lamx, const double *lamy,
                const double *az, const double *bz, const double *cz, double sigma,

@@ -12,7 +12,7 @@
  * n'/2 disjoint rotations, which commute, so a round is one orthogonal
  * similarity A <- J^T A J, V <- V J.  Sweeps repeat until one sweep finds
  * every off-diagonal entry negligible (|a_pq| <= tol sqrt(|a_pp a_qq|), the
- * relative criterion of Demmel & Veselic, or |a_pq| <= tol^2 max|a|).
+ * relative criterion of Demmel & Veselic, or |a_pq| <= tol max|a|).
  *
  * Plain C, no BLAS/LAPACK.  OpenMP only splits the independent row/column
  * updates of a round across threads.
@@ -61,11 +61,13 @@ int oracle_jacobi(int n, double *Ad, double *Vd, double *w, double tol, int max_
     real *cs = (real *)malloc(sizeof(real) * m);   /* c, s per pair */
     int *pq = (int *)malloc(sizeof(int) * m);           /* active p, q per pair */
     /* A rotation is skipped (and a_pq treated as zero) when
-     * |a_pq| <= tol * sqrt(|a_pp a_qq|) or |a_pq| <= tol^2 max|a_ij|; the
-     * iteration stops after a sweep with no rotation. */
+     * |a_pq| <= tol * sqrt(|a_pp a_qq|) or |a_pq| <= tol * max|a_ij|; the
+     * iteration stops after a sweep with no rotation.  The absolute floor
+     * matters for (near-)zero eigenvalues, whose couplings cannot fall below
+     * the rounding level of the whole matrix. */
     real amax = 0.0L;
     for (size_t e = 0; e < (size_t)n * n; ++e) amax = fmaxl(amax, fabsl(A[e]));
-    const real rtol = (real)tol, atol = (real)tol * (real)tol * amax;
+    const real rtol = (real)tol, atol = (real)tol * amax;
     int sweeps = -1;
     for (int sweep = 0; sweep <= max_sweeps; ++sweep) {
         int rotations = 0;

@@ -210,7 +210,7 @@ template <int BM, int BN> struct SmemB {
     static constexpr int P = BK + 8;  // row stride in bf16 (16-byte padding)
     static constexpr int A_ELEMS = BM * P;
     static constexpr int B_ELEMS = BN * P;
-    static constexpr int TOTAL = 2 * 2 * (A_ELEMS + B_ELEMS);  // [buffer][hi, lo][A | B]
+    static constexpr int TOTAL = 2 * (A_ELEMS + B_ELEMS);  // [hi, lo][A | B], single buffer
 };
 
 // 8 consecutive k of one row of a k-contiguous operand: pre-split planes or
@@ -267,7 +267,7 @@ __device__ __forceinline__ void gemm_tile_b(const GemmDesc& g, long long lb, uin
     constexpr int CB = BN * BK / 8 / NT;
     static_assert(CA >= 1 && CB >= 1, "tile too small for the thread count");
     uint16_t* sm_hi = smem;
-    uint16_t* sm_lo = smem + 2 * (S::A_ELEMS + S::B_ELEMS);
+    uint16_t* sm_lo = smem + (S::A_ELEMS + S::B_ELEMS);
 
     int b, tm, tn;
     decode_tile(g, lb, b, tm, tn);
@@ -324,9 +324,9 @@ __device__ __forceinline__ void gemm_tile_b(const GemmDesc& g, long long lb, uin
             }
         }
     };
-    auto sstore = [&](int buf) {
-        uint16_t* ah = sm_hi + buf * (S::A_ELEMS + S::B_ELEMS);
-        uint16_t* al = sm_lo + buf * (S::A_ELEMS + S::B_ELEMS);
+    auto sstore = [&]() {
+        uint16_t* ah = sm_hi;
+        uint16_t* al = sm_lo;
 #pragma unroll
         for (int t = 0; t < CA; ++t) {
             const int c = tid + NT * t;
@@ -352,15 +352,18 @@ __device__ __forceinline__ void gemm_tile_b(const GemmDesc& g, long long lb, uin
         }
     };
 
+    // single LDS buffer (keeps the tile small enough for two or three
+    // workgroups per CU); the next tile is prefetched into registers while
+    // the current one is multiplied
     const int nk = (K + BK - 1) / BK;
     gload(0);
-    sstore(0);
-    __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
-        const int cur = kt & 1;
+        if (kt > 0) __syncthreads();  // every wave is done reading the previous tile
+        sstore();
+        __syncthreads();
         if (kt + 1 < nk) gload((kt + 1) * BK);
-        const uint16_t* ah = sm_hi + cur * (S::A_ELEMS + S::B_ELEMS);
-        const uint16_t* al = sm_lo + cur * (S::A_ELEMS + S::B_ELEMS);
+        const uint16_t* ah = sm_hi;
+        const uint16_t* al = sm_lo;
         const uint16_t* bh = ah + S::A_ELEMS;
         const uint16_t* bl = al + S::A_ELEMS;
         bf16x8 fah[C::MI], fal[C::MI], fbh[C::NI], fbl[C::NI];
@@ -384,9 +387,8 @@ __device__ __forceinline__ void gemm_tile_b(const GemmDesc& g, long long lb, uin
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fah[i], fbl[j], acc[i][j], 0, 0, 0);
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fah[i], fbh[j], acc[i][j], 0, 0, 0);
             }
-        if (kt + 1 < nk) sstore(cur ^ 1);
-        __syncthreads();
     }
+    __syncthreads();
 
     double se = 0.0, sx = 0.0;
     TC* __restrict__ Cb = (TC*)g.C + (long long)b * g.sC + (long long)m0 * g.ldc + n0;

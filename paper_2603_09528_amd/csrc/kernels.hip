@@ -64,13 +64,14 @@ hipError_t launch_gemm_multi(const GemmDesc& rep, const GemmDesc* d_work, int nw
 // k the lanes of a wave touch consecutive addresses (stride N_x N_y between k
 // planes).  Arithmetic in FP64 whatever the storage type of f and x.
 //
-// Traffic: the forward sweep stores only d' (into x when x is FP64, else into
-// an FP64 scratch) and, every THOMAS_KC planes, a checkpoint of c'; the
-// backward sweep recomputes c' chunk by chunk from its checkpoint in
-// registers instead of reading it back.  Loads of the next chunk are issued
-// before the current chunk is computed (one lane per line leaves only one
-// wave per SIMD at the workload sizes, so latency is hidden by prefetching,
-// not by occupancy).
+// Traffic: the forward elimination keeps c' and d' in registers and stores
+// only a checkpoint (c', d') every THOMAS_KC planes; the back substitution
+// walks the chunks from the top, re-reads the chunk of f, recomputes its c'
+// and d' from the checkpoint and substitutes.  So f is read twice and x
+// written once (no per-unknown scratch), and x may alias f.  Loads of the
+// next chunk are issued before the current chunk is computed: one lane per
+// line leaves about one wave per SIMD at the workload sizes, so latency is
+// hidden by prefetching rather than by occupancy.
 //
 // The line pin_line is the null line of a singular Poisson problem: its final
 // pivot vanishes and its last unknown is set to zero (§3).
@@ -78,9 +79,10 @@ hipError_t launch_gemm_multi(const GemmDesc& rep, const GemmDesc* d_work, int nw
 constexpr int THOMAS_KC = 16;
 
 long long thomas_scratch_doubles(int nx, int ny, int nz, int nsys, int tx) {
+    (void)tx;
     const long long lines = (long long)nx * ny * nsys;
     const long long nck = (nz + THOMAS_KC - 1) / THOMAS_KC;
-    return lines * nck + (tx == DT_F64 ? 0 : lines * nz);
+    return 2 * lines * nck;
 }
 
 template <typename TF, typename TX>
@@ -97,14 +99,21 @@ __device__ __forceinline__ void thomas_line(const ThomasDesc& t, long long gl) {
     const long long base = (long long)sys * S * nz + line;
     const TF* f = (const TF*)t.f + base;
     TX* x = (TX*)t.x + base;
-    // checkpoints ck[c][gl] (c' entering chunk c), then (FP32 x) d' [sys][k][line]
-    double* ck = t.scratch + gl;
-    double* dst = sizeof(TX) == 8 ? (double*)((TX*)t.x + base) : t.scratch + lines * nc + base;
+    double2* ck = (double2*)t.scratch + gl;  // ck[c * lines]: (c', d') entering chunk c
     const bool pinned = line == t.pin_line;
     const double sig = t.sigma, tau = t.tau;
     const double* __restrict__ az = t.az;
     const double* __restrict__ bz = t.bz;
     const double* __restrict__ cz = t.cz;
+
+    // one elimination step: (cp, dp) <- step k with right-hand side fk
+    auto step = [&](int k, double fk, double& cp, double& dp) {
+        const double sub = k > 0 ? tau * az[k] : 0.0;
+        const double den = sig + tau * (lam + bz[k]) - sub * cp;
+        const double inv = (pinned && k == nz - 1) ? 0.0 : 1.0 / den;
+        cp = k < nz - 1 ? tau * cz[k] * inv : 0.0;
+        dp = (fk - sub * dp) * inv;
+    };
 
     // ---- forward elimination ----
     double cp = 0.0, dp = 0.0;
@@ -113,7 +122,7 @@ __device__ __forceinline__ void thomas_line(const ThomasDesc& t, long long gl) {
     for (int e = 0; e < KC; ++e) fb[e] = e < nz ? (double)f[(long long)e * S] : 0.0;
     for (int c = 0; c < nc; ++c) {
         const int k0 = c * KC;
-        ck[(long long)c * lines] = cp;
+        ck[(long long)c * lines] = make_double2(cp, dp);
 #pragma unroll
         for (int e = 0; e < KC; ++e) {
             const int k = k0 + KC + e;
@@ -122,60 +131,48 @@ __device__ __forceinline__ void thomas_line(const ThomasDesc& t, long long gl) {
 #pragma unroll
         for (int e = 0; e < KC; ++e) {
             const int k = k0 + e;
-            if (k < nz) {
-                const double sub = k > 0 ? tau * az[k] : 0.0;
-                const double den = sig + tau * (lam + bz[k]) - sub * cp;
-                const double inv = (pinned && k == nz - 1) ? 0.0 : 1.0 / den;
-                cp = k < nz - 1 ? tau * cz[k] * inv : 0.0;
-                dp = (fb[e] - sub * dp) * inv;
-                dst[(long long)k * S] = dp;
-            }
+            if (k < nz) step(k, fb[e], cp, dp);
         }
 #pragma unroll
         for (int e = 0; e < KC; ++e) fb[e] = fn[e];
     }
 
-    // ---- back substitution, c' recomputed per chunk from its checkpoint ----
-    double xv = dp;  // x_{nz-1} (0 on the pinned line: inv = 0 there)
-    x[(long long)(nz - 1) * S] = (TX)xv;
-    double db[KC], dn[KC];
+    // ---- back substitution chunk by chunk from the top ----
+    double xv = 0.0;  // x_{k0 + KC} entering each chunk from above
     {
         const int k0 = (nc - 1) * KC;
 #pragma unroll
         for (int e = 0; e < KC; ++e) {
             const int k = k0 + e;
-            db[e] = k < nz - 1 ? dst[(long long)k * S] : 0.0;
+            fb[e] = k < nz ? (double)f[(long long)k * S] : 0.0;
         }
     }
     for (int c = nc - 1; c >= 0; --c) {
         const int k0 = c * KC;
         if (c > 0) {
 #pragma unroll
-            for (int e = 0; e < KC; ++e) dn[e] = dst[(long long)(k0 - KC + e) * S];
+            for (int e = 0; e < KC; ++e) fn[e] = (double)f[(long long)(k0 - KC + e) * S];
         }
-        double cb[KC];
-        double cpr = ck[(long long)c * lines];
+        const double2 c0 = ck[(long long)c * lines];
+        double cb[KC], db[KC];
+        double cpr = c0.x, dpr = c0.y;
 #pragma unroll
         for (int e = 0; e < KC; ++e) {
             const int k = k0 + e;
-            if (k < nz) {
-                const double sub = k > 0 ? tau * az[k] : 0.0;
-                const double den = sig + tau * (lam + bz[k]) - sub * cpr;
-                const double inv = (pinned && k == nz - 1) ? 0.0 : 1.0 / den;
-                cpr = k < nz - 1 ? tau * cz[k] * inv : 0.0;
-            }
+            if (k < nz) step(k, fb[e], cpr, dpr);
             cb[e] = cpr;
+            db[e] = dpr;
         }
 #pragma unroll
         for (int e = KC - 1; e >= 0; --e) {
             const int k = k0 + e;
-            if (k < nz - 1) {
-                xv = db[e] - cb[e] * xv;
+            if (k < nz) {
+                xv = (k == nz - 1) ? db[e] : db[e] - cb[e] * xv;  // last: x = d' (0 on the pinned line)
                 x[(long long)k * S] = (TX)xv;
             }
         }
 #pragma unroll
-        for (int e = 0; e < KC; ++e) db[e] = dn[e];
+        for (int e = 0; e < KC; ++e) fb[e] = fn[e];
     }
 }
 

@@ -184,8 +184,8 @@ static size_t partial_slots(const tpt_plan_s* p) {
 size_t plan_workspace_bytes(const tpt_plan_s* p) {
     const size_t n = (size_t)p->dof * p->desc.nrhs;
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    const size_t main = (p->desc.precision == TPT_FP64) ? 2 * al(8 * n) + al(16 * n)
-                                                         : al(16 * n) + 3 * al(4 * n);
+    const size_t tsc = 8 * (size_t)thomas_scratch_doubles(p->N[0], p->N[1], p->N[2], p->desc.nrhs, DT_F64);
+    const size_t main = (p->desc.precision == TPT_FP64) ? 2 * al(8 * n) + al(tsc) : al(tsc) + 3 * al(4 * n);
     return main + 16 * partial_slots(p) + 256;
 }
 

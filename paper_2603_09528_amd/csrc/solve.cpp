@@ -244,13 +244,14 @@ Ws carve(const tpt_plan_s* p, void* ws) {
     w.n = (size_t)p->dof * p->desc.nrhs;
     const size_t n = w.n;
     size_t o = 0;
+    const size_t tsc = 8 * (size_t)thomas_scratch_doubles(p->N[0], p->N[1], p->N[2], p->desc.nrhs, DT_F64);
     if (p->desc.precision == TPT_FP64) {
         w.w1 = w.base + o; o += al256(8 * n);
         w.w2 = w.base + o; o += al256(8 * n);
-        w.scratch = (double*)(w.base + o); o += al256(16 * n);
+        w.scratch = (double*)(w.base + o); o += al256(tsc);
         w.r = nullptr;
     } else {
-        w.scratch = (double*)(w.base + o); o += al256(16 * n);
+        w.scratch = (double*)(w.base + o); o += al256(tsc);
         w.w1 = w.base + o; o += al256(4 * n);
         w.w2 = w.base + o; o += al256(4 * n);
         w.r = (float*)(w.base + o); o += al256(4 * n);

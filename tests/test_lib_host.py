@@ -123,4 +123,4 @@ def test_workspace_size_reported():
     T = _lib()
     p = W.make_problem((10, 9, 8), (1.0, 1.0, 1.0), (W.NN, W.NN, W.NN))
     plan = T.Plan.from_problem(p, host_only=True)
-    assert plan.workspace_bytes() >= 32 * p.dof
+    assert plan.workspace_bytes() >= 16 * p.dof
