@@ -215,12 +215,19 @@ int tpt_thomas(int nx, int ny, int nz, int nsys, const double *lamx, const doubl
                double tau, int pin_line, const double *f, double *x, double *scratch,
                void *stream);
 
-/* Strided-batched row-major GEMM C_b = A_b B_b (M x K times K x N) with the
- * library's MFMA kernels.  prec: TPT_FP64 (double operands), TPT_MIXED_FP32
- * (float operands) or TPT_MIXED_BF16X3 (float operands split to bf16 pairs).
- * Leading dimensions are K, N, N; batch strides in elements (0 = shared). */
-int tpt_gemm(int prec, int M, int N, int K, int batch, const void *A, long long strideA,
-             const void *B, long long strideB, void *C, long long strideC, void *stream);
+/* Strided-batched GEMM with the library's MFMA kernels (the transform
+ * kernels of §2.2.2 on explicit operands).  A is M x K row-major (lda = K);
+ * b_nk = 0: C_b = A_b B_b with B stored K x N (ldb = N), the y-pass form;
+ * b_nk = 1: C_b = A_b B_b^T with B stored N x K (ldb = K), the x-pass form.
+ * C is M x N (ldc = N).  prec: TPT_FP64 (double operands), TPT_MIXED_FP32
+ * (float) or TPT_MIXED_BF16X3 (float operands; the basis-side operand — B for
+ * b_nk = 1, A for b_nk = 0 — is split once into bf16 planes in a temporary
+ * device buffer, the other on the fly).  variant: tile shape 0..4 (128x128,
+ * 64x128, 128x64, 64x64, 32x64) or -1 for the tile table.  Batch strides in
+ * elements (0 = shared).  Synchronises the stream for TPT_MIXED_BF16X3. */
+int tpt_gemm(int prec, int b_nk, int variant, int M, int N, int K, int batch, const void *A,
+             long long strideA, const void *B, long long strideB, void *C, long long strideC,
+             void *stream);
 
 /* Per-kernel timing with HIP events recorded on the launch stream around
  * every library kernel while enabled (process-wide). */

@@ -99,7 +99,7 @@ def lib():
             "tpt_server_drain": (i, [vp]),
             "tpt_server_destroy": (i, [vp]),
             "tpt_thomas": (i, [i, i, i, i, vp, vp, vp, vp, vp, d, d, i, vp, vp, vp, vp]),
-            "tpt_gemm": (i, [i, i, i, i, i, vp, ctypes.c_longlong, vp, ctypes.c_longlong, vp,
+            "tpt_gemm": (i, [i, i, i, i, i, i, i, vp, ctypes.c_longlong, vp, ctypes.c_longlong, vp,
                              ctypes.c_longlong, vp]),
             "tpt_timing_enable": (i, [i]),
             "tpt_timing_collect": (i, [ctypes.POINTER(ctypes.c_int), ctypes.c_char_p, sz, dp,
@@ -360,10 +360,12 @@ def thomas(nx, ny, nz, nsys, lamx, lamy, az, bz, cz, sigma, tau, pin_line, f, x,
     return x
 
 
-def gemm(prec, A, B, C, M, N, K, batch=1, sA=0, sB=0, sC=0, stream=None):
-    """Kernel-level strided-batched GEMM C_b = A_b B_b with the MFMA kernels."""
+def gemm(prec, A, B, C, M, N, K, batch=1, sA=0, sB=0, sC=0, b_nk=False, variant=-1, stream=None):
+    """Kernel-level strided-batched GEMM with the MFMA kernels: C = A B
+    (B stored K x N) or, with b_nk, C = A B^T (B stored N x K)."""
     p = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
-    _check(lib().tpt_gemm(p, M, N, K, batch, _ptr(A), sA, _ptr(B), sB, _ptr(C), sC, _stream(stream)))
+    _check(lib().tpt_gemm(p, 1 if b_nk else 0, int(variant), M, N, K, batch, _ptr(A), sA, _ptr(B), sB, _ptr(C), sC,
+                          _stream(stream)))
     return C
 
 

@@ -76,13 +76,24 @@ hipError_t launch_gemm_multi(const GemmDesc& rep, const GemmDesc* d_work, int nw
 // The line pin_line is the null line of a singular Poisson problem: its final
 // pivot vanishes and its last unknown is set to zero (§3).
 // ---------------------------------------------------------------------------
-constexpr int THOMAS_KC = 16;
+constexpr int THOMAS_KC = 32;
 
 long long thomas_scratch_doubles(int nx, int ny, int nz, int nsys, int tx) {
     (void)tx;
     const long long lines = (long long)nx * ny * nsys;
     const long long nck = (nz + THOMAS_KC - 1) / THOMAS_KC;
     return 2 * lines * nck;
+}
+
+// 1/d from the hardware reciprocal and two Newton steps (about 1 ulp): the
+// Thomas recurrence is a chain of dependent operations, so a short chain is
+// what matters here.
+__device__ __forceinline__ double recip(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    double e = __builtin_fma(-d, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-d, r, 1.0);
+    return __builtin_fma(r, e, r);
 }
 
 template <typename TF, typename TX>
@@ -110,7 +121,7 @@ __device__ __forceinline__ void thomas_line(const ThomasDesc& t, long long gl) {
     auto step = [&](int k, double fk, double& cp, double& dp) {
         const double sub = k > 0 ? tau * az[k] : 0.0;
         const double den = sig + tau * (lam + bz[k]) - sub * cp;
-        const double inv = (pinned && k == nz - 1) ? 0.0 : 1.0 / den;
+        const double inv = (pinned && k == nz - 1) ? 0.0 : recip(den);
         cp = k < nz - 1 ? tau * cz[k] * inv : 0.0;
         dp = (fk - sub * dp) * inv;
     };
@@ -138,7 +149,7 @@ __device__ __forceinline__ void thomas_line(const ThomasDesc& t, long long gl) {
     }
 
     // ---- back substitution chunk by chunk from the top ----
-    double xv = 0.0;  // x_{k0 + KC} entering each chunk from above
+    double xv = 0.0;  // x_{k+1} entering each step from above
     {
         const int k0 = (nc - 1) * KC;
 #pragma unroll
@@ -154,20 +165,20 @@ __device__ __forceinline__ void thomas_line(const ThomasDesc& t, long long gl) {
             for (int e = 0; e < KC; ++e) fn[e] = (double)f[(long long)(k0 - KC + e) * S];
         }
         const double2 c0 = ck[(long long)c * lines];
-        double cb[KC], db[KC];
+        double cb[KC];
         double cpr = c0.x, dpr = c0.y;
 #pragma unroll
-        for (int e = 0; e < KC; ++e) {
+        for (int e = 0; e < KC; ++e) {  // recompute c', d' of the chunk (d' replaces f in fb)
             const int k = k0 + e;
             if (k < nz) step(k, fb[e], cpr, dpr);
             cb[e] = cpr;
-            db[e] = dpr;
+            fb[e] = dpr;
         }
 #pragma unroll
         for (int e = KC - 1; e >= 0; --e) {
             const int k = k0 + e;
             if (k < nz) {
-                xv = (k == nz - 1) ? db[e] : db[e] - cb[e] * xv;  // last: x = d' (0 on the pinned line)
+                xv = (k == nz - 1) ? fb[e] : fb[e] - cb[e] * xv;  // last: x = d' (0 on the pinned line)
                 x[(long long)k * S] = (TX)xv;
             }
         }

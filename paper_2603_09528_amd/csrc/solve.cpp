@@ -429,47 +429,52 @@ int tpt_thomas(int nx, int ny, int nz, int nsys, const double* lamx, const doubl
     return TPT_OK;
 }
 
-int tpt_gemm(int prec, int M, int N, int K, int batch, const void* A, long long strideA, const void* B,
-             long long strideB, void* C, long long strideC, void* stream) {
+int tpt_gemm(int prec, int b_nk, int variant, int M, int N, int K, int batch, const void* A, long long strideA,
+             const void* B, long long strideB, void* C, long long strideC, void* stream) {
     if (M < 1 || N < 1 || K < 1 || batch < 1 || !A || !B || !C) return fail(TPT_ERR_INVALID, "bad GEMM arguments");
     if (prec < TPT_FP64 || prec > TPT_MIXED_BF16X3) return fail(TPT_ERR_INVALID, "bad precision");
+    if (variant < -1 || variant >= TV_COUNT) return fail(TPT_ERR_INVALID, "bad tile variant");
+    hipStream_t s = (hipStream_t)stream;
     GemmDesc g{};
     g.A = A; g.B = B; g.C = C;
-    g.M = M; g.N = N; g.K = K; g.lda = K; g.ldb = N; g.ldc = N;
+    g.M = M; g.N = N; g.K = K;
+    g.lda = K; g.ldb = b_nk ? K : N; g.ldc = N;
     g.sA = strideA; g.sB = strideB; g.sC = strideC; g.batch = batch;
-    g.b_nk = 0;
+    g.b_nk = b_nk ? 1 : 0;
     const int t = prec == TPT_FP64 ? DT_F64 : DT_F32;
     g.tA = g.tB = g.tC = t;
     g.epi = EPI_STORE;
     const int gp = prec == TPT_FP64 ? GP_F64 : (prec == TPT_MIXED_FP32 ? GP_F32 : GP_BF16X3);
-    std::vector<uint16_t> dummy;
     void* planes = nullptr;
     if (gp == GP_BF16X3) {
-        // split the shared-or-batched A operand into bf16 planes on the device
-        const long long na = strideA ? strideA * batch : (long long)M * K;
+        // split the basis-side operand into bf16 planes
+        const void* src = b_nk ? B : A;
+        const long long stride = b_nk ? strideB : strideA;
+        const long long one = b_nk ? (long long)N * K : (long long)M * K;
+        const long long na = stride ? stride * (batch - 1) + one : one;
         if (hipMalloc(&planes, 2 * sizeof(uint16_t) * na) != hipSuccess) {
             (void)hipGetLastError();
             return fail(TPT_ERR_OOM, "GEMM planes");
         }
         uint16_t* hi = (uint16_t*)planes;
         uint16_t* lo = hi + na;
-        hipError_t e = launch_split_bf16((const float*)A, hi, lo, na, (hipStream_t)stream);
+        hipError_t e = launch_split_bf16((const float*)src, hi, lo, na, s);
         if (e != hipSuccess) {
             (void)hipFree(planes);
             return fail(TPT_ERR_HIP, hipGetErrorString(e));
         }
         g.basis_hi = hi;
         g.basis_lo = lo;
-        g.basis_is_A = 1;
+        g.basis_is_A = b_nk ? 0 : 1;
     }
-    const int v = choose_variant(gp, 1, M, N, K);
+    const int v = variant >= 0 ? variant : choose_variant(gp, b_nk ? 0 : 1, M, N, K);
     hipError_t e;
     {
-        TimedScope ts("gemm_test", (hipStream_t)stream);
-        e = launch_gemm(g, gp, v, (hipStream_t)stream);
+        TimedScope ts("gemm_test", s);
+        e = launch_gemm(g, gp, v, s);
     }
     if (planes) {
-        (void)hipStreamSynchronize((hipStream_t)stream);
+        (void)hipStreamSynchronize(s);
         (void)hipFree(planes);
     }
     if (e != hipSuccess) return fail(TPT_ERR_HIP, hipGetErrorString(e));

@@ -72,15 +72,16 @@ GEMM_SHAPES = [(1, 1, 1, 1), (16, 16, 16, 1), (37, 53, 29, 3), (128, 128, 128, 1
                (256, 64, 256, 1), (33, 300, 17, 1)]
 
 
+@pytest.mark.parametrize("b_nk", [False, True], ids=["kn", "nk"])
 @pytest.mark.parametrize("M,N,K,batch", GEMM_SHAPES)
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
-def test_gemm_matches_numpy(prec, M, N, K, batch):
+def test_gemm_matches_numpy(prec, M, N, K, batch, b_nk):
     import torch
     T = _T()
-    say("gemm", prec, M, N, K, batch)
+    say("gemm", prec, M, N, K, batch, b_nk)
     rng = np.random.default_rng(M + 7 * N + 13 * K)
     A = rng.standard_normal((batch, M, K))
-    B = rng.standard_normal((batch, K, N))
+    B = rng.standard_normal((batch, N, K) if b_nk else (batch, K, N))
     if prec == "fp64":
         dt, tol = torch.float64, 1e-14
     else:
@@ -88,13 +89,15 @@ def test_gemm_matches_numpy(prec, M, N, K, batch):
         A = A.astype(np.float32).astype(np.float64)
         B = B.astype(np.float32).astype(np.float64)
         tol = 2e-6 if prec == "fp32" else 2e-5
-    ref = A @ B
+    ref = A @ (np.transpose(B, (0, 2, 1)) if b_nk else B)
     Ad = torch.from_numpy(A).to("cuda", dt)
     Bd = torch.from_numpy(B).to("cuda", dt)
     C = torch.empty((batch, M, N), dtype=dt, device="cuda")
-    T.gemm(prec, Ad, Bd, C, M, N, K, batch, M * K, K * N, M * N)
-    torch.cuda.synchronize()
-    got = host(C).astype(np.float64)
     scale = np.abs(A).max() * np.abs(B).max() * K
-    err = np.abs(got - ref).max() / scale
-    assert err <= tol, err
+    for variant in range(5):
+        C.fill_(float("nan"))
+        T.gemm(prec, Ad, Bd, C, M, N, K, batch, M * K, K * N, M * N, b_nk=b_nk, variant=variant)
+        torch.cuda.synchronize()
+        got = host(C).astype(np.float64)
+        err = np.abs(got - ref).max() / scale
+        assert err <= tol, (variant, err)
