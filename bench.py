@@ -43,6 +43,10 @@ def parse():
     ap.add_argument("--n", type=int, default=256, help="cells per direction (default: the 256^3 workload)")
     ap.add_argument("--serve-requests", type=int, default=400,
                     help="requests per serving run (0 disables the serving measurement)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--helmholtz-steps", type=int, default=3,
+                    help="timed solves of the 1024x768x512 Helmholtz workload (0 disables it)")
     return ap.parse_args()
 
 
@@ -99,6 +103,43 @@ def run_serving(args, T, W):
             "closed_loop_fp64": closed, "open_loop_fp64": open64, "open_loop_bf16x3": openb}
 
 
+def run_helmholtz(args, T, W):
+    """The implicit-diffusion workload: (I - alpha L) u = f, alpha = 1e-4, on
+    1024x768x512 cells (x periodic uniform, y and z Dirichlet walls, tanh beta
+    = 2), the three staggered velocity components as one batch of three plans;
+    FP64 against split-BF16x3 with FP64 refinement."""
+    import torch
+    comps = W.helmholtz3()
+    rhs = [torch.from_numpy(W.rhs(p, s)).to("cuda") for p, s in comps]
+    outs = [torch.empty_like(r) for r in rhs]
+    dof = sum(p.dof for p, _ in comps)
+    res = {"dof": dof}
+    for prec in ("fp64", "bf16x3"):
+        t0 = time.time()
+        if prec == "fp64":
+            plans = [T.Plan.from_problem(p) for p, _ in comps]
+            iters = 0
+        else:
+            cal = T.Plan.from_problem(comps[0][0], precision=prec, rtol=1e-11, max_refine=12)
+            cal.solve(rhs[0], outs[0])
+            iters = cal.info().iters
+            del cal
+            plans = [T.Plan.from_problem(p, precision=prec, fixed_refine=iters) for p, _ in comps]
+        b = T.Batch(plans)
+        log(f"helmholtz {prec}: plans {time.time() - t0:.1f}s, corrections {iters}")
+        b.solve(rhs, outs, use_graph=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.helmholtz_steps):
+            b.solve(rhs, outs, use_graph=False)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.helmholtz_steps
+        res[prec] = {"ms_per_solve_3rhs": ms, "gdofs": dof / (ms * 1e-3) / 1e9, "corrections": iters}
+        log(f"helmholtz {prec}: {ms:.1f} ms per 3-rhs solve, {res[prec]['gdofs']:.2f} GDOF/s")
+        del b, plans
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -119,6 +160,16 @@ def main():
     dof = prob.dof
     stream = torch.cuda.current_stream()
     modes = [m for m in args.modes.split(",") if m]
+
+    if args.copy_calibration:
+        # a plain copy of known size: FETCH_SIZE / WRITE_SIZE of this kernel
+        # calibrate the counters of the solver's kernels (1 GiB read + 1 GiB written)
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").normal_()
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     results = {}
     outs = {}
@@ -200,6 +251,10 @@ def main():
             results[mode]["rel_err_vs_oracle"] = O.relative_error(prob, out, ref)
             log(f"{mode}: rel err vs oracle {results[mode]['rel_err_vs_oracle']:.3e}")
 
+    helm = None
+    if args.helmholtz_steps > 0:
+        helm = run_helmholtz(args, T, W)
+
     # ---- serving loop: 10 grid families 64^3..512^3, Poisson arrivals -------------
     serving = None
     if args.serve_requests > 0:
@@ -261,6 +316,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "serving": serving,
+        "helmholtz_1024x768x512_3rhs": helm,
     }
     print(json.dumps(line))
 

@@ -108,8 +108,24 @@ __device__ __forceinline__ void gemm_tile_f(const GemmDesc& g, long long lb, TM*
 
     // fixed per-thread load geometry: A slot t covers row tid/BK + t*(NT/BK), column tid%BK
     const int arow = tid / BK, acol = tid % BK;
+    // interior tiles (whole tile inside M x N, K a multiple of BK) load without predicates
+    const bool full = mrem >= BM && nrem >= BN && (K % BK) == 0;
     TM ra[LA], rb[LB];
     auto gload = [&](int k0) {
+        if (full) {
+#pragma unroll
+            for (int t = 0; t < LA; ++t) ra[t] = (TM)Ab[(arow + t * (NT / BK)) * lda + k0 + acol];
+#pragma unroll
+            for (int t = 0; t < LB; ++t) {
+                if constexpr (BNK) {
+                    rb[t] = (TM)Bb[(arow + t * (NT / BK)) * ldb + k0 + acol];
+                } else {
+                    const int e = tid + NT * t;
+                    rb[t] = (TM)Bb[(k0 + e / BN) * ldb + e % BN];
+                }
+            }
+            return;
+        }
         const bool kok = k0 + acol < K;
 #pragma unroll
         for (int t = 0; t < LA; ++t) {
@@ -182,7 +198,7 @@ __device__ __forceinline__ void gemm_tile_f(const GemmDesc& g, long long lb, TM*
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int m = wm * C::WM + i * 16 + MM::row(lg, r);
-                if (m < mrem && n < nrem)
+                if (full || (m < mrem && n < nrem))
                     epi_store<TC, EPI>(Cb, (long long)m * g.ldc + n, (double)acc[i][j][r], se, sx);
             }
         }
