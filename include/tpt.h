@@ -92,7 +92,9 @@ typedef struct {
     int kind;               /* TPT_POISSON or TPT_HELMHOLTZ */
     double alpha;           /* Helmholtz coefficient (> 0), ignored for Poisson */
     int precision;          /* TPT_FP64, TPT_MIXED_FP32, TPT_MIXED_BF16X3 */
-    double rtol;            /* mixed modes: stop when ||e||_2/||x||_2 <= rtol (default 1e-12 if <= 0) */
+    double rtol;            /* mixed modes (adaptive): stop when the estimated remaining error
+                               ||e_k|| min(1, ||e_k|| / ||e_{k-1}||) / ||x|| <= rtol, where e_k is
+                               the k-th correction and e_0 = x (default 1e-12 if <= 0) */
     int max_refine;         /* mixed modes: cap on corrections (default 8 if <= 0) */
     int fixed_refine;       /* mixed modes: >= 0 runs exactly this many corrections with
                                no host synchronisation (stream-ordered, capturable);

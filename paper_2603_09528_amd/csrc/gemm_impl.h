@@ -44,14 +44,17 @@ template <int BM, int BN> struct TileCfg {
 };
 
 // LDS layout of the FP64/FP32 tile: A as [m][k], B as [n][k] (x pass) or
-// [k][n] (y pass), double-buffered, rows padded against bank conflicts.
-template <typename TM, int BM, int BN, bool BNK> struct SmemF {
-    static constexpr int BK = 16;
+// [k][n] (y pass), rows padded against bank conflicts.  NBUF = 2: double
+// buffered (one barrier per K tile); NBUF = 1: single buffer, two barriers
+// per K tile, room for a deeper K tile.
+template <typename TM, int BM, int BN, bool BNK, int BK_ = 16, int NBUF_ = 2> struct SmemF {
+    static constexpr int BK = BK_;
+    static constexpr int NBUF = NBUF_;
     static constexpr int PA = BK + 1;
     static constexpr int PB = BNK ? BK + 1 : BN + 2;
     static constexpr int A_ELEMS = BM * PA;
     static constexpr int B_ELEMS = BNK ? BN * PB : BK * PB;
-    static constexpr int TOTAL = 2 * (A_ELEMS + B_ELEMS);
+    static constexpr int TOTAL = NBUF * (A_ELEMS + B_ELEMS);
 };
 
 __device__ __forceinline__ void decode_tile(const GemmDesc& g, long long lb, int& b, int& tm, int& tn) {
@@ -75,10 +78,11 @@ __device__ __forceinline__ void epi_store(TC* __restrict__ C, long long idx, dou
     }
 }
 
-template <typename TM, typename TA, typename TB, typename TC, int EPI, int BM, int BN, bool BNK>
+template <typename TM, typename TA, typename TB, typename TC, int EPI, int BM, int BN, bool BNK, int BK_ = 16,
+          int NBUF = 2>
 __device__ __forceinline__ void gemm_tile_f(const GemmDesc& g, long long lb, TM* smem, double* red) {
     typedef TileCfg<BM, BN> C;
-    typedef SmemF<TM, BM, BN, BNK> S;
+    typedef SmemF<TM, BM, BN, BNK, BK_, NBUF> S;
     typedef Mfma<TM> MM;
     constexpr int BK = S::BK;
     constexpr int NT = C::NT;
@@ -86,7 +90,7 @@ __device__ __forceinline__ void gemm_tile_f(const GemmDesc& g, long long lb, TM*
     constexpr int LB = BN * BK / NT;
     static_assert(NT % BK == 0, "thread count must be a multiple of BK");
     TM* As = smem;
-    TM* Bs = smem + 2 * S::A_ELEMS;
+    TM* Bs = smem + S::NBUF * S::A_ELEMS;
 
     int b, tm, tn;
     decode_tile(g, lb, b, tm, tn);
@@ -162,10 +166,17 @@ __device__ __forceinline__ void gemm_tile_f(const GemmDesc& g, long long lb, TM*
 
     const int nk = (K + BK - 1) / BK;
     gload(0);
-    sstore(0);
-    __syncthreads();
+    if constexpr (NBUF == 2) {
+        sstore(0);
+        __syncthreads();
+    }
     for (int kt = 0; kt < nk; ++kt) {
-        const int cur = kt & 1;
+        const int cur = NBUF == 2 ? (kt & 1) : 0;
+        if constexpr (NBUF == 1) {
+            if (kt > 0) __syncthreads();  // every wave is done with the previous tile
+            sstore(0);
+            __syncthreads();
+        }
         if (kt + 1 < nk) gload((kt + 1) * BK);
         const TM* a = As + cur * S::A_ELEMS + (wm * C::WM + lr) * S::PA + lg;
         const TM* bb = Bs + cur * S::B_ELEMS;
@@ -184,9 +195,12 @@ __device__ __forceinline__ void gemm_tile_f(const GemmDesc& g, long long lb, TM*
 #pragma unroll
                 for (int j = 0; j < C::NI; ++j) acc[i][j] = MM::mma(fa[i], fb[j], acc[i][j]);
         }
-        if (kt + 1 < nk) sstore(cur ^ 1);
-        __syncthreads();
+        if constexpr (NBUF == 2) {
+            if (kt + 1 < nk) sstore(cur ^ 1);
+            __syncthreads();
+        }
     }
+    if constexpr (NBUF == 1) __syncthreads();
 
     double se = 0.0, sx = 0.0;
     TC* __restrict__ Cb = (TC*)g.C + (long long)b * g.sC + (long long)m0 * g.ldc + n0;
@@ -305,6 +319,9 @@ __device__ __forceinline__ void gemm_tile_b(const GemmDesc& g, long long lb, uin
         for (int j = 0; j < C::NI; ++j) acc[i][j] = (f4){0.f, 0.f, 0.f, 0.f};
 
     u16x8 rah[CA], ral[CA], rbh[CB], rbl[CB];
+    static_assert(BNK || CB % 2 == 0, "pair chunks need an even chunk count");
+    // y pass: 8-byte loads of column pairs when every row start is 8-byte aligned
+    const bool bvec = !BNK && (ldb % 2) == 0 && (offB % 2) == 0 && ((((uintptr_t)g.B) & 7) == 0);
     auto gload = [&](int k0) {
 #pragma unroll
         for (int t = 0; t < CA; ++t) {
@@ -318,24 +335,42 @@ __device__ __forceinline__ void gemm_tile_b(const GemmDesc& g, long long lb, uin
                              k0 + kc * 8, K, rah[t], ral[t]);
         }
 #pragma unroll
-        for (int t = 0; t < CB; ++t) {
+        for (int t = 0; t < (BNK ? CB : 0); ++t) {
             const int c = tid + NT * t;
             if constexpr (BNK) {
                 const int row = c / (BK / 8), kc = c % (BK / 8);
                 load8_planes(g.basis_hi + offB + (long long)row * ldb, g.basis_lo + offB + (long long)row * ldb,
                              row < nrem, k0 + kc * 8, K, rbh[t], rbl[t]);
-            } else {
-                // B data stored [k][n]: chunk c covers column n = c % BN, k = 8 (c / BN) .. +7
-                const int nn = c % BN, kc = c / BN;
+            }
+        }
+        if constexpr (!BNK) {
+            // B data stored [k][n]: pair chunk c covers columns 2 (c % (BN/2)) + {0, 1}
+            // and k = 8 (c / (BN/2)) .. +7; one 8-byte load per row when aligned
+#pragma unroll
+            for (int t = 0; t < CB / 2; ++t) {
+                const int c = tid + NT * t;
+                const int np = c % (BN / 2), kc = c / (BN / 2);
+                const int nn = 2 * np;
                 const TD* pb = (const TD*)g.B + offB + nn;
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
                     const int k = k0 + kc * 8 + e;
-                    const float v = (nn < nrem && k < K) ? (float)pb[(long long)k * ldb] : 0.f;
+                    float v0, v1;
+                    if (bvec && k < K && nn + 1 < nrem) {
+                        const float2 q = *(const float2*)(pb + (long long)k * ldb);
+                        v0 = q.x;
+                        v1 = q.y;
+                    } else {
+                        v0 = (nn < nrem && k < K) ? (float)pb[(long long)k * ldb] : 0.f;
+                        v1 = (nn + 1 < nrem && k < K) ? (float)pb[(long long)k * ldb + 1] : 0.f;
+                    }
                     uint16_t hh, ll;
-                    split_bf16(v, hh, ll);
-                    rbh[t][e] = hh;
-                    rbl[t][e] = ll;
+                    split_bf16(v0, hh, ll);
+                    rbh[2 * t][e] = hh;
+                    rbl[2 * t][e] = ll;
+                    split_bf16(v1, hh, ll);
+                    rbh[2 * t + 1][e] = hh;
+                    rbl[2 * t + 1][e] = ll;
                 }
             }
         }
@@ -354,14 +389,15 @@ __device__ __forceinline__ void gemm_tile_b(const GemmDesc& g, long long lb, uin
         uint16_t* bl = al + S::A_ELEMS;
 #pragma unroll
         for (int t = 0; t < CB; ++t) {
-            const int c = tid + NT * t;
             int row, kc;
             if constexpr (BNK) {
+                const int c = tid + NT * t;
                 row = c / (BK / 8);
                 kc = c % (BK / 8);
             } else {
-                row = c % BN;
-                kc = c / BN;
+                const int c = tid + NT * (t / 2);
+                row = 2 * (c % (BN / 2)) + (t & 1);
+                kc = c / (BN / 2);
             }
             *(u16x8*)(bh + row * P + kc * 8) = rbh[t];
             *(u16x8*)(bl + row * P + kc * 8) = rbl[t];
@@ -436,7 +472,8 @@ __device__ __forceinline__ void gemm_tile_b(const GemmDesc& g, long long lb, uin
 // ---------------------------------------------------------------------------
 // PREC: GP_F64 / GP_F32 / GP_BF16X3; TA: data type of the x-pass A (or of A
 // for a plain GEMM), TB: data type of the y-pass B, TC output type.
-template <int PREC, typename TA, typename TB, typename TC, int EPI, int BM, int BN, bool BNK>
+// DEEP = 1: K tile of 32 with a single LDS buffer (FP64/FP32 only).
+template <int PREC, typename TA, typename TB, typename TC, int EPI, int BM, int BN, bool BNK, int DEEP>
 struct GemmKernel {
     static __device__ __forceinline__ void tile(const GemmDesc& g, long long lb) {
         if constexpr (PREC == GP_BF16X3) {
@@ -446,20 +483,23 @@ struct GemmKernel {
             else gemm_tile_b<TB, TC, EPI, BM, BN, false>(g, lb, smem, red);
         } else {
             typedef typename std::conditional<PREC == GP_F64, double, float>::type T;
-            __shared__ __attribute__((aligned(16))) T smem[SmemF<T, BM, BN, BNK>::TOTAL];
+            constexpr int BKd = DEEP ? 32 : 16, NB = DEEP ? 1 : 2;
+            __shared__ __attribute__((aligned(16))) T smem[SmemF<T, BM, BN, BNK, BKd, NB>::TOTAL];
             __shared__ double red[2 * TileCfg<BM, BN>::NT / 64];
-            gemm_tile_f<T, TA, TB, TC, EPI, BM, BN, BNK>(g, lb, smem, red);
+            gemm_tile_f<T, TA, TB, TC, EPI, BM, BN, BNK, BKd, NB>(g, lb, smem, red);
         }
     }
 };
 
-template <int PREC, typename TA, typename TB, typename TC, int EPI, int BM, int BN, bool BNK>
-__global__ __launch_bounds__((TileCfg<BM, BN>::NT)) void gemm_kernel(GemmDesc g) {
-    GemmKernel<PREC, TA, TB, TC, EPI, BM, BN, BNK>::tile(g, blockIdx.x);
+#define TPT_GEMM_ATTR __launch_bounds__((TileCfg<BM, BN>::NT))
+
+template <int PREC, typename TA, typename TB, typename TC, int EPI, int BM, int BN, bool BNK, int DEEP>
+__global__ TPT_GEMM_ATTR void gemm_kernel(GemmDesc g) {
+    GemmKernel<PREC, TA, TB, TC, EPI, BM, BN, BNK, DEEP>::tile(g, blockIdx.x);
 }
 
-template <int PREC, typename TA, typename TB, typename TC, int EPI, int BM, int BN, bool BNK>
-__global__ __launch_bounds__((TileCfg<BM, BN>::NT)) void gemm_multi_kernel(const GemmDesc* __restrict__ work,
+template <int PREC, typename TA, typename TB, typename TC, int EPI, int BM, int BN, bool BNK, int DEEP>
+__global__ TPT_GEMM_ATTR void gemm_multi_kernel(const GemmDesc* __restrict__ work,
                                                                             int nwork, long long total) {
     for (long long blk = blockIdx.x; blk < total; blk += gridDim.x) {
         int lo = 0, hi = nwork - 1;
@@ -469,7 +509,7 @@ __global__ __launch_bounds__((TileCfg<BM, BN>::NT)) void gemm_multi_kernel(const
             else hi = mid - 1;
         }
         const GemmDesc g = work[lo];
-        GemmKernel<PREC, TA, TB, TC, EPI, BM, BN, BNK>::tile(g, blk - g.block_begin);
+        GemmKernel<PREC, TA, TB, TC, EPI, BM, BN, BNK, DEEP>::tile(g, blk - g.block_begin);
         __syncthreads();
     }
 }
@@ -479,23 +519,27 @@ hipError_t launch_gemm_typed(const GemmDesc& g, const GemmDesc* d_work, int nwor
                              hipStream_t s) {
     if (blocks <= 0) return hipSuccess;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-#define TPT_LAUNCH(BM_, BN_)                                                                                     \
+#define TPT_LAUNCH(BM_, BN_, DEEP_)                                                                              \
     do {                                                                                                         \
         constexpr int NT_ = TileCfg<BM_, BN_>::NT;                                                               \
         if (d_work)                                                                                              \
-            hipLaunchKernelGGL((gemm_multi_kernel<PREC, TA, TB, TC, EPI, BM_, BN_, BNK>),                        \
+            hipLaunchKernelGGL((gemm_multi_kernel<PREC, TA, TB, TC, EPI, BM_, BN_, BNK, DEEP_>),                 \
                                dim3((unsigned)(blocks < PERSISTENT_BLOCKS ? blocks : PERSISTENT_BLOCKS)),        \
                                dim3(NT_), 0, s, d_work, nwork, blocks);                                          \
         else                                                                                                     \
-            hipLaunchKernelGGL((gemm_kernel<PREC, TA, TB, TC, EPI, BM_, BN_, BNK>), dim3((unsigned)blocks),      \
-                               dim3(NT_), 0, s, g);                                                              \
+            hipLaunchKernelGGL((gemm_kernel<PREC, TA, TB, TC, EPI, BM_, BN_, BNK, DEEP_>),                       \
+                               dim3((unsigned)blocks), dim3(NT_), 0, s, g);                                      \
     } while (0)
     switch (variant) {
-        case TV_128x128: TPT_LAUNCH(128, 128); break;
-        case TV_64x128: TPT_LAUNCH(64, 128); break;
-        case TV_128x64: TPT_LAUNCH(128, 64); break;
-        case TV_64x64: TPT_LAUNCH(64, 64); break;
-        case TV_32x64: TPT_LAUNCH(32, 64); break;
+        case TV_128x128: TPT_LAUNCH(128, 128, 0); break;
+        case TV_64x128: TPT_LAUNCH(64, 128, 0); break;
+        case TV_128x64: TPT_LAUNCH(128, 64, 0); break;
+        case TV_64x64: TPT_LAUNCH(64, 64, 0); break;
+        case TV_32x64: TPT_LAUNCH(32, 64, 0); break;
+        case TV_128x128_K32:
+            if constexpr (PREC == GP_BF16X3) return hipErrorInvalidValue;
+            else TPT_LAUNCH(128, 128, 1);
+            break;
         default: return hipErrorInvalidValue;
     }
 #undef TPT_LAUNCH

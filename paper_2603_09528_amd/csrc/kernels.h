@@ -16,7 +16,11 @@ enum Epilogue {
 };
 
 // Tile shapes (BM x BN) compiled for every precision; the autotuner picks.
-enum TileVariant { TV_128x128 = 0, TV_64x128 = 1, TV_128x64 = 2, TV_64x64 = 3, TV_32x64 = 4, TV_COUNT = 5 };
+// TV_128x128_K32: 128 x 128 with a 32-deep K tile in a single LDS buffer
+// (FP64 and FP32 only).
+enum TileVariant {
+    TV_128x128 = 0, TV_64x128 = 1, TV_128x64 = 2, TV_64x64 = 3, TV_32x64 = 4, TV_128x128_K32 = 5, TV_COUNT = 6
+};
 const char* tile_variant_name(int v);
 void tile_variant_shape(int v, int* bm, int* bn);
 

@@ -83,7 +83,7 @@ int choose_variant(int prec, int kind, int M, int N, int K) {
     // heuristic: least padded area, then the larger tile
     int best = TV_128x128;
     double best_cost = 1e300;
-    for (int v = 0; v < TV_COUNT; ++v) {
+    for (int v = 0; v <= TV_32x64; ++v) {
         int bm, bn;
         tile_variant_shape(v, &bm, &bn);
         const double pm = std::ceil((double)M / bm) * bm, pn = std::ceil((double)N / bn) * bn;
@@ -306,7 +306,7 @@ static int solve_mixed(tpt_plan_s* p, const double* rhs, double* out, const Ws& 
     const int max_it = adaptive ? p->desc.max_refine : p->desc.fixed_refine;
     double* dn = p->buf.norms;  // [0,1] = (r^2, f^2), [2,3] = (e^2, x^2)
     int it = 0;
-    double rel_e = 0.0, rel_r = -1.0;
+    double rel_e = 0.0, rel_r = -1.0, prev_e = 1.0, est = 1.0;  // the first solve counts as a correction of size ||x||
     for (it = 0; it < max_it;) {
         // residual of every rhs, partials packed back to back
         long long pb = 0;
@@ -337,7 +337,11 @@ static int solve_mixed(tpt_plan_s* p, const double* rhs, double* out, const Ws& 
             rel_r = h[1] > 0 ? std::sqrt(h[0] / h[1]) : 0.0;
             rel_e = h[3] > 0 ? std::sqrt(h[2] / h[3]) : 0.0;
             if (!(rel_e == rel_e)) return fail(TPT_ERR_NOT_CONVERGED, "non-finite correction");
-            if (rel_e <= p->desc.rtol) break;
+            // error left after this correction ~ contraction rate * ||e_k||, with
+            // the rate estimated from two successive corrections
+            est = rel_e * std::min(1.0, rel_e / prev_e);
+            prev_e = rel_e;
+            if (est <= p->desc.rtol) break;
         }
     }
     p->info.iters = it;
@@ -348,8 +352,8 @@ static int solve_mixed(tpt_plan_s* p, const double* rhs, double* out, const Ws& 
     } else {
         p->info.rel_correction = rel_e;
         p->info.rel_residual = rel_r;
-        if (rel_e > p->desc.rtol && it >= max_it)
-            return fail(TPT_ERR_NOT_CONVERGED, "refinement stopped at ||e||/||x|| = " + std::to_string(rel_e));
+        if (est > p->desc.rtol && it >= max_it)
+            return fail(TPT_ERR_NOT_CONVERGED, "refinement stopped with estimated error " + std::to_string(est));
     }
     return TPT_OK;
 }
