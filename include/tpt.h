@@ -72,9 +72,12 @@ enum { TPT_FP64 = 0, TPT_MIXED_FP32 = 1, TPT_MIXED_BF16X3 = 2 };
 
 /* Plan flags. */
 enum {
-    TPT_FLAG_HOST_ONLY = 1  /* build the host-side operators and eigenbases
+    TPT_FLAG_HOST_ONLY = 1, /* build the host-side operators and eigenbases
                                only (no device memory, no GPU needed); such a
                                plan can be inspected but not solved */
+    TPT_FLAG_DENSE_X = 2    /* apply the x eigenbasis as a dense GEMM even where
+                               the fast real-Fourier transform applies (the
+                               "GG" variant; default is "FG" there) */
 };
 
 typedef struct tpt_plan_s *tpt_plan;
@@ -140,6 +143,12 @@ int tpt_plan_eigen(tpt_plan plan, int dir, double *lam, double *Qt);
  * diagonal b, super-diagonal c and control volumes vol, N entries each (for a
  * periodic direction a[0] and c[N-1] are the cyclic corners). */
 int tpt_plan_operator(tpt_plan plan, int dir, double *a, double *b, double *c, double *vol);
+
+/* *x_fft = 1 if the plan applies the x eigenbasis with the fast real-Fourier
+ * transform (uniform periodic x with a power-of-two N_x in 8..2048, and no
+ * TPT_FLAG_DENSE_X; §3 lets a uniform direction use FFT-based transforms),
+ * 0 if with dense GEMMs. */
+int tpt_plan_x_fft(tpt_plan plan, int *x_fft);
 
 /* Solve A x = rhs for the plan's nrhs right-hand sides.  rhs, out: device
  * FP64 fields (nrhs * Nz*Ny*Nx each); rhs is read only and must not overlap

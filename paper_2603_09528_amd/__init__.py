@@ -84,6 +84,7 @@ def lib():
             "tpt_plan_workspace_bytes": (i, [vp, ctypes.POINTER(sz)]),
             "tpt_plan_eigen": (i, [vp, i, dp, dp]),
             "tpt_plan_operator": (i, [vp, i, dp, dp, dp, dp]),
+            "tpt_plan_x_fft": (i, [vp, ctypes.POINTER(ctypes.c_int)]),
             "tpt_solve": (i, [vp, vp, vp, vp, sz, vp]),
             "tpt_solve_info": (i, [vp, ctypes.POINTER(Info)]),
             "tpt_batch_create": (i, [i, ctypes.POINTER(vp), ctypes.POINTER(vp)]),
@@ -116,7 +117,7 @@ def lib():
 
 
 EXPORTED = ("tpt_plan_desc_init", "tpt_plan_create", "tpt_plan_destroy", "tpt_plan_shape",
-            "tpt_plan_workspace_bytes", "tpt_plan_eigen", "tpt_plan_operator", "tpt_solve",
+            "tpt_plan_workspace_bytes", "tpt_plan_eigen", "tpt_plan_operator", "tpt_plan_x_fft", "tpt_solve",
             "tpt_solve_info", "tpt_batch_create", "tpt_batch_destroy", "tpt_batch_workspace_bytes",
             "tpt_batch_solve", "tpt_autotune", "tpt_autotune_save", "tpt_autotune_load",
             "tpt_server_create", "tpt_server_submit", "tpt_server_poll", "tpt_server_drain",
@@ -162,7 +163,7 @@ class Plan:
     """
 
     def __init__(self, n, faces, bc, loc=("C", "C", "C"), kind="poisson", alpha=0.0, precision="fp64",
-                 rtol=1e-12, max_refine=8, fixed_refine=-1, nrhs=1, host_only=False):
+                 rtol=1e-12, max_refine=8, fixed_refine=-1, nrhs=1, host_only=False, dense_x=False):
         L = lib()
         d = _Desc()
         L.tpt_plan_desc_init(ctypes.byref(d))
@@ -180,7 +181,7 @@ class Plan:
         d.max_refine = int(max_refine)
         d.fixed_refine = int(fixed_refine)
         d.nrhs = int(nrhs)
-        d.flags = 1 if host_only else 0
+        d.flags = (1 if host_only else 0) | (2 if dense_x else 0)
         h = ctypes.c_void_p()
         _check(L.tpt_plan_create(ctypes.byref(d), ctypes.byref(h)))
         self._h = h
@@ -209,6 +210,13 @@ class Plan:
     def dof(self):
         nx, ny, nz = self.nxyz
         return nx * ny * nz
+
+    @property
+    def x_fft(self) -> bool:
+        """True if the x eigenbasis is applied by the real-Fourier transform."""
+        v = ctypes.c_int()
+        _check(lib().tpt_plan_x_fft(self._h, ctypes.byref(v)))
+        return bool(v.value)
 
     def workspace_bytes(self) -> int:
         b = ctypes.c_size_t()
@@ -271,6 +279,13 @@ class Batch:
         _check(lib().tpt_batch_create(len(self.plans), arr, ctypes.byref(h)))
         self._h = h
         self._ws = None
+
+    @property
+    def x_fft(self) -> bool:
+        """True if the x eigenbasis is applied by the real-Fourier transform."""
+        v = ctypes.c_int()
+        _check(lib().tpt_plan_x_fft(self._h, ctypes.byref(v)))
+        return bool(v.value)
 
     def workspace_bytes(self) -> int:
         b = ctypes.c_size_t()

@@ -66,6 +66,27 @@ hipError_t launch_gemm_f32(const GemmDesc& g, const GemmDesc* d_work, int nwork,
 hipError_t launch_gemm_bf16(const GemmDesc& g, const GemmDesc* d_work, int nwork, long long blocks, int variant,
                             hipStream_t s);
 
+// Fast real-Fourier transform of x-lines (uniform periodic x direction):
+// forward fhat = sqrt(h) Q~^T f or inverse phi = Q~ phihat / sqrt(h) for
+// `lines` contiguous lines of length n (a power of two, 8..2048) in the
+// orthonormal cos/sin basis order of the analytic eigenbasis.
+struct FftDesc {
+    int n;
+    long long lines;
+    const void* in;
+    void* out;
+    int tin, tout;          // DType of in / out
+    int epi;                // EPI_STORE, or EPI_ACCUM_F64 (inverse only, FP64 out)
+    int inverse;
+    double scale;           // sqrt(h) forward, 1/sqrt(h) inverse
+    const double2* twiddle; // e^{-2 pi i k / n}, k < n/2
+    double* partials;       // EPI_ACCUM_F64: 2 doubles per block
+    long long block_begin;  // multi-problem
+};
+bool fft_supported(int n);
+long long fft_blocks(const FftDesc& d);
+hipError_t launch_fft(const FftDesc& rep, const FftDesc* d_work, int nwork, long long blocks, hipStream_t s);
+
 // Thomas solve along z (§2.2.2 step 2.3) for nsys systems of nx*ny lines.
 struct ThomasDesc {
     int nx, ny, nz, nsys;

@@ -53,10 +53,10 @@ static size_t append(std::vector<char>& blob, const std::vector<T>& v) {
     return off;
 }
 
-int MultiExec::add_gemm_stage(int stage, int prec, const std::vector<GemmDesc>& gs) {
+int MultiExec::add_gemm_stage(int stage, int prec, const std::vector<GemmDesc>& gs, const std::vector<char>& use) {
     // group problems by tile variant; each group is one persistent launch
     std::vector<int> var(gs.size());
-    for (size_t i = 0; i < gs.size(); ++i) var[i] = stage_variant(plans_[i], stage, gs[i], prec);
+    for (size_t i = 0; i < gs.size(); ++i) var[i] = use[i] ? stage_variant(plans_[i], stage, gs[i], prec) : -1;
     for (int v = 0; v < TV_COUNT; ++v) {
         std::vector<GemmDesc> grp;
         long long total = 0;
@@ -85,6 +85,31 @@ int MultiExec::add_gemm_stage(int stage, int prec, const std::vector<GemmDesc>& 
     return TPT_OK;
 }
 
+int MultiExec::add_fft_stage(const std::vector<FftDesc>& fs, const std::vector<char>& use) {
+    // one persistent launch per line length (block shape and LDS depend on it)
+    std::vector<int> lens;
+    for (size_t i = 0; i < fs.size(); ++i)
+        if (use[i] && std::find(lens.begin(), lens.end(), fs[i].n) == lens.end()) lens.push_back(fs[i].n);
+    for (int n : lens) {
+        std::vector<FftDesc> grp;
+        long long total = 0;
+        for (size_t i = 0; i < fs.size(); ++i) {
+            if (!use[i] || fs[i].n != n) continue;
+            FftDesc f = fs[i];
+            f.block_begin = total;
+            total += fft_blocks(f);
+            grp.push_back(f);
+        }
+        Launch L{};
+        L.kind = 4;
+        L.off = append(blob_, grp);
+        L.nwork = (int)grp.size();
+        L.total = total;
+        seq_.push_back(L);
+    }
+    return TPT_OK;
+}
+
 int MultiExec::build(const double* const* rhs, double* const* out, void* ws) {
     blob_.clear();
     seq_.clear();
@@ -95,17 +120,28 @@ int MultiExec::build(const double* const* rhs, double* const* out, void* ws) {
         if (!rhs[i] || !out[i]) return fail(TPT_ERR_INVALID, "NULL rhs/out in batch");
         w[i] = carve(plans_[i], (char*)ws + ws_off_[i]);
     }
+    std::vector<char> all(n, 1), gx(n), fx(n);
+    for (int i = 0; i < n; ++i) {
+        fx[i] = plans_[i]->x_fft ? 1 : 0;
+        gx[i] = !fx[i];
+    }
+    // one application of M^{-1}; returns the x-inverse block count of every
+    // problem (the number of norm partials it wrote)
     auto minv = [&](bool from_rhs, int epi) {
         const int tin0 = from_rhs ? DT_F64 : DT_F32;
         const int tmid = mixed_ ? DT_F32 : DT_F64;
         std::vector<GemmDesc> g(n);
-        for (int i = 0; i < n; ++i)
-            g[i] = stage_gemm(plans_[i], ST_XF, prec_, from_rhs ? (const void*)rhs[i] : (const void*)w[i].r, tin0,
-                              w[i].w1, tmid, EPI_STORE, nullptr, 1);
-        add_gemm_stage(ST_XF, prec_, g);
+        std::vector<FftDesc> f(n);
+        for (int i = 0; i < n; ++i) {
+            const void* in = from_rhs ? (const void*)rhs[i] : (const void*)w[i].r;
+            if (fx[i]) f[i] = stage_fft(plans_[i], ST_XF, in, tin0, w[i].w1, tmid, EPI_STORE, nullptr, 1);
+            else g[i] = stage_gemm(plans_[i], ST_XF, prec_, in, tin0, w[i].w1, tmid, EPI_STORE, nullptr, 1);
+        }
+        add_gemm_stage(ST_XF, prec_, g, gx);
+        add_fft_stage(f, fx);
         for (int i = 0; i < n; ++i)
             g[i] = stage_gemm(plans_[i], ST_YF, prec_, w[i].w1, tmid, w[i].w2, tmid, EPI_STORE, nullptr, 1);
-        add_gemm_stage(ST_YF, prec_, g);
+        add_gemm_stage(ST_YF, prec_, g, all);
         std::vector<ThomasDesc> t(n);
         long long lines = 0;
         for (int i = 0; i < n; ++i) {
@@ -121,13 +157,22 @@ int MultiExec::build(const double* const* rhs, double* const* out, void* ws) {
         seq_.push_back(L);
         for (int i = 0; i < n; ++i)
             g[i] = stage_gemm(plans_[i], ST_YI, prec_, w[i].w2, tmid, w[i].w1, tmid, EPI_STORE, nullptr, 1);
-        add_gemm_stage(ST_YI, prec_, g);
-        for (int i = 0; i < n; ++i)
-            g[i] = stage_gemm(plans_[i], ST_XI, prec_, w[i].w1, tmid, out[i], DT_F64, epi, w[i].partials, 1);
-        add_gemm_stage(ST_XI, prec_, g);
-        return g;
+        add_gemm_stage(ST_YI, prec_, g, all);
+        std::vector<long long> nb(n);
+        for (int i = 0; i < n; ++i) {
+            if (fx[i]) {
+                f[i] = stage_fft(plans_[i], ST_XI, w[i].w1, tmid, out[i], DT_F64, epi, w[i].partials, 1);
+                nb[i] = fft_blocks(f[i]);
+            } else {
+                g[i] = stage_gemm(plans_[i], ST_XI, prec_, w[i].w1, tmid, out[i], DT_F64, epi, w[i].partials, 1);
+                nb[i] = gemm_blocks(g[i], stage_variant(plans_[i], ST_XI, g[i], prec_));
+            }
+        }
+        add_gemm_stage(ST_XI, prec_, g, gx);
+        add_fft_stage(f, fx);
+        return nb;
     };
-    std::vector<GemmDesc> xi = minv(true, EPI_STORE);
+    std::vector<long long> xi = minv(true, EPI_STORE);
     for (int it = 0; it < iters_; ++it) {
         std::vector<StencilDesc> st(n);
         std::vector<ReduceDesc> rd(n);
@@ -154,9 +199,8 @@ int MultiExec::build(const double* const* rhs, double* const* out, void* ws) {
         seq_.push_back(R);
         xi = minv(false, EPI_ACCUM_F64);
         for (int i = 0; i < n; ++i) {
-            const int v = stage_variant(plans_[i], ST_XI, xi[i], prec_);
             rd[i].partials = w[i].partials;
-            rd[i].n = (int)gemm_blocks(xi[i], v);
+            rd[i].n = (int)xi[i];
             rd[i].out = (double*)((char*)ws + norm_off_[i]) + 2;
         }
         Launch R2{};
@@ -207,6 +251,12 @@ int MultiExec::enqueue(hipStream_t s) const {
             case 3: {
                 TimedScope ts("multi_reduce", s);
                 e = launch_reduce_pairs_multi((const ReduceDesc*)(d_desc_ + L.off), L.nwork, s);
+                break;
+            }
+            case 4: {
+                TimedScope ts("multi_fft", s);
+                const FftDesc& rep = *(const FftDesc*)(blob_.data() + L.off);
+                e = launch_fft(rep, (const FftDesc*)(d_desc_ + L.off), L.nwork, L.total, s);
                 break;
             }
         }

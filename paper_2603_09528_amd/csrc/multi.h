@@ -32,13 +32,14 @@ class MultiExec {
 
    private:
     struct Launch {
-        int kind;     // 0 gemm, 1 thomas, 2 residual, 3 reduce
+        int kind;     // 0 gemm, 1 thomas, 2 residual, 3 reduce, 4 x-line FFT
         int prec, variant, b_nk;
         size_t off;   // byte offset of the first descriptor in the blob
         int nwork;
         long long total;
     };
-    int add_gemm_stage(int stage, int prec, const std::vector<GemmDesc>& g);
+    int add_gemm_stage(int stage, int prec, const std::vector<GemmDesc>& g, const std::vector<char>& use);
+    int add_fft_stage(const std::vector<FftDesc>& f, const std::vector<char>& use);
     std::vector<tpt_plan_s*> plans_;
     int prec_ = GP_F64;
     bool mixed_ = false;

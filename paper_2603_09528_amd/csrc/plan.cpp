@@ -93,7 +93,9 @@ std::shared_ptr<DirBasis> basis_cache_get(int ncells, const double* faces, int b
         const size_t o_lqinv = o_hqinv + al(2 * nn);
         const size_t o_hq = o_lqinv + al(2 * nn);
         const size_t o_lq = o_hq + al(2 * nn);
-        const size_t total = o_lq + al(2 * nn);
+        const bool fft = b->eig.analytic && op.periodic && fft_supported(n);
+        const size_t o_tw = o_lq + al(2 * nn);
+        const size_t total = o_tw + (fft ? al(16 * (size_t)(n / 2)) : 0);
         std::vector<char> host(total, 0);
         double* lam = (double*)(host.data() + o_lam);
         double* qinv = (double*)(host.data() + o_qinv);
@@ -113,6 +115,17 @@ std::shared_ptr<DirBasis> basis_cache_get(int ncells, const double* faces, int b
                 q[(size_t)i * n + p] = qt / si;     // Q = D^{-1/2} Q~
             }
         }
+        if (fft) {
+            // twiddles of the length-n real transform, in long double
+            double* tw = (double*)(host.data() + o_tw);
+            const long double pi = 3.14159265358979323846264338327950288L;
+            for (int k = 0; k < n / 2; ++k) {
+                const long double a = 2.0L * pi * (long double)k / (long double)n;
+                tw[2 * k] = (double)std::cos(a);
+                tw[2 * k + 1] = (double)-std::sin(a);
+            }
+        }
+        b->h = op.vol[0];
         for (size_t e = 0; e < nn; ++e) {
             sqinv[e] = (float)qinv[e];
             sq[e] = (float)q[e];
@@ -146,6 +159,7 @@ std::shared_ptr<DirBasis> basis_cache_get(int ncells, const double* faces, int b
         b->l_qinv = (uint16_t*)(d + o_lqinv);
         b->h_q = (uint16_t*)(d + o_hq);
         b->l_q = (uint16_t*)(d + o_lq);
+        if (fft) b->d_twiddle = (double2*)(d + o_tw);
     }
     g_cache[key] = b;
     return b;
@@ -177,8 +191,10 @@ static size_t partial_slots(const tpt_plan_s* p) {
     long long res = 0;
     for (int r = 0; r < p->desc.nrhs; ++r) res += (p->dof + 255) / 256;
     long long xi = ((long long)p->N[1] * p->N[2] * p->desc.nrhs + 31) / 32 * ((p->N[0] + 63) / 64);
+    // the x-inverse transform: at most one block per line
+    const long long fx = (long long)p->N[1] * p->N[2] * p->desc.nrhs;
     (void)dof;
-    return (size_t)std::max(res, xi) + 8;
+    return (size_t)std::max(std::max(res, xi), fx) + 8;
 }
 
 size_t plan_workspace_bytes(const tpt_plan_s* p) {
@@ -273,6 +289,7 @@ int tpt_plan_create(const tpt_plan_desc* desc, tpt_plan* out) {
         p->op[2].null_mode)
         p->null_line = p->bx->eig.null_index + p->N[0] * p->by->eig.null_index;
     p->info.null_line = p->null_line;
+    p->x_fft = !p->host_only && p->bx->d_twiddle && !(desc->flags & TPT_FLAG_DENSE_X);
     p->info.rel_residual = -1.0;
     if (!p->host_only) {
         const size_t nx = p->N[0], ny = p->N[1], nz = p->N[2];
@@ -340,6 +357,12 @@ int tpt_plan_operator(tpt_plan p, int dir, double* a, double* b, double* c, doub
     if (b) std::memcpy(b, op.b.data(), n);
     if (c) std::memcpy(c, op.c.data(), n);
     if (vol) std::memcpy(vol, op.vol.data(), n);
+    return TPT_OK;
+}
+
+int tpt_plan_x_fft(tpt_plan p, int* x_fft) {
+    if (!p || !x_fft) return fail(TPT_ERR_INVALID, "NULL argument");
+    *x_fft = p->x_fft ? 1 : 0;
     return TPT_OK;
 }
 

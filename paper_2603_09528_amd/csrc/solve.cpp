@@ -161,6 +161,24 @@ GemmDesc stage_gemm(const tpt_plan_s* p, int stage, int prec, const void* in, in
     return g;
 }
 
+FftDesc stage_fft(const tpt_plan_s* p, int stage, const void* in, int tin, void* out, int tout, int epi,
+                  double* partials, int nrhs) {
+    FftDesc f{};
+    f.n = p->N[0];
+    f.lines = (long long)p->N[1] * p->N[2] * nrhs;
+    f.in = in;
+    f.out = out;
+    f.tin = tin;
+    f.tout = tout;
+    f.epi = epi;
+    f.inverse = stage == ST_XI ? 1 : 0;
+    // forward Q^{-1} = sqrt(h) Q~^T, inverse Q = Q~ / sqrt(h) (uniform D = h I)
+    f.scale = f.inverse ? 1.0 / std::sqrt(p->bx->h) : std::sqrt(p->bx->h);
+    f.twiddle = p->bx->d_twiddle;
+    f.partials = partials;
+    return f;
+}
+
 ThomasDesc plan_thomas(const tpt_plan_s* p, const void* f, int tf, void* x, int tx, double* scratch, int nrhs) {
     ThomasDesc t{};
     t.nx = p->N[0];
@@ -227,6 +245,21 @@ static int run_gemm(const tpt_plan_s* p, int stage, int prec, const void* in, in
     return TPT_OK;
 }
 
+// x stages: the real-Fourier transform where the plan uses it, else the GEMM.
+static int run_x(const tpt_plan_s* p, int stage, int prec, const void* in, int tin, void* out, int tout, int epi,
+                 double* partials, int nrhs, hipStream_t s, long long* nblocks = nullptr) {
+    if (!p->x_fft) return run_gemm(p, stage, prec, in, tin, out, tout, epi, partials, nrhs, s, nblocks);
+    FftDesc f = stage_fft(p, stage, in, tin, out, tout, epi, partials, nrhs);
+    const long long nb = fft_blocks(f);
+    if (nblocks) *nblocks = nb;
+    TimedScope ts(stage == ST_XF ? (tin == DT_F64 && tout == DT_F64 ? "fft_x_fwd_f64" : "fft_x_fwd_f32io")
+                                 : (tin == DT_F64 ? "fft_x_inv_f64" : "fft_x_inv_f32io"),
+                  s);
+    hipError_t e = launch_fft(f, nullptr, 0, nb, s);
+    if (e != hipSuccess) return fail(TPT_ERR_HIP, std::string("FFT launch: ") + hipGetErrorString(e));
+    return TPT_OK;
+}
+
 static int run_thomas(const tpt_plan_s* p, const void* f, int tf, void* x, int tx, double* scratch, int nrhs,
                       hipStream_t s) {
     ThomasDesc t = plan_thomas(p, f, tf, x, tx, scratch, nrhs);
@@ -269,11 +302,11 @@ long long plan_residual_blocks(const tpt_plan_s* p) {
 static int solve_fp64(tpt_plan_s* p, const double* rhs, double* out, const Ws& w, hipStream_t s) {
     const int R = p->desc.nrhs;
     int rc;
-    if ((rc = run_gemm(p, ST_XF, GP_F64, rhs, DT_F64, w.w1, DT_F64, EPI_STORE, nullptr, R, s))) return rc;
+    if ((rc = run_x(p, ST_XF, GP_F64, rhs, DT_F64, w.w1, DT_F64, EPI_STORE, nullptr, R, s))) return rc;
     if ((rc = run_gemm(p, ST_YF, GP_F64, w.w1, DT_F64, w.w2, DT_F64, EPI_STORE, nullptr, R, s))) return rc;
     if ((rc = run_thomas(p, w.w2, DT_F64, w.w2, DT_F64, w.scratch, R, s))) return rc;
     if ((rc = run_gemm(p, ST_YI, GP_F64, w.w2, DT_F64, w.w1, DT_F64, EPI_STORE, nullptr, R, s))) return rc;
-    if ((rc = run_gemm(p, ST_XI, GP_F64, w.w1, DT_F64, out, DT_F64, EPI_STORE, nullptr, R, s))) return rc;
+    if ((rc = run_x(p, ST_XI, GP_F64, w.w1, DT_F64, out, DT_F64, EPI_STORE, nullptr, R, s))) return rc;
     p->info.iters = 0;
     p->info.rel_correction = 0.0;
     p->info.rel_residual = -1.0;
@@ -287,11 +320,11 @@ static int apply_minv(tpt_plan_s* p, int prec, const void* in, int tin, double* 
                       hipStream_t s, long long* xi_blocks) {
     const int R = p->desc.nrhs;
     int rc;
-    if ((rc = run_gemm(p, ST_XF, prec, in, tin, w.w1, DT_F32, EPI_STORE, nullptr, R, s))) return rc;
+    if ((rc = run_x(p, ST_XF, prec, in, tin, w.w1, DT_F32, EPI_STORE, nullptr, R, s))) return rc;
     if ((rc = run_gemm(p, ST_YF, prec, w.w1, DT_F32, w.w2, DT_F32, EPI_STORE, nullptr, R, s))) return rc;
     if ((rc = run_thomas(p, w.w2, DT_F32, w.w2, DT_F32, w.scratch, R, s))) return rc;
     if ((rc = run_gemm(p, ST_YI, prec, w.w2, DT_F32, w.w1, DT_F32, EPI_STORE, nullptr, R, s))) return rc;
-    if ((rc = run_gemm(p, ST_XI, prec, w.w1, DT_F32, out, DT_F64, epi, w.partials, R, s, xi_blocks))) return rc;
+    if ((rc = run_x(p, ST_XI, prec, w.w1, DT_F32, out, DT_F64, epi, w.partials, R, s, xi_blocks))) return rc;
     return TPT_OK;
 }
 

@@ -124,3 +124,22 @@ def test_workspace_size_reported():
     p = W.make_problem((10, 9, 8), (1.0, 1.0, 1.0), (W.NN, W.NN, W.NN))
     plan = T.Plan.from_problem(p, host_only=True)
     assert plan.workspace_bytes() >= 16 * p.dof
+
+
+def test_autotune_table_roundtrip(tmp_path):
+    T = _lib()
+    src = tmp_path / "table.txt"
+    src.write_text("# prec kind M N K variant\n0 0 0 256 256 5\n2 1 96 96 96 3\nbogus line\n1 0 0 48 48 9\n")
+    T.autotune_load(str(src))
+    out = tmp_path / "out.txt"
+    T.autotune_save(str(out))
+    lines = [l for l in out.read_text().splitlines() if l and not l.startswith("#")]
+    assert "0 0 0 256 256 5" in lines
+    assert "2 1 96 96 96 3" in lines
+    assert not any(l.endswith(" 9") for l in lines)  # out-of-range variant ignored
+
+
+def test_timing_collect_empty():
+    T = _lib()
+    T.timing_enable(False)
+    assert T.timing_collect() == {}
