@@ -49,6 +49,9 @@ def parse():
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--helmholtz-steps", type=int, default=3,
                     help="timed solves of the 1024x768x512 Helmholtz workload (0 disables it)")
+    ap.add_argument("--variants-n", type=int, default=1024,
+                    help="cells per direction of the FF/FG/GF/GG comparison (0 disables it)")
+    ap.add_argument("--variants-steps", type=int, default=3)
     return ap.parse_args()
 
 
@@ -110,6 +113,55 @@ def run_serving(args, T, W):
     openb["corrections"] = iters
     return {"families": [p.name + f" {p.n[0]}^3 {''.join(b[0] + b[1] for b in p.bc)}" for p in fams],
             "closed_loop_fp64": closed, "open_loop_fp64": open64, "open_loop_bf16x3": openb}
+
+
+# single-GPU FP64 Poisson solve times of the paper (§4.2.2: 1024^3, periodic x,
+# Neumann y and z, uniform mesh, one GB200), seconds
+PAPER_1024_VARIANT_S = {"FF": 0.094, "FG": 0.163, "GF": 0.199, "GG": 0.267}
+
+
+def run_variants(args, T, W):
+    """The paper's transform-variant comparison on one GPU: the uniform
+    n^3 Poisson problem (periodic x, Neumann y and z) in FP64 with x and y
+    each by fast transform (F) or dense GEMM (G)."""
+    import torch
+    n = args.variants_n
+    prob = W.make_problem((n, n, n), (0.0, 0.0, 0.0), (W.PP, W.NN, W.NN), name=f"uniform{n}_pnn")
+    f = torch.from_numpy(W.rhs(prob, 7)).to("cuda")
+    out = torch.empty_like(f)
+    ref = None
+    res = {"workload": f"{n}^3 Poisson, periodic x, Neumann y and z, uniform, FP64", "dof": prob.dof,
+           "paper_gb200_s": PAPER_1024_VARIANT_S if n == 1024 else None}
+    for name, dx, dy in (("FF", False, False), ("FG", False, True), ("GF", True, False), ("GG", True, True)):
+        t0 = time.time()
+        plan = T.Plan.from_problem(prob, dense_x=dx, dense_y=dy)
+        ws = plan.workspace()
+        plan.solve(f, out, ws)
+        torch.cuda.synchronize()
+        log(f"variants {name}: plan+first solve {time.time() - t0:.1f}s, transforms {plan.transforms}")
+        T.timing_collect()
+        T.timing_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(args.variants_steps):
+            plan.solve(f, out, ws)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.variants_steps
+        T.timing_enable(False)
+        kern = T.timing_collect()
+        o = out.detach().cpu().numpy()
+        if ref is None:
+            ref = o
+            diff = 0.0
+        else:
+            diff = float(np.linalg.norm(o - ref) / np.linalg.norm(ref))
+        res[name] = {"ms_per_solve": ms, "gdofs": prob.dof / (ms * 1e-3) / 1e9, "transforms": plan.transforms,
+                     "rel_diff_vs_FF": diff,
+                     "kernels_ms_per_solve": {k: v[0] / args.variants_steps for k, v in kern.items()}}
+        log(f"variants {name}: {ms:.2f} ms/solve, {res[name]['gdofs']:.2f} GDOF/s, diff vs FF {diff:.2e}")
+        del plan, ws
+        torch.cuda.empty_cache()
+    res["GG_over_FF"] = res["GG"]["ms_per_solve"] / res["FF"]["ms_per_solve"]
+    return res
 
 
 def run_helmholtz(args, T, W):
@@ -176,7 +228,7 @@ def main():
         src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").normal_()
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.mul(src, 1.0, out=dst)  # an elementwise kernel, not a DMA copy
         torch.cuda.synchronize()
         del src, dst
 
@@ -200,7 +252,8 @@ def main():
                 log(f"{mode}: refinement did not converge ({e}); skipped")
                 continue
             plan = T.Plan.from_problem(prob, precision=prec, fixed_refine=iters, dense_x=dense_x)
-        log(f"{mode}: plan {time.time() - t0:.2f}s, corrections {iters}")
+        T.autotune([plan])  # tile variant per GEMM shape, timed on this GPU
+        log(f"{mode}: plan + autotune {time.time() - t0:.2f}s, corrections {iters}, transforms {plan.transforms}")
         out = torch.empty_like(f)
         ws = plan.workspace()
         for _ in range(args.warmup):
@@ -267,6 +320,10 @@ def main():
     if args.helmholtz_steps > 0:
         helm = run_helmholtz(args, T, W)
 
+    variants = None
+    if args.variants_n > 0:
+        variants = run_variants(args, T, W)
+
     # ---- serving loop: 10 grid families 64^3..512^3, Poisson arrivals -------------
     serving = None
     if args.serve_requests > 0:
@@ -330,6 +387,7 @@ def main():
         "cpu_baseline": cpu,
         "serving": serving,
         "helmholtz_1024x768x512_3rhs": helm,
+        "transform_variants": variants,
     }
     print(json.dumps(line))
 

@@ -75,9 +75,17 @@ enum {
     TPT_FLAG_HOST_ONLY = 1, /* build the host-side operators and eigenbases
                                only (no device memory, no GPU needed); such a
                                plan can be inspected but not solved */
-    TPT_FLAG_DENSE_X = 2    /* apply the x eigenbasis as a dense GEMM even where
-                               the fast real-Fourier transform applies (the
-                               "GG" variant; default is "FG" there) */
+    TPT_FLAG_DENSE_X = 2,   /* apply the x eigenbasis by dense GEMM even where a
+                               fast transform applies (see tpt_plan_transforms) */
+    TPT_FLAG_DENSE_Y = 4    /* the same for y */
+};
+
+/* How a plan applies the eigenbasis of x or y (tpt_plan_transforms). */
+enum {
+    TPT_XFORM_GEMM = 0,     /* dense eigenbasis product (MFMA GEMM) */
+    TPT_XFORM_FFT = 1,      /* uniform periodic: real Fourier transform */
+    TPT_XFORM_DCT = 2,      /* uniform Neumann-Neumann, cell centres: DCT-II */
+    TPT_XFORM_DST = 3       /* uniform Dirichlet-Dirichlet, cell centres: DST-II */
 };
 
 typedef struct tpt_plan_s *tpt_plan;
@@ -90,7 +98,8 @@ typedef struct {
                                coordinates (copied; caller keeps ownership).
                                A periodic direction must be uniform only if
                                its analytic basis is wanted; any spacing works */
-    int bc[3][2];           /* [direction][lower, upper], TPT_BC_*; z may not be periodic */
+    int bc[3][2];           /* [direction][lower, upper], TPT_BC_*; periodic must be paired
+                               (a periodic z makes the Thomas lines cyclic) */
     int loc[3];             /* TPT_LOC_*; FACE needs periodic or Dirichlet-Dirichlet */
     int kind;               /* TPT_POISSON or TPT_HELMHOLTZ */
     double alpha;           /* Helmholtz coefficient (> 0), ignored for Poisson */
@@ -144,11 +153,11 @@ int tpt_plan_eigen(tpt_plan plan, int dir, double *lam, double *Qt);
  * periodic direction a[0] and c[N-1] are the cyclic corners). */
 int tpt_plan_operator(tpt_plan plan, int dir, double *a, double *b, double *c, double *vol);
 
-/* *x_fft = 1 if the plan applies the x eigenbasis with the fast real-Fourier
- * transform (uniform periodic x with a power-of-two N_x in 8..2048, and no
- * TPT_FLAG_DENSE_X; §3 lets a uniform direction use FFT-based transforms),
- * 0 if with dense GEMMs. */
-int tpt_plan_x_fft(tpt_plan plan, int *x_fft);
+/* kinds[0], kinds[1]: TPT_XFORM_* used for x and y.  A direction gets a fast
+ * transform (§3: a uniform direction may use FFT-based transforms) when its
+ * analytic basis is one of the three listed, its unknown count is a power of
+ * two in 8..2048, and its TPT_FLAG_DENSE_* flag is not set; otherwise GEMM. */
+int tpt_plan_transforms(tpt_plan plan, int kinds[2]);
 
 /* Solve A x = rhs for the plan's nrhs right-hand sides.  rhs, out: device
  * FP64 fields (nrhs * Nz*Ny*Nx each); rhs is read only and must not overlap
@@ -217,14 +226,16 @@ int tpt_server_destroy(tpt_server server);
  * l = i + nx*j of each of nsys systems,
  *   (sigma + tau*(lamx[i] + lamy[j] + T_z)) x = f,
  * T_z with sub-diagonal az, diagonal bz, super-diagonal cz (device, nz each);
- * f, x: device FP64 [nsys][nz][ny][nx]; scratch: device FP64 of at least
- * 2 * nx * ny * nsys * ceil(nz / 16) elements (chunk checkpoints).
- * pin_line >= 0 sets the last unknown of that line to zero (§3 gauge).
- * f may equal x. */
+ * with periodic_z != 0 the lines are cyclic: az[0] couples row 0 to x[nz-1]
+ * and cz[nz-1] couples row nz-1 to x[0] (nz >= 2).  f, x: device FP64
+ * [nsys][nz][ny][nx]; scratch: device FP64 of at least
+ * 4 * nx * ny * nsys * ceil(nz / 16) elements (chunk checkpoints).
+ * pin_line >= 0 sets the last unknown of that line to zero and drops its
+ * last equation (§3 gauge).  f may equal x. */
 int tpt_thomas(int nx, int ny, int nz, int nsys, const double *lamx, const double *lamy,
-               const double *az, const double *bz, const double *cz, double sigma,
-               double tau, int pin_line, const double *f, double *x, double *scratch,
-               void *stream);
+               const double *az, const double *bz, const double *cz, int periodic_z,
+               double sigma, double tau, int pin_line, const double *f, double *x,
+               double *scratch, void *stream);
 
 /* Strided-batched GEMM with the library's MFMA kernels (the transform
  * kernels of §2.2.2 on explicit operands).  A is M x K row-major (lda = K);

@@ -19,6 +19,10 @@ Poisson is sigma = 0, tau = 1.
 Gauge (§3): for a Poisson problem with a constant null mode, the line whose
 shift is lambda_x = lambda_y = 0 has a vanishing final pivot; its last modal
 unknown is set to zero and back substitution proceeds from there.
+
+A periodic z direction makes every line cyclic; those lines are solved by
+their plain definition (dense LU per line), with the same gauge on the
+singular line (last unknown zero, last equation dropped).
 """
 from __future__ import annotations
 
@@ -58,6 +62,36 @@ def thomas_lines(az, bz, cz, lam, sigma, tau, rhs, pin=None):
     return x, last_pivot
 
 
+def cyclic_lines(az, bz, cz, lam, sigma, tau, rhs, pin=None):
+    """Solve (sigma + tau (lam + T_z)) x = rhs for every line when z is
+    periodic: T_z is cyclic (az[0] couples to x[nz-1], cz[nz-1] to x[0]).
+    The plain definition: a dense LU solve of each line's matrix (no cyclic
+    reduction).  On the pinned line of a singular problem the last unknown is
+    set to zero and the last equation dropped, as the final-pivot gauge of §3
+    does for the Thomas lines.  Returns x."""
+    from .operator import dense_1d
+    nz = len(bz)
+    shape = rhs.shape
+    lamf = np.broadcast_to(lam, shape[1:]).reshape(-1)
+    R = rhs.reshape(nz, -1).T                      # (lines, nz)
+    X = np.empty_like(R)
+    T = dense_1d(az, bz, cz, True)
+    eye = np.eye(nz)
+    pin_flat = None if pin is None else int(np.ravel_multi_index(tuple(pin), shape[1:]))
+    chunk = max(1, (1 << 22) // (nz * nz))         # lines per batched solve
+    for s in range(0, R.shape[0], chunk):
+        e = min(R.shape[0], s + chunk)
+        M = sigma * eye + tau * (lamf[s:e, None, None] * eye + T)
+        if pin_flat is not None and s <= pin_flat < e:
+            M[pin_flat - s] = eye                  # placeholder row set; solved apart below
+        X[s:e] = np.linalg.solve(M, R[s:e, :, None])[:, :, 0]
+    if pin_flat is not None:
+        M = sigma * eye + tau * (lamf[pin_flat] * eye + T)
+        X[pin_flat, :nz - 1] = np.linalg.solve(M[:nz - 1, :nz - 1], R[pin_flat, :nz - 1])
+        X[pin_flat, nz - 1] = 0.0
+    return X.T.reshape(shape)
+
+
 def _coeffs(p):
     if p.kind == "poisson":
         return 0.0, 1.0
@@ -70,9 +104,8 @@ class Plan:
     """Initialization steps 1.1-1.3 for x and y, and T_z, for one problem."""
 
     def __init__(self, p):
-        if p.bc[2][0] == "P":
-            raise ValueError("periodic z (cyclic Thomas) is not part of this solver")
         self.p = p
+        self.zper = p.bc[2][0] == "P"
         self.ex = eig_direction(p.faces[0], p.bc[0], p.loc[0])
         self.ey = eig_direction(p.faces[1], p.bc[1], p.loc[1])
         self.az, self.bz, self.cz, _ = operator_1d(p.faces[2], p.bc[2], p.loc[2])
@@ -88,6 +121,8 @@ class Plan:
 
     def modal(self, fxy):
         lam = self.ey.lam[:, None] + self.ex.lam[None, :]
+        if self.zper:
+            return cyclic_lines(self.az, self.bz, self.cz, lam, self.sigma, self.tau, fxy, self.pin)
         x, piv = thomas_lines(self.az, self.bz, self.cz, lam, self.sigma, self.tau, fxy, self.pin)
         self.last_pivot = piv
         return x

@@ -84,7 +84,7 @@ def lib():
             "tpt_plan_workspace_bytes": (i, [vp, ctypes.POINTER(sz)]),
             "tpt_plan_eigen": (i, [vp, i, dp, dp]),
             "tpt_plan_operator": (i, [vp, i, dp, dp, dp, dp]),
-            "tpt_plan_x_fft": (i, [vp, ctypes.POINTER(ctypes.c_int)]),
+            "tpt_plan_transforms": (i, [vp, ctypes.POINTER(ctypes.c_int)]),
             "tpt_solve": (i, [vp, vp, vp, vp, sz, vp]),
             "tpt_solve_info": (i, [vp, ctypes.POINTER(Info)]),
             "tpt_batch_create": (i, [i, ctypes.POINTER(vp), ctypes.POINTER(vp)]),
@@ -99,7 +99,7 @@ def lib():
             "tpt_server_poll": (i, [vp, ctypes.c_ulonglong, ctypes.POINTER(Info), dp, dp, dp]),
             "tpt_server_drain": (i, [vp]),
             "tpt_server_destroy": (i, [vp]),
-            "tpt_thomas": (i, [i, i, i, i, vp, vp, vp, vp, vp, d, d, i, vp, vp, vp, vp]),
+            "tpt_thomas": (i, [i, i, i, i, vp, vp, vp, vp, vp, i, d, d, i, vp, vp, vp, vp]),
             "tpt_gemm": (i, [i, i, i, i, i, i, i, vp, ctypes.c_longlong, vp, ctypes.c_longlong, vp,
                              ctypes.c_longlong, vp]),
             "tpt_timing_enable": (i, [i]),
@@ -117,7 +117,7 @@ def lib():
 
 
 EXPORTED = ("tpt_plan_desc_init", "tpt_plan_create", "tpt_plan_destroy", "tpt_plan_shape",
-            "tpt_plan_workspace_bytes", "tpt_plan_eigen", "tpt_plan_operator", "tpt_plan_x_fft", "tpt_solve",
+            "tpt_plan_workspace_bytes", "tpt_plan_eigen", "tpt_plan_operator", "tpt_plan_transforms", "tpt_solve",
             "tpt_solve_info", "tpt_batch_create", "tpt_batch_destroy", "tpt_batch_workspace_bytes",
             "tpt_batch_solve", "tpt_autotune", "tpt_autotune_save", "tpt_autotune_load",
             "tpt_server_create", "tpt_server_submit", "tpt_server_poll", "tpt_server_drain",
@@ -159,11 +159,14 @@ class Plan:
     n: cells (nx, ny, nz); faces: three arrays of n+1 face coordinates;
     bc: three (lower, upper) pairs; loc: three of 'C'/'F'; kind 'poisson' or
     'helmholtz' with alpha; precision 'fp64', 'fp32' or 'bf16x3';
-    fixed_refine >= 0 runs that many corrections without host synchronisation.
+    fixed_refine >= 0 runs that many corrections without host synchronisation;
+    dense_x / dense_y force the dense GEMM for a direction where a fast
+    transform (FFT, DCT-II, DST-II of a uniform direction) would apply.
     """
 
     def __init__(self, n, faces, bc, loc=("C", "C", "C"), kind="poisson", alpha=0.0, precision="fp64",
-                 rtol=1e-12, max_refine=8, fixed_refine=-1, nrhs=1, host_only=False, dense_x=False):
+                 rtol=1e-12, max_refine=8, fixed_refine=-1, nrhs=1, host_only=False, dense_x=False,
+                 dense_y=False):
         L = lib()
         d = _Desc()
         L.tpt_plan_desc_init(ctypes.byref(d))
@@ -181,7 +184,7 @@ class Plan:
         d.max_refine = int(max_refine)
         d.fixed_refine = int(fixed_refine)
         d.nrhs = int(nrhs)
-        d.flags = (1 if host_only else 0) | (2 if dense_x else 0)
+        d.flags = (1 if host_only else 0) | (2 if dense_x else 0) | (4 if dense_y else 0)
         h = ctypes.c_void_p()
         _check(L.tpt_plan_create(ctypes.byref(d), ctypes.byref(h)))
         self._h = h
@@ -212,11 +215,17 @@ class Plan:
         return nx * ny * nz
 
     @property
+    def transforms(self):
+        """How x and y are transformed: each of 'gemm', 'fft', 'dct', 'dst'."""
+        v = (ctypes.c_int * 2)()
+        _check(lib().tpt_plan_transforms(self._h, v))
+        names = ("gemm", "fft", "dct", "dst")
+        return names[v[0]], names[v[1]]
+
+    @property
     def x_fft(self) -> bool:
-        """True if the x eigenbasis is applied by the real-Fourier transform."""
-        v = ctypes.c_int()
-        _check(lib().tpt_plan_x_fft(self._h, ctypes.byref(v)))
-        return bool(v.value)
+        """True if the x eigenbasis is applied by a fast transform."""
+        return self.transforms[0] != "gemm"
 
     def workspace_bytes(self) -> int:
         b = ctypes.c_size_t()
@@ -281,11 +290,17 @@ class Batch:
         self._ws = None
 
     @property
+    def transforms(self):
+        """How x and y are transformed: each of 'gemm', 'fft', 'dct', 'dst'."""
+        v = (ctypes.c_int * 2)()
+        _check(lib().tpt_plan_transforms(self._h, v))
+        names = ("gemm", "fft", "dct", "dst")
+        return names[v[0]], names[v[1]]
+
+    @property
     def x_fft(self) -> bool:
-        """True if the x eigenbasis is applied by the real-Fourier transform."""
-        v = ctypes.c_int()
-        _check(lib().tpt_plan_x_fft(self._h, ctypes.byref(v)))
-        return bool(v.value)
+        """True if the x eigenbasis is applied by a fast transform."""
+        return self.transforms[0] != "gemm"
 
     def workspace_bytes(self) -> int:
         b = ctypes.c_size_t()
@@ -368,10 +383,13 @@ class Server:
             self._h = None
 
 
-def thomas(nx, ny, nz, nsys, lamx, lamy, az, bz, cz, sigma, tau, pin_line, f, x, scratch, stream=None):
-    """Kernel-level batched Thomas solve on explicit device inputs."""
-    _check(lib().tpt_thomas(nx, ny, nz, nsys, _ptr(lamx), _ptr(lamy), _ptr(az), _ptr(bz), _ptr(cz), float(sigma),
-                            float(tau), int(pin_line), _ptr(f), _ptr(x), _ptr(scratch), _stream(stream)))
+def thomas(nx, ny, nz, nsys, lamx, lamy, az, bz, cz, sigma, tau, pin_line, f, x, scratch, stream=None,
+           periodic_z=False):
+    """Kernel-level batched Thomas solve on explicit device inputs (cyclic
+    lines with periodic_z)."""
+    _check(lib().tpt_thomas(nx, ny, nz, nsys, _ptr(lamx), _ptr(lamy), _ptr(az), _ptr(bz), _ptr(cz),
+                            1 if periodic_z else 0, float(sigma), float(tau), int(pin_line), _ptr(f), _ptr(x),
+                            _ptr(scratch), _stream(stream)))
     return x
 
 

@@ -66,6 +66,15 @@ __device__ __forceinline__ void split_bf16(float x, uint16_t& hi, uint16_t& lo) 
     lo = bf16_rne(x - bf16_to_f(hi));
 }
 
+// Blocks of one launch are dealt round-robin to the 8 XCDs, each with its own
+// L2.  Renumbering block b of nb this way gives every XCD one contiguous range
+// of logical blocks, so tiles that read the same operand rows (neighbouring
+// logical blocks) share that XCD's L2 instead of fetching them once per XCD.
+__device__ __forceinline__ long long xcd_block(long long b, long long nb) {
+    const long long q = nb / 8, r = nb % 8, x = b % 8, i = b / 8;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
 // Upper bound on the grid of a persistent multi-problem launch.
 constexpr long long PERSISTENT_BLOCKS = 2048;
 

@@ -1,48 +1,48 @@
-// Uniform periodic x direction: the real-Fourier eigenbasis applied with a
-// fast transform instead of a dense GEMM (the "F" option of §3: a uniform
-// direction may use FFT-based transforms; the eigenvalues are the analytic
-// modified wavenumbers of §2.2.1).
+// Fast transforms for uniform directions.  On a uniform grid the eigenbases
+// of §2.2.1 are known in closed form: the real Fourier basis (periodic), the
+// cosine basis DCT-II (Neumann-Neumann, cell centres) and the sine basis
+// DST-II (Dirichlet-Dirichlet, cell centres); §3 lets such a direction use
+// FFT-based transforms in place of the dense eigenbasis product.
 //
-// Basis (orthonormal, matching the analytic basis of the plan): column 0 is
-// 1/sqrt(N); columns 2m-1, 2m (m = 1 .. N/2-1) are sqrt(2/N) cos(2 pi m i/N)
-// and sqrt(2/N) sin(2 pi m i/N); column N-1 is (-1)^i / sqrt(N) (N even).
-// Forward  fhat = Q^{-1} f = sqrt(h) Q~^T f ; inverse phi = Q phihat = Q~ phihat / sqrt(h).
+// Bases (orthonormal; the column order of the plan's analytic bases):
+//   Fourier: column 0 = 1/sqrt(N); columns 2m-1, 2m (m = 1 .. N/2-1) =
+//            sqrt(2/N) cos(2 pi m i/N), sqrt(2/N) sin(2 pi m i/N); column N-1
+//            = (-1)^i / sqrt(N).
+//   DCT-II:  column k = c_k cos(pi k (i + 1/2)/N), c_0 = sqrt(1/N), else sqrt(2/N).
+//   DST-II:  column k-1 = c_k sin(pi k (i + 1/2)/N), k = 1..N, c_N = sqrt(1/N).
+// Forward fhat = Q^{-1} f = sqrt(h) Q~^T f; inverse phi = Q phihat = Q~ phihat / sqrt(h).
 //
-// A length-N real line is packed as N/2 complex points z_n = f_2n + i f_2n+1,
-// transformed by a radix-2 decimation-in-time FFT in LDS (bit-reversed load,
-// in-place butterflies), and split into the half spectrum
-// F_m = (Z_m + conj Z_{M-m})/2 - i W^m (Z_m - conj Z_{M-m})/2, W = e^{-2 pi i/N};
-// the inverse runs the same steps backwards.  Arithmetic is FP64 whatever the
-// storage types.  One wave per line, four lines per block; the pass is
-// memory-bound (16 B per unknown in FP64).
+// Each transform is one real length-N FFT (N a power of two) done as an
+// N/2-point complex FFT of z_n = v_2n + i v_2n+1 in LDS, with the half
+// spectrum V_m = (Z_m + conj Z_{M-m})/2 - i W^m (Z_m - conj Z_{M-m})/2
+// (W = e^{-2 pi i/N}, M = N/2):
+//   Fourier: v = f; the outputs are the real and imaginary parts of V_m.
+//   DCT-II (Makhoul's reordering): v_n = f_2n, v_{N-1-n} = f_2n+1; then
+//            X_k = Re(e^{-i pi k/2N} V_k) and X_{N-k} = -Im(e^{-i pi k/2N} V_k).
+//   DST-II:  the DCT-II of (-1)^i f_i with the output order reversed, since
+//            sin(pi k (2i+1)/2N) = (-1)^i cos(pi (N-k) (2i+1)/2N).
+// The inverses run the same steps backwards: build the half spectrum, fold it
+// into Z, inverse complex FFT (decimation in frequency: natural order in,
+// bit-reversed out), unpack.  Arithmetic is FP64 whatever the storage types.
+//
+// Lines are either contiguous (x direction, element stride 1) or strided (y
+// direction: the lines of one z slab are its Nx columns, element stride Nx).
+// A block of 256 threads holds LPB lines in LDS (8N bytes each, 32 KB per
+// block for N >= 64).  Loads and stores walk the lines so that consecutive
+// lanes touch consecutive addresses: along a line for x, across lines for y.
+// The pass is memory-bound: 16 B per unknown in FP64.
 #include "device_common.h"
 
 namespace tpt {
 
-// Lines (waves) per block: 4 up to N = 512, 2 for N = 1024, 1 for N = 2048,
-// so that F (N/2 + 1 points) and Z (N/2 points) of every line fit in 64 KB.
-static int fft_lines_per_block(int n) { return n <= 512 ? 4 : (n <= 1024 ? 2 : 1); }
+namespace {
 
-// Sum (a, b) over the waves of the block; thread 0 gets the result.
-__device__ __forceinline__ void block_sum2_rt(double& a, double& b, double* red) {
-    a = wave_sum(a);
-    b = wave_sum(b);
-    const int w = threadIdx.x / 64, l = threadIdx.x % 64, nw = blockDim.x / 64;
-    __syncthreads();
-    if (l == 0) {
-        red[2 * w] = a;
-        red[2 * w + 1] = b;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double sa = 0.0, sb = 0.0;
-        for (int i = 0; i < nw; ++i) {
-            sa += red[2 * i];
-            sb += red[2 * i + 1];
-        }
-        a = sa;
-        b = sb;
-    }
+constexpr int UT_NT = 256;
+constexpr int UT_LDS_DOUBLES = 4096;  // 32 KB per block: up to 5 blocks (20 waves) per CU
+
+__host__ __device__ inline int ut_lines_per_block(int n) {
+    const int l = UT_LDS_DOUBLES / n;
+    return l > 64 ? 64 : l;
 }
 
 __device__ __forceinline__ int bitrev(int v, int bits) { return (int)(__brev((unsigned)v) >> (32 - bits)); }
@@ -51,127 +51,245 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 __device__ __forceinline__ double2 conj2(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
 
-template <typename T>
-__device__ __forceinline__ double ld(const T* p, long long i) {
-    return (double)p[i];
+// Offset of element e of line `line` (line index within the descriptor).
+__device__ __forceinline__ long long ut_offset(const FftDesc& d, long long line, int e) {
+    if (!d.ylines) return line * (long long)d.n + e;
+    const long long slab = line / d.inner, col = line - slab * d.inner;
+    return slab * d.s_outer + col + (long long)e * d.s_elem;
 }
 
-// In-place radix-2 DIT butterflies over M points held in LDS (bit-reversed
-// order on entry, natural order on exit).  W: e^{-2 pi i k/N}, k < N/2.
-template <bool INV>
-__device__ __forceinline__ void fft_stages(double2* a, int M, int N, const double2* __restrict__ W, int lane) {
+// Work item idx -> (line in block l, index e) for cnt items per line: the
+// index runs fastest for contiguous lines, the line for strided lines.
+__device__ __forceinline__ void ut_map(int ylines, int lpb, int cnt, int idx, int& l, int& e) {
+    if (ylines) {
+        l = idx % lpb;
+        e = idx / lpb;
+    } else {
+        l = idx / cnt;
+        e = idx - l * cnt;
+    }
+}
+
+// Position in v (the sequence whose real FFT is taken) of line element e.
+__device__ __forceinline__ int ut_vpos(int kind, int n, int e) {
+    if (kind == UT_FOURIER) return e;
+    return (e & 1) ? n - 1 - (e >> 1) : (e >> 1);
+}
+
+// Forward radix-2 decimation in time over M points per line (bit-reversed
+// in, natural out).
+__device__ __forceinline__ void ut_dit(double2* lds, int lpb, int M, int N, const double2* __restrict__ W) {
+    const int g = UT_NT / lpb;  // threads per line
+    const int l = threadIdx.x / g, t = threadIdx.x - l * g;
+    double2* a = lds + (size_t)l * M;
     for (int L = 2; L <= M; L <<= 1) {
-        const int half = L >> 1;
-        const int tstep = N / L;
-        for (int b = lane; b < (M >> 1); b += 64) {
-            const int g = b / half, pos = b - g * half;
-            const int i0 = g * L + pos, i1 = i0 + half;
-            double2 w = W[pos * tstep];
-            if (INV) w = conj2(w);
+        const int half = L >> 1, tstep = N / L;
+        for (int b = t; b < (M >> 1); b += g) {
+            const int grp = b / half, pos = b - grp * half;
+            const int i0 = grp * L + pos, i1 = i0 + half;
             const double2 u = a[i0];
-            const double2 v = cmul(a[i1], w);
-            a[i0] = make_double2(u.x + v.x, u.y + v.y);
-            a[i1] = make_double2(u.x - v.x, u.y - v.y);
+            const double2 v = cmul(a[i1], W[pos * tstep]);
+            a[i0] = cadd(u, v);
+            a[i1] = csub(u, v);
         }
         __syncthreads();
     }
 }
 
-template <typename TI, typename TO, int EPI>
-__device__ __forceinline__ void fft_fwd_block(const FftDesc& d, long long blk, double2* smem, double* red) {
-    const int N = d.n, M = N >> 1, bits = 31 - __clz(M);
-    const int w = threadIdx.x / 64, lane = threadIdx.x % 64, lpb = blockDim.x / 64;
-    const long long line = blk * lpb + w;
-    const bool valid = line < d.lines;
-    double2* a = smem + w * (2 * M + 1);
-    const TI* in = (const TI*)d.in + line * (long long)N;
-    if (valid)
-        for (int n = lane; n < M; n += 64) a[bitrev(n, bits)] = make_double2(ld(in, 2 * n), ld(in, 2 * n + 1));
-    __syncthreads();
-    fft_stages<false>(a, M, N, d.twiddle, lane);
-    double se = 0.0, sx = 0.0;
-    if (valid) {
-        TO* out = (TO*)d.out + line * (long long)N;
-        const double c0 = d.scale / sqrt((double)N), c1 = d.scale * sqrt(2.0 / N);
-        for (int m = lane; m <= M; m += 64) {
-            const double2 zm = a[m == M ? 0 : m];
-            const double2 zc = conj2(a[m == 0 ? 0 : M - m]);
-            if (m == 0) {
-                out[0] = (TO)(c0 * (zm.x + zm.y));  // F_0 = Re Z_0 + Im Z_0
-            } else if (m == M) {
-                out[N - 1] = (TO)(c0 * (zm.x - zm.y));  // F_M = Re Z_0 - Im Z_0
-            } else {
-                const double2 s = make_double2(0.5 * (zm.x + zc.x), 0.5 * (zm.y + zc.y));
-                const double2 df = make_double2(0.5 * (zm.x - zc.x), 0.5 * (zm.y - zc.y));
-                const double2 t = cmul(d.twiddle[m], df);  // W^m (Z_m - conj Z_{M-m}) / 2
-                // F_m = s - i t
-                const double fr = s.x + t.y, fi = s.y - t.x;
-                out[2 * m - 1] = (TO)(c1 * fr);
-                out[2 * m] = (TO)(-c1 * fi);
-            }
+// Inverse complex FFT (conjugate twiddles), decimation in frequency: natural
+// in, bit-reversed out, unnormalised.
+__device__ __forceinline__ void ut_dif_inv(double2* lds, int lpb, int M, int N, const double2* __restrict__ W) {
+    const int g = UT_NT / lpb;
+    const int l = threadIdx.x / g, t = threadIdx.x - l * g;
+    double2* a = lds + (size_t)l * M;
+    for (int L = M; L >= 2; L >>= 1) {
+        const int half = L >> 1, tstep = N / L;
+        for (int b = t; b < (M >> 1); b += g) {
+            const int grp = b / half, pos = b - grp * half;
+            const int i0 = grp * L + pos, i1 = i0 + half;
+            const double2 u = a[i0];
+            const double2 v = a[i1];
+            a[i0] = cadd(u, v);
+            a[i1] = cmul(csub(u, v), conj2(W[pos * tstep]));
         }
+        __syncthreads();
     }
-    (void)se;
-    (void)sx;
-    (void)red;
 }
 
+template <typename TI, typename TO>
+__device__ __forceinline__ void ut_forward(const FftDesc& d, long long blk, double2* lds) {
+    const int N = d.n, M = N >> 1, bits = 31 - __clz(M), kind = d.kind;
+    const int lpb = ut_lines_per_block(N);
+    const long long line0 = blk * lpb;
+    const TI* in = (const TI*)d.in;
+    TO* out = (TO*)d.out;
+    double* ldsd = (double*)lds;
+    // 1) load into bit-reversed complex slots (v_j -> slot j/2, part j%2);
+    //    eight loads in flight per thread before the LDS stores
+    const int total = lpb * N;
+    for (int base = 0; base < total; base += 8 * UT_NT) {
+        double v[8];
+        int pos[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = base + u * UT_NT + (int)threadIdx.x;
+            int l, e;
+            ut_map(d.ylines, lpb, N, idx, l, e);
+            const long long line = line0 + l;
+            pos[u] = -1;
+            v[u] = 0.0;
+            if (idx < total && line < d.lines) {
+                double x = (double)in[ut_offset(d, line, e)];
+                if (kind == UT_DST && (e & 1)) x = -x;
+                const int j = ut_vpos(kind, N, e);
+                pos[u] = l * N + 2 * bitrev(j >> 1, bits) + (j & 1);
+                v[u] = x;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (pos[u] >= 0) ldsd[pos[u]] = v[u];
+    }
+    __syncthreads();
+    // 2) complex FFT
+    ut_dit(lds, lpb, M, N, d.twiddle);
+    // 3) half spectrum and outputs, from LDS straight to memory
+    const double s = d.scale;
+    const int cnt = M + 1;
+    for (int idx = threadIdx.x; idx < lpb * cnt; idx += UT_NT) {
+        int l, m;
+        ut_map(d.ylines, lpb, cnt, idx, l, m);
+        const long long line = line0 + l;
+        if (line >= d.lines) continue;
+        const double2* a = lds + (size_t)l * M;
+        const double2 z0 = a[0];
+        if (kind == UT_FOURIER) {
+            const double c0 = s / sqrt((double)N), c1 = s * sqrt(2.0 / N);
+            if (m == 0) {
+                out[ut_offset(d, line, 0)] = (TO)(c0 * (z0.x + z0.y));  // V_0 = Re Z_0 + Im Z_0
+            } else if (m == M) {
+                out[ut_offset(d, line, N - 1)] = (TO)(c0 * (z0.x - z0.y));  // V_M = Re Z_0 - Im Z_0
+            } else {
+                const double2 zm = a[m], zc = conj2(a[M - m]);
+                const double2 e = cscale(cadd(zm, zc), 0.5);
+                const double2 t = cmul(d.twiddle[m], cscale(csub(zm, zc), 0.5));
+                // V_m = e - i t; column 2m-1 takes Re V_m, column 2m takes -Im V_m
+                out[ut_offset(d, line, 2 * m - 1)] = (TO)(c1 * (e.x + t.y));
+                out[ut_offset(d, line, 2 * m)] = (TO)(-c1 * (e.y - t.x));
+            }
+        } else {
+            const double ca = s * sqrt(1.0 / N), cb = s * sqrt(2.0 / N);
+            const bool rev = kind == UT_DST;
+            if (m == 0) {
+                out[ut_offset(d, line, rev ? N - 1 : 0)] = (TO)(ca * (z0.x + z0.y));
+            } else if (m == M) {
+                // X_M = cos(pi/4) V_M
+                out[ut_offset(d, line, rev ? N - 1 - M : M)] = (TO)(cb * sqrt(0.5) * (z0.x - z0.y));
+            } else {
+                const double2 zm = a[m], zc = conj2(a[M - m]);
+                const double2 e = cscale(cadd(zm, zc), 0.5);
+                const double2 t = cmul(d.twiddle[m], cscale(csub(zm, zc), 0.5));
+                const double2 r = cmul(d.qtw[m], make_double2(e.x + t.y, e.y - t.x));  // e^{-i pi m/2N} V_m
+                out[ut_offset(d, line, rev ? N - 1 - m : m)] = (TO)(cb * r.x);
+                out[ut_offset(d, line, rev ? m - 1 : N - m)] = (TO)(-cb * r.y);
+            }
+        }
+    }
+}
 
 template <typename TI, typename TO, int EPI>
-__device__ __forceinline__ void fft_inv_block(const FftDesc& d, long long blk, double2* smem, double* red) {
-    const int N = d.n, M = N >> 1, bits = 31 - __clz(M);
-    const int w = threadIdx.x / 64, lane = threadIdx.x % 64, lpb = blockDim.x / 64;
-    const long long line = blk * lpb + w;
-    const bool valid = line < d.lines;
-    double2* F = smem + w * (2 * M + 1);  // half spectrum F_0 .. F_M
-    double2* Z = F + (M + 1);             // Z in bit-reversed order
-    const TI* in = (const TI*)d.in + line * (long long)N;
+__device__ __forceinline__ void ut_inverse(const FftDesc& d, long long blk, double2* lds, double* red) {
+    const int N = d.n, M = N >> 1, bits = 31 - __clz(M), kind = d.kind;
+    const int lpb = ut_lines_per_block(N);
+    const long long line0 = blk * lpb;
+    const TI* in = (const TI*)d.in;
     const double s = d.scale;  // 1 / sqrt(h)
-    const double cN = s * sqrt((double)N), cH = s * sqrt(0.5 * N);
-    if (valid) {
-        for (int m = lane; m <= M; m += 64) {
-            double2 v;
-            if (m == 0) v = make_double2(cN * ld(in, 0), 0.0);
-            else if (m == M) v = make_double2(cN * ld(in, N - 1), 0.0);
-            else v = make_double2(cH * ld(in, 2 * m - 1), -cH * ld(in, 2 * m));
-            F[m] = v;
-        }
-    }
-    __syncthreads();
-    // Z_m = E_m + i O_m, E = (F_m + conj F_{M-m})/2, O = conj(W^m) (F_m - conj F_{M-m})/2
-    if (valid) {
-        for (int m = lane; m < M; m += 64) {
-            const double2 fm = F[m], fc = conj2(F[M - m]);
-            const double2 e = make_double2(0.5 * (fm.x + fc.x), 0.5 * (fm.y + fc.y));
-            const double2 df = make_double2(0.5 * (fm.x - fc.x), 0.5 * (fm.y - fc.y));
-            const double2 o = cmul(conj2(d.twiddle[m]), df);
-            Z[bitrev(m, bits)] = make_double2(e.x - o.y, e.y + o.x);  // e + i o
-        }
-    }
-    __syncthreads();
-    fft_stages<true>(Z, M, N, d.twiddle, lane);
-    double se = 0.0, sx = 0.0;
-    if (valid) {
-        TO* out = (TO*)d.out + line * (long long)N;
-        const double inv = 1.0 / M;
-        for (int n = lane; n < M; n += 64) {
-            const double2 z = Z[n];
-            const double v0 = z.x * inv, v1 = z.y * inv;
-            if constexpr (EPI == EPI_ACCUM_F64) {
-                const double x0 = (double)out[2 * n] + v0, x1 = (double)out[2 * n + 1] + v1;
-                out[2 * n] = (TO)x0;
-                out[2 * n + 1] = (TO)x1;
-                se += v0 * v0 + v1 * v1;
-                sx += x0 * x0 + x1 * x1;
+    // 1) half spectrum F_m, m = 0 .. M-1, in natural order; F_0 and F_M are
+    //    real, and F_M rides in the imaginary part of slot 0
+    for (int idx = threadIdx.x; idx < lpb * M; idx += UT_NT) {
+        int l, m;
+        ut_map(d.ylines, lpb, M, idx, l, m);
+        const long long line = line0 + l;
+        double2 F = make_double2(0.0, 0.0);
+        if (line < d.lines) {
+            if (kind == UT_FOURIER) {
+                const double cN = s * sqrt((double)N), cH = s * sqrt(0.5 * N);
+                if (m == 0)
+                    F = make_double2(cN * (double)in[ut_offset(d, line, 0)], cN * (double)in[ut_offset(d, line, N - 1)]);
+                else
+                    F = make_double2(cH * (double)in[ut_offset(d, line, 2 * m - 1)],
+                                     -cH * (double)in[ut_offset(d, line, 2 * m)]);
             } else {
-                out[2 * n] = (TO)v0;
-                out[2 * n + 1] = (TO)v1;
+                // X_k = s c_k phihat_k (DST: phihat read in reverse), X_0 doubled
+                const bool rev = kind == UT_DST;
+                const double ca = s * sqrt(1.0 / N), cb = s * sqrt(2.0 / N);
+                auto X = [&](int k) -> double {
+                    return (k == 0 ? 2.0 * ca : cb) * (double)in[ut_offset(d, line, rev ? N - 1 - k : k)];
+                };
+                if (m == 0)
+                    F = make_double2(X(0), sqrt(2.0) * X(M));  // V_0 = X_0, V_M = sqrt(2) X_M
+                else
+                    F = cmul(conj2(d.qtw[m]), make_double2(X(m), -X(N - m)));  // e^{i pi m/2N}(X_m - i X_{N-m})
             }
+        }
+        lds[(size_t)l * M + m] = F;
+    }
+    __syncthreads();
+    // 2) fold the pairs (m, M-m) into Z_m = E_m + i O_m in place, with
+    //    E_m = (F_m + conj F_{M-m})/2 and O_m = conj(W^m) (F_m - conj F_{M-m})/2
+    const int pairs = M / 2 + 1;
+    for (int idx = threadIdx.x; idx < lpb * pairs; idx += UT_NT) {
+        const int l = idx / pairs, m = idx - l * pairs;
+        double2* a = lds + (size_t)l * M;
+        if (m == 0) {
+            const double f0 = a[0].x, fM = a[0].y;
+            a[0] = make_double2(0.5 * (f0 + fM), 0.5 * (f0 - fM));
+        } else {
+            const int mc = M - m;
+            const double2 fm = a[m], fc = a[mc];
+            const double2 Em = cscale(cadd(fm, conj2(fc)), 0.5);
+            const double2 Om = cmul(conj2(d.twiddle[m]), cscale(csub(fm, conj2(fc)), 0.5));
+            if (mc != m) {
+                // E_{M-m} = conj E_m and conj(W^{M-m}) = -W^m
+                const double2 Ec = conj2(Em);
+                const double2 Oc = cmul(cscale(d.twiddle[m], -1.0), cscale(csub(fc, conj2(fm)), 0.5));
+                a[mc] = make_double2(Ec.x - Oc.y, Ec.y + Oc.x);
+            }
+            a[m] = make_double2(Em.x - Om.y, Em.y + Om.x);
+        }
+    }
+    __syncthreads();
+    // 3) inverse complex FFT, natural in, bit-reversed out
+    ut_dif_inv(lds, lpb, M, N, d.twiddle);
+    // 4) unpack and store
+    const double* ldsd = (const double*)lds;
+    const double post = (kind == UT_FOURIER) ? 1.0 / M : 1.0;
+    TO* out = (TO*)d.out;
+    double se = 0.0, sx = 0.0;
+    for (int idx = threadIdx.x; idx < lpb * N; idx += UT_NT) {
+        int l, e;
+        ut_map(d.ylines, lpb, N, idx, l, e);
+        const long long line = line0 + l;
+        if (line >= d.lines) continue;
+        const int j = ut_vpos(kind, N, e);
+        double v = ldsd[l * N + 2 * bitrev(j >> 1, bits) + (j & 1)] * post;
+        if (kind == UT_DST && (e & 1)) v = -v;
+        const long long o = ut_offset(d, line, e);
+        if constexpr (EPI == EPI_ACCUM_F64) {
+            const double x = (double)out[o] + v;
+            out[o] = (TO)x;
+            se += v * v;
+            sx += x * x;
+        } else {
+            out[o] = (TO)v;
         }
     }
     if constexpr (EPI == EPI_ACCUM_F64) {
-        block_sum2_rt(se, sx, red);
+        block_sum2<UT_NT>(se, sx, red);
         if (threadIdx.x == 0) {
             d.partials[2 * blk] = se;
             d.partials[2 * blk + 1] = sx;
@@ -180,21 +298,24 @@ __device__ __forceinline__ void fft_inv_block(const FftDesc& d, long long blk, d
 }
 
 template <typename TI, typename TO, int EPI, bool INV>
-__device__ __forceinline__ void fft_block(const FftDesc& d, long long blk) {
-    extern __shared__ double2 fft_smem[];
-    __shared__ double red[2 * 4];
-    if constexpr (INV) fft_inv_block<TI, TO, EPI>(d, blk, fft_smem, red);
-    else fft_fwd_block<TI, TO, EPI>(d, blk, fft_smem, red);
+__device__ __forceinline__ void ut_block(const FftDesc& d, long long blk) {
+    extern __shared__ double2 ut_smem[];
+    __shared__ double red[2 * (UT_NT / 64)];
+    if constexpr (INV) ut_inverse<TI, TO, EPI>(d, blk, ut_smem, red);
+    else ut_forward<TI, TO>(d, blk, ut_smem);
+}
+
+// Consecutive blocks of strided lines share cache lines: y launches number
+// their blocks per XCD (xcd_block).
+template <typename TI, typename TO, int EPI, bool INV>
+__global__ __launch_bounds__(UT_NT) void ut_kernel(FftDesc d, long long nblocks) {
+    const long long b = d.ylines ? xcd_block(blockIdx.x, nblocks) : (long long)blockIdx.x;
+    ut_block<TI, TO, EPI, INV>(d, b);
 }
 
 template <typename TI, typename TO, int EPI, bool INV>
-__global__ __launch_bounds__(256) void fft_kernel(FftDesc d) {
-    fft_block<TI, TO, EPI, INV>(d, blockIdx.x);
-}
-
-template <typename TI, typename TO, int EPI, bool INV>
-__global__ __launch_bounds__(256) void fft_multi_kernel(const FftDesc* __restrict__ work, int nwork,
-                                                                   long long total) {
+__global__ __launch_bounds__(UT_NT) void ut_multi_kernel(const FftDesc* __restrict__ work, int nwork,
+                                                         long long total) {
     for (long long blk = blockIdx.x; blk < total; blk += gridDim.x) {
         int lo = 0, hi = nwork - 1;
         while (lo < hi) {
@@ -203,54 +324,55 @@ __global__ __launch_bounds__(256) void fft_multi_kernel(const FftDesc* __restric
             else hi = mid - 1;
         }
         const FftDesc d = work[lo];
-        fft_block<TI, TO, EPI, INV>(d, blk - d.block_begin);
+        ut_block<TI, TO, EPI, INV>(d, blk - d.block_begin);
         __syncthreads();
     }
 }
 
-long long fft_blocks(const FftDesc& d) {
-    const int lpb = fft_lines_per_block(d.n);
-    return (d.lines + lpb - 1) / lpb;
-}
-
-bool fft_supported(int n) { return n >= 8 && n <= 2048 && (n & (n - 1)) == 0; }
-
 template <typename TI, typename TO, int EPI, bool INV>
-static hipError_t launch_fft_t(const FftDesc& d, const FftDesc* d_work, int nwork, long long blocks, int n,
-                               hipStream_t s) {
-    const int lpb = fft_lines_per_block(n);
-    const size_t sm = (size_t)lpb * (n + 1) * sizeof(double2);
+hipError_t launch_ut_t(const FftDesc& d, const FftDesc* d_work, int nwork, long long blocks, hipStream_t s) {
+    const size_t sm = (size_t)ut_lines_per_block(d.n) * d.n * sizeof(double);
     if (d_work)
-        hipLaunchKernelGGL((fft_multi_kernel<TI, TO, EPI, INV>),
+        hipLaunchKernelGGL((ut_multi_kernel<TI, TO, EPI, INV>),
                            dim3((unsigned)(blocks < 4 * PERSISTENT_BLOCKS ? blocks : 4 * PERSISTENT_BLOCKS)),
-                           dim3(64 * lpb), sm, s, d_work, nwork, blocks);
+                           dim3(UT_NT), sm, s, d_work, nwork, blocks);
     else
-        hipLaunchKernelGGL((fft_kernel<TI, TO, EPI, INV>), dim3((unsigned)blocks), dim3(64 * lpb), sm, s, d);
+        hipLaunchKernelGGL((ut_kernel<TI, TO, EPI, INV>), dim3((unsigned)blocks), dim3(UT_NT), sm, s, d, blocks);
     return hipGetLastError();
 }
 
-// rep: a representative descriptor (types, direction, epilogue); every
-// descriptor of a work list has the same line length n (the block shape and
-// LDS size depend on it).
+}  // namespace
+
+bool fft_supported(int n) { return n >= 8 && n <= 2048 && (n & (n - 1)) == 0; }
+
+long long fft_blocks(const FftDesc& d) {
+    const int lpb = ut_lines_per_block(d.n);
+    return (d.lines + lpb - 1) / lpb;
+}
+
+// rep: a representative descriptor (types, direction, epilogue, line length);
+// every descriptor of a work list has the same line length n, since the
+// block's line count and LDS size depend on it.
 hipError_t launch_fft(const FftDesc& rep, const FftDesc* d_work, int nwork, long long blocks, hipStream_t s) {
-    const int nmax = rep.n;
     if (blocks <= 0) return hipSuccess;
-    if (blocks > 0x7fffffffLL || !fft_supported(nmax)) return hipErrorInvalidValue;
+    if (blocks > 0x7fffffffLL || !fft_supported(rep.n)) return hipErrorInvalidValue;
+    if (rep.kind < UT_FOURIER || rep.kind > UT_DST) return hipErrorInvalidValue;
+    if (rep.ylines && (rep.inner <= 0 || rep.s_elem <= 0)) return hipErrorInvalidValue;
     if (!rep.inverse) {
         if (rep.epi != EPI_STORE) return hipErrorInvalidValue;
-        if (rep.tin == DT_F64 && rep.tout == DT_F64) return launch_fft_t<double, double, EPI_STORE, false>(rep, d_work, nwork, blocks, nmax, s);
-        if (rep.tin == DT_F64 && rep.tout == DT_F32) return launch_fft_t<double, float, EPI_STORE, false>(rep, d_work, nwork, blocks, nmax, s);
-        if (rep.tin == DT_F32 && rep.tout == DT_F32) return launch_fft_t<float, float, EPI_STORE, false>(rep, d_work, nwork, blocks, nmax, s);
+        if (rep.tin == DT_F64 && rep.tout == DT_F64) return launch_ut_t<double, double, EPI_STORE, false>(rep, d_work, nwork, blocks, s);
+        if (rep.tin == DT_F64 && rep.tout == DT_F32) return launch_ut_t<double, float, EPI_STORE, false>(rep, d_work, nwork, blocks, s);
+        if (rep.tin == DT_F32 && rep.tout == DT_F32) return launch_ut_t<float, float, EPI_STORE, false>(rep, d_work, nwork, blocks, s);
         return hipErrorInvalidValue;
     }
     if (rep.tin == DT_F64 && rep.tout == DT_F64 && rep.epi == EPI_STORE)
-        return launch_fft_t<double, double, EPI_STORE, true>(rep, d_work, nwork, blocks, nmax, s);
+        return launch_ut_t<double, double, EPI_STORE, true>(rep, d_work, nwork, blocks, s);
     if (rep.tin == DT_F32 && rep.tout == DT_F64 && rep.epi == EPI_STORE)
-        return launch_fft_t<float, double, EPI_STORE, true>(rep, d_work, nwork, blocks, nmax, s);
+        return launch_ut_t<float, double, EPI_STORE, true>(rep, d_work, nwork, blocks, s);
     if (rep.tin == DT_F32 && rep.tout == DT_F64 && rep.epi == EPI_ACCUM_F64)
-        return launch_fft_t<float, double, EPI_ACCUM_F64, true>(rep, d_work, nwork, blocks, nmax, s);
+        return launch_ut_t<float, double, EPI_ACCUM_F64, true>(rep, d_work, nwork, blocks, s);
     if (rep.tin == DT_F32 && rep.tout == DT_F32 && rep.epi == EPI_STORE)
-        return launch_fft_t<float, float, EPI_STORE, true>(rep, d_work, nwork, blocks, nmax, s);
+        return launch_ut_t<float, float, EPI_STORE, true>(rep, d_work, nwork, blocks, s);
     return hipErrorInvalidValue;
 }
 

@@ -495,7 +495,9 @@ struct GemmKernel {
 
 template <int PREC, typename TA, typename TB, typename TC, int EPI, int BM, int BN, bool BNK, int DEEP>
 __global__ TPT_GEMM_ATTR void gemm_kernel(GemmDesc g) {
-    GemmKernel<PREC, TA, TB, TC, EPI, BM, BN, BNK, DEEP>::tile(g, blockIdx.x);
+    // neighbouring tiles share an operand (the same data rows in the x pass,
+    // the same slab in the y pass): keep them on one XCD
+    GemmKernel<PREC, TA, TB, TC, EPI, BM, BN, BNK, DEEP>::tile(g, xcd_block(blockIdx.x, gridDim.x));
 }
 
 template <int PREC, typename TA, typename TB, typename TC, int EPI, int BM, int BN, bool BNK, int DEEP>

@@ -164,7 +164,9 @@ static bool analytic_basis(const Op1D& op, Eig1D& e) {
         // cosine basis cos(pi k (i + 1/2) / n)
         for (int k = 0; k < n; ++k) {
             real nc = (k == 0) ? std::sqrt(1.0L / n) : std::sqrt(2.0L / n);
-            for (int i = 0; i < n; ++i) Q(i, k) = (double)(nc * std::cos(pi * k * (i + 0.5L) / n));
+            // angle pi k (2i+1) / (2n), reduced exactly modulo 2 pi first
+            for (int i = 0; i < n; ++i)
+                Q(i, k) = (double)(nc * std::cos(pi * (real)(((long long)k * (2 * i + 1)) % (4LL * n)) / (2.0L * n)));
             real th = pi * k / (2.0L * n);
             e.lam[k] = (double)(-s4 * std::sin(th) * std::sin(th));
         }
@@ -177,7 +179,9 @@ static bool analytic_basis(const Op1D& op, Eig1D& e) {
         // sine basis sin(pi k (i + 1/2) / n), k = 1..n
         for (int k = 1; k <= n; ++k) {
             real nc = (k == n) ? std::sqrt(1.0L / n) : std::sqrt(2.0L / n);
-            for (int i = 0; i < n; ++i) Q(i, k - 1) = (double)(nc * std::sin(pi * k * (i + 0.5L) / n));
+            for (int i = 0; i < n; ++i)
+                Q(i, k - 1) =
+                    (double)(nc * std::sin(pi * (real)(((long long)k * (2 * i + 1)) % (4LL * n)) / (2.0L * n)));
             real th = pi * k / (2.0L * n);
             e.lam[k - 1] = (double)(-s4 * std::sin(th) * std::sin(th));
         }
@@ -190,7 +194,8 @@ static bool analytic_basis(const Op1D& op, Eig1D& e) {
         const int m = n + 1;
         for (int k = 1; k <= n; ++k) {
             real nc = std::sqrt(2.0L / m);
-            for (int i = 0; i < n; ++i) Q(i, k - 1) = (double)(nc * std::sin(pi * k * (i + 1.0L) / m));
+            for (int i = 0; i < n; ++i)
+                Q(i, k - 1) = (double)(nc * std::sin(pi * (real)(((long long)k * (i + 1)) % (2LL * m)) / m));
             real th = pi * k / (2.0L * m);
             e.lam[k - 1] = (double)(-s4 * std::sin(th) * std::sin(th));
         }

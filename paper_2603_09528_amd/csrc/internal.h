@@ -43,7 +43,9 @@ struct DirBasis {
     uint16_t* l_qinv = nullptr;
     uint16_t* h_q = nullptr;
     uint16_t* l_q = nullptr;
-    double2* d_twiddle = nullptr;    // e^{-2 pi i k/n}, k < n/2 (uniform periodic, power-of-two n)
+    int fast_kind = -1;              // XformKind of the fast transform, -1 = none
+    double2* d_twiddle = nullptr;    // e^{-2 pi i k/n}, k < n/2 (fast transform)
+    double2* d_qtw = nullptr;        // e^{-i pi k/2n}, k <= n/2 (DCT, DST)
     double h = 0.0;                  // uniform spacing (analytic bases)
     void* block = nullptr;           // single allocation holding all of the above
     size_t bytes = 0;
@@ -83,7 +85,7 @@ struct tpt_plan_s {
     double* h_norms = nullptr;       // pinned host copy of norms (adaptive mode)
     tpt_info info{};
     int gemm_variant[4] = {-1, -1, -1, -1};  // per stage (x fwd, y fwd, y inv, x inv); -1 = table
-    bool x_fft = false;              // x stages by the real-Fourier transform
+    int fast[2] = {-1, -1};          // x, y: XformKind of the fast transform, -1 = GEMM
     ~tpt_plan_s();
 };
 
@@ -96,7 +98,8 @@ size_t plan_workspace_bytes(const tpt_plan_s* p);
 enum Stage { ST_XF = 0, ST_YF = 1, ST_YI = 2, ST_XI = 3 };
 GemmDesc stage_gemm(const tpt_plan_s* p, int stage, int prec, const void* in, int tin, void* out, int tout,
                     int epi, double* partials, int nrhs);
-// x stages of a plan with x_fft: the real-Fourier transform of every x-line.
+// Stages of a direction with a fast transform: all lines of that direction.
+bool stage_is_fast(const tpt_plan_s* p, int stage);
 FftDesc stage_fft(const tpt_plan_s* p, int stage, const void* in, int tin, void* out, int tout, int epi,
                   double* partials, int nrhs);
 ThomasDesc plan_thomas(const tpt_plan_s* p, const void* f, int tf, void* x, int tx, double* scratch, int nrhs);

@@ -66,20 +66,29 @@ hipError_t launch_gemm_f32(const GemmDesc& g, const GemmDesc* d_work, int nwork,
 hipError_t launch_gemm_bf16(const GemmDesc& g, const GemmDesc* d_work, int nwork, long long blocks, int variant,
                             hipStream_t s);
 
-// Fast real-Fourier transform of x-lines (uniform periodic x direction):
-// forward fhat = sqrt(h) Q~^T f or inverse phi = Q~ phihat / sqrt(h) for
-// `lines` contiguous lines of length n (a power of two, 8..2048) in the
-// orthonormal cos/sin basis order of the analytic eigenbasis.
+// Fast transforms of the lines of a uniform direction (analytic bases:
+// real Fourier for periodic, DCT-II for Neumann-Neumann, DST-II for
+// Dirichlet-Dirichlet, cell-centred): forward fhat = sqrt(h) Q~^T f or inverse
+// phi = Q~ phihat / sqrt(h) for `lines` lines of length n (a power of two,
+// 8..2048), either contiguous (x lines) or strided (y lines: column `col` of
+// slab `slab` starts at slab * s_outer + col, element stride s_elem).
+enum XformKind { UT_FOURIER = 0, UT_DCT = 1, UT_DST = 2 };
 struct FftDesc {
     int n;
+    int kind;               // XformKind
+    int inverse;
+    int ylines;             // 0: line l starts at l * n; 1: strided as above
     long long lines;
+    long long inner;        // ylines: lines per slab (Nx)
+    long long s_elem;       // ylines: element stride (Nx)
+    long long s_outer;      // ylines: slab stride (Nx Ny)
     const void* in;
     void* out;
     int tin, tout;          // DType of in / out
     int epi;                // EPI_STORE, or EPI_ACCUM_F64 (inverse only, FP64 out)
-    int inverse;
     double scale;           // sqrt(h) forward, 1/sqrt(h) inverse
     const double2* twiddle; // e^{-2 pi i k / n}, k < n/2
+    const double2* qtw;     // e^{-i pi k / 2n}, k <= n/2 (DCT, DST)
     double* partials;       // EPI_ACCUM_F64: 2 doubles per block
     long long block_begin;  // multi-problem
 };
@@ -97,6 +106,7 @@ struct ThomasDesc {
     const double* cz;
     double sigma, tau;
     int pin_line;
+    int periodic;          // cyclic z lines (corners az[0], cz[nz-1])
     const void* f;
     void* x;
     double* scratch;       // thomas_scratch_doubles() doubles
@@ -104,9 +114,9 @@ struct ThomasDesc {
     long long line_begin;  // multi-problem: first global line
 };
 hipError_t launch_thomas(const ThomasDesc& t, hipStream_t s);
-// Scratch the Thomas kernel needs: c' checkpoints (one per line every
-// THOMAS_KC planes) and, when x is FP32, the FP64 d' of every unknown.
-long long thomas_scratch_doubles(int nx, int ny, int nz, int nsys, int tx);
+// Scratch the Thomas kernel needs: (c', d') checkpoints, one per line every
+// 32 planes, and for cyclic lines also the d' of the second right-hand side.
+long long thomas_scratch_doubles(int nx, int ny, int nz, int nsys, int periodic);
 hipError_t launch_thomas_multi(const ThomasDesc* d_work, int nwork, long long total_lines, hipStream_t s);
 
 // Residual r = f - A x of the 7-point operator in FP64, r stored as float,
@@ -116,7 +126,7 @@ struct StencilDesc {
     const double* ax; const double* bx; const double* cx;
     const double* ay; const double* by; const double* cy;
     const double* az; const double* bz; const double* cz;
-    int perx, pery;
+    int perx, pery, perz;
     int helmholtz;
     double alpha;
     const double* x;

@@ -78,11 +78,10 @@ hipError_t launch_gemm_multi(const GemmDesc& rep, const GemmDesc* d_work, int nw
 // ---------------------------------------------------------------------------
 constexpr int THOMAS_KC = 32;
 
-long long thomas_scratch_doubles(int nx, int ny, int nz, int nsys, int tx) {
-    (void)tx;
+long long thomas_scratch_doubles(int nx, int ny, int nz, int nsys, int periodic) {
     const long long lines = (long long)nx * ny * nsys;
     const long long nck = (nz + THOMAS_KC - 1) / THOMAS_KC;
-    return 2 * lines * nck;
+    return (periodic ? 4 : 2) * lines * nck;
 }
 
 // 1/d from the hardware reciprocal and two Newton steps (about 1 ulp): the
@@ -187,7 +186,132 @@ __device__ __forceinline__ void thomas_line(const ThomasDesc& t, long long gl) {
     }
 }
 
+// Periodic z: every line is cyclic, with corners tau az[0] (row 0, column
+// nz-1) and tau cz[nz-1] (row nz-1, column 0).  Eliminating the last unknown
+// leaves the tridiagonal system of rows 0..nz-2,
+//   A' x' = f' - x_{nz-1} e,  e = tau az[0] e_0 + tau cz[nz-2] e_{nz-2},
+// so x' = y - x_{nz-1} v with A' y = f', A' v = e (one forward elimination
+// for both right-hand sides), and the last row gives
+//   x_{nz-1} = (f_{nz-1} - tau cz[nz-1] y_0 - tau az[nz-1] y_{nz-2})
+//            / (d_{nz-1} - tau cz[nz-1] v_0 - tau az[nz-1] v_{nz-2}).
+// Passes: forward elimination (checkpoints of c', d'_y, d'_v), a back
+// substitution that only finds y_0 and v_0, and a second one that writes
+// x = y - x_{nz-1} v.  On the pinned line (singular Poisson) x_{nz-1} = 0 and
+// the last equation is dropped, the gauge of §3.  nz >= 2.
+template <typename TF, typename TX>
+__device__ __forceinline__ void thomas_line_cyclic(const ThomasDesc& t, long long gl) {
+    constexpr int KC = THOMAS_KC;
+    const long long S = (long long)t.nx * t.ny;
+    const int sys = (int)(gl / S);
+    const long long line = gl - (long long)sys * S;
+    const int i = (int)(line % t.nx), j = (int)(line / t.nx);
+    const int nz = t.nz, nr = nz - 1;  // reduced system rows 0 .. nr-1
+    const int nc = (nr + KC - 1) / KC;
+    const long long lines = S * t.nsys;
+    const double lam = t.lamx[i] + t.lamy[j];
+    const long long base = (long long)sys * S * nz + line;
+    const TF* f = (const TF*)t.f + base;
+    TX* x = (TX*)t.x + base;
+    double2* ck = (double2*)t.scratch + gl;  // ck[2 c * lines]: (c', d'_y), ck[(2c+1) lines]: (d'_v, -)
+    const bool pinned = line == t.pin_line;
+    const double sig = t.sigma, tau = t.tau;
+    const double* __restrict__ az = t.az;
+    const double* __restrict__ bz = t.bz;
+    const double* __restrict__ cz = t.cz;
+    // coupling of row k of the reduced system to x_{nz-1}
+    auto ecoef = [&](int k) { return (k == 0 ? tau * az[0] : 0.0) + (k == nr - 1 ? tau * cz[nr - 1] : 0.0); };
+    auto step = [&](int k, double fk, double& cp, double& dy, double& dv) {
+        const double sub = k > 0 ? tau * az[k] : 0.0;
+        const double den = sig + tau * (lam + bz[k]) - sub * cp;
+        const double inv = recip(den);
+        cp = k < nr - 1 ? tau * cz[k] * inv : 0.0;
+        dy = (fk - sub * dy) * inv;
+        dv = (ecoef(k) - sub * dv) * inv;
+    };
+    double fb[KC], fn[KC];
+    // ---- forward elimination of the reduced system ----
+    double cp = 0.0, dy = 0.0, dv = 0.0;
+#pragma unroll
+    for (int e = 0; e < KC; ++e) fb[e] = e < nr ? (double)f[(long long)e * S] : 0.0;
+    for (int c = 0; c < nc; ++c) {
+        const int k0 = c * KC;
+        ck[(long long)(2 * c) * lines] = make_double2(cp, dy);
+        ck[(long long)(2 * c + 1) * lines] = make_double2(dv, 0.0);
+#pragma unroll
+        for (int e = 0; e < KC; ++e) {
+            const int k = k0 + KC + e;
+            fn[e] = k < nr ? (double)f[(long long)k * S] : 0.0;
+        }
+#pragma unroll
+        for (int e = 0; e < KC; ++e) {
+            const int k = k0 + e;
+            if (k < nr) step(k, fb[e], cp, dy, dv);
+        }
+#pragma unroll
+        for (int e = 0; e < KC; ++e) fb[e] = fn[e];
+    }
+    const double ytop = dy, vtop = dv;  // y_{nr-1}, v_{nr-1}
+    const double flast = (double)f[(long long)nr * S];
+    // ---- back substitutions from the top: pass 0 finds y_0, v_0; pass 1 writes ----
+    double xlast = 0.0;
+    for (int pass = pinned ? 1 : 0; pass < 2; ++pass) {
+        if (pass == 1) x[(long long)nr * S] = (TX)xlast;
+        double yv = 0.0, vv = 0.0;  // y_{k+1}, v_{k+1}
+        {
+            const int k0 = (nc - 1) * KC;
+#pragma unroll
+            for (int e = 0; e < KC; ++e) {
+                const int k = k0 + e;
+                fb[e] = k < nr ? (double)f[(long long)k * S] : 0.0;
+            }
+        }
+        for (int c = nc - 1; c >= 0; --c) {
+            const int k0 = c * KC;
+            if (c > 0) {
+#pragma unroll
+                for (int e = 0; e < KC; ++e) fn[e] = (double)f[(long long)(k0 - KC + e) * S];
+            }
+            const double2 c0 = ck[(long long)(2 * c) * lines];
+            const double2 c1 = ck[(long long)(2 * c + 1) * lines];
+            double cb[KC], db[KC];
+            double cpr = c0.x, dyr = c0.y, dvr = c1.x;
+#pragma unroll
+            for (int e = 0; e < KC; ++e) {
+                const int k = k0 + e;
+                if (k < nr) step(k, fb[e], cpr, dyr, dvr);
+                cb[e] = cpr;
+                fb[e] = dyr;
+                db[e] = dvr;
+            }
+#pragma unroll
+            for (int e = KC - 1; e >= 0; --e) {
+                const int k = k0 + e;
+                if (k < nr) {
+                    yv = (k == nr - 1) ? fb[e] : fb[e] - cb[e] * yv;
+                    vv = (k == nr - 1) ? db[e] : db[e] - cb[e] * vv;
+                    if (pass == 1) x[(long long)k * S] = (TX)(yv - xlast * vv);
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < KC; ++e) fb[e] = fn[e];
+        }
+        if (pass == 0) {
+            // yv, vv now hold y_0, v_0
+            const double cl = tau * cz[nz - 1], al = tau * az[nz - 1];
+            const double dl = sig + tau * (lam + bz[nz - 1]);
+            xlast = (flast - cl * yv - al * ytop) * recip(dl - cl * vv - al * vtop);
+        }
+    }
+}
+
 __device__ __forceinline__ void thomas_dispatch(const ThomasDesc& t, long long gl) {
+    if (t.periodic) {
+        if (t.tf == DT_F64 && t.tx == DT_F64) thomas_line_cyclic<double, double>(t, gl);
+        else if (t.tf == DT_F32 && t.tx == DT_F32) thomas_line_cyclic<float, float>(t, gl);
+        else if (t.tf == DT_F64) thomas_line_cyclic<double, float>(t, gl);
+        else thomas_line_cyclic<float, double>(t, gl);
+        return;
+    }
     if (t.tf == DT_F64 && t.tx == DT_F64) thomas_line<double, double>(t, gl);
     else if (t.tf == DT_F32 && t.tx == DT_F32) thomas_line<float, float>(t, gl);
     else if (t.tf == DT_F64) thomas_line<double, float>(t, gl);
@@ -273,9 +397,11 @@ __device__ __forceinline__ void residual_block(const StencilDesc& st, long long 
             else if (st.pery) lap += st.ay[0] * x[idx + (long long)(ny - 1) * nx];
             if (j < ny - 1) lap += st.cy[j] * x[idx + nx];
             else if (st.pery) lap += st.cy[ny - 1] * x[idx - (long long)(ny - 1) * nx];
-            // z direction (never periodic)
+            // z direction
             if (k > 0) lap += st.az[k] * x[idx - sxy];
+            else if (st.perz) lap += st.az[0] * x[idx + (long long)(nz - 1) * sxy];
             if (k < nz - 1) lap += st.cz[k] * x[idx + sxy];
+            else if (st.perz) lap += st.cz[nz - 1] * x[idx - (long long)(nz - 1) * sxy];
             const double ax = st.helmholtz ? xc - st.alpha * lap : lap;
             const double fv = st.f[idx];
             const double r = fv - ax;

@@ -120,28 +120,49 @@ int MultiExec::build(const double* const* rhs, double* const* out, void* ws) {
         if (!rhs[i] || !out[i]) return fail(TPT_ERR_INVALID, "NULL rhs/out in batch");
         w[i] = carve(plans_[i], (char*)ws + ws_off_[i]);
     }
-    std::vector<char> all(n, 1), gx(n), fx(n);
+    // per stage: which problems take the fast transform, which the GEMM
+    auto fast_mask = [&](int stage, bool fast) {
+        std::vector<char> m(n);
+        for (int i = 0; i < n; ++i) m[i] = stage_is_fast(plans_[i], stage) == fast ? 1 : 0;
+        return m;
+    };
+    // one transform stage of every problem: GEMM launches grouped by tile
+    // variant, fast-transform launches grouped by line length
+    auto stage = [&](int st, const std::vector<const void*>& in, int tin, const std::vector<void*>& outp, int tout,
+                     int epi, std::vector<long long>* nb) {
+        std::vector<GemmDesc> g(n);
+        std::vector<FftDesc> f(n);
+        for (int i = 0; i < n; ++i) {
+            double* part = epi == EPI_ACCUM_F64 ? w[i].partials : nullptr;
+            if (stage_is_fast(plans_[i], st)) {
+                f[i] = stage_fft(plans_[i], st, in[i], tin, outp[i], tout, epi, part, 1);
+                if (nb) (*nb)[i] = fft_blocks(f[i]);
+            } else {
+                g[i] = stage_gemm(plans_[i], st, prec_, in[i], tin, outp[i], tout, epi, part, 1);
+                if (nb) (*nb)[i] = gemm_blocks(g[i], stage_variant(plans_[i], st, g[i], prec_));
+            }
+        }
+        add_gemm_stage(st, prec_, g, fast_mask(st, false));
+        add_fft_stage(f, fast_mask(st, true));
+    };
+    std::vector<void*> w1(n), w2(n), outv(n);
+    std::vector<const void*> w1c(n), w2c(n), rhsv(n), resv(n);
     for (int i = 0; i < n; ++i) {
-        fx[i] = plans_[i]->x_fft ? 1 : 0;
-        gx[i] = !fx[i];
+        w1[i] = w[i].w1;
+        w2[i] = w[i].w2;
+        w1c[i] = w[i].w1;
+        w2c[i] = w[i].w2;
+        outv[i] = out[i];
+        rhsv[i] = rhs[i];
+        resv[i] = w[i].r;
     }
     // one application of M^{-1}; returns the x-inverse block count of every
     // problem (the number of norm partials it wrote)
     auto minv = [&](bool from_rhs, int epi) {
-        const int tin0 = from_rhs ? DT_F64 : DT_F32;
         const int tmid = mixed_ ? DT_F32 : DT_F64;
-        std::vector<GemmDesc> g(n);
-        std::vector<FftDesc> f(n);
-        for (int i = 0; i < n; ++i) {
-            const void* in = from_rhs ? (const void*)rhs[i] : (const void*)w[i].r;
-            if (fx[i]) f[i] = stage_fft(plans_[i], ST_XF, in, tin0, w[i].w1, tmid, EPI_STORE, nullptr, 1);
-            else g[i] = stage_gemm(plans_[i], ST_XF, prec_, in, tin0, w[i].w1, tmid, EPI_STORE, nullptr, 1);
-        }
-        add_gemm_stage(ST_XF, prec_, g, gx);
-        add_fft_stage(f, fx);
-        for (int i = 0; i < n; ++i)
-            g[i] = stage_gemm(plans_[i], ST_YF, prec_, w[i].w1, tmid, w[i].w2, tmid, EPI_STORE, nullptr, 1);
-        add_gemm_stage(ST_YF, prec_, g, all);
+        std::vector<long long> nb(n);
+        stage(ST_XF, from_rhs ? rhsv : resv, from_rhs ? DT_F64 : DT_F32, w1, tmid, EPI_STORE, nullptr);
+        stage(ST_YF, w1c, tmid, w2, tmid, EPI_STORE, nullptr);
         std::vector<ThomasDesc> t(n);
         long long lines = 0;
         for (int i = 0; i < n; ++i) {
@@ -155,21 +176,8 @@ int MultiExec::build(const double* const* rhs, double* const* out, void* ws) {
         L.nwork = n;
         L.total = lines;
         seq_.push_back(L);
-        for (int i = 0; i < n; ++i)
-            g[i] = stage_gemm(plans_[i], ST_YI, prec_, w[i].w2, tmid, w[i].w1, tmid, EPI_STORE, nullptr, 1);
-        add_gemm_stage(ST_YI, prec_, g, all);
-        std::vector<long long> nb(n);
-        for (int i = 0; i < n; ++i) {
-            if (fx[i]) {
-                f[i] = stage_fft(plans_[i], ST_XI, w[i].w1, tmid, out[i], DT_F64, epi, w[i].partials, 1);
-                nb[i] = fft_blocks(f[i]);
-            } else {
-                g[i] = stage_gemm(plans_[i], ST_XI, prec_, w[i].w1, tmid, out[i], DT_F64, epi, w[i].partials, 1);
-                nb[i] = gemm_blocks(g[i], stage_variant(plans_[i], ST_XI, g[i], prec_));
-            }
-        }
-        add_gemm_stage(ST_XI, prec_, g, gx);
-        add_fft_stage(f, fx);
+        stage(ST_YI, w2c, tmid, w1, tmid, EPI_STORE, nullptr);
+        stage(ST_XI, w1c, tmid, outv, DT_F64, epi, &nb);
         return nb;
     };
     std::vector<long long> xi = minv(true, EPI_STORE);
@@ -406,6 +414,7 @@ int tpt_autotune(int count, const tpt_plan* plans, void* stream) {
         }
         (void)hipMemsetAsync(in, 0, bytes, s);
         for (int stage : {ST_XF, ST_YF}) {
+            if (stage_is_fast(p, stage)) continue;  // no GEMM in this pass
             const int dt = prec == GP_F64 ? DT_F64 : DT_F32;
             GemmDesc g = stage_gemm(p, stage, prec, in, dt, outb, dt, EPI_STORE, nullptr, 1);
             const int kind = stage == ST_XF ? 0 : 1;

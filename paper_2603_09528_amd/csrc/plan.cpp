@@ -93,9 +93,16 @@ std::shared_ptr<DirBasis> basis_cache_get(int ncells, const double* faces, int b
         const size_t o_lqinv = o_hqinv + al(2 * nn);
         const size_t o_hq = o_lqinv + al(2 * nn);
         const size_t o_lq = o_hq + al(2 * nn);
-        const bool fft = b->eig.analytic && op.periodic && fft_supported(n);
+        int fk = -1;
+        if (b->eig.analytic && fft_supported(n)) {
+            if (op.periodic) fk = UT_FOURIER;
+            else if (op.loc == LOC_C && op.bc_lo == BC_N && op.bc_hi == BC_N) fk = UT_DCT;
+            else if (op.loc == LOC_C && op.bc_lo == BC_D && op.bc_hi == BC_D) fk = UT_DST;
+        }
+        const bool fft = fk >= 0;
         const size_t o_tw = o_lq + al(2 * nn);
-        const size_t total = o_tw + (fft ? al(16 * (size_t)(n / 2)) : 0);
+        const size_t o_qtw = o_tw + (fft ? al(16 * (size_t)(n / 2)) : 0);
+        const size_t total = o_qtw + (fft ? al(16 * (size_t)(n / 2 + 1)) : 0);
         std::vector<char> host(total, 0);
         double* lam = (double*)(host.data() + o_lam);
         double* qinv = (double*)(host.data() + o_qinv);
@@ -116,15 +123,23 @@ std::shared_ptr<DirBasis> basis_cache_get(int ncells, const double* faces, int b
             }
         }
         if (fft) {
-            // twiddles of the length-n real transform, in long double
+            // twiddles of the length-n real transform and the quarter-wave
+            // factors of the cosine / sine transforms, in long double
             double* tw = (double*)(host.data() + o_tw);
+            double* qw = (double*)(host.data() + o_qtw);
             const long double pi = 3.14159265358979323846264338327950288L;
             for (int k = 0; k < n / 2; ++k) {
                 const long double a = 2.0L * pi * (long double)k / (long double)n;
                 tw[2 * k] = (double)std::cos(a);
                 tw[2 * k + 1] = (double)-std::sin(a);
             }
+            for (int k = 0; k <= n / 2; ++k) {
+                const long double a = pi * (long double)k / (2.0L * n);
+                qw[2 * k] = (double)std::cos(a);
+                qw[2 * k + 1] = (double)-std::sin(a);
+            }
         }
+        b->fast_kind = fk;
         b->h = op.vol[0];
         for (size_t e = 0; e < nn; ++e) {
             sqinv[e] = (float)qinv[e];
@@ -159,7 +174,10 @@ std::shared_ptr<DirBasis> basis_cache_get(int ncells, const double* faces, int b
         b->l_qinv = (uint16_t*)(d + o_lqinv);
         b->h_q = (uint16_t*)(d + o_hq);
         b->l_q = (uint16_t*)(d + o_lq);
-        if (fft) b->d_twiddle = (double2*)(d + o_tw);
+        if (fft) {
+            b->d_twiddle = (double2*)(d + o_tw);
+            b->d_qtw = (double2*)(d + o_qtw);
+        }
     }
     g_cache[key] = b;
     return b;
@@ -191,7 +209,7 @@ static size_t partial_slots(const tpt_plan_s* p) {
     long long res = 0;
     for (int r = 0; r < p->desc.nrhs; ++r) res += (p->dof + 255) / 256;
     long long xi = ((long long)p->N[1] * p->N[2] * p->desc.nrhs + 31) / 32 * ((p->N[0] + 63) / 64);
-    // the x-inverse transform: at most one block per line
+    // the x-inverse fast transform: at most one block per x line
     const long long fx = (long long)p->N[1] * p->N[2] * p->desc.nrhs;
     (void)dof;
     return (size_t)std::max(std::max(res, xi), fx) + 8;
@@ -200,7 +218,7 @@ static size_t partial_slots(const tpt_plan_s* p) {
 size_t plan_workspace_bytes(const tpt_plan_s* p) {
     const size_t n = (size_t)p->dof * p->desc.nrhs;
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    const size_t tsc = 8 * (size_t)thomas_scratch_doubles(p->N[0], p->N[1], p->N[2], p->desc.nrhs, DT_F64);
+    const size_t tsc = 8 * (size_t)thomas_scratch_doubles(p->N[0], p->N[1], p->N[2], p->desc.nrhs, p->op[2].periodic ? 1 : 0);
     const size_t main = (p->desc.precision == TPT_FP64) ? 2 * al(8 * n) + al(tsc) : al(tsc) + 3 * al(4 * n);
     return main + 16 * partial_slots(p) + 256;
 }
@@ -248,8 +266,6 @@ int tpt_plan_create(const tpt_plan_desc* desc, tpt_plan* out) {
         return fail(TPT_ERR_INVALID, "Helmholtz needs alpha > 0");
     if (desc->precision < TPT_FP64 || desc->precision > TPT_MIXED_BF16X3)
         return fail(TPT_ERR_INVALID, "unknown precision");
-    if (desc->bc[2][0] == TPT_BC_PERIODIC || desc->bc[2][1] == TPT_BC_PERIODIC)
-        return fail(TPT_ERR_UNSUPPORTED, "z (the Thomas direction) cannot be periodic");
     for (int d = 0; d < 3; ++d) {
         if (desc->n[d] < 2) return fail(TPT_ERR_INVALID, "need at least 2 cells per direction");
         if (!desc->faces[d]) return fail(TPT_ERR_INVALID, "faces pointer is NULL");
@@ -289,7 +305,10 @@ int tpt_plan_create(const tpt_plan_desc* desc, tpt_plan* out) {
         p->op[2].null_mode)
         p->null_line = p->bx->eig.null_index + p->N[0] * p->by->eig.null_index;
     p->info.null_line = p->null_line;
-    p->x_fft = !p->host_only && p->bx->d_twiddle && !(desc->flags & TPT_FLAG_DENSE_X);
+    if (!p->host_only) {
+        if (p->bx->fast_kind >= 0 && !(desc->flags & TPT_FLAG_DENSE_X)) p->fast[0] = p->bx->fast_kind;
+        if (p->by->fast_kind >= 0 && !(desc->flags & TPT_FLAG_DENSE_Y)) p->fast[1] = p->by->fast_kind;
+    }
     p->info.rel_residual = -1.0;
     if (!p->host_only) {
         const size_t nx = p->N[0], ny = p->N[1], nz = p->N[2];
@@ -360,9 +379,9 @@ int tpt_plan_operator(tpt_plan p, int dir, double* a, double* b, double* c, doub
     return TPT_OK;
 }
 
-int tpt_plan_x_fft(tpt_plan p, int* x_fft) {
-    if (!p || !x_fft) return fail(TPT_ERR_INVALID, "NULL argument");
-    *x_fft = p->x_fft ? 1 : 0;
+int tpt_plan_transforms(tpt_plan p, int kinds[2]) {
+    if (!p || !kinds) return fail(TPT_ERR_INVALID, "NULL argument");
+    for (int d = 0; d < 2; ++d) kinds[d] = p->fast[d] < 0 ? TPT_XFORM_GEMM : TPT_XFORM_FFT + p->fast[d];
     return TPT_OK;
 }
 

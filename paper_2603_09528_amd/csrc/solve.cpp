@@ -161,20 +161,40 @@ GemmDesc stage_gemm(const tpt_plan_s* p, int stage, int prec, const void* in, in
     return g;
 }
 
+bool stage_is_fast(const tpt_plan_s* p, int stage) {
+    return p->fast[(stage == ST_XF || stage == ST_XI) ? 0 : 1] >= 0;
+}
+
 FftDesc stage_fft(const tpt_plan_s* p, int stage, const void* in, int tin, void* out, int tout, int epi,
                   double* partials, int nrhs) {
+    const bool xdir = stage == ST_XF || stage == ST_XI;
+    const DirBasis* b = xdir ? p->bx.get() : p->by.get();
+    const int nx = p->N[0], ny = p->N[1], nz = p->N[2];
     FftDesc f{};
-    f.n = p->N[0];
-    f.lines = (long long)p->N[1] * p->N[2] * nrhs;
+    f.kind = p->fast[xdir ? 0 : 1];
+    f.inverse = (stage == ST_XI || stage == ST_YI) ? 1 : 0;
+    if (xdir) {
+        f.n = nx;
+        f.ylines = 0;
+        f.lines = (long long)ny * nz * nrhs;
+    } else {
+        // the columns of every z slab: line (slab, i) starts at slab nx ny + i
+        f.n = ny;
+        f.ylines = 1;
+        f.lines = (long long)nx * nz * nrhs;
+        f.inner = nx;
+        f.s_elem = nx;
+        f.s_outer = (long long)nx * ny;
+    }
     f.in = in;
     f.out = out;
     f.tin = tin;
     f.tout = tout;
     f.epi = epi;
-    f.inverse = stage == ST_XI ? 1 : 0;
     // forward Q^{-1} = sqrt(h) Q~^T, inverse Q = Q~ / sqrt(h) (uniform D = h I)
-    f.scale = f.inverse ? 1.0 / std::sqrt(p->bx->h) : std::sqrt(p->bx->h);
-    f.twiddle = p->bx->d_twiddle;
+    f.scale = f.inverse ? 1.0 / std::sqrt(b->h) : std::sqrt(b->h);
+    f.twiddle = b->d_twiddle;
+    f.qtw = b->d_qtw;
     f.partials = partials;
     return f;
 }
@@ -193,6 +213,7 @@ ThomasDesc plan_thomas(const tpt_plan_s* p, const void* f, int tf, void* x, int 
     t.sigma = p->sigma;
     t.tau = p->tau;
     t.pin_line = p->null_line;
+    t.periodic = p->op[2].periodic ? 1 : 0;
     t.f = f;
     t.tf = tf;
     t.x = x;
@@ -211,6 +232,7 @@ StencilDesc plan_stencil(const tpt_plan_s* p, const double* x, const double* f, 
     st.az = p->buf.az; st.bz = p->buf.bz; st.cz = p->buf.cz;
     st.perx = p->op[0].periodic ? 1 : 0;
     st.pery = p->op[1].periodic ? 1 : 0;
+    st.perz = p->op[2].periodic ? 1 : 0;
     st.helmholtz = p->desc.kind == TPT_HELMHOLTZ ? 1 : 0;
     st.alpha = p->desc.alpha;
     st.x = x;
@@ -245,18 +267,25 @@ static int run_gemm(const tpt_plan_s* p, int stage, int prec, const void* in, in
     return TPT_OK;
 }
 
-// x stages: the real-Fourier transform where the plan uses it, else the GEMM.
-static int run_x(const tpt_plan_s* p, int stage, int prec, const void* in, int tin, void* out, int tout, int epi,
-                 double* partials, int nrhs, hipStream_t s, long long* nblocks = nullptr) {
-    if (!p->x_fft) return run_gemm(p, stage, prec, in, tin, out, tout, epi, partials, nrhs, s, nblocks);
+static const char* fast_name(int stage, int tin, int tout) {
+    static const char* n[4][2] = {{"fft_x_fwd_f64", "fft_x_fwd_f32io"},
+                                  {"fft_y_fwd_f64", "fft_y_fwd_f32io"},
+                                  {"fft_y_inv_f64", "fft_y_inv_f32io"},
+                                  {"fft_x_inv_f64", "fft_x_inv_f32io"}};
+    return n[stage][(tin == DT_F64 && tout == DT_F64) ? 0 : 1];
+}
+
+// One transform stage: the fast transform where the plan uses one for that
+// direction, else the GEMM.
+static int run_stage(const tpt_plan_s* p, int stage, int prec, const void* in, int tin, void* out, int tout,
+                     int epi, double* partials, int nrhs, hipStream_t s, long long* nblocks = nullptr) {
+    if (!stage_is_fast(p, stage)) return run_gemm(p, stage, prec, in, tin, out, tout, epi, partials, nrhs, s, nblocks);
     FftDesc f = stage_fft(p, stage, in, tin, out, tout, epi, partials, nrhs);
     const long long nb = fft_blocks(f);
     if (nblocks) *nblocks = nb;
-    TimedScope ts(stage == ST_XF ? (tin == DT_F64 && tout == DT_F64 ? "fft_x_fwd_f64" : "fft_x_fwd_f32io")
-                                 : (tin == DT_F64 ? "fft_x_inv_f64" : "fft_x_inv_f32io"),
-                  s);
+    TimedScope ts(fast_name(stage, tin, tout), s);
     hipError_t e = launch_fft(f, nullptr, 0, nb, s);
-    if (e != hipSuccess) return fail(TPT_ERR_HIP, std::string("FFT launch: ") + hipGetErrorString(e));
+    if (e != hipSuccess) return fail(TPT_ERR_HIP, std::string("fast transform launch: ") + hipGetErrorString(e));
     return TPT_OK;
 }
 
@@ -277,7 +306,7 @@ Ws carve(const tpt_plan_s* p, void* ws) {
     w.n = (size_t)p->dof * p->desc.nrhs;
     const size_t n = w.n;
     size_t o = 0;
-    const size_t tsc = 8 * (size_t)thomas_scratch_doubles(p->N[0], p->N[1], p->N[2], p->desc.nrhs, DT_F64);
+    const size_t tsc = 8 * (size_t)thomas_scratch_doubles(p->N[0], p->N[1], p->N[2], p->desc.nrhs, p->op[2].periodic ? 1 : 0);
     if (p->desc.precision == TPT_FP64) {
         w.w1 = w.base + o; o += al256(8 * n);
         w.w2 = w.base + o; o += al256(8 * n);
@@ -302,11 +331,11 @@ long long plan_residual_blocks(const tpt_plan_s* p) {
 static int solve_fp64(tpt_plan_s* p, const double* rhs, double* out, const Ws& w, hipStream_t s) {
     const int R = p->desc.nrhs;
     int rc;
-    if ((rc = run_x(p, ST_XF, GP_F64, rhs, DT_F64, w.w1, DT_F64, EPI_STORE, nullptr, R, s))) return rc;
-    if ((rc = run_gemm(p, ST_YF, GP_F64, w.w1, DT_F64, w.w2, DT_F64, EPI_STORE, nullptr, R, s))) return rc;
+    if ((rc = run_stage(p, ST_XF, GP_F64, rhs, DT_F64, w.w1, DT_F64, EPI_STORE, nullptr, R, s))) return rc;
+    if ((rc = run_stage(p, ST_YF, GP_F64, w.w1, DT_F64, w.w2, DT_F64, EPI_STORE, nullptr, R, s))) return rc;
     if ((rc = run_thomas(p, w.w2, DT_F64, w.w2, DT_F64, w.scratch, R, s))) return rc;
-    if ((rc = run_gemm(p, ST_YI, GP_F64, w.w2, DT_F64, w.w1, DT_F64, EPI_STORE, nullptr, R, s))) return rc;
-    if ((rc = run_x(p, ST_XI, GP_F64, w.w1, DT_F64, out, DT_F64, EPI_STORE, nullptr, R, s))) return rc;
+    if ((rc = run_stage(p, ST_YI, GP_F64, w.w2, DT_F64, w.w1, DT_F64, EPI_STORE, nullptr, R, s))) return rc;
+    if ((rc = run_stage(p, ST_XI, GP_F64, w.w1, DT_F64, out, DT_F64, EPI_STORE, nullptr, R, s))) return rc;
     p->info.iters = 0;
     p->info.rel_correction = 0.0;
     p->info.rel_residual = -1.0;
@@ -320,11 +349,11 @@ static int apply_minv(tpt_plan_s* p, int prec, const void* in, int tin, double* 
                       hipStream_t s, long long* xi_blocks) {
     const int R = p->desc.nrhs;
     int rc;
-    if ((rc = run_x(p, ST_XF, prec, in, tin, w.w1, DT_F32, EPI_STORE, nullptr, R, s))) return rc;
-    if ((rc = run_gemm(p, ST_YF, prec, w.w1, DT_F32, w.w2, DT_F32, EPI_STORE, nullptr, R, s))) return rc;
+    if ((rc = run_stage(p, ST_XF, prec, in, tin, w.w1, DT_F32, EPI_STORE, nullptr, R, s))) return rc;
+    if ((rc = run_stage(p, ST_YF, prec, w.w1, DT_F32, w.w2, DT_F32, EPI_STORE, nullptr, R, s))) return rc;
     if ((rc = run_thomas(p, w.w2, DT_F32, w.w2, DT_F32, w.scratch, R, s))) return rc;
-    if ((rc = run_gemm(p, ST_YI, prec, w.w2, DT_F32, w.w1, DT_F32, EPI_STORE, nullptr, R, s))) return rc;
-    if ((rc = run_x(p, ST_XI, prec, w.w1, DT_F32, out, DT_F64, epi, w.partials, R, s, xi_blocks))) return rc;
+    if ((rc = run_stage(p, ST_YI, prec, w.w2, DT_F32, w.w1, DT_F32, EPI_STORE, nullptr, R, s))) return rc;
+    if ((rc = run_stage(p, ST_XI, prec, w.w1, DT_F32, out, DT_F64, epi, w.partials, R, s, xi_blocks))) return rc;
     return TPT_OK;
 }
 
@@ -450,15 +479,16 @@ int tpt_solve_info(tpt_plan plan, tpt_info* info) {
 }
 
 int tpt_thomas(int nx, int ny, int nz, int nsys, const double* lamx, const double* lamy, const double* az,
-               const double* bz, const double* cz, double sigma, double tau, int pin_line, const double* f, double* x,
-               double* scratch, void* stream) {
+               const double* bz, const double* cz, int periodic_z, double sigma, double tau, int pin_line,
+               const double* f, double* x, double* scratch, void* stream) {
     if (nx < 1 || ny < 1 || nz < 1 || nsys < 1) return fail(TPT_ERR_INVALID, "bad sizes");
+    if (periodic_z && nz < 2) return fail(TPT_ERR_INVALID, "cyclic lines need nz >= 2");
     if (!lamx || !lamy || !az || !bz || !cz || !f || !x || !scratch) return fail(TPT_ERR_INVALID, "NULL pointer");
     if (pin_line >= nx * ny) return fail(TPT_ERR_INVALID, "pin_line out of range");
     ThomasDesc t{};
     t.nx = nx; t.ny = ny; t.nz = nz; t.nsys = nsys;
     t.lamx = lamx; t.lamy = lamy; t.az = az; t.bz = bz; t.cz = cz;
-    t.sigma = sigma; t.tau = tau; t.pin_line = pin_line;
+    t.sigma = sigma; t.tau = tau; t.pin_line = pin_line; t.periodic = periodic_z ? 1 : 0;
     t.f = f; t.tf = DT_F64; t.x = x; t.tx = DT_F64; t.scratch = scratch;
     TimedScope ts("thomas_f64", (hipStream_t)stream);
     hipError_t e = launch_thomas(t, (hipStream_t)stream);

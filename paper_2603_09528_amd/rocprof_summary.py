@@ -1,6 +1,7 @@
 """Summarise rocprofv3 output (the rocpd SQLite database it writes) as text.
 
     python -m paper_2603_09528_amd.rocprof_summary RESULTS.db [--command "..."]
+    python -m paper_2603_09528_amd.rocprof_summary traffic FETCH.db WRITE.db --stages a,b,...
 
 Prints a markdown table of kernel dispatches (calls, total / average / min /
 max duration, share of GPU time) and, if the run collected counters
@@ -17,8 +18,9 @@ from collections import defaultdict
 
 
 def short_name(name: str) -> str:
-    n = re.sub(r"\(.*$", "", name) if not name.startswith("void ") else name[5:]
-    n = re.sub(r"\(.*$", "", n)
+    n = name[5:] if name.startswith("void ") else name
+    n = n.replace("(anonymous namespace)::", "")
+    n = re.sub(r"\(.*$", "", n)  # drop the argument list
     return n[:110]
 
 
@@ -64,7 +66,68 @@ def counters(db: str):
     return res
 
 
+def dispatch_counter(db: str, counter: str):
+    """[(dispatch_id, kernel_name, value)] of one counter, in dispatch order
+    (values summed over the dimensions rocprofv3 reports them in)."""
+    c = sqlite3.connect(db)
+    agg = {}
+    for disp, kname, val in c.execute(
+            "select dispatch_id, kernel_name, value from counters_collection where counter_name = ?", (counter,)):
+        k = agg.setdefault(disp, [kname, 0.0])
+        k[1] += float(val)
+    return [(d, v[0], v[1]) for d, v in sorted(agg.items())]
+
+
+def traffic(fetch_db: str, write_db: str, stages, lib_pattern: str, copy_pattern: str, copy_bytes: float):
+    """HBM bytes per launch of the library's kernels from two --pmc runs
+    (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch), each scaled by the ratio
+    of the known size of a plain copy kernel to what the same counter reads
+    for it.  Library dispatches are labelled with `stages` in launch order
+    (one solve = one cycle of stages)."""
+    out = {"copy_bytes": copy_bytes, "kernels": {}}
+    for which, db, cname in (("fetch", fetch_db, "FETCH_SIZE"), ("write", write_db, "WRITE_SIZE")):
+        rows = dispatch_counter(db, cname)
+        copies = [v for _, k, v in rows if re.search(copy_pattern, k)]
+        if not copies:
+            raise SystemExit(f"no copy-kernel dispatch matching {copy_pattern!r} in {db}")
+        kib = sorted(copies)[len(copies) // 2]  # median over the calibration copies
+        scale = copy_bytes / kib                # bytes per counted KiB
+        out[f"{which}_scale_bytes_per_kib"] = scale
+        out[f"copy_{which}_kib"] = kib
+        lib = [(k, v) for _, k, v in rows if re.search(lib_pattern, k)]
+        for i, (k, v) in enumerate(lib):
+            name = stages[i % len(stages)]
+            e = out["kernels"].setdefault(name, {"symbol": short_name(k)})
+            e.setdefault(which, []).append(v * scale)
+    for name, e in out["kernels"].items():
+        for which in ("fetch", "write"):
+            vals = e.pop(which, [])
+            e[f"{which}_bytes_per_launch"] = sum(vals) / len(vals) if vals else None
+            e[f"{which}_launches"] = len(vals)
+        if e["fetch_bytes_per_launch"] is not None and e["write_bytes_per_launch"] is not None:
+            e["hbm_bytes_per_launch"] = e["fetch_bytes_per_launch"] + e["write_bytes_per_launch"]
+    return out
+
+
 def main(argv=None):
+    argv = sys.argv[1:] if argv is None else argv
+    if argv and argv[0] == "traffic":
+        import json
+        ap = argparse.ArgumentParser(prog="rocprof_summary traffic")
+        ap.add_argument("fetch_db")
+        ap.add_argument("write_db")
+        ap.add_argument("--stages", required=True, help="comma-separated stage names in launch order")
+        ap.add_argument("--lib-pattern", default=r"tpt::")
+        ap.add_argument("--copy-pattern", default=r"elementwise")
+        ap.add_argument("--copy-bytes", type=float, default=float(1 << 30))
+        ap.add_argument("--kernel-hash", default="")
+        ap.add_argument("--command", default="")
+        a = ap.parse_args(argv[1:])
+        res = traffic(a.fetch_db, a.write_db, a.stages.split(","), a.lib_pattern, a.copy_pattern, a.copy_bytes)
+        res["kernels_hip_sha256_16"] = a.kernel_hash
+        res["command"] = a.command
+        print(json.dumps(res, indent=1))
+        return 0
     ap = argparse.ArgumentParser()
     ap.add_argument("db")
     ap.add_argument("--command", default="")

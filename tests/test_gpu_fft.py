@@ -1,6 +1,7 @@
-"""The real-Fourier x transform (uniform periodic x, power-of-two N_x): solves
-through it against the CPU oracle, against the dense-GEMM x pass of the same
-plan, inside batches next to GEMM plans, and the selection rule itself."""
+"""Fast transforms of uniform directions (real Fourier, DCT-II, DST-II along x
+and along y, power-of-two N): solves through them against the CPU oracle,
+against the dense-GEMM passes of the same plan, inside batches next to GEMM
+plans, and the selection rule itself."""
 import numpy as np
 import pytest
 
@@ -115,8 +116,11 @@ def test_fft_selection_rule():
     assert not T.Plan.from_problem(_prob(4, 4, 4)).x_fft           # below 8
     assert not T.Plan.from_problem(_prob(4096, 2, 2)).x_fft        # above 2048
     assert not T.Plan.from_problem(_stretched_x(_prob(32, 4, 4))).x_fft           # stretched
-    q = W.make_problem((32, 4, 4), (0.0, 0.0, 0.0), (W.NN, W.PP, W.DD))
-    assert not T.Plan.from_problem(q).x_fft                          # x not periodic
+    q = W.make_problem((32, 4, 4), (1.0, 0.0, 0.0), (W.NN, W.PP, W.DD))
+    assert T.Plan.from_problem(q).transforms == ("gemm", "gemm")     # stretched NN x; y below 8
+    q = W.make_problem((32, 16, 4), (0.0, 0.0, 0.0), (("N", "D"), W.DD, W.DD))
+    assert T.Plan.from_problem(q).transforms == ("gemm", "dst")      # mixed N/D x: no fast form
+    assert T.Plan.from_problem(q, dense_y=True).transforms == ("gemm", "gemm")
 
 
 def test_fft_nrhs_and_repeat():
@@ -143,6 +147,95 @@ def test_batch_mixing_fft_and_gemm_plans(prec, fixed):
     plans = [T.Plan.from_problem(p, **kw) for p in probs]
     assert [pl.x_fft for pl in plans] == [True, False, True, False, True]
     fs = [W.rhs(p, 60 + i) for i, p in enumerate(probs)]
+    rhs = [cuda(f) for f in fs]
+    outs = [torch.empty_like(r) for r in rhs]
+    batch = T.Batch(plans)
+    for use_graph in (False, True):
+        for o in outs:
+            o.zero_()
+        batch.solve(rhs, outs, use_graph=use_graph)
+        torch.cuda.synchronize()
+        for i, p in enumerate(probs):
+            single = host(plans[i].solve(rhs[i]))
+            assert np.array_equal(host(outs[i]), single), (i, use_graph)
+            err = O.relative_error(p, single, O.solve(p, fs[i]))
+            assert err <= (FP64_TOL if prec == "fp64" else MIXED_TOL), (i, err)
+
+
+# (cells, bc, loc, kind, beta, expected (x, y) transforms)
+KIND_CASES = [
+    ((64, 32, 9), (W.PP, W.NN, W.NN), ("C", "C", "C"), "poisson", (0, 0, 1.5), ("fft", "dct")),
+    ((32, 64, 7), (W.NN, W.DD, W.DD), ("C", "C", "C"), "poisson", (0, 0, 1.5), ("dct", "dst")),
+    ((16, 128, 5), (W.DD, W.PP, ("D", "N")), ("C", "C", "C"), "helmholtz", (0, 0, 2.0), ("dst", "fft")),
+    ((128, 16, 6), (W.DD, W.NN, W.NN), ("C", "C", "C"), "helmholtz", (0, 0, 1.0), ("dst", "dct")),
+    ((8, 256, 3), (W.NN, W.PP, W.DD), ("C", "C", "F"), "poisson", (0, 0, 1.0), ("dct", "fft")),
+    ((32, 32, 8), (W.NN, W.NN, W.NN), ("C", "C", "C"), "poisson", (0, 0, 0.0), ("dct", "dct")),
+    ((64, 16, 10), (W.PP, W.PP, W.NN), ("C", "C", "C"), "poisson", (0, 0, 2.5), ("fft", "fft")),
+    ((48, 64, 5), (W.NN, W.NN, W.DD), ("C", "C", "C"), "poisson", (0, 0, 1.5), ("gemm", "dct")),
+    ((64, 33, 5), (W.NN, W.DD, W.NN), ("C", "F", "C"), "helmholtz", (0, 0, 1.5), ("dct", "gemm")),
+    ((512, 8, 4), (W.NN, W.DD, W.NN), ("C", "C", "C"), "poisson", (0, 0, 1.5), ("dct", "dst")),
+    ((8, 512, 4), (W.DD, W.NN, W.NN), ("C", "C", "C"), "helmholtz", (0, 0, 1.5), ("dst", "dct")),
+]
+
+
+def _kind_problem(case):
+    n, bc, loc, kind, beta, _ = case
+    return W.make_problem(n, beta, bc, loc=loc, kind=kind, alpha=1e-3 if kind == "helmholtz" else 0.0)
+
+
+def _kid(c):
+    return f"{c[0][0]}x{c[0][1]}x{c[0][2]}-{c[5][0]}-{c[5][1]}"
+
+
+@pytest.mark.parametrize("case", KIND_CASES, ids=_kid)
+def test_transform_kinds_match_oracle(case):
+    p = _kind_problem(case)
+    f = W.rhs(p, 71)
+    say("kinds fp64", p.n, p.bc, p.loc, case[5])
+    got, plan = _solve(p, f)
+    assert plan.transforms == case[5]
+    ref = O.solve(p, f)
+    err = O.relative_error(p, got, ref)
+    assert err <= FP64_TOL, err
+
+
+@pytest.mark.parametrize("case", KIND_CASES[:4], ids=_kid)
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_transform_kinds_mixed_match_oracle(case, prec):
+    p = _kind_problem(case)
+    f = W.rhs(p, 72)
+    say("kinds mixed", prec, p.n, case[5])
+    got, plan = _solve(p, f, precision=prec, rtol=1e-13, max_refine=12)
+    assert plan.transforms == case[5]
+    err = O.relative_error(p, got, O.solve(p, f))
+    say("  iters", plan.info().iters, "err", err)
+    assert err <= MIXED_TOL, err
+
+
+@pytest.mark.parametrize("ny,bcy,want", [(1024, W.NN, "dct"), (2048, W.DD, "dst"), (1024, W.PP, "fft")])
+def test_long_y_lines_match_dense_y(ny, bcy, want):
+    p = W.make_problem((12, ny, 4), (0, 0, 1.5), (W.DD, bcy, W.DD), kind="helmholtz", alpha=1e-3)
+    f = W.rhs(p, 73)
+    say("y fast vs dense", p.n, want)
+    a, pa = _solve(p, f)
+    b, pb = _solve(p, f, dense_y=True)
+    assert pa.transforms[1] == want and pb.transforms[1] == "gemm"
+    assert np.linalg.norm(a - b) / np.linalg.norm(b) <= FP64_TOL
+    r = O.residual(p, f, a)
+    eta = np.abs(r).max() / (_norm_inf_bound(p) * np.abs(a).max() + np.abs(f).max())
+    say("  backward error", eta)
+    assert eta <= 5e-14, eta
+
+
+@pytest.mark.parametrize("prec,fixed", [("fp64", -1), ("fp32", 3)])
+def test_batch_mixing_all_transform_kinds(prec, fixed):
+    import torch
+    T = _T()
+    probs = [_kind_problem(c) for c in KIND_CASES[:9]]
+    kw = dict(precision=prec, fixed_refine=fixed) if prec != "fp64" else {}
+    plans = [T.Plan.from_problem(p, **kw) for p in probs]
+    assert [pl.transforms for pl in plans] == [c[5] for c in KIND_CASES[:9]]
+    fs = [W.rhs(p, 80 + i) for i, p in enumerate(probs)]
     rhs = [cuda(f) for f in fs]
     outs = [torch.empty_like(r) for r in rhs]
     batch = T.Batch(plans)

@@ -106,9 +106,9 @@ def test_analytic_uniform_bases(bc, loc):
 def test_invalid_arguments_rejected():
     T = _lib()
     f = W.tanh_faces(8, 1.0)
-    with pytest.raises(T.TptError) as ei:
-        T.Plan((8, 8, 8), (f, f, f), (W.NN, W.NN, W.PP), host_only=True)
-    assert ei.value.code == -2  # periodic z unsupported
+    T.Plan((8, 8, 8), (f, f, f), (W.NN, W.NN, W.PP), host_only=True)  # periodic z: cyclic lines
+    with pytest.raises(T.TptError):
+        T.Plan((8, 8, 8), (f, f, f), (W.NN, W.NN, ("P", "N")), host_only=True)
     with pytest.raises(T.TptError):
         T.Plan((8, 8, 8), (f, f[::-1].copy(), f), (W.NN, W.NN, W.NN), host_only=True)
     with pytest.raises(T.TptError):
@@ -143,3 +143,31 @@ def test_timing_collect_empty():
     T = _lib()
     T.timing_enable(False)
     assert T.timing_collect() == {}
+
+
+def test_host_only_plan_reports_dense_transforms():
+    # fast transforms need device twiddle tables: a host-only plan has none
+    T = _lib()
+    p = W.make_problem((64, 32, 8), (0.0, 0.0, 1.0), (W.PP, W.NN, W.NN))
+    assert T.Plan.from_problem(p, host_only=True).transforms == ("gemm", "gemm")
+
+
+@pytest.mark.parametrize("bc", [W.NN, W.DD])
+def test_analytic_cosine_sine_bases_large_n(bc):
+    # closed forms with the angle reduced exactly in integers: c_k cos(pi k (2i+1)/2N)
+    # (Neumann) and c_k sin(pi k (2i+1)/2N), k = 1..N (Dirichlet), cell centres
+    T = _lib()
+    n = 1024
+    faces = [W.tanh_faces(n, 0.0, 1.0), W.tanh_faces(4, 1.0), W.tanh_faces(4, 1.0)]
+    plan = T.Plan((n, 4, 4), faces, (bc, W.NN, W.NN), host_only=True)
+    _, Qt = plan.eigen(0)
+    i = np.arange(n)[:, None]
+    if bc == W.NN:
+        k = np.arange(n)[None, :]
+        c = np.where(k == 0, np.sqrt(1.0 / n), np.sqrt(2.0 / n))
+        ref = c * np.cos(np.pi * ((k * (2 * i + 1)) % (4 * n)) / (2 * n))
+    else:
+        k = np.arange(1, n + 1)[None, :]
+        c = np.where(k == n, np.sqrt(1.0 / n), np.sqrt(2.0 / n))
+        ref = c * np.sin(np.pi * ((k * (2 * i + 1)) % (4 * n)) / (2 * n))
+    assert np.abs(Qt - ref).max() <= 4e-16

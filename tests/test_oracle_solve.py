@@ -1,7 +1,8 @@
 """Pins of the oracle's tensor-product--Thomas solve.
 
 * Thomas lines against a dense solve of each line (brute force), and the
-  gauge pin of §3 on a singular line;
+  gauge pin of §3 on a singular line (also for the cyclic lines of a
+  periodic z);
 * the whole solve against the plain definition x = A^{-1} f (dense LU of the
   assembled operator, bordered for singular problems) on grids up to 12^3,
   over boundary conditions, staggering, stretching and Poisson/Helmholtz;
@@ -55,6 +56,8 @@ BCS = [
     (W.PP, W.PP, W.DD),
     (W.DD, ("N", "D"), ("D", "N")),
     (("N", "D"), W.PP, W.NN),
+    (W.NN, W.DD, W.PP),
+    (W.PP, W.PP, W.PP),
 ]
 
 
@@ -68,6 +71,26 @@ def test_solve_matches_dense_lu(bc, kind, alpha, n, beta):
     x = O.solve(p, f)
     ref = O.solve_dense(p, f)
     assert O.relative_error(p, x, ref) <= 5e-14
+
+
+def test_cyclic_lines_pinned_singular_line():
+    # periodic z, zero shift: the cyclic T_z is singular; the pinned line has
+    # its last unknown zero and satisfies every equation but the last
+    nz = 10
+    az, bz, cz, _ = O.operator_1d(W.tanh_faces(nz, 0.0), W.PP, "C")
+    rng = np.random.default_rng(3)
+    rhs = rng.standard_normal((nz, 1, 2))
+    rhs[:, 0, 0] -= rhs[:, 0, 0].mean()
+    lam = np.array([[0.0, -3.0]])
+    x = O.solver.cyclic_lines(az, bz, cz, lam, 0.0, 1.0, rhs, pin=(0, 0))
+    Tz = O.dense_1d(az, bz, cz, True)
+    assert x[-1, 0, 0] == 0.0
+    r = Tz @ x[:, 0, 0] - rhs[:, 0, 0]
+    assert np.abs(r[:-1]).max() <= 1e-12 * np.abs(rhs).max()
+    # a compatible right-hand side satisfies the dropped equation too
+    assert abs(r[-1]) <= 1e-12 * np.abs(rhs).max()
+    r2 = (Tz - 3.0 * np.eye(nz)) @ x[:, 0, 1] - rhs[:, 0, 1]
+    assert np.abs(r2).max() <= 1e-12 * np.abs(rhs).max()
 
 
 @pytest.mark.parametrize("loc", [("F", "C", "C"), ("C", "F", "C"), ("C", "C", "F"), ("F", "F", "F")])
@@ -133,7 +156,16 @@ def _mk_pnn(n):
     return p, -(4 + 1 + 1) * np.pi ** 2 * u, u
 
 
-@pytest.mark.parametrize("make", [_mk_nn, _mk_dd_helm, _mk_pnn], ids=["nnn", "ddd_helm", "pnn"])
+def _mk_nnp(n):
+    # u = cos(pi x) cos(pi y) sin(2 pi z), z periodic (x, y stretched)
+    p = W.make_problem((n, n, n), (1.5, 2.0, 0.0), (W.NN, W.NN, W.PP))
+    xs = [W.centres(p.faces[d], p.bc[d], "C") for d in range(3)]
+    u = (np.sin(2 * np.pi * xs[2])[:, None, None] * np.cos(np.pi * xs[1])[None, :, None]
+         * np.cos(np.pi * xs[0])[None, None, :])
+    return p, -(1 + 1 + 4) * np.pi ** 2 * u, u
+
+
+@pytest.mark.parametrize("make", [_mk_nn, _mk_dd_helm, _mk_pnn, _mk_nnp], ids=["nnn", "ddd_helm", "pnn", "nnp"])
 def test_mms_second_order(make):
     e = _mms_errors(make, [16, 32, 64])
     order_l2 = np.log2(e[:-1, 0] / e[1:, 0])
