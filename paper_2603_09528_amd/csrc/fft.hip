@@ -40,11 +40,15 @@ namespace {
 constexpr int UT_NT = 256;
 constexpr int UT_LDS_DOUBLES = 4096;  // 32 KB per block: up to 5 blocks (20 waves) per CU
 
+// Lines per block: 32 KB of line data (at most 64 lines); one line for
+// N = 2048, whose twiddle tables take another 32 KB.
 __host__ __device__ inline int ut_lines_per_block(int n) {
+    if (n > 1024) return 1;
     const int l = UT_LDS_DOUBLES / n;
     return l > 64 ? 64 : l;
 }
 
+__device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }
 __device__ __forceinline__ int bitrev(int v, int bits) { return (int)(__brev((unsigned)v) >> (32 - bits)); }
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
@@ -55,23 +59,60 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_doub
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
 
-// Offset of element e of line `line` (line index within the descriptor).
-__device__ __forceinline__ long long ut_offset(const FftDesc& d, long long line, int e) {
-    if (!d.ylines) return line * (long long)d.n + e;
-    const long long slab = line / d.inner, col = line - slab * d.inner;
-    return slab * d.s_outer + col + (long long)e * d.s_elem;
+// Block geometry.  All sizes are powers of two, so work items map to (line,
+// index) with shifts and masks.  Strided (y) lines: a thread always serves
+// the same line (lpb divides the block size), whose start is computed once.
+struct UtGeom {
+    int N, M, nlog, mlog, lpb, llog;
+    long long line0;
+    int ly;          // y lines: this thread's line in the block
+    long long ybase; // y lines: offset of element 0 of that line
+    bool yvalid;
+};
+
+__device__ __forceinline__ UtGeom ut_geom(const FftDesc& d, long long blk) {
+    UtGeom g;
+    g.N = d.n;
+    g.M = d.n >> 1;
+    g.nlog = ilog2(g.N);
+    g.mlog = g.nlog - 1;
+    g.lpb = ut_lines_per_block(g.N);
+    g.llog = ilog2(g.lpb);
+    g.line0 = blk << g.llog;
+    g.ly = threadIdx.x & (g.lpb - 1);
+    g.ybase = 0;
+    g.yvalid = false;
+    if (d.ylines) {
+        const long long line = g.line0 + g.ly;
+        g.yvalid = line < d.lines;
+        if (g.yvalid) {
+            const long long slab = line / d.inner;
+            g.ybase = slab * d.s_outer + (line - slab * d.inner);
+        }
+    }
+    return g;
 }
 
-// Work item idx -> (line in block l, index e) for cnt items per line: the
-// index runs fastest for contiguous lines, the line for strided lines.
-__device__ __forceinline__ void ut_map(int ylines, int lpb, int cnt, int idx, int& l, int& e) {
-    if (ylines) {
-        l = idx % lpb;
-        e = idx / lpb;
+// Work item idx with 2^clog items per line -> line in block l and index e:
+// the index runs fastest for contiguous lines, the line for strided lines.
+__device__ __forceinline__ void ut_item(const FftDesc& d, const UtGeom& g, int clog, int idx, int& l, int& e) {
+    if (d.ylines) {
+        l = idx & (g.lpb - 1);
+        e = idx >> g.llog;
     } else {
-        l = idx / cnt;
-        e = idx - l * cnt;
+        l = idx >> clog;
+        e = idx & ((1 << clog) - 1);
     }
+}
+
+__device__ __forceinline__ bool ut_valid(const FftDesc& d, const UtGeom& g, int l) {
+    return d.ylines ? g.yvalid : (g.line0 + l) < d.lines;
+}
+
+// Offset of element e of block line l.
+__device__ __forceinline__ long long ut_off(const FftDesc& d, const UtGeom& g, int l, int e) {
+    if (d.ylines) return g.ybase + (long long)e * d.s_elem;
+    return ((g.line0 + l) << g.nlog) + e;
 }
 
 // Position in v (the sequence whose real FFT is taken) of line element e.
@@ -82,17 +123,19 @@ __device__ __forceinline__ int ut_vpos(int kind, int n, int e) {
 
 // Forward radix-2 decimation in time over M points per line (bit-reversed
 // in, natural out).
-__device__ __forceinline__ void ut_dit(double2* lds, int lpb, int M, int N, const double2* __restrict__ W) {
-    const int g = UT_NT / lpb;  // threads per line
-    const int l = threadIdx.x / g, t = threadIdx.x - l * g;
-    double2* a = lds + (size_t)l * M;
-    for (int L = 2; L <= M; L <<= 1) {
-        const int half = L >> 1, tstep = N / L;
-        for (int b = t; b < (M >> 1); b += g) {
-            const int grp = b / half, pos = b - grp * half;
-            const int i0 = grp * L + pos, i1 = i0 + half;
+__device__ __forceinline__ void ut_dit(double2* lds, const UtGeom& g, const double2* __restrict__ W) {
+    const int glog = 8 - g.llog;  // threads per line: 256 / lpb
+    const int l = threadIdx.x >> glog, t = threadIdx.x & ((1 << glog) - 1);
+    double2* a = lds + ((size_t)l << g.mlog);
+    const int nb = g.M >> 1;
+    for (int hlog = 0; hlog < g.mlog; ++hlog) {
+        const int half = 1 << hlog, wsh = g.nlog - hlog - 1;  // twiddle stride N / L, L = 2 half
+#pragma unroll 4
+        for (int b = t; b < nb; b += (1 << glog)) {
+            const int pos = b & (half - 1);
+            const int i0 = ((b >> hlog) << (hlog + 1)) + pos, i1 = i0 + half;
             const double2 u = a[i0];
-            const double2 v = cmul(a[i1], W[pos * tstep]);
+            const double2 v = cmul(a[i1], W[pos << wsh]);
             a[i0] = cadd(u, v);
             a[i1] = csub(u, v);
         }
@@ -102,35 +145,50 @@ __device__ __forceinline__ void ut_dit(double2* lds, int lpb, int M, int N, cons
 
 // Inverse complex FFT (conjugate twiddles), decimation in frequency: natural
 // in, bit-reversed out, unnormalised.
-__device__ __forceinline__ void ut_dif_inv(double2* lds, int lpb, int M, int N, const double2* __restrict__ W) {
-    const int g = UT_NT / lpb;
-    const int l = threadIdx.x / g, t = threadIdx.x - l * g;
-    double2* a = lds + (size_t)l * M;
-    for (int L = M; L >= 2; L >>= 1) {
-        const int half = L >> 1, tstep = N / L;
-        for (int b = t; b < (M >> 1); b += g) {
-            const int grp = b / half, pos = b - grp * half;
-            const int i0 = grp * L + pos, i1 = i0 + half;
+__device__ __forceinline__ void ut_dif_inv(double2* lds, const UtGeom& g, const double2* __restrict__ W) {
+    const int glog = 8 - g.llog;
+    const int l = threadIdx.x >> glog, t = threadIdx.x & ((1 << glog) - 1);
+    double2* a = lds + ((size_t)l << g.mlog);
+    const int nb = g.M >> 1;
+    for (int hlog = g.mlog - 1; hlog >= 0; --hlog) {
+        const int half = 1 << hlog, wsh = g.nlog - hlog - 1;
+#pragma unroll 4
+        for (int b = t; b < nb; b += (1 << glog)) {
+            const int pos = b & (half - 1);
+            const int i0 = ((b >> hlog) << (hlog + 1)) + pos, i1 = i0 + half;
             const double2 u = a[i0];
             const double2 v = a[i1];
             a[i0] = cadd(u, v);
-            a[i1] = cmul(csub(u, v), conj2(W[pos * tstep]));
+            a[i1] = cmul(csub(u, v), conj2(W[pos << wsh]));
         }
         __syncthreads();
     }
 }
 
+// Copy the twiddle tables of the descriptor into LDS (after the line data):
+// W^k (k < N/2) and, for the cosine and sine transforms, e^{-i pi k/2N}
+// (k <= N/2).  Returns the LDS copies; the caller synchronises.
+__device__ __forceinline__ void ut_tables(const FftDesc& d, const UtGeom& g, double2* lds, double2*& W,
+                                          double2*& Q) {
+    W = lds + ((size_t)g.lpb << g.mlog);
+    Q = W + g.M;
+    for (int k = threadIdx.x; k < g.M; k += UT_NT) W[k] = d.twiddle[k];
+    if (d.kind != UT_FOURIER)
+        for (int k = threadIdx.x; k <= g.M; k += UT_NT) Q[k] = d.qtw[k];
+}
+
 template <typename TI, typename TO>
 __device__ __forceinline__ void ut_forward(const FftDesc& d, long long blk, double2* lds) {
-    const int N = d.n, M = N >> 1, bits = 31 - __clz(M), kind = d.kind;
-    const int lpb = ut_lines_per_block(N);
-    const long long line0 = blk * lpb;
+    const UtGeom g = ut_geom(d, blk);
+    double2 *W, *Q;
+    ut_tables(d, g, lds, W, Q);
+    const int N = g.N, M = g.M, bits = g.mlog, kind = d.kind;
     const TI* in = (const TI*)d.in;
     TO* out = (TO*)d.out;
     double* ldsd = (double*)lds;
     // 1) load into bit-reversed complex slots (v_j -> slot j/2, part j%2);
     //    eight loads in flight per thread before the LDS stores
-    const int total = lpb * N;
+    const int total = g.lpb << g.nlog;
     for (int base = 0; base < total; base += 8 * UT_NT) {
         double v[8];
         int pos[8];
@@ -138,15 +196,14 @@ __device__ __forceinline__ void ut_forward(const FftDesc& d, long long blk, doub
         for (int u = 0; u < 8; ++u) {
             const int idx = base + u * UT_NT + (int)threadIdx.x;
             int l, e;
-            ut_map(d.ylines, lpb, N, idx, l, e);
-            const long long line = line0 + l;
+            ut_item(d, g, g.nlog, idx, l, e);
             pos[u] = -1;
             v[u] = 0.0;
-            if (idx < total && line < d.lines) {
-                double x = (double)in[ut_offset(d, line, e)];
+            if (idx < total && ut_valid(d, g, l)) {
+                double x = (double)in[ut_off(d, g, l, e)];
                 if (kind == UT_DST && (e & 1)) x = -x;
                 const int j = ut_vpos(kind, N, e);
-                pos[u] = l * N + 2 * bitrev(j >> 1, bits) + (j & 1);
+                pos[u] = (l << g.nlog) + 2 * bitrev(j >> 1, bits) + (j & 1);
                 v[u] = x;
             }
         }
@@ -156,46 +213,44 @@ __device__ __forceinline__ void ut_forward(const FftDesc& d, long long blk, doub
     }
     __syncthreads();
     // 2) complex FFT
-    ut_dit(lds, lpb, M, N, d.twiddle);
-    // 3) half spectrum and outputs, from LDS straight to memory
+    ut_dit(lds, g, W);
+    // 3) half spectrum and outputs, from LDS straight to memory; item m = 0
+    //    also writes the output of V_M
     const double s = d.scale;
-    const int cnt = M + 1;
-    for (int idx = threadIdx.x; idx < lpb * cnt; idx += UT_NT) {
+    for (int idx = threadIdx.x; idx < (g.lpb << g.mlog); idx += UT_NT) {
         int l, m;
-        ut_map(d.ylines, lpb, cnt, idx, l, m);
-        const long long line = line0 + l;
-        if (line >= d.lines) continue;
-        const double2* a = lds + (size_t)l * M;
-        const double2 z0 = a[0];
+        ut_item(d, g, g.mlog, idx, l, m);
+        if (!ut_valid(d, g, l)) continue;
+        const double2* a = lds + ((size_t)l << g.mlog);
         if (kind == UT_FOURIER) {
             const double c0 = s / sqrt((double)N), c1 = s * sqrt(2.0 / N);
             if (m == 0) {
-                out[ut_offset(d, line, 0)] = (TO)(c0 * (z0.x + z0.y));  // V_0 = Re Z_0 + Im Z_0
-            } else if (m == M) {
-                out[ut_offset(d, line, N - 1)] = (TO)(c0 * (z0.x - z0.y));  // V_M = Re Z_0 - Im Z_0
+                const double2 z0 = a[0];
+                out[ut_off(d, g, l, 0)] = (TO)(c0 * (z0.x + z0.y));      // V_0 = Re Z_0 + Im Z_0
+                out[ut_off(d, g, l, N - 1)] = (TO)(c0 * (z0.x - z0.y));  // V_M = Re Z_0 - Im Z_0
             } else {
                 const double2 zm = a[m], zc = conj2(a[M - m]);
                 const double2 e = cscale(cadd(zm, zc), 0.5);
-                const double2 t = cmul(d.twiddle[m], cscale(csub(zm, zc), 0.5));
+                const double2 t = cmul(W[m], cscale(csub(zm, zc), 0.5));
                 // V_m = e - i t; column 2m-1 takes Re V_m, column 2m takes -Im V_m
-                out[ut_offset(d, line, 2 * m - 1)] = (TO)(c1 * (e.x + t.y));
-                out[ut_offset(d, line, 2 * m)] = (TO)(-c1 * (e.y - t.x));
+                out[ut_off(d, g, l, 2 * m - 1)] = (TO)(c1 * (e.x + t.y));
+                out[ut_off(d, g, l, 2 * m)] = (TO)(-c1 * (e.y - t.x));
             }
         } else {
             const double ca = s * sqrt(1.0 / N), cb = s * sqrt(2.0 / N);
             const bool rev = kind == UT_DST;
             if (m == 0) {
-                out[ut_offset(d, line, rev ? N - 1 : 0)] = (TO)(ca * (z0.x + z0.y));
-            } else if (m == M) {
+                const double2 z0 = a[0];
+                out[ut_off(d, g, l, rev ? N - 1 : 0)] = (TO)(ca * (z0.x + z0.y));
                 // X_M = cos(pi/4) V_M
-                out[ut_offset(d, line, rev ? N - 1 - M : M)] = (TO)(cb * sqrt(0.5) * (z0.x - z0.y));
+                out[ut_off(d, g, l, rev ? N - 1 - M : M)] = (TO)(cb * sqrt(0.5) * (z0.x - z0.y));
             } else {
                 const double2 zm = a[m], zc = conj2(a[M - m]);
                 const double2 e = cscale(cadd(zm, zc), 0.5);
-                const double2 t = cmul(d.twiddle[m], cscale(csub(zm, zc), 0.5));
-                const double2 r = cmul(d.qtw[m], make_double2(e.x + t.y, e.y - t.x));  // e^{-i pi m/2N} V_m
-                out[ut_offset(d, line, rev ? N - 1 - m : m)] = (TO)(cb * r.x);
-                out[ut_offset(d, line, rev ? m - 1 : N - m)] = (TO)(-cb * r.y);
+                const double2 t = cmul(W[m], cscale(csub(zm, zc), 0.5));
+                const double2 r = cmul(Q[m], make_double2(e.x + t.y, e.y - t.x));  // e^{-i pi m/2N} V_m
+                out[ut_off(d, g, l, rev ? N - 1 - m : m)] = (TO)(cb * r.x);
+                out[ut_off(d, g, l, rev ? m - 1 : N - m)] = (TO)(-cb * r.y);
             }
         }
     }
@@ -203,60 +258,64 @@ __device__ __forceinline__ void ut_forward(const FftDesc& d, long long blk, doub
 
 template <typename TI, typename TO, int EPI>
 __device__ __forceinline__ void ut_inverse(const FftDesc& d, long long blk, double2* lds, double* red) {
-    const int N = d.n, M = N >> 1, bits = 31 - __clz(M), kind = d.kind;
-    const int lpb = ut_lines_per_block(N);
-    const long long line0 = blk * lpb;
+    const UtGeom g = ut_geom(d, blk);
+    double2 *W, *Q;
+    ut_tables(d, g, lds, W, Q);
+    __syncthreads();
+    const int N = g.N, M = g.M, bits = g.mlog, kind = d.kind;
     const TI* in = (const TI*)d.in;
     const double s = d.scale;  // 1 / sqrt(h)
     // 1) half spectrum F_m, m = 0 .. M-1, in natural order; F_0 and F_M are
     //    real, and F_M rides in the imaginary part of slot 0
-    for (int idx = threadIdx.x; idx < lpb * M; idx += UT_NT) {
+    for (int idx = threadIdx.x; idx < (g.lpb << g.mlog); idx += UT_NT) {
         int l, m;
-        ut_map(d.ylines, lpb, M, idx, l, m);
-        const long long line = line0 + l;
+        ut_item(d, g, g.mlog, idx, l, m);
         double2 F = make_double2(0.0, 0.0);
-        if (line < d.lines) {
+        if (ut_valid(d, g, l)) {
             if (kind == UT_FOURIER) {
                 const double cN = s * sqrt((double)N), cH = s * sqrt(0.5 * N);
                 if (m == 0)
-                    F = make_double2(cN * (double)in[ut_offset(d, line, 0)], cN * (double)in[ut_offset(d, line, N - 1)]);
+                    F = make_double2(cN * (double)in[ut_off(d, g, l, 0)], cN * (double)in[ut_off(d, g, l, N - 1)]);
                 else
-                    F = make_double2(cH * (double)in[ut_offset(d, line, 2 * m - 1)],
-                                     -cH * (double)in[ut_offset(d, line, 2 * m)]);
+                    F = make_double2(cH * (double)in[ut_off(d, g, l, 2 * m - 1)],
+                                     -cH * (double)in[ut_off(d, g, l, 2 * m)]);
             } else {
                 // X_k = s c_k phihat_k (DST: phihat read in reverse), X_0 doubled
                 const bool rev = kind == UT_DST;
                 const double ca = s * sqrt(1.0 / N), cb = s * sqrt(2.0 / N);
                 auto X = [&](int k) -> double {
-                    return (k == 0 ? 2.0 * ca : cb) * (double)in[ut_offset(d, line, rev ? N - 1 - k : k)];
+                    return (k == 0 ? 2.0 * ca : cb) * (double)in[ut_off(d, g, l, rev ? N - 1 - k : k)];
                 };
                 if (m == 0)
                     F = make_double2(X(0), sqrt(2.0) * X(M));  // V_0 = X_0, V_M = sqrt(2) X_M
                 else
-                    F = cmul(conj2(d.qtw[m]), make_double2(X(m), -X(N - m)));  // e^{i pi m/2N}(X_m - i X_{N-m})
+                    F = cmul(conj2(Q[m]), make_double2(X(m), -X(N - m)));  // e^{i pi m/2N}(X_m - i X_{N-m})
             }
         }
-        lds[(size_t)l * M + m] = F;
+        lds[((size_t)l << g.mlog) + m] = F;
     }
     __syncthreads();
     // 2) fold the pairs (m, M-m) into Z_m = E_m + i O_m in place, with
-    //    E_m = (F_m + conj F_{M-m})/2 and O_m = conj(W^m) (F_m - conj F_{M-m})/2
-    const int pairs = M / 2 + 1;
-    for (int idx = threadIdx.x; idx < lpb * pairs; idx += UT_NT) {
-        const int l = idx / pairs, m = idx - l * pairs;
-        double2* a = lds + (size_t)l * M;
-        if (m == 0) {
-            const double f0 = a[0].x, fM = a[0].y;
-            a[0] = make_double2(0.5 * (f0 + fM), 0.5 * (f0 - fM));
-        } else {
+    //    E_m = (F_m + conj F_{M-m})/2 and O_m = conj(W^m) (F_m - conj F_{M-m})/2;
+    //    item 0 folds slot 0 and the self-paired slot M/2
+    for (int idx = threadIdx.x; idx < (g.lpb << (g.mlog - 1)); idx += UT_NT) {
+        const int l = idx >> (g.mlog - 1), m0 = idx & ((M >> 1) - 1);
+        double2* a = lds + ((size_t)l << g.mlog);
+        for (int rep = 0; rep < (m0 == 0 ? 2 : 1); ++rep) {
+            const int m = rep == 0 ? m0 : (M >> 1);
+            if (m == 0) {
+                const double f0 = a[0].x, fM = a[0].y;
+                a[0] = make_double2(0.5 * (f0 + fM), 0.5 * (f0 - fM));
+                continue;
+            }
             const int mc = M - m;
             const double2 fm = a[m], fc = a[mc];
             const double2 Em = cscale(cadd(fm, conj2(fc)), 0.5);
-            const double2 Om = cmul(conj2(d.twiddle[m]), cscale(csub(fm, conj2(fc)), 0.5));
+            const double2 Om = cmul(conj2(W[m]), cscale(csub(fm, conj2(fc)), 0.5));
             if (mc != m) {
                 // E_{M-m} = conj E_m and conj(W^{M-m}) = -W^m
                 const double2 Ec = conj2(Em);
-                const double2 Oc = cmul(cscale(d.twiddle[m], -1.0), cscale(csub(fc, conj2(fm)), 0.5));
+                const double2 Oc = cmul(cscale(W[m], -1.0), cscale(csub(fc, conj2(fm)), 0.5));
                 a[mc] = make_double2(Ec.x - Oc.y, Ec.y + Oc.x);
             }
             a[m] = make_double2(Em.x - Om.y, Em.y + Om.x);
@@ -264,21 +323,20 @@ __device__ __forceinline__ void ut_inverse(const FftDesc& d, long long blk, doub
     }
     __syncthreads();
     // 3) inverse complex FFT, natural in, bit-reversed out
-    ut_dif_inv(lds, lpb, M, N, d.twiddle);
+    ut_dif_inv(lds, g, W);
     // 4) unpack and store
     const double* ldsd = (const double*)lds;
     const double post = (kind == UT_FOURIER) ? 1.0 / M : 1.0;
     TO* out = (TO*)d.out;
     double se = 0.0, sx = 0.0;
-    for (int idx = threadIdx.x; idx < lpb * N; idx += UT_NT) {
+    for (int idx = threadIdx.x; idx < (g.lpb << g.nlog); idx += UT_NT) {
         int l, e;
-        ut_map(d.ylines, lpb, N, idx, l, e);
-        const long long line = line0 + l;
-        if (line >= d.lines) continue;
+        ut_item(d, g, g.nlog, idx, l, e);
+        if (!ut_valid(d, g, l)) continue;
         const int j = ut_vpos(kind, N, e);
-        double v = ldsd[l * N + 2 * bitrev(j >> 1, bits) + (j & 1)] * post;
+        double v = ldsd[(l << g.nlog) + 2 * bitrev(j >> 1, bits) + (j & 1)] * post;
         if (kind == UT_DST && (e & 1)) v = -v;
-        const long long o = ut_offset(d, line, e);
+        const long long o = ut_off(d, g, l, e);
         if constexpr (EPI == EPI_ACCUM_F64) {
             const double x = (double)out[o] + v;
             out[o] = (TO)x;
@@ -331,7 +389,8 @@ __global__ __launch_bounds__(UT_NT) void ut_multi_kernel(const FftDesc* __restri
 
 template <typename TI, typename TO, int EPI, bool INV>
 hipError_t launch_ut_t(const FftDesc& d, const FftDesc* d_work, int nwork, long long blocks, hipStream_t s) {
-    const size_t sm = (size_t)ut_lines_per_block(d.n) * d.n * sizeof(double);
+    // line data, then W (N/2 entries) and the quarter-wave table (N/2 + 1)
+    const size_t sm = (size_t)ut_lines_per_block(d.n) * d.n * sizeof(double) + (size_t)(d.n + 1) * sizeof(double2);
     if (d_work)
         hipLaunchKernelGGL((ut_multi_kernel<TI, TO, EPI, INV>),
                            dim3((unsigned)(blocks < 4 * PERSISTENT_BLOCKS ? blocks : 4 * PERSISTENT_BLOCKS)),

@@ -111,13 +111,16 @@ struct ThomasDesc {
     void* x;
     double* scratch;       // thomas_scratch_doubles() doubles
     int tf, tx;            // DType of f and x
-    long long line_begin;  // multi-problem: first global line
+    long long block_begin; // multi-problem: first block of this problem
 };
 hipError_t launch_thomas(const ThomasDesc& t, hipStream_t s);
+long long thomas_blocks(const ThomasDesc& t);
 // Scratch the Thomas kernel needs: (c', d') checkpoints, one per line every
 // 32 planes, and for cyclic lines also the d' of the second right-hand side.
 long long thomas_scratch_doubles(int nx, int ny, int nz, int nsys, int periodic);
-hipError_t launch_thomas_multi(const ThomasDesc* d_work, int nwork, long long total_lines, hipStream_t s);
+// nz_max: the largest nz of the work list (LDS for its coefficients)
+hipError_t launch_thomas_multi(const ThomasDesc* d_work, int nwork, long long total_blocks, int nz_max,
+                               hipStream_t s);
 
 // Residual r = f - A x of the 7-point operator in FP64, r stored as float,
 // with per-block partial sums (r^2, f^2).

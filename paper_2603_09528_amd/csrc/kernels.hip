@@ -69,14 +69,18 @@ hipError_t launch_gemm_multi(const GemmDesc& rep, const GemmDesc* d_work, int nw
 // walks the chunks from the top, re-reads the chunk of f, recomputes its c'
 // and d' from the checkpoint and substitutes.  So f is read twice and x
 // written once (no per-unknown scratch), and x may alias f.  Loads of the
-// next chunk are issued before the current chunk is computed: one lane per
-// line leaves about one wave per SIMD at the workload sizes, so latency is
-// hidden by prefetching rather than by occupancy.
+// next chunk are issued before the current chunk is computed.
+//
+// The line-independent coefficients A_k = tau a_k, D_k = sigma + tau b_k,
+// C_k = tau c_k are staged in LDS once per block: the elimination is one
+// dependent chain per line, and a coefficient fetched from memory inside it
+// would also wait for the prefetched chunk.
 //
 // The line pin_line is the null line of a singular Poisson problem: its final
 // pivot vanishes and its last unknown is set to zero (§3).
 // ---------------------------------------------------------------------------
-constexpr int THOMAS_KC = 32;
+constexpr int THOMAS_KC = 16;
+constexpr int THOMAS_NT = 256;
 
 long long thomas_scratch_doubles(int nx, int ny, int nz, int nsys, int periodic) {
     const long long lines = (long long)nx * ny * nsys;
@@ -95,8 +99,28 @@ __device__ __forceinline__ double recip(double d) {
     return __builtin_fma(r, e, r);
 }
 
+// Stage the coefficients of one problem in LDS as planes of nz doubles:
+// A_k (0 at k = 0), D_k, C_k (0 at k = nz-1) and AC_k = A_{k+1} C_k (the
+// coupling of pivot k+1 to pivot k; 0 at k = nz-1).
+constexpr int THOMAS_LDS_PLANES = 4;
+__device__ __forceinline__ void thomas_stage(const ThomasDesc& t, double* lds) {
+    const int nz = t.nz;
+    for (int k = threadIdx.x; k < nz; k += blockDim.x) {
+        const double a = k > 0 ? t.tau * t.az[k] : 0.0;
+        const double c = k < nz - 1 ? t.tau * t.cz[k] : 0.0;
+        lds[k] = a;
+        lds[nz + k] = t.sigma + t.tau * t.bz[k];
+        lds[2 * nz + k] = c;
+        lds[3 * nz + k] = k < nz - 1 ? t.tau * t.az[k + 1] * c : 0.0;
+    }
+}
+
+// The elimination carries the inverse pivot: pivot k is
+// q_k = D_k + tau lambda - AC_{k-1} / q_{k-1} and d'_k = (f_k - A_k d'_{k-1}) / q_k,
+// so the dependent chain per step is one FMA and the reciprocal; c'_k = C_k / q_k
+// is only needed by the back substitution.
 template <typename TF, typename TX>
-__device__ __forceinline__ void thomas_line(const ThomasDesc& t, long long gl) {
+__device__ __forceinline__ void thomas_line(const ThomasDesc& t, long long gl, const double* __restrict__ cf) {
     constexpr int KC = THOMAS_KC;
     const long long S = (long long)t.nx * t.ny;
     const int sys = (int)(gl / S);
@@ -105,43 +129,72 @@ __device__ __forceinline__ void thomas_line(const ThomasDesc& t, long long gl) {
     const int nz = t.nz;
     const int nc = (nz + KC - 1) / KC;
     const long long lines = S * t.nsys;
-    const double lam = t.lamx[i] + t.lamy[j];
+    const double tl = t.tau * (t.lamx[i] + t.lamy[j]);
     const long long base = (long long)sys * S * nz + line;
     const TF* f = (const TF*)t.f + base;
     TX* x = (TX*)t.x + base;
-    double2* ck = (double2*)t.scratch + gl;  // ck[c * lines]: (c', d') entering chunk c
+    double2* ck = (double2*)t.scratch + gl;  // ck[c * lines]: (1/q, d') entering chunk c
     const bool pinned = line == t.pin_line;
-    const double sig = t.sigma, tau = t.tau;
-    const double* __restrict__ az = t.az;
-    const double* __restrict__ bz = t.bz;
-    const double* __restrict__ cz = t.cz;
+    const double* __restrict__ cA = cf;
+    const double* __restrict__ cD = cf + nz;
+    const double* __restrict__ cC = cf + 2 * nz;
+    const double* __restrict__ cAC = cf + 3 * nz;
 
-    // one elimination step: (cp, dp) <- step k with right-hand side fk
-    auto step = [&](int k, double fk, double& cp, double& dp) {
-        const double sub = k > 0 ? tau * az[k] : 0.0;
-        const double den = sig + tau * (lam + bz[k]) - sub * cp;
-        const double inv = (pinned && k == nz - 1) ? 0.0 : recip(den);
-        cp = k < nz - 1 ? tau * cz[k] * inv : 0.0;
-        dp = (fk - sub * dp) * inv;
+    // step k below the top plane: (ip, dp) <- (1/q_k, d'_k)
+    auto step = [&](int k, double fk, double& ip, double& dp) {
+        const double acp = k > 0 ? cAC[k - 1] : 0.0;
+        ip = recip(cD[k] + tl - acp * ip);
+        dp = (fk - cA[k] * dp) * ip;
+    };
+    // any step, including the top plane (pinned line: last unknown zero)
+    auto step_top = [&](int k, double fk, double& ip, double& dp) {
+        step(k, fk, ip, dp);
+        if (k == nz - 1 && pinned) {
+            ip = 0.0;
+            dp = 0.0;
+        }
     };
 
     // ---- forward elimination ----
-    double cp = 0.0, dp = 0.0;
+    // (chunks below the top run without guards, so the coefficient reads of a
+    // chunk can be issued ahead of its dependent chain)
+    double ip = 0.0, dp = 0.0;
     double fb[KC], fn[KC];
 #pragma unroll
     for (int e = 0; e < KC; ++e) fb[e] = e < nz ? (double)f[(long long)e * S] : 0.0;
     for (int c = 0; c < nc; ++c) {
         const int k0 = c * KC;
-        ck[(long long)c * lines] = make_double2(cp, dp);
+        ck[(long long)c * lines] = make_double2(ip, dp);
+        if (k0 + 2 * KC <= nz) {
 #pragma unroll
-        for (int e = 0; e < KC; ++e) {
-            const int k = k0 + KC + e;
-            fn[e] = k < nz ? (double)f[(long long)k * S] : 0.0;
+            for (int e = 0; e < KC; ++e) fn[e] = (double)f[(long long)(k0 + KC + e) * S];
+        } else {
+#pragma unroll
+            for (int e = 0; e < KC; ++e) {
+                const int k = k0 + KC + e;
+                fn[e] = k < nz ? (double)f[(long long)k * S] : 0.0;
+            }
         }
+        if (k0 + KC < nz) {
+            // coefficients read one step ahead of the chain that uses them
+            double nA = cA[k0], nD = cD[k0], nAC = k0 > 0 ? cAC[k0 - 1] : 0.0;
 #pragma unroll
-        for (int e = 0; e < KC; ++e) {
-            const int k = k0 + e;
-            if (k < nz) step(k, fb[e], cp, dp);
+            for (int e = 0; e < KC; ++e) {
+                const double a = nA, d = nD, acp = nAC;
+                if (e + 1 < KC) {
+                    nA = cA[k0 + e + 1];
+                    nD = cD[k0 + e + 1];
+                    nAC = cAC[k0 + e];
+                }
+                ip = recip(d + tl - acp * ip);
+                dp = (fb[e] - a * dp) * ip;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < KC; ++e) {
+                const int k = k0 + e;
+                if (k < nz) step_top(k, fb[e], ip, dp);
+            }
         }
 #pragma unroll
         for (int e = 0; e < KC; ++e) fb[e] = fn[e];
@@ -165,20 +218,44 @@ __device__ __forceinline__ void thomas_line(const ThomasDesc& t, long long gl) {
         }
         const double2 c0 = ck[(long long)c * lines];
         double cb[KC];
-        double cpr = c0.x, dpr = c0.y;
+        double ipr = c0.x, dpr = c0.y;
+        if (k0 + KC < nz) {
+            // a whole chunk below the top plane: no guards; recompute the
+            // chunk (c' into cb, d' replaces f in fb)
+            double nA = cA[k0], nD = cD[k0], nAC = k0 > 0 ? cAC[k0 - 1] : 0.0;
 #pragma unroll
-        for (int e = 0; e < KC; ++e) {  // recompute c', d' of the chunk (d' replaces f in fb)
-            const int k = k0 + e;
-            if (k < nz) step(k, fb[e], cpr, dpr);
-            cb[e] = cpr;
-            fb[e] = dpr;
-        }
+            for (int e = 0; e < KC; ++e) {
+                const double a = nA, d = nD, acp = nAC;
+                if (e + 1 < KC) {
+                    nA = cA[k0 + e + 1];
+                    nD = cD[k0 + e + 1];
+                    nAC = cAC[k0 + e];
+                }
+                ipr = recip(d + tl - acp * ipr);
+                dpr = (fb[e] - a * dpr) * ipr;
+                cb[e] = cC[k0 + e] * ipr;
+                fb[e] = dpr;
+            }
 #pragma unroll
-        for (int e = KC - 1; e >= 0; --e) {
-            const int k = k0 + e;
-            if (k < nz) {
-                xv = (k == nz - 1) ? fb[e] : fb[e] - cb[e] * xv;  // last: x = d' (0 on the pinned line)
-                x[(long long)k * S] = (TX)xv;
+            for (int e = KC - 1; e >= 0; --e) {
+                xv = fb[e] - cb[e] * xv;
+                x[(long long)(k0 + e) * S] = (TX)xv;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < KC; ++e) {
+                const int k = k0 + e;
+                if (k < nz) step_top(k, fb[e], ipr, dpr);
+                cb[e] = k < nz ? cC[k] * ipr : 0.0;
+                fb[e] = dpr;
+            }
+#pragma unroll
+            for (int e = KC - 1; e >= 0; --e) {
+                const int k = k0 + e;
+                if (k < nz) {
+                    xv = (k == nz - 1) ? fb[e] : fb[e] - cb[e] * xv;  // top: x = d' (0 on the pinned line)
+                    x[(long long)k * S] = (TX)xv;
+                }
             }
         }
 #pragma unroll
@@ -199,7 +276,7 @@ __device__ __forceinline__ void thomas_line(const ThomasDesc& t, long long gl) {
 // x = y - x_{nz-1} v.  On the pinned line (singular Poisson) x_{nz-1} = 0 and
 // the last equation is dropped, the gauge of §3.  nz >= 2.
 template <typename TF, typename TX>
-__device__ __forceinline__ void thomas_line_cyclic(const ThomasDesc& t, long long gl) {
+__device__ __forceinline__ void thomas_line_cyclic(const ThomasDesc& t, long long gl, const double* __restrict__ cf) {
     constexpr int KC = THOMAS_KC;
     const long long S = (long long)t.nx * t.ny;
     const int sys = (int)(gl / S);
@@ -208,25 +285,26 @@ __device__ __forceinline__ void thomas_line_cyclic(const ThomasDesc& t, long lon
     const int nz = t.nz, nr = nz - 1;  // reduced system rows 0 .. nr-1
     const int nc = (nr + KC - 1) / KC;
     const long long lines = S * t.nsys;
-    const double lam = t.lamx[i] + t.lamy[j];
+    const double tl = t.tau * (t.lamx[i] + t.lamy[j]);
     const long long base = (long long)sys * S * nz + line;
     const TF* f = (const TF*)t.f + base;
     TX* x = (TX*)t.x + base;
-    double2* ck = (double2*)t.scratch + gl;  // ck[2 c * lines]: (c', d'_y), ck[(2c+1) lines]: (d'_v, -)
+    double2* ck = (double2*)t.scratch + gl;  // ck[2 c lines]: (c', d'_y), ck[(2c+1) lines]: (d'_v, -)
     const bool pinned = line == t.pin_line;
-    const double sig = t.sigma, tau = t.tau;
-    const double* __restrict__ az = t.az;
-    const double* __restrict__ bz = t.bz;
-    const double* __restrict__ cz = t.cz;
-    // coupling of row k of the reduced system to x_{nz-1}
-    auto ecoef = [&](int k) { return (k == 0 ? tau * az[0] : 0.0) + (k == nr - 1 ? tau * cz[nr - 1] : 0.0); };
+    const double tau = t.tau;
+    const double* __restrict__ cA = cf;
+    const double* __restrict__ cD = cf + nz;
+    const double* __restrict__ cC = cf + 2 * nz;
+    // coupling of rows 0 and nr-1 of the reduced system to x_{nz-1}
+    const double e0 = tau * t.az[0], e1 = tau * t.cz[nr - 1];
     auto step = [&](int k, double fk, double& cp, double& dy, double& dv) {
-        const double sub = k > 0 ? tau * az[k] : 0.0;
-        const double den = sig + tau * (lam + bz[k]) - sub * cp;
+        const double a = cA[k];
+        const double den = cD[k] + tl - a * cp;
         const double inv = recip(den);
-        cp = k < nr - 1 ? tau * cz[k] * inv : 0.0;
-        dy = (fk - sub * dy) * inv;
-        dv = (ecoef(k) - sub * dv) * inv;
+        const double ek = (k == 0 ? e0 : 0.0) + (k == nr - 1 ? e1 : 0.0);
+        cp = k < nr - 1 ? cC[k] * inv : 0.0;
+        dy = (fk - a * dy) * inv;
+        dv = (ek - a * dv) * inv;
     };
     double fb[KC], fn[KC];
     // ---- forward elimination of the reduced system ----
@@ -297,63 +375,91 @@ __device__ __forceinline__ void thomas_line_cyclic(const ThomasDesc& t, long lon
         }
         if (pass == 0) {
             // yv, vv now hold y_0, v_0
-            const double cl = tau * cz[nz - 1], al = tau * az[nz - 1];
-            const double dl = sig + tau * (lam + bz[nz - 1]);
+            const double cl = tau * t.cz[nz - 1], al = tau * t.az[nz - 1];
+            const double dl = cD[nz - 1] + tl;
             xlast = (flast - cl * yv - al * ytop) * recip(dl - cl * vv - al * vtop);
         }
     }
 }
 
-__device__ __forceinline__ void thomas_dispatch(const ThomasDesc& t, long long gl) {
-    if (t.periodic) {
-        if (t.tf == DT_F64 && t.tx == DT_F64) thomas_line_cyclic<double, double>(t, gl);
-        else if (t.tf == DT_F32 && t.tx == DT_F32) thomas_line_cyclic<float, float>(t, gl);
-        else if (t.tf == DT_F64) thomas_line_cyclic<double, float>(t, gl);
-        else thomas_line_cyclic<float, double>(t, gl);
-        return;
-    }
-    if (t.tf == DT_F64 && t.tx == DT_F64) thomas_line<double, double>(t, gl);
-    else if (t.tf == DT_F32 && t.tx == DT_F32) thomas_line<float, float>(t, gl);
-    else if (t.tf == DT_F64) thomas_line<double, float>(t, gl);
-    else thomas_line<float, double>(t, gl);
+template <typename TF, typename TX>
+__device__ __forceinline__ void thomas_any(const ThomasDesc& t, long long gl, const double* cf) {
+    if (t.periodic) thomas_line_cyclic<TF, TX>(t, gl, cf);
+    else thomas_line<TF, TX>(t, gl, cf);
 }
 
-constexpr int THOMAS_NT = 64;
+__device__ __forceinline__ void thomas_dispatch(const ThomasDesc& t, long long gl, const double* cf) {
+    if (t.tf == DT_F64 && t.tx == DT_F64) thomas_any<double, double>(t, gl, cf);
+    else if (t.tf == DT_F32 && t.tx == DT_F32) thomas_any<float, float>(t, gl, cf);
+    else if (t.tf == DT_F64) thomas_any<double, float>(t, gl, cf);
+    else thomas_any<float, double>(t, gl, cf);
+}
 
+// Single-problem launches: one kernel per storage-type pair and line kind,
+// so each keeps only its own registers.  Dynamic LDS: 3 nz doubles.
+template <typename TF, typename TX, bool CYC>
 __global__ __launch_bounds__(THOMAS_NT) void thomas_kernel(ThomasDesc t, long long nlines) {
-    const long long gl = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gl < nlines) thomas_dispatch(t, gl);
+    extern __shared__ double th_lds[];
+    thomas_stage(t, th_lds);
+    __syncthreads();
+    const long long gl = (long long)blockIdx.x * THOMAS_NT + threadIdx.x;
+    if (gl >= nlines) return;
+    if constexpr (CYC) thomas_line_cyclic<TF, TX>(t, gl, th_lds);
+    else thomas_line<TF, TX>(t, gl, th_lds);
 }
 
+// Multi-problem: blocks never straddle problems (block_begin counts blocks of
+// THOMAS_NT lines per problem), so each block stages one problem's
+// coefficients.
 __global__ __launch_bounds__(THOMAS_NT) void thomas_multi_kernel(const ThomasDesc* __restrict__ work, int nwork,
-                                                                 long long total) {
-    for (long long gl = (long long)blockIdx.x * blockDim.x + threadIdx.x; gl < total;
-         gl += (long long)gridDim.x * blockDim.x) {
+                                                                 long long total_blocks) {
+    extern __shared__ double th_lds[];
+    for (long long blk = blockIdx.x; blk < total_blocks; blk += gridDim.x) {
         int lo = 0, hi = nwork - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) / 2;
-            if (work[mid].line_begin <= gl) lo = mid;
+            if (work[mid].block_begin <= blk) lo = mid;
             else hi = mid - 1;
         }
         const ThomasDesc t = work[lo];
-        const long long local = gl - t.line_begin;
-        if (local < (long long)t.nx * t.ny * t.nsys) thomas_dispatch(t, local);
+        thomas_stage(t, th_lds);
+        __syncthreads();
+        const long long gl = (blk - t.block_begin) * THOMAS_NT + threadIdx.x;
+        if (gl < (long long)t.nx * t.ny * t.nsys) thomas_dispatch(t, gl, th_lds);
+        __syncthreads();
     }
+}
+
+long long thomas_blocks(const ThomasDesc& t) {
+    return ((long long)t.nx * t.ny * t.nsys + THOMAS_NT - 1) / THOMAS_NT;
 }
 
 hipError_t launch_thomas(const ThomasDesc& t, hipStream_t s) {
     const long long n = (long long)t.nx * t.ny * t.nsys;
     if (n <= 0) return hipSuccess;
-    const long long blocks = (n + THOMAS_NT - 1) / THOMAS_NT;
-    hipLaunchKernelGGL(thomas_kernel, dim3((unsigned)blocks), dim3(THOMAS_NT), 0, s, t, n);
+    const long long blocks = thomas_blocks(t);
+    const dim3 gr((unsigned)blocks), bl(THOMAS_NT);
+    const size_t sm = THOMAS_LDS_PLANES * sizeof(double) * (size_t)t.nz;
+#define TPT_THOMAS_LAUNCH(TF, TX)                                                                    \
+    do {                                                                                           \
+        if (t.periodic) hipLaunchKernelGGL((thomas_kernel<TF, TX, true>), gr, bl, sm, s, t, n);     \
+        else hipLaunchKernelGGL((thomas_kernel<TF, TX, false>), gr, bl, sm, s, t, n);               \
+    } while (0)
+    if (t.tf == DT_F64 && t.tx == DT_F64) TPT_THOMAS_LAUNCH(double, double);
+    else if (t.tf == DT_F32 && t.tx == DT_F32) TPT_THOMAS_LAUNCH(float, float);
+    else if (t.tf == DT_F64) TPT_THOMAS_LAUNCH(double, float);
+    else TPT_THOMAS_LAUNCH(float, double);
+#undef TPT_THOMAS_LAUNCH
     return hipGetLastError();
 }
 
-hipError_t launch_thomas_multi(const ThomasDesc* d_work, int nwork, long long total_lines, hipStream_t s) {
-    if (total_lines <= 0) return hipSuccess;
-    const long long blocks = std::min((total_lines + THOMAS_NT - 1) / THOMAS_NT, 32 * PERSISTENT_BLOCKS);
-    hipLaunchKernelGGL(thomas_multi_kernel, dim3((unsigned)blocks), dim3(THOMAS_NT), 0, s, d_work, nwork,
-                       total_lines);
+hipError_t launch_thomas_multi(const ThomasDesc* d_work, int nwork, long long total_blocks, int nz_max,
+                               hipStream_t s) {
+    if (total_blocks <= 0) return hipSuccess;
+    const long long grid = std::min(total_blocks, 4 * PERSISTENT_BLOCKS);
+    const size_t sm = THOMAS_LDS_PLANES * sizeof(double) * (size_t)nz_max;
+    hipLaunchKernelGGL(thomas_multi_kernel, dim3((unsigned)grid), dim3(THOMAS_NT), sm, s, d_work, nwork,
+                       total_blocks);
     return hipGetLastError();
 }
 
@@ -377,14 +483,32 @@ __device__ __forceinline__ void residual_block(const StencilDesc& st, long long 
     const long long sxy = (long long)nx * ny;
     const double* __restrict__ x = st.x;
     double sr = 0.0, sf = 0.0;
+    // (i, j, k) of the thread's first unknown, then advanced by the block
+    // size with carries (one 64-bit division per thread, not per unknown)
+    const long long idx0 = lb * RES_CHUNK + threadIdx.x;
+    int i = (int)(idx0 % nx), j, k;
+    {
+        const long long jk = idx0 / nx;
+        j = (int)(jk % ny);
+        k = (int)(jk / ny);
+    }
 #pragma unroll
     for (int u = 0; u < RES_PER_THREAD; ++u) {
-        const long long idx = lb * RES_CHUNK + (long long)u * RES_NT + threadIdx.x;
+        const long long idx = idx0 + (long long)u * RES_NT;
+        if (u > 0) {
+            i += RES_NT;
+            if (i >= nx) {
+                const int c = i / nx;
+                i -= c * nx;
+                j += c;
+                if (j >= ny) {
+                    const int c2 = j / ny;
+                    j -= c2 * ny;
+                    k += c2;
+                }
+            }
+        }
         if (idx < n) {
-            const int i = (int)(idx % nx);
-            const long long jk = idx / nx;
-            const int j = (int)(jk % ny);
-            const int k = (int)(jk / ny);
             const double xc = x[idx];
             double lap = (st.bx[i] + st.by[j] + st.bz[k]) * xc;
             // x direction

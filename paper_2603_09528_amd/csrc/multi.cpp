@@ -164,17 +164,20 @@ int MultiExec::build(const double* const* rhs, double* const* out, void* ws) {
         stage(ST_XF, from_rhs ? rhsv : resv, from_rhs ? DT_F64 : DT_F32, w1, tmid, EPI_STORE, nullptr);
         stage(ST_YF, w1c, tmid, w2, tmid, EPI_STORE, nullptr);
         std::vector<ThomasDesc> t(n);
-        long long lines = 0;
+        long long blocks = 0;
+        int nz_max = 1;
         for (int i = 0; i < n; ++i) {
             t[i] = plan_thomas(plans_[i], w[i].w2, tmid, w[i].w2, tmid, w[i].scratch, 1);
-            t[i].line_begin = lines;
-            lines += (long long)t[i].nx * t[i].ny;
+            t[i].block_begin = blocks;
+            blocks += thomas_blocks(t[i]);
+            nz_max = std::max(nz_max, t[i].nz);
         }
         Launch L{};
         L.kind = 1;
         L.off = append(blob_, t);
         L.nwork = n;
-        L.total = lines;
+        L.total = blocks;
+        L.variant = nz_max;
         seq_.push_back(L);
         stage(ST_YI, w2c, tmid, w1, tmid, EPI_STORE, nullptr);
         stage(ST_XI, w1c, tmid, outv, DT_F64, epi, &nb);
@@ -248,7 +251,7 @@ int MultiExec::enqueue(hipStream_t s) const {
             }
             case 1: {
                 TimedScope ts("multi_thomas", s);
-                e = launch_thomas_multi((const ThomasDesc*)(d_desc_ + L.off), L.nwork, L.total, s);
+                e = launch_thomas_multi((const ThomasDesc*)(d_desc_ + L.off), L.nwork, L.total, L.variant, s);
                 break;
             }
             case 2: {

@@ -33,7 +33,7 @@ class MultiExec {
    private:
     struct Launch {
         int kind;     // 0 gemm, 1 thomas, 2 residual, 3 reduce, 4 x-line FFT
-        int prec, variant, b_nk;
+        int prec, variant, b_nk;  // thomas: variant holds the largest nz
         size_t off;   // byte offset of the first descriptor in the blob
         int nwork;
         long long total;
