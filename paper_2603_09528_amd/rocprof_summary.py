@@ -78,12 +78,14 @@ def dispatch_counter(db: str, counter: str):
     return [(d, v[0], v[1]) for d, v in sorted(agg.items())]
 
 
-def traffic(fetch_db: str, write_db: str, stages, lib_pattern: str, copy_pattern: str, copy_bytes: float):
+def traffic(fetch_db: str, write_db: str, stages, lib_pattern: str, copy_pattern: str, copy_bytes: float,
+            last: int = 0):
     """HBM bytes per launch of the library's kernels from two --pmc runs
     (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch), each scaled by the ratio
     of the known size of a plain copy kernel to what the same counter reads
     for it.  Library dispatches are labelled with `stages` in launch order
-    (one solve = one cycle of stages)."""
+    (one solve = one cycle of stages); with `last`, only the last that many
+    library dispatches are labelled (the timed solves after any set-up work)."""
     out = {"copy_bytes": copy_bytes, "kernels": {}}
     for which, db, cname in (("fetch", fetch_db, "FETCH_SIZE"), ("write", write_db, "WRITE_SIZE")):
         rows = dispatch_counter(db, cname)
@@ -95,6 +97,8 @@ def traffic(fetch_db: str, write_db: str, stages, lib_pattern: str, copy_pattern
         out[f"{which}_scale_bytes_per_kib"] = scale
         out[f"copy_{which}_kib"] = kib
         lib = [(k, v) for _, k, v in rows if re.search(lib_pattern, k)]
+        if last:
+            lib = lib[-last:]
         for i, (k, v) in enumerate(lib):
             name = stages[i % len(stages)]
             e = out["kernels"].setdefault(name, {"symbol": short_name(k)})
@@ -118,12 +122,14 @@ def main(argv=None):
         ap.add_argument("write_db")
         ap.add_argument("--stages", required=True, help="comma-separated stage names in launch order")
         ap.add_argument("--lib-pattern", default=r"tpt::")
-        ap.add_argument("--copy-pattern", default=r"elementwise")
+        ap.add_argument("--copy-pattern", default=r"vectorized_elementwise")
         ap.add_argument("--copy-bytes", type=float, default=float(1 << 30))
         ap.add_argument("--kernel-hash", default="")
+        ap.add_argument("--last", type=int, default=0, help="label only the last N library dispatches")
         ap.add_argument("--command", default="")
         a = ap.parse_args(argv[1:])
-        res = traffic(a.fetch_db, a.write_db, a.stages.split(","), a.lib_pattern, a.copy_pattern, a.copy_bytes)
+        res = traffic(a.fetch_db, a.write_db, a.stages.split(","), a.lib_pattern, a.copy_pattern, a.copy_bytes,
+                      a.last)
         res["kernels_hip_sha256_16"] = a.kernel_hash
         res["command"] = a.command
         print(json.dumps(res, indent=1))
