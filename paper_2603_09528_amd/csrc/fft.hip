@@ -27,8 +27,8 @@
 //
 // Lines are either contiguous (x direction, element stride 1) or strided (y
 // direction: the lines of one z slab are its Nx columns, element stride Nx).
-// A block of 256 threads holds LPB lines in LDS (8N bytes each, 32 KB per
-// block for N >= 64).  Loads and stores walk the lines so that consecutive
+// A block of 256 threads holds LPB lines in LDS (8N bytes each; 16 KB per
+// block for x lines, 32 KB for y lines).  Loads and stores walk the lines so that consecutive
 // lanes touch consecutive addresses: along a line for x, across lines for y.
 // The pass is memory-bound: 16 B per unknown in FP64.
 #include "device_common.h"
@@ -38,13 +38,14 @@ namespace tpt {
 namespace {
 
 constexpr int UT_NT = 256;
-constexpr int UT_LDS_DOUBLES = 4096;  // 32 KB per block: up to 5 blocks (20 waves) per CU
-
-// Lines per block: 32 KB of line data (at most 64 lines); one line for
-// N = 2048, whose twiddle tables take another 32 KB.
-__host__ __device__ inline int ut_lines_per_block(int n) {
-    if (n > 1024) return 1;
-    const int l = UT_LDS_DOUBLES / n;
+// Lines per block: 16 KB of line data for contiguous lines, so that several
+// blocks per CU overlap their load, butterfly and store phases; 32 KB for
+// strided lines, whose loads and stores run across the lines of the block
+// (16 lines = 128-byte runs at N = 256).  At most 64 lines; one line at
+// N = 2048, whose twiddle tables take 32 KB.
+__host__ __device__ inline int ut_lines_per_block(int n, int ylines) {
+    if (n >= 2048) return 1;
+    const int l = (ylines ? 4096 : 2048) / n;
     return l > 64 ? 64 : l;
 }
 
@@ -76,7 +77,7 @@ __device__ __forceinline__ UtGeom ut_geom(const FftDesc& d, long long blk) {
     g.M = d.n >> 1;
     g.nlog = ilog2(g.N);
     g.mlog = g.nlog - 1;
-    g.lpb = ut_lines_per_block(g.N);
+    g.lpb = ut_lines_per_block(g.N, d.ylines);
     g.llog = ilog2(g.lpb);
     g.line0 = blk << g.llog;
     g.ly = threadIdx.x & (g.lpb - 1);
@@ -187,13 +188,14 @@ __device__ __forceinline__ void ut_forward(const FftDesc& d, long long blk, doub
     TO* out = (TO*)d.out;
     double* ldsd = (double*)lds;
     // 1) load into bit-reversed complex slots (v_j -> slot j/2, part j%2);
-    //    eight loads in flight per thread before the LDS stores
+    //    up to sixteen loads in flight per thread before the LDS stores
+    constexpr int UL = 16;
     const int total = g.lpb << g.nlog;
-    for (int base = 0; base < total; base += 8 * UT_NT) {
-        double v[8];
-        int pos[8];
+    for (int base = 0; base < total; base += UL * UT_NT) {
+        double v[UL];
+        int pos[UL];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < UL; ++u) {
             const int idx = base + u * UT_NT + (int)threadIdx.x;
             int l, e;
             ut_item(d, g, g.nlog, idx, l, e);
@@ -208,7 +210,7 @@ __device__ __forceinline__ void ut_forward(const FftDesc& d, long long blk, doub
             }
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+        for (int u = 0; u < UL; ++u)
             if (pos[u] >= 0) ldsd[pos[u]] = v[u];
     }
     __syncthreads();
@@ -390,7 +392,7 @@ __global__ __launch_bounds__(UT_NT) void ut_multi_kernel(const FftDesc* __restri
 template <typename TI, typename TO, int EPI, bool INV>
 hipError_t launch_ut_t(const FftDesc& d, const FftDesc* d_work, int nwork, long long blocks, hipStream_t s) {
     // line data, then W (N/2 entries) and the quarter-wave table (N/2 + 1)
-    const size_t sm = (size_t)ut_lines_per_block(d.n) * d.n * sizeof(double) + (size_t)(d.n + 1) * sizeof(double2);
+    const size_t sm = (size_t)ut_lines_per_block(d.n, d.ylines) * d.n * sizeof(double) + (size_t)(d.n + 1) * sizeof(double2);
     if (d_work)
         hipLaunchKernelGGL((ut_multi_kernel<TI, TO, EPI, INV>),
                            dim3((unsigned)(blocks < 4 * PERSISTENT_BLOCKS ? blocks : 4 * PERSISTENT_BLOCKS)),
@@ -405,7 +407,7 @@ hipError_t launch_ut_t(const FftDesc& d, const FftDesc* d_work, int nwork, long 
 bool fft_supported(int n) { return n >= 8 && n <= 2048 && (n & (n - 1)) == 0; }
 
 long long fft_blocks(const FftDesc& d) {
-    const int lpb = ut_lines_per_block(d.n);
+    const int lpb = ut_lines_per_block(d.n, d.ylines);
     return (d.lines + lpb - 1) / lpb;
 }
 

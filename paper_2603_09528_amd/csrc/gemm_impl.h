@@ -115,21 +115,27 @@ __device__ __forceinline__ void gemm_tile_f(const GemmDesc& g, long long lb, TM*
     // interior tiles (whole tile inside M x N, K a multiple of BK) load without predicates
     const bool full = mrem >= BM && nrem >= BN && (K % BK) == 0;
     TM ra[LA], rb[LB];
-    auto gload = [&](int k0) {
-        if (full) {
+    // FULL is a compile-time copy of `full`: the K loop is instantiated once
+    // per case, so the interior loop has no divergent loads and the loads of
+    // tile k+1 stay in flight while tile k is multiplied
+    auto gload = [&](int k0, auto full_tag) {
+        constexpr bool FULL = decltype(full_tag)::value;
+        if constexpr (FULL) {
+            // offsets within the tile are small and non-negative: 32-bit
+            // unsigned offsets from the block's (uniform) operand bases
 #pragma unroll
-            for (int t = 0; t < LA; ++t) ra[t] = (TM)Ab[(arow + t * (NT / BK)) * lda + k0 + acol];
+            for (int t = 0; t < LA; ++t) ra[t] = (TM)Ab[(unsigned)((arow + t * (NT / BK)) * lda + k0 + acol)];
 #pragma unroll
             for (int t = 0; t < LB; ++t) {
                 if constexpr (BNK) {
-                    rb[t] = (TM)Bb[(arow + t * (NT / BK)) * ldb + k0 + acol];
+                    rb[t] = (TM)Bb[(unsigned)((arow + t * (NT / BK)) * ldb + k0 + acol)];
                 } else {
                     const int e = tid + NT * t;
-                    rb[t] = (TM)Bb[(k0 + e / BN) * ldb + e % BN];
+                    rb[t] = (TM)Bb[(unsigned)((k0 + e / BN) * ldb + e % BN)];
                 }
             }
             return;
-        }
+        } else {
         const bool kok = k0 + acol < K;
 #pragma unroll
         for (int t = 0; t < LA; ++t) {
@@ -146,6 +152,7 @@ __device__ __forceinline__ void gemm_tile_f(const GemmDesc& g, long long lb, TM*
                 const int row = e / BN, col = e % BN;  // row over k, col over n
                 rb[t] = (k0 + row < K && col < nrem) ? (TM)Bb[(k0 + row) * ldb + col] : (TM)0;
             }
+        }
         }
     };
     auto sstore = [&](int buf) {
@@ -165,7 +172,8 @@ __device__ __forceinline__ void gemm_tile_f(const GemmDesc& g, long long lb, TM*
     };
 
     const int nk = (K + BK - 1) / BK;
-    gload(0);
+    auto kloop = [&](auto full_tag) {
+    gload(0, full_tag);
     if constexpr (NBUF == 2) {
         sstore(0);
         __syncthreads();
@@ -177,7 +185,7 @@ __device__ __forceinline__ void gemm_tile_f(const GemmDesc& g, long long lb, TM*
             sstore(0);
             __syncthreads();
         }
-        if (kt + 1 < nk) gload((kt + 1) * BK);
+        if (kt + 1 < nk) gload((kt + 1) * BK, full_tag);
         const TM* a = As + cur * S::A_ELEMS + (wm * C::WM + lr) * S::PA + lg;
         const TM* bb = Bs + cur * S::B_ELEMS;
 #pragma unroll
@@ -200,6 +208,9 @@ __device__ __forceinline__ void gemm_tile_f(const GemmDesc& g, long long lb, TM*
             __syncthreads();
         }
     }
+    };
+    if (full) kloop(std::true_type{});
+    else kloop(std::false_type{});
     if constexpr (NBUF == 1) __syncthreads();
 
     double se = 0.0, sx = 0.0;
