@@ -122,45 +122,100 @@ __device__ __forceinline__ int ut_vpos(int kind, int n, int e) {
     return (e & 1) ? n - 1 - (e >> 1) : (e >> 1);
 }
 
-// Forward radix-2 decimation in time over M points per line (bit-reversed
-// in, natural out).
+// Forward decimation in time over M points per line (bit-reversed in,
+// natural out).  Radix-2 stages are taken in pairs: a thread owns the four
+// points that stages L and 2L combine (one LDS round trip and one barrier per
+// pair); an odd stage count starts with one plain radix-2 stage (L = 2,
+// twiddle 1).
 __device__ __forceinline__ void ut_dit(double2* lds, const UtGeom& g, const double2* __restrict__ W) {
     const int glog = 8 - g.llog;  // threads per line: 256 / lpb
     const int l = threadIdx.x >> glog, t = threadIdx.x & ((1 << glog) - 1);
     double2* a = lds + ((size_t)l << g.mlog);
-    const int nb = g.M >> 1;
-    for (int hlog = 0; hlog < g.mlog; ++hlog) {
-        const int half = 1 << hlog, wsh = g.nlog - hlog - 1;  // twiddle stride N / L, L = 2 half
+    int hlog = 0;
+    if (g.mlog & 1) {
 #pragma unroll 4
-        for (int b = t; b < nb; b += (1 << glog)) {
-            const int pos = b & (half - 1);
-            const int i0 = ((b >> hlog) << (hlog + 1)) + pos, i1 = i0 + half;
-            const double2 u = a[i0];
-            const double2 v = cmul(a[i1], W[pos << wsh]);
-            a[i0] = cadd(u, v);
-            a[i1] = csub(u, v);
+        for (int b = t; b < (g.M >> 1); b += (1 << glog)) {
+            const double2 u = a[2 * b], v = a[2 * b + 1];
+            a[2 * b] = cadd(u, v);
+            a[2 * b + 1] = csub(u, v);
+        }
+        __syncthreads();
+        hlog = 1;
+    }
+    for (; hlog < g.mlog; hlog += 2) {
+        const int half = 1 << hlog, L = half << 1;
+        const int s1 = g.nlog - hlog - 1;  // twiddle stride N / L
+        const int s2 = s1 - 1;             // N / 2L
+#pragma unroll 2
+        for (int b = t; b < (g.M >> 2); b += (1 << glog)) {
+            const int p = b & (half - 1);
+            const int i0 = ((b >> hlog) << (hlog + 2)) + p, i1 = i0 + half, i2 = i0 + L, i3 = i2 + half;
+            double2 x0 = a[i0], x1 = a[i1], x2 = a[i2], x3 = a[i3];
+            const double2 w1 = W[p << s1], w2 = W[p << s2], w3 = W[(p + half) << s2];
+            double2 u = cmul(x1, w1);
+            x1 = csub(x0, u);
+            x0 = cadd(x0, u);
+            u = cmul(x3, w1);
+            x3 = csub(x2, u);
+            x2 = cadd(x2, u);
+            u = cmul(x2, w2);
+            x2 = csub(x0, u);
+            x0 = cadd(x0, u);
+            u = cmul(x3, w3);
+            x3 = csub(x1, u);
+            x1 = cadd(x1, u);
+            a[i0] = x0;
+            a[i1] = x1;
+            a[i2] = x2;
+            a[i3] = x3;
         }
         __syncthreads();
     }
 }
 
 // Inverse complex FFT (conjugate twiddles), decimation in frequency: natural
-// in, bit-reversed out, unnormalised.
+// in, bit-reversed out, unnormalised.  Stages L and L/2 taken in pairs as in
+// ut_dit; an odd stage count ends with one radix-2 stage (L = 2).
 __device__ __forceinline__ void ut_dif_inv(double2* lds, const UtGeom& g, const double2* __restrict__ W) {
     const int glog = 8 - g.llog;
     const int l = threadIdx.x >> glog, t = threadIdx.x & ((1 << glog) - 1);
     double2* a = lds + ((size_t)l << g.mlog);
-    const int nb = g.M >> 1;
-    for (int hlog = g.mlog - 1; hlog >= 0; --hlog) {
-        const int half = 1 << hlog, wsh = g.nlog - hlog - 1;
+    int hlog = g.mlog - 1;  // stage span L = 2^(hlog + 1)
+    for (; hlog >= 1; hlog -= 2) {
+        const int q4 = 1 << (hlog - 1);    // L / 4
+        const int sa = g.nlog - hlog - 1;  // twiddle stride N / L
+        const int sc = sa + 1;             // 2N / L
+#pragma unroll 2
+        for (int b = t; b < (g.M >> 2); b += (1 << glog)) {
+            const int p = b & (q4 - 1);
+            const int i0 = ((b >> (hlog - 1)) << (hlog + 1)) + p, i1 = i0 + q4, i2 = i1 + q4, i3 = i2 + q4;
+            double2 x0 = a[i0], x1 = a[i1], x2 = a[i2], x3 = a[i3];
+            const double2 wa = conj2(W[p << sa]), wb = conj2(W[(p + q4) << sa]), wc = conj2(W[p << sc]);
+            double2 d = csub(x0, x2);
+            x0 = cadd(x0, x2);
+            x2 = cmul(d, wa);
+            d = csub(x1, x3);
+            x1 = cadd(x1, x3);
+            x3 = cmul(d, wb);
+            d = csub(x0, x1);
+            x0 = cadd(x0, x1);
+            x1 = cmul(d, wc);
+            d = csub(x2, x3);
+            x2 = cadd(x2, x3);
+            x3 = cmul(d, wc);
+            a[i0] = x0;
+            a[i1] = x1;
+            a[i2] = x2;
+            a[i3] = x3;
+        }
+        __syncthreads();
+    }
+    if (hlog == 0) {
 #pragma unroll 4
-        for (int b = t; b < nb; b += (1 << glog)) {
-            const int pos = b & (half - 1);
-            const int i0 = ((b >> hlog) << (hlog + 1)) + pos, i1 = i0 + half;
-            const double2 u = a[i0];
-            const double2 v = a[i1];
-            a[i0] = cadd(u, v);
-            a[i1] = cmul(csub(u, v), conj2(W[pos << wsh]));
+        for (int b = t; b < (g.M >> 1); b += (1 << glog)) {
+            const double2 u = a[2 * b], v = a[2 * b + 1];
+            a[2 * b] = cadd(u, v);
+            a[2 * b + 1] = csub(u, v);
         }
         __syncthreads();
     }
