@@ -238,6 +238,199 @@ __device__ __forceinline__ void gemm_tile_f(const GemmDesc& g, long long lb, TM*
 }
 
 // ---------------------------------------------------------------------------
+// Persistent form of the FP64/FP32 tile for problems whose tiles are all
+// interior (M, N multiples of 128, K a multiple of 16).  Each block walks
+// tiles v = blockIdx.x, + gridDim.x, ... (numbered per XCD as in gemm_kernel)
+// and, during the last K step of a tile, already loads the first K tile of
+// its next tile, which it stores to the free LDS buffer before writing the
+// finished tile out: the load latency at the start of a tile and the result
+// stores at its end overlap the multiplications (a 256-deep K has only 16 K
+// steps per tile, so these ends are a large share of a tile).  Operands are
+// read and results written through buffer resources (base in scalar
+// registers, 32-bit per-thread offsets, block-uniform K steps as scalar
+// offsets), which keeps the address state small enough for two blocks per CU.
+// ---------------------------------------------------------------------------
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+constexpr int BUF_RSRC_WORD3 = 0x00020000;  // raw 32-bit buffer (gfx9 family)
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, 0x7fffffff, BUF_RSRC_WORD3);
+}
+template <typename T> struct BufIO;
+template <> struct BufIO<double> {
+    static __device__ __forceinline__ double ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, 0));
+    }
+    static __device__ __forceinline__ void st(double v, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, (int)vo, (int)so, 0);
+    }
+};
+template <> struct BufIO<float> {
+    static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, 0));
+    }
+    static __device__ __forceinline__ void st(float v, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)vo, (int)so, 0);
+    }
+};
+
+template <typename TM, typename TA, typename TB, typename TC, int EPI, bool BNK>
+__device__ __forceinline__ void gemm_tiles_persist_f(const GemmDesc& g, long long ntiles, TM* smem, double* red) {
+    constexpr int BM = 128, BN = 128, BK = 16;
+    typedef TileCfg<BM, BN> C;
+    typedef SmemF<TM, BM, BN, BNK, BK, 2> S;
+    typedef Mfma<TM> MM;
+    constexpr int NT = C::NT;
+    constexpr int LA = BM * BK / NT;
+    constexpr int LB = BN * BK / NT;
+    TM* As = smem;
+    TM* Bs = smem + 2 * S::A_ELEMS;
+    const int tid = threadIdx.x;
+    const int w = tid / 64, l = tid % 64, lr = l % 16, lg = l / 16;
+    const int wm = w / C::WAVES_N, wn = w % C::WAVES_N;
+    const int arow = tid / BK, acol = tid % BK;
+    const int lda = g.lda, ldb = g.ldb, ldc = g.ldc;
+    const int nk = g.K / BK;
+    const long long grid = gridDim.x;
+    // K-step scalar offsets (bytes) of the A and B tiles
+    const unsigned kstepA = BK * (unsigned)sizeof(TA);
+    const unsigned kstepB = BNK ? BK * (unsigned)sizeof(TB) : (unsigned)(BK * ldb) * (unsigned)sizeof(TB);
+
+    auto tile_ptrs = [&](long long v, const TA*& a, const TB*& bp, TC*& c) {
+        int b, tm, tn;
+        decode_tile(g, xcd_block(v, ntiles), b, tm, tn);
+        const int m0 = tm * BM, n0 = tn * BN;
+        a = (const TA*)g.A + (long long)b * g.sA + (long long)m0 * lda;
+        bp = BNK ? (const TB*)g.B + (long long)b * g.sB + (long long)n0 * ldb : (const TB*)g.B + (long long)b * g.sB + n0;
+        c = (TC*)g.C + (long long)b * g.sC + (long long)m0 * ldc + n0;
+    };
+    TM ra[LA], rb[LB];
+    auto gload = [&](__amdgpu_buffer_rsrc_t rA, __amdgpu_buffer_rsrc_t rB, int kt) {
+#pragma unroll
+        for (int q = 0; q < LA; ++q)
+            ra[q] = (TM)BufIO<TA>::ld(rA, (unsigned)(((arow + q * (NT / BK)) * lda + acol) * (int)sizeof(TA)),
+                                      kt * kstepA);
+#pragma unroll
+        for (int q = 0; q < LB; ++q) {
+            unsigned vo;
+            if constexpr (BNK) {
+                vo = (unsigned)(((arow + q * (NT / BK)) * ldb + acol) * (int)sizeof(TB));
+            } else {
+                const int e = tid + NT * q;
+                vo = (unsigned)(((e / BN) * ldb + e % BN) * (int)sizeof(TB));
+            }
+            rb[q] = (TM)BufIO<TB>::ld(rB, vo, kt * kstepB);
+        }
+    };
+    auto sstore = [&](int buf) {
+        TM* a = As + buf * S::A_ELEMS;
+        TM* bb = Bs + buf * S::B_ELEMS;
+#pragma unroll
+        for (int q = 0; q < LA; ++q) a[(arow + q * (NT / BK)) * S::PA + acol] = ra[q];
+#pragma unroll
+        for (int q = 0; q < LB; ++q) {
+            if constexpr (BNK) {
+                bb[(arow + q * (NT / BK)) * S::PB + acol] = rb[q];
+            } else {
+                const int e = tid + NT * q;
+                bb[(e / BN) * S::PB + (e % BN)] = rb[q];
+            }
+        }
+    };
+
+    long long v = blockIdx.x;
+    if (v >= ntiles) return;
+    const TA* pa;
+    const TB* pb;
+    TC* pc;
+    tile_ptrs(v, pa, pb, pc);
+    __amdgpu_buffer_rsrc_t rA = buf_rsrc(pa), rB = buf_rsrc(pb), rC = buf_rsrc(pc);
+    gload(rA, rB, 0);
+    sstore(0);
+    __syncthreads();
+    int buf = 0;
+    const unsigned tbase = (unsigned)(((wm * C::WM + MM::row(lg, 0)) * ldc + wn * C::WN + lr) * (int)sizeof(TC));
+    for (; v < ntiles; v += grid) {
+        const bool more = v + grid < ntiles;
+        typename MM::acc acc[C::MI][C::NI];
+#pragma unroll
+        for (int i = 0; i < C::MI; ++i)
+#pragma unroll
+            for (int j = 0; j < C::NI; ++j) acc[i][j] = MM::zero();
+        __amdgpu_buffer_rsrc_t rAn = rA, rBn = rB, rCn = rC;
+        for (int kt = 0; kt < nk; ++kt) {
+            if (kt + 1 < nk) {
+                gload(rA, rB, kt + 1);
+            } else if (more) {
+                tile_ptrs(v + grid, pa, pb, pc);
+                rAn = buf_rsrc(pa);
+                rBn = buf_rsrc(pb);
+                rCn = buf_rsrc(pc);
+                gload(rAn, rBn, 0);
+            }
+            const TM* a = As + buf * S::A_ELEMS + (wm * C::WM + lr) * S::PA + lg;
+            const TM* bb = Bs + buf * S::B_ELEMS;
+#pragma unroll
+            for (int kk = 0; kk < BK / 4; ++kk) {
+                TM fa[C::MI], fb[C::NI];
+#pragma unroll
+                for (int i = 0; i < C::MI; ++i) fa[i] = a[i * 16 * S::PA + kk * 4];
+#pragma unroll
+                for (int j = 0; j < C::NI; ++j) {
+                    if constexpr (BNK) fb[j] = bb[(wn * C::WN + j * 16 + lr) * S::PB + kk * 4 + lg];
+                    else fb[j] = bb[(kk * 4 + lg) * S::PB + wn * C::WN + j * 16 + lr];
+                }
+#pragma unroll
+                for (int i = 0; i < C::MI; ++i)
+#pragma unroll
+                    for (int j = 0; j < C::NI; ++j) acc[i][j] = MM::mma(fa[i], fb[j], acc[i][j]);
+            }
+            if (kt + 1 < nk) {
+                sstore(buf ^ 1);
+                __syncthreads();
+                buf ^= 1;
+            }
+        }
+        // the next tile's first K tile goes to the other buffer (last read
+        // before the latest barrier, or by the previous tile)
+        if (more) sstore(buf ^ 1);
+        double se = 0.0, sx = 0.0;
+#pragma unroll
+        for (int i = 0; i < C::MI; ++i) {
+#pragma unroll
+            for (int j = 0; j < C::NI; ++j) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const unsigned so = (unsigned)(((i * 16 + MM::row(0, r)) * ldc + j * 16) * (int)sizeof(TC));
+                    const double val = (double)acc[i][j][r];
+                    if constexpr (EPI == EPI_ACCUM_F64) {
+                        const double x = BufIO<double>::ld(rC, tbase, so) + val;
+                        BufIO<double>::st(x, rC, tbase, so);
+                        se += val * val;
+                        sx += x * x;
+                    } else {
+                        BufIO<TC>::st((TC)val, rC, tbase, so);
+                    }
+                }
+            }
+        }
+        if constexpr (EPI == EPI_ACCUM_F64) {
+            const long long lt = xcd_block(v, ntiles);
+            block_sum2<NT>(se, sx, red);
+            if (threadIdx.x == 0) {
+                g.partials[2 * lt] = se;
+                g.partials[2 * lt + 1] = sx;
+            }
+        }
+        __syncthreads();
+        buf ^= 1;
+        rA = rAn;
+        rB = rBn;
+        rC = rCn;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Split-BF16 x3 (v_mfma_f32_16x16x32_bf16, FP32 accumulate): each operand is
 // x = hi + lo (hi = bf16(x), lo = bf16(x - hi), round to nearest even) and
 // C = A_lo B_hi + A_hi B_lo + A_hi B_hi, small products first.  Fragments:
@@ -511,6 +704,15 @@ __global__ TPT_GEMM_ATTR void gemm_kernel(GemmDesc g) {
     GemmKernel<PREC, TA, TB, TC, EPI, BM, BN, BNK, DEEP>::tile(g, xcd_block(blockIdx.x, gridDim.x));
 }
 
+// Persistent single-problem kernel (interior tiles only, FP64 / FP32).
+template <int PREC, typename TA, typename TB, typename TC, int EPI, bool BNK>
+__global__ __launch_bounds__(256) void gemm_persist_kernel(GemmDesc g, long long ntiles) {
+    typedef typename std::conditional<PREC == GP_F64, double, float>::type T;
+    __shared__ __attribute__((aligned(16))) T smem[SmemF<T, 128, 128, BNK, 16, 2>::TOTAL];
+    __shared__ double red[2 * 4];
+    gemm_tiles_persist_f<T, TA, TB, TC, EPI, BNK>(g, ntiles, smem, red);
+}
+
 template <int PREC, typename TA, typename TB, typename TC, int EPI, int BM, int BN, bool BNK, int DEEP>
 __global__ TPT_GEMM_ATTR void gemm_multi_kernel(const GemmDesc* __restrict__ work,
                                                                             int nwork, long long total) {
@@ -552,6 +754,20 @@ hipError_t launch_gemm_typed(const GemmDesc& g, const GemmDesc* d_work, int nwor
         case TV_128x128_K32:
             if constexpr (PREC == GP_BF16X3) return hipErrorInvalidValue;
             else TPT_LAUNCH(128, 128, 1);
+            break;
+        case TV_128x128_P:
+            if constexpr (PREC == GP_BF16X3) {
+                return hipErrorInvalidValue;
+            } else {
+                if (d_work) {  // work lists run the plain 128 x 128 tile
+                    TPT_LAUNCH(128, 128, 0);
+                    break;
+                }
+                if (g.M % 128 || g.N % 128 || g.K % 16 || g.K < 16) return hipErrorInvalidValue;
+                const long long grid = persistent_gemm_grid(blocks);
+                hipLaunchKernelGGL((gemm_persist_kernel<PREC, TA, TB, TC, EPI, BNK>), dim3((unsigned)grid), dim3(256),
+                                   0, s, g, blocks);
+            }
             break;
         default: return hipErrorInvalidValue;
     }

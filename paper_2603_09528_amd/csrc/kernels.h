@@ -18,9 +18,15 @@ enum Epilogue {
 // Tile shapes (BM x BN) compiled for every precision; the autotuner picks.
 // TV_128x128_K32: 128 x 128 with a 32-deep K tile in a single LDS buffer
 // (FP64 and FP32 only).
+// TV_128x128_P: the 128 x 128 tile in a persistent grid that loads the next
+// tile's first K tile during the current one (FP64 / FP32, interior tiles only).
 enum TileVariant {
-    TV_128x128 = 0, TV_64x128 = 1, TV_128x64 = 2, TV_64x64 = 3, TV_32x64 = 4, TV_128x128_K32 = 5, TV_COUNT = 6
+    TV_128x128 = 0, TV_64x128 = 1, TV_128x64 = 2, TV_64x64 = 3, TV_32x64 = 4, TV_128x128_K32 = 5,
+    TV_128x128_P = 6, TV_COUNT = 7
 };
+// Grid of the persistent GEMM: two blocks per CU (a multiple of 8, so that a
+// block keeps its XCD), at most the tile count.
+long long persistent_gemm_grid(long long tiles);
 const char* tile_variant_name(int v);
 void tile_variant_shape(int v, int* bm, int* bn);
 

@@ -15,17 +15,32 @@
 namespace tpt {
 
 const char* tile_variant_name(int v) {
-    static const char* names[TV_COUNT] = {"128x128", "64x128", "128x64", "64x64", "32x64", "128x128k32"};
+    static const char* names[TV_COUNT] = {"128x128", "64x128", "128x64", "64x64", "32x64", "128x128k32", "128x128p"};
     return (v >= 0 && v < TV_COUNT) ? names[v] : "?";
 }
 
 void tile_variant_shape(int v, int* bm, int* bn) {
-    static const int s[TV_COUNT][2] = {{128, 128}, {64, 128}, {128, 64}, {64, 64}, {32, 64}, {128, 128}};
+    static const int s[TV_COUNT][2] = {{128, 128}, {64, 128}, {128, 64}, {64, 64}, {32, 64}, {128, 128}, {128, 128}};
     *bm = s[v][0];
     *bn = s[v][1];
 }
 
 static inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+long long persistent_gemm_grid(long long tiles) {
+    static int cus[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+    if (cus[dev] == 0) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+        cus[dev] = n;
+    }
+    long long grid = 2LL * cus[dev];
+    grid -= grid % 8;
+    if (grid < 8) grid = 8;
+    return tiles < grid ? tiles : grid;
+}
 
 long long gemm_blocks(const GemmDesc& g, int variant) {
     int bm, bn;

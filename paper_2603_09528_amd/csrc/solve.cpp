@@ -243,9 +243,15 @@ StencilDesc plan_stencil(const tpt_plan_s* p, const double* x, const double* f, 
 }
 
 int stage_variant(const tpt_plan_s* p, int stage, const GemmDesc& g, int prec) {
-    if (p->gemm_variant[stage] >= 0) return p->gemm_variant[stage];
-    const int kind = (stage == ST_XF || stage == ST_XI) ? 0 : 1;
-    return choose_variant(prec, kind, g.M, g.N, g.K);
+    int v = p->gemm_variant[stage];
+    if (v < 0) {
+        const int kind = (stage == ST_XF || stage == ST_XI) ? 0 : 1;
+        v = choose_variant(prec, kind, g.M, g.N, g.K);
+    }
+    // the persistent tile needs interior tiles; the x-pass table entry is
+    // shared by every row count, so check this problem's own shape
+    if (v == TV_128x128_P && (prec == GP_BF16X3 || g.M % 128 || g.N % 128 || g.K % 16)) v = TV_128x128;
+    return v;
 }
 
 const char* stage_name(int stage, int prec) {
@@ -534,7 +540,8 @@ int tpt_gemm(int prec, int b_nk, int variant, int M, int N, int K, int batch, co
         g.basis_lo = lo;
         g.basis_is_A = b_nk ? 0 : 1;
     }
-    const int v = variant >= 0 ? variant : choose_variant(gp, b_nk ? 0 : 1, M, N, K);
+    int v = variant >= 0 ? variant : choose_variant(gp, b_nk ? 0 : 1, M, N, K);
+    if (variant < 0 && v == TV_128x128_P && (gp == GP_BF16X3 || M % 128 || N % 128 || K % 16)) v = TV_128x128;
     hipError_t e;
     {
         TimedScope ts("gemm_test", s);
