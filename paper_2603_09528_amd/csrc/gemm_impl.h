@@ -447,34 +447,8 @@ template <int BM, int BN> struct SmemB {
     static constexpr int TOTAL = 2 * (A_ELEMS + B_ELEMS);  // [hi, lo][A | B], single buffer
 };
 
-// 8 consecutive k of one row of a k-contiguous operand: pre-split planes or
-// data to split.  Returns zeros outside [0, nrows) x [0, K).
-template <typename TD>
-__device__ __forceinline__ void load8_data(const TD* __restrict__ p, bool rowok, int k, int K, u16x8& h, u16x8& lo) {
-    float v[8];
-    if constexpr (sizeof(TD) == 4) {
-        if (rowok && k + 8 <= K && ((((uintptr_t)(p + k)) & 15) == 0)) {
-            const float4 p0 = *(const float4*)(p + k);
-            const float4 p1 = *(const float4*)(p + k + 4);
-            v[0] = p0.x; v[1] = p0.y; v[2] = p0.z; v[3] = p0.w;
-            v[4] = p1.x; v[5] = p1.y; v[6] = p1.z; v[7] = p1.w;
-        } else {
-#pragma unroll
-            for (int e = 0; e < 8; ++e) v[e] = (rowok && k + e < K) ? (float)p[k + e] : 0.f;
-        }
-    } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) v[e] = (rowok && k + e < K) ? (float)p[k + e] : 0.f;
-    }
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        uint16_t hh, ll;
-        split_bf16(v[e], hh, ll);
-        h[e] = hh;
-        lo[e] = ll;
-    }
-}
-
+// 8 consecutive k of one row of pre-split bf16 planes (row start ph / pl);
+// zeros outside [0, nrows) x [0, K).
 __device__ __forceinline__ void load8_planes(const uint16_t* __restrict__ ph, const uint16_t* __restrict__ pl,
                                              bool rowok, int k, int K, u16x8& h, u16x8& lo) {
     if (rowok && k + 8 <= K && ((((uintptr_t)(ph + k)) & 15) == 0)) {
@@ -522,34 +496,65 @@ __device__ __forceinline__ void gemm_tile_b(const GemmDesc& g, long long lb, uin
 #pragma unroll
         for (int j = 0; j < C::NI; ++j) acc[i][j] = (f4){0.f, 0.f, 0.f, 0.f};
 
-    u16x8 rah[CA], ral[CA], rbh[CB], rbl[CB];
+    // Registers between the load of a K tile and its store to LDS: the basis
+    // operand arrives pre-split (bf16 planes); the data operand is kept as
+    // raw FP32 values and split into hi/lo only when stored, so the loads of
+    // tile k+1 stay in flight while tile k is multiplied.
+    u16x8 rph[BNK ? CB : CA], rpl[BNK ? CB : CA];  // basis planes (x pass: B, y pass: A)
+    float rd[BNK ? CA : CB][8];                     // data (x pass: A rows, y pass: B column pairs)
     static_assert(BNK || CB % 2 == 0, "pair chunks need an even chunk count");
-    // y pass: 8-byte loads of column pairs when every row start is 8-byte aligned
-    const bool bvec = !BNK && (ldb % 2) == 0 && (offB % 2) == 0 && ((((uintptr_t)g.B) & 7) == 0);
-    auto gload = [&](int k0) {
+    // interior tiles with aligned rows load without predicates, as vectors
+    const bool aligned_data = BNK ? ((lda % 8) == 0 && (offA % 8) == 0 && ((((uintptr_t)g.A) & 31) == 0))
+                                  : ((ldb % 2) == 0 && (offB % 2) == 0 &&
+                                     ((((uintptr_t)g.B) & (2 * sizeof(TD) - 1)) == 0));
+    const bool aligned_planes = BNK ? ((ldb % 8) == 0 && (offB % 8) == 0) : ((lda % 8) == 0 && (offA % 8) == 0);
+    const bool full = mrem >= BM && nrem >= BN && (K % BK) == 0 && aligned_data && aligned_planes;
+    auto gload = [&](int k0, auto full_tag) {
+        constexpr bool FULL = decltype(full_tag)::value;
+        // basis planes
 #pragma unroll
-        for (int t = 0; t < CA; ++t) {
+        for (int t = 0; t < (BNK ? CB : CA); ++t) {
             const int c = tid + NT * t;
             const int row = c / (BK / 8), kc = c % (BK / 8);
-            const bool rok = row < mrem;
-            if constexpr (BNK)
-                load8_data<TD>((const TD*)g.A + offA + (long long)row * lda, rok, k0 + kc * 8, K, rah[t], ral[t]);
-            else
-                load8_planes(g.basis_hi + offA + (long long)row * lda, g.basis_lo + offA + (long long)row * lda, rok,
-                             k0 + kc * 8, K, rah[t], ral[t]);
-        }
-#pragma unroll
-        for (int t = 0; t < (BNK ? CB : 0); ++t) {
-            const int c = tid + NT * t;
-            if constexpr (BNK) {
-                const int row = c / (BK / 8), kc = c % (BK / 8);
-                load8_planes(g.basis_hi + offB + (long long)row * ldb, g.basis_lo + offB + (long long)row * ldb,
-                             row < nrem, k0 + kc * 8, K, rbh[t], rbl[t]);
+            const long long off = (BNK ? offB + (long long)row * ldb : offA + (long long)row * lda) + k0 + kc * 8;
+            if constexpr (FULL) {
+                rph[t] = *(const u16x8*)(g.basis_hi + off);
+                rpl[t] = *(const u16x8*)(g.basis_lo + off);
+            } else {
+                const bool rok = row < (BNK ? nrem : mrem);
+                load8_planes(g.basis_hi + off - (k0 + kc * 8), g.basis_lo + off - (k0 + kc * 8), rok, k0 + kc * 8, K,
+                             rph[t], rpl[t]);
             }
         }
-        if constexpr (!BNK) {
-            // B data stored [k][n]: pair chunk c covers columns 2 (c % (BN/2)) + {0, 1}
-            // and k = 8 (c / (BN/2)) .. +7; one 8-byte load per row when aligned
+        if constexpr (BNK) {
+            // x pass: A data [m][k], 8 consecutive k of one row per chunk
+#pragma unroll
+            for (int t = 0; t < CA; ++t) {
+                const int c = tid + NT * t;
+                const int row = c / (BK / 8), kc = c % (BK / 8);
+                const TD* pa = (const TD*)g.A + offA + (long long)row * lda + k0 + kc * 8;
+                if constexpr (FULL) {
+                    if constexpr (sizeof(TD) == 4) {
+                        const float4 p0 = *(const float4*)pa, p1 = *(const float4*)(pa + 4);
+                        rd[t][0] = p0.x; rd[t][1] = p0.y; rd[t][2] = p0.z; rd[t][3] = p0.w;
+                        rd[t][4] = p1.x; rd[t][5] = p1.y; rd[t][6] = p1.z; rd[t][7] = p1.w;
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 8; e += 2) {
+                            const double2 q = *(const double2*)(pa + e);
+                            rd[t][e] = (float)q.x;
+                            rd[t][e + 1] = (float)q.y;
+                        }
+                    }
+                } else {
+                    const bool rok = row < mrem;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) rd[t][e] = (rok && k0 + kc * 8 + e < K) ? (float)pa[e] : 0.f;
+                }
+            }
+        } else {
+            // y pass: B data [k][n]; pair chunk c covers columns 2 (c % (BN/2)) + {0, 1}
+            // and k = 8 (c / (BN/2)) .. +7
 #pragma unroll
             for (int t = 0; t < CB / 2; ++t) {
                 const int c = tid + NT * t;
@@ -559,22 +564,20 @@ __device__ __forceinline__ void gemm_tile_b(const GemmDesc& g, long long lb, uin
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
                     const int k = k0 + kc * 8 + e;
-                    float v0, v1;
-                    if (bvec && k < K && nn + 1 < nrem) {
-                        const float2 q = *(const float2*)(pb + (long long)k * ldb);
-                        v0 = q.x;
-                        v1 = q.y;
+                    if constexpr (FULL) {
+                        if constexpr (sizeof(TD) == 4) {
+                            const float2 q = *(const float2*)(pb + (long long)k * ldb);
+                            rd[2 * t][e] = q.x;
+                            rd[2 * t + 1][e] = q.y;
+                        } else {
+                            const double2 q = *(const double2*)(pb + (long long)k * ldb);
+                            rd[2 * t][e] = (float)q.x;
+                            rd[2 * t + 1][e] = (float)q.y;
+                        }
                     } else {
-                        v0 = (nn < nrem && k < K) ? (float)pb[(long long)k * ldb] : 0.f;
-                        v1 = (nn + 1 < nrem && k < K) ? (float)pb[(long long)k * ldb + 1] : 0.f;
+                        rd[2 * t][e] = (nn < nrem && k < K) ? (float)pb[(long long)k * ldb] : 0.f;
+                        rd[2 * t + 1][e] = (nn + 1 < nrem && k < K) ? (float)pb[(long long)k * ldb + 1] : 0.f;
                     }
-                    uint16_t hh, ll;
-                    split_bf16(v0, hh, ll);
-                    rbh[2 * t][e] = hh;
-                    rbl[2 * t][e] = ll;
-                    split_bf16(v1, hh, ll);
-                    rbh[2 * t + 1][e] = hh;
-                    rbl[2 * t + 1][e] = ll;
                 }
             }
         }
@@ -582,17 +585,19 @@ __device__ __forceinline__ void gemm_tile_b(const GemmDesc& g, long long lb, uin
     auto sstore = [&]() {
         uint16_t* ah = sm_hi;
         uint16_t* al = sm_lo;
-#pragma unroll
-        for (int t = 0; t < CA; ++t) {
-            const int c = tid + NT * t;
-            const int row = c / (BK / 8), kc = c % (BK / 8);
-            *(u16x8*)(ah + row * P + kc * 8) = rah[t];
-            *(u16x8*)(al + row * P + kc * 8) = ral[t];
-        }
         uint16_t* bh = ah + S::A_ELEMS;
         uint16_t* bl = al + S::A_ELEMS;
+        // basis planes as loaded
 #pragma unroll
-        for (int t = 0; t < CB; ++t) {
+        for (int t = 0; t < (BNK ? CB : CA); ++t) {
+            const int c = tid + NT * t;
+            const int row = c / (BK / 8), kc = c % (BK / 8);
+            *(u16x8*)((BNK ? bh : ah) + row * P + kc * 8) = rph[t];
+            *(u16x8*)((BNK ? bl : al) + row * P + kc * 8) = rpl[t];
+        }
+        // data split into hi / lo planes
+#pragma unroll
+        for (int t = 0; t < (BNK ? CA : CB); ++t) {
             int row, kc;
             if constexpr (BNK) {
                 const int c = tid + NT * t;
@@ -603,8 +608,16 @@ __device__ __forceinline__ void gemm_tile_b(const GemmDesc& g, long long lb, uin
                 row = 2 * (c % (BN / 2)) + (t & 1);
                 kc = c / (BN / 2);
             }
-            *(u16x8*)(bh + row * P + kc * 8) = rbh[t];
-            *(u16x8*)(bl + row * P + kc * 8) = rbl[t];
+            u16x8 h, lo;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                uint16_t hh, ll;
+                split_bf16(rd[t][e], hh, ll);
+                h[e] = hh;
+                lo[e] = ll;
+            }
+            *(u16x8*)((BNK ? ah : bh) + row * P + kc * 8) = h;
+            *(u16x8*)((BNK ? al : bl) + row * P + kc * 8) = lo;
         }
     };
 
@@ -612,12 +625,13 @@ __device__ __forceinline__ void gemm_tile_b(const GemmDesc& g, long long lb, uin
     // workgroups per CU); the next tile is prefetched into registers while
     // the current one is multiplied
     const int nk = (K + BK - 1) / BK;
-    gload(0);
+    auto kloop = [&](auto full_tag) {
+    gload(0, full_tag);
     for (int kt = 0; kt < nk; ++kt) {
         if (kt > 0) __syncthreads();  // every wave is done reading the previous tile
         sstore();
         __syncthreads();
-        if (kt + 1 < nk) gload((kt + 1) * BK);
+        if (kt + 1 < nk) gload((kt + 1) * BK, full_tag);
         const uint16_t* ah = sm_hi;
         const uint16_t* al = sm_lo;
         const uint16_t* bh = ah + S::A_ELEMS;
@@ -644,6 +658,9 @@ __device__ __forceinline__ void gemm_tile_b(const GemmDesc& g, long long lb, uin
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fah[i], fbh[j], acc[i][j], 0, 0, 0);
             }
     }
+    };
+    if (full) kloop(std::true_type{});
+    else kloop(std::false_type{});
     __syncthreads();
 
     double se = 0.0, sx = 0.0;

@@ -80,7 +80,9 @@ int choose_variant(int prec, int kind, int M, int N, int K) {
         auto it = g_tune.find(tune_key(prec, kind, M, N, K));
         if (it != g_tune.end()) return it->second;
     }
-    // heuristic: least padded area, then the larger tile
+    // heuristic: the persistent 128 x 128 tile where every tile is interior
+    // (FP64 / FP32); else least padded area, then the larger tile
+    if (prec != GP_BF16X3 && M % 128 == 0 && N % 128 == 0 && K % 16 == 0 && K >= 16) return TV_128x128_P;
     int best = TV_128x128;
     double best_cost = 1e300;
     for (int v = 0; v <= TV_32x64; ++v) {
