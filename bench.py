@@ -288,6 +288,24 @@ def main():
         log(f"{mode}: {ms:.3f} ms/solve, {results[mode]['gdofs']:.2f} GDOF/s")
         del plan
 
+    # tile variants the autotuner chose (precision, pass, M, N, K -> tile)
+    tiles = {}
+    try:
+        import tempfile
+        with tempfile.NamedTemporaryFile("r", suffix=".txt") as tf:
+            T.autotune_save(tf.name)
+            names = ("128x128", "64x128", "128x64", "64x64", "32x64", "128x128k32", "128x128p")
+            precs = ("fp64", "fp32", "bf16x3")
+            for ln in open(tf.name):
+                if ln.startswith("#") or not ln.strip():
+                    continue
+                pr, kind, M, N, K, v = (int(t) for t in ln.split())
+                key = f"{precs[pr]} {'x' if kind == 0 else 'y'} M={M or 'any'} N={N} K={K}"
+                tiles[key] = names[v] if 0 <= v < len(names) else str(v)
+    except Exception as e:  # the table is informative only
+        tiles = {"error": str(e)}
+    log(f"autotuned tiles: {tiles}")
+
     # ---- CPU oracle: baseline timing on a bounded sample, and the error check ----
     cpu = None
     if not args.no_cpu_baseline:
@@ -388,6 +406,7 @@ def main():
         "serving": serving,
         "helmholtz_1024x768x512_3rhs": helm,
         "transform_variants": variants,
+        "gemm_tiles": tiles,
     }
     print(json.dumps(line))
 

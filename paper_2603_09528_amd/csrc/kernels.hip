@@ -480,73 +480,65 @@ hipError_t launch_thomas_multi(const ThomasDesc* d_work, int nwork, long long to
 
 // ---------------------------------------------------------------------------
 // FP64 residual of the 7-point operator (the Kronecker sum of §2.2.2 with the
-// same boundary rows as the plan), r = f - A x, A = L or I - alpha L.
-// One thread per unknown; partial sums of r^2 and f^2 per block.
+// same boundary rows as the plan), r = f - A x, A = L or I - alpha L, with
+// partial sums of r^2 and f^2 per block.
 // ---------------------------------------------------------------------------
 constexpr int RES_NT = 256;
-constexpr int RES_PER_THREAD = 8;  // unknowns per thread (strided by the block size)
-constexpr int RES_CHUNK = RES_NT * RES_PER_THREAD;
+constexpr int RES_RZ = 32;  // z planes per thread
 
+// Blocks: 256 consecutive (i, j) columns times one chunk of RES_RZ planes.
 int residual_blocks(const StencilDesc& st) {
-    const long long n = (long long)st.nx * st.ny * st.nz;
-    return (int)((n + RES_CHUNK - 1) / RES_CHUNK);
+    const long long ncb = ((long long)st.nx * st.ny + RES_NT - 1) / RES_NT;
+    const long long nzc = (st.nz + RES_RZ - 1) / RES_RZ;
+    return (int)(ncb * nzc);
 }
 
+// Each thread marches up one column through RES_RZ planes, keeping the z
+// neighbours in registers: per unknown it loads the next plane's value, f and
+// the four x / y neighbours (cache hits), with the x / y coefficients of its
+// column held in registers.  A missing neighbour (a wall) gets coefficient 0
+// and offset 0, so the stencil needs no branches.
 __device__ __forceinline__ void residual_block(const StencilDesc& st, long long lb, double* red) {
-    const long long n = (long long)st.nx * st.ny * st.nz;
     const int nx = st.nx, ny = st.ny, nz = st.nz;
     const long long sxy = (long long)nx * ny;
-    const double* __restrict__ x = st.x;
+    const long long ncb = (sxy + RES_NT - 1) / RES_NT;
+    const long long zc = lb / ncb, cbk = lb - zc * ncb;
+    const long long c = cbk * RES_NT + threadIdx.x;  // column i + nx j
     double sr = 0.0, sf = 0.0;
-    // (i, j, k) of the thread's first unknown, then advanced by the block
-    // size with carries (one 64-bit division per thread, not per unknown)
-    const long long idx0 = lb * RES_CHUNK + threadIdx.x;
-    int i = (int)(idx0 % nx), j, k;
-    {
-        const long long jk = idx0 / nx;
-        j = (int)(jk % ny);
-        k = (int)(jk / ny);
-    }
-#pragma unroll
-    for (int u = 0; u < RES_PER_THREAD; ++u) {
-        const long long idx = idx0 + (long long)u * RES_NT;
-        if (u > 0) {
-            i += RES_NT;
-            if (i >= nx) {
-                const int c = i / nx;
-                i -= c * nx;
-                j += c;
-                if (j >= ny) {
-                    const int c2 = j / ny;
-                    j -= c2 * ny;
-                    k += c2;
-                }
-            }
-        }
-        if (idx < n) {
-            const double xc = x[idx];
-            double lap = (st.bx[i] + st.by[j] + st.bz[k]) * xc;
-            // x direction
-            if (i > 0) lap += st.ax[i] * x[idx - 1];
-            else if (st.perx) lap += st.ax[0] * x[idx + nx - 1];
-            if (i < nx - 1) lap += st.cx[i] * x[idx + 1];
-            else if (st.perx) lap += st.cx[nx - 1] * x[idx - (nx - 1)];
-            // y direction
-            if (j > 0) lap += st.ay[j] * x[idx - nx];
-            else if (st.pery) lap += st.ay[0] * x[idx + (long long)(ny - 1) * nx];
-            if (j < ny - 1) lap += st.cy[j] * x[idx + nx];
-            else if (st.pery) lap += st.cy[ny - 1] * x[idx - (long long)(ny - 1) * nx];
-            // z direction
-            if (k > 0) lap += st.az[k] * x[idx - sxy];
-            else if (st.perz) lap += st.az[0] * x[idx + (long long)(nz - 1) * sxy];
-            if (k < nz - 1) lap += st.cz[k] * x[idx + sxy];
-            else if (st.perz) lap += st.cz[nz - 1] * x[idx - (long long)(nz - 1) * sxy];
+    if (c < sxy) {
+        const int j = (int)(c / nx), i = (int)(c - (long long)j * nx);
+        const double* __restrict__ x = st.x;
+        // x / y neighbours: offsets (elements) and coefficients, 0 where absent
+        long long oxm = 0, oxp = 0, oym = 0, oyp = 0;
+        double axm = 0.0, axp = 0.0, aym = 0.0, ayp = 0.0;
+        if (i > 0) { oxm = -1; axm = st.ax[i]; } else if (st.perx) { oxm = nx - 1; axm = st.ax[0]; }
+        if (i < nx - 1) { oxp = 1; axp = st.cx[i]; } else if (st.perx) { oxp = -(long long)(nx - 1); axp = st.cx[nx - 1]; }
+        if (j > 0) { oym = -nx; aym = st.ay[j]; } else if (st.pery) { oym = (long long)(ny - 1) * nx; aym = st.ay[0]; }
+        if (j < ny - 1) { oyp = nx; ayp = st.cy[j]; } else if (st.pery) { oyp = -(long long)(ny - 1) * nx; ayp = st.cy[ny - 1]; }
+        const double bxy = st.bx[i] + st.by[j];
+        const int k0 = (int)zc * RES_RZ, k1 = min(nz, k0 + RES_RZ);
+        // z window: the value below k0 (or its periodic image) and at k0
+        double xm = 0.0;
+        if (k0 > 0) xm = x[(long long)(k0 - 1) * sxy + c];
+        else if (st.perz) xm = x[(long long)(nz - 1) * sxy + c];
+        double xc = x[(long long)k0 * sxy + c];
+        for (int k = k0; k < k1; ++k) {
+            const long long idx = (long long)k * sxy + c;
+            double xp = 0.0;
+            if (k + 1 < nz) xp = x[idx + sxy];
+            else if (st.perz) xp = x[c];
+            const double azk = (k > 0 || st.perz) ? st.az[k] : 0.0;
+            const double czk = (k < nz - 1 || st.perz) ? st.cz[k] : 0.0;
+            double lap = (bxy + st.bz[k]) * xc + azk * xm + czk * xp;
+            lap += axm * x[idx + oxm] + axp * x[idx + oxp] + aym * x[idx + oym] + ayp * x[idx + oyp];
             const double ax = st.helmholtz ? xc - st.alpha * lap : lap;
             const double fv = st.f[idx];
             const double r = fv - ax;
             st.r[idx] = (float)r;
             sr += r * r;
             sf += fv * fv;
+            xm = xc;
+            xc = xp;
         }
     }
     block_sum2<RES_NT>(sr, sf, red);
