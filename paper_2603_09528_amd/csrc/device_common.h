@@ -2,9 +2,24 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <hip/hip_ext.h>
+
 #include <cstdint>
 
 #include "kernels.h"
+
+// Launch through hipExtLaunchKernel with the timing events of an open timed
+// scope (first launch only), else a plain launch.
+#define TPT_KLAUNCH(KERNEL, GRID, BLOCK, SHM, STREAM, ...)                                                  \
+    do {                                                                                                    \
+        ::tpt::LaunchEvents& le_ = ::tpt::launch_events();                                                  \
+        if (le_.start && !le_.used) {                                                                       \
+            le_.used = true;                                                                                \
+            hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, SHM, STREAM, le_.start, le_.stop, 0u, __VA_ARGS__);  \
+        } else {                                                                                            \
+            hipLaunchKernelGGL(KERNEL, GRID, BLOCK, SHM, STREAM, __VA_ARGS__);                              \
+        }                                                                                                   \
+    } while (0)
 
 namespace tpt {
 

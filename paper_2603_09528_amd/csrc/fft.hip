@@ -449,11 +449,11 @@ hipError_t launch_ut_t(const FftDesc& d, const FftDesc* d_work, int nwork, long 
     // line data, then W (N/2 entries) and the quarter-wave table (N/2 + 1)
     const size_t sm = (size_t)ut_lines_per_block(d.n, d.ylines) * d.n * sizeof(double) + (size_t)(d.n + 1) * sizeof(double2);
     if (d_work)
-        hipLaunchKernelGGL((ut_multi_kernel<TI, TO, EPI, INV>),
+        TPT_KLAUNCH((ut_multi_kernel<TI, TO, EPI, INV>),
                            dim3((unsigned)(blocks < 4 * PERSISTENT_BLOCKS ? blocks : 4 * PERSISTENT_BLOCKS)),
                            dim3(UT_NT), sm, s, d_work, nwork, blocks);
     else
-        hipLaunchKernelGGL((ut_kernel<TI, TO, EPI, INV>), dim3((unsigned)blocks), dim3(UT_NT), sm, s, d, blocks);
+        TPT_KLAUNCH((ut_kernel<TI, TO, EPI, INV>), dim3((unsigned)blocks), dim3(UT_NT), sm, s, d, blocks);
     return hipGetLastError();
 }
 

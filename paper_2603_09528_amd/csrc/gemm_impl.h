@@ -755,11 +755,11 @@ hipError_t launch_gemm_typed(const GemmDesc& g, const GemmDesc* d_work, int nwor
     do {                                                                                                         \
         constexpr int NT_ = TileCfg<BM_, BN_>::NT;                                                               \
         if (d_work)                                                                                              \
-            hipLaunchKernelGGL((gemm_multi_kernel<PREC, TA, TB, TC, EPI, BM_, BN_, BNK, DEEP_>),                 \
+            TPT_KLAUNCH((gemm_multi_kernel<PREC, TA, TB, TC, EPI, BM_, BN_, BNK, DEEP_>),                 \
                                dim3((unsigned)(blocks < PERSISTENT_BLOCKS ? blocks : PERSISTENT_BLOCKS)),        \
                                dim3(NT_), 0, s, d_work, nwork, blocks);                                          \
         else                                                                                                     \
-            hipLaunchKernelGGL((gemm_kernel<PREC, TA, TB, TC, EPI, BM_, BN_, BNK, DEEP_>),                       \
+            TPT_KLAUNCH((gemm_kernel<PREC, TA, TB, TC, EPI, BM_, BN_, BNK, DEEP_>),                       \
                                dim3((unsigned)blocks), dim3(NT_), 0, s, g);                                      \
     } while (0)
     switch (variant) {
@@ -782,7 +782,7 @@ hipError_t launch_gemm_typed(const GemmDesc& g, const GemmDesc* d_work, int nwor
                 }
                 if (g.M % 128 || g.N % 128 || g.K % 16 || g.K < 16) return hipErrorInvalidValue;
                 const long long grid = persistent_gemm_grid(blocks);
-                hipLaunchKernelGGL((gemm_persist_kernel<PREC, TA, TB, TC, EPI, BNK>), dim3((unsigned)grid), dim3(256),
+                TPT_KLAUNCH((gemm_persist_kernel<PREC, TA, TB, TC, EPI, BNK>), dim3((unsigned)grid), dim3(256),
                                    0, s, g, blocks);
             }
             break;

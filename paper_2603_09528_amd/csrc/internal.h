@@ -113,13 +113,16 @@ void autotune_record(int prec, int stage_kind, int M, int N, int K, int variant)
 
 // ---- kernel timing ------------------------------------------------------------
 bool timing_enabled();
-// Launch wrapper: records events around f() on stream s when timing is on.
+// Scope around one kernel launch on stream s: when timing is on (and s is
+// not capturing a graph) the launch records a pair of events at the kernel's
+// own start and end, collected by tpt_timing_collect under `name`.
 struct TimedScope {
     TimedScope(const char* name, hipStream_t s);
     ~TimedScope();
     const char* name;
     hipStream_t s;
     hipEvent_t e0 = nullptr;
+    hipEvent_t e1 = nullptr;
     bool on = false;
 };
 

@@ -5,6 +5,16 @@
 
 namespace tpt {
 
+// Kernel timing: while a timed scope is open on this thread, the next kernel
+// launch records these events at the kernel's own start and end
+// (hipExtLaunchKernel), so a timed duration is the kernel's execution time.
+struct LaunchEvents {
+    hipEvent_t start = nullptr;
+    hipEvent_t stop = nullptr;
+    bool used = false;
+};
+LaunchEvents& launch_events();  // thread-local
+
 // Element types of GEMM operands/results in global memory.
 enum DType { DT_F64 = 0, DT_F32 = 1 };
 // MFMA arithmetic of a GEMM.

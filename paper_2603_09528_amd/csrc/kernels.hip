@@ -457,8 +457,8 @@ hipError_t launch_thomas(const ThomasDesc& t, hipStream_t s) {
     const size_t sm = THOMAS_LDS_PLANES * sizeof(double) * (size_t)t.nz;
 #define TPT_THOMAS_LAUNCH(TF, TX)                                                                    \
     do {                                                                                           \
-        if (t.periodic) hipLaunchKernelGGL((thomas_kernel<TF, TX, true>), gr, bl, sm, s, t, n);     \
-        else hipLaunchKernelGGL((thomas_kernel<TF, TX, false>), gr, bl, sm, s, t, n);               \
+        if (t.periodic) TPT_KLAUNCH((thomas_kernel<TF, TX, true>), gr, bl, sm, s, t, n);     \
+        else TPT_KLAUNCH((thomas_kernel<TF, TX, false>), gr, bl, sm, s, t, n);               \
     } while (0)
     if (t.tf == DT_F64 && t.tx == DT_F64) TPT_THOMAS_LAUNCH(double, double);
     else if (t.tf == DT_F32 && t.tx == DT_F32) TPT_THOMAS_LAUNCH(float, float);
@@ -473,7 +473,7 @@ hipError_t launch_thomas_multi(const ThomasDesc* d_work, int nwork, long long to
     if (total_blocks <= 0) return hipSuccess;
     const long long grid = std::min(total_blocks, 4 * PERSISTENT_BLOCKS);
     const size_t sm = THOMAS_LDS_PLANES * sizeof(double) * (size_t)nz_max;
-    hipLaunchKernelGGL(thomas_multi_kernel, dim3((unsigned)grid), dim3(THOMAS_NT), sm, s, d_work, nwork,
+    TPT_KLAUNCH(thomas_multi_kernel, dim3((unsigned)grid), dim3(THOMAS_NT), sm, s, d_work, nwork,
                        total_blocks);
     return hipGetLastError();
 }
@@ -573,13 +573,13 @@ __global__ __launch_bounds__(RES_NT) void residual_multi_kernel(const StencilDes
 hipError_t launch_residual(const StencilDesc& st, hipStream_t s) {
     const int nb = residual_blocks(st);
     if (nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(residual_kernel, dim3(nb), dim3(RES_NT), 0, s, st);
+    TPT_KLAUNCH(residual_kernel, dim3(nb), dim3(RES_NT), 0, s, st);
     return hipGetLastError();
 }
 
 hipError_t launch_residual_multi(const StencilDesc* d_work, int nwork, long long total_blocks, hipStream_t s) {
     if (total_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(residual_multi_kernel, dim3((unsigned)std::min(total_blocks, 4 * PERSISTENT_BLOCKS)),
+    TPT_KLAUNCH(residual_multi_kernel, dim3((unsigned)std::min(total_blocks, 4 * PERSISTENT_BLOCKS)),
                        dim3(RES_NT), 0, s, d_work, nwork, total_blocks);
     return hipGetLastError();
 }
@@ -615,13 +615,13 @@ __global__ __launch_bounds__(RED_NT) void reduce_pairs_multi_kernel(const Reduce
 }
 
 hipError_t launch_reduce_pairs(const double* partials, int n, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(reduce_pairs_kernel, dim3(1), dim3(RED_NT), 0, s, partials, n, out);
+    TPT_KLAUNCH(reduce_pairs_kernel, dim3(1), dim3(RED_NT), 0, s, partials, n, out);
     return hipGetLastError();
 }
 
 hipError_t launch_reduce_pairs_multi(const ReduceDesc* d_work, int nwork, hipStream_t s) {
     if (nwork <= 0) return hipSuccess;
-    hipLaunchKernelGGL(reduce_pairs_multi_kernel, dim3(nwork), dim3(RED_NT), 0, s, d_work, nwork);
+    TPT_KLAUNCH(reduce_pairs_multi_kernel, dim3(nwork), dim3(RED_NT), 0, s, d_work, nwork);
     return hipGetLastError();
 }
 
@@ -645,13 +645,13 @@ __global__ void convert_kernel(const double* x, float* y, long long n) {
 
 hipError_t launch_split_bf16(const float* x, uint16_t* hi, uint16_t* lo, long long n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(split_bf16_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, hi, lo, n);
+    TPT_KLAUNCH(split_bf16_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, hi, lo, n);
     return hipGetLastError();
 }
 
 hipError_t launch_convert_f64_f32(const double* x, float* y, long long n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(convert_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, y, n);
+    TPT_KLAUNCH(convert_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, y, n);
     return hipGetLastError();
 }
 

@@ -35,24 +35,45 @@ hipEvent_t get_event() {
 
 bool timing_enabled() { return g_timing; }
 
+LaunchEvents& launch_events() {
+    static thread_local LaunchEvents le;
+    return le;
+}
+
+// A timed scope wraps one kernel launch: it hands a pair of events to that
+// launch (recorded at the kernel's start and end) and keeps the pair.
 TimedScope::TimedScope(const char* n, hipStream_t st) : name(n), s(st) {
     if (!g_timing) return;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
     std::lock_guard<std::mutex> lock(g_timing_mu);
     e0 = get_event();
-    if (!e0) return;
-    if (hipEventRecord(e0, s) != hipSuccess) return;
+    e1 = get_event();
+    if (!e0 || !e1) {
+        if (e0) g_pool.push_back(e0);
+        if (e1) g_pool.push_back(e1);
+        return;
+    }
+    LaunchEvents& le = launch_events();
+    le.start = e0;
+    le.stop = e1;
+    le.used = false;
     on = true;
 }
 
 TimedScope::~TimedScope() {
     if (!on) return;
+    LaunchEvents& le = launch_events();
+    const bool used = le.used;
+    le.start = le.stop = nullptr;
+    le.used = false;
     std::lock_guard<std::mutex> lock(g_timing_mu);
-    hipEvent_t e1 = get_event();
-    if (!e1) return;
-    if (hipEventRecord(e1, s) != hipSuccess) return;
-    g_recs.push_back({name, e0, e1});
+    if (used) {
+        g_recs.push_back({name, e0, e1});
+    } else {
+        g_pool.push_back(e0);
+        g_pool.push_back(e1);
+    }
 }
 
 // ---- GEMM tile selection ---------------------------------------------------------
