@@ -22,35 +22,63 @@
 //   DST-II:  the DCT-II of (-1)^i f_i with the output order reversed, since
 //            sin(pi k (2i+1)/2N) = (-1)^i cos(pi (N-k) (2i+1)/2N).
 // The inverses run the same steps backwards: build the half spectrum, fold it
-// into Z, inverse complex FFT (decimation in frequency: natural order in,
-// bit-reversed out), unpack.  Arithmetic is FP64 whatever the storage types.
+// into Z, inverse complex FFT (conjugate twiddles), unpack.  Arithmetic is
+// FP64 whatever the storage types.
+//
+// Complex FFT of M = 2^m points: radix-2 decimation in time grouped into
+// passes of up to three stages.  A thread holds the 8 points one pass
+// combines in registers (the 2^q points base + k 2^h of a radix-2^q group,
+// pre-multiplied by W_{2^(h+q)}^(b bitrev(k)), b = base mod 2^h, then q
+// radix-2 stages with constant twiddles); the passes exchange points through
+// LDS.  The first pass takes the natural-order input at stride M/2^q, which
+// is where the bit-reversed order of the usual in-place algorithm puts a
+// group, so no separate reordering is needed and the output comes out in
+// natural order.  LDS positions are padded by one complex per sixteen, which
+// keeps the power-of-two strides of the passes off a single bank.
 //
 // Lines are either contiguous (x direction, element stride 1) or strided (y
 // direction: the lines of one z slab are its Nx columns, element stride Nx).
-// A block of 256 threads holds LPB lines in LDS (8N bytes each; 16 KB per
-// block for x lines, 32 KB for y lines).  Loads and stores walk the lines so that consecutive
-// lanes touch consecutive addresses: along a line for x, across lines for y.
-// The pass is memory-bound: 16 B per unknown in FP64.
+// A block holds LPB lines, M/8 threads per line (one thread for M <= 8),
+// 256 threads (128 for N = 2048, one line): 2048 complex points, 34 KB of LDS
+// plus the twiddle tables (four blocks per CU at N = 256).  Eight points per
+// thread rather than sixteen: the register and LDS footprint per thread then
+// allows twice the resident waves, which the memory-bound pass needs more
+// than the fewer LDS round trips of radix 16.  Loads and stores walk the lines so that
+// consecutive lanes touch consecutive addresses: along a line for x (16-byte
+// pairs), across lines for y.  The pass is memory-bound: 16 B per unknown in
+// FP64.
 #include "device_common.h"
 
 namespace tpt {
 
 namespace {
 
-constexpr int UT_NT = 256;
-// Lines per block: 16 KB of line data for contiguous lines, so that several
-// blocks per CU overlap their load, butterfly and store phases; 32 KB for
-// strided lines, whose loads and stores run across the lines of the block
-// (16 lines = 128-byte runs at N = 256).  At most 64 lines; one line at
-// N = 2048, whose twiddle tables take 32 KB.
-__host__ __device__ inline int ut_lines_per_block(int n, int ylines) {
-    if (n >= 2048) return 1;
-    const int l = (ylines ? 4096 : 2048) / n;
-    return l > 64 ? 64 : l;
+constexpr int UT_Q = 3;               // radix-2 stages per pass (points per thread = 2^UT_Q)
+constexpr int UT_NT = 256;            // block size (fewer for N = 2048)
+
+__host__ __device__ inline int ut_log2(int v) {
+    int l = 0;
+    while ((2 << l) <= v) ++l;
+    return l;
+}
+// threads per line, lines per block and block size for real length n
+__host__ __device__ inline int ut_tpl(int n) { return (n >> 1) > (1 << UT_Q) ? (n >> 1) >> UT_Q : 1; }
+__host__ __device__ inline int ut_lines_per_block(int n) { return n >= 2048 ? 1 : UT_NT / ut_tpl(n); }
+__host__ __device__ inline int ut_threads(int n) { return ut_lines_per_block(n) * ut_tpl(n); }
+// LDS line stride in complex points: M plus one pad slot per sixteen
+__host__ __device__ inline int ut_line_stride(int n) { return (n >> 1) + (n >> 5); }
+__host__ __device__ inline size_t ut_lds_bytes(int n) {
+    // line data, then W (N/2 entries) and the quarter-wave table (N/2 + 1)
+    return ((size_t)ut_lines_per_block(n) * ut_line_stride(n) + (size_t)n + 1) * sizeof(double2);
 }
 
-__device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }
-__device__ __forceinline__ int bitrev(int v, int bits) { return (int)(__brev((unsigned)v) >> (32 - bits)); }
+__device__ __forceinline__ int pad16(int c) { return c + (c >> 4); }
+__device__ __forceinline__ int bitrev(int v, int bits) { return bits ? (int)(__brev((unsigned)v) >> (32 - bits)) : 0; }
+__host__ __device__ constexpr int brev_c(int v, int bits) {
+    int r = 0;
+    for (int i = 0; i < bits; ++i) r |= ((v >> i) & 1) << (bits - 1 - i);
+    return r;
+}
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -60,11 +88,146 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_doub
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
 
+// cos and sin of 2 pi e / 16, e = 0 .. 7
+__host__ __device__ constexpr double w16c(int e) {
+    return e == 0 ? 1.0 : e == 1 ? 0.92387953251128674 : e == 2 ? 0.70710678118654752 : e == 3 ? 0.38268343236508977
+         : e == 4 ? 0.0 : e == 5 ? -0.38268343236508977 : e == 6 ? -0.70710678118654752 : -0.92387953251128674;
+}
+__host__ __device__ constexpr double w16s(int e) {
+    return e == 0 ? 0.0 : e == 1 ? 0.38268343236508977 : e == 2 ? 0.70710678118654752 : e == 3 ? 0.92387953251128674
+         : e == 4 ? 1.0 : e == 5 ? 0.92387953251128674 : e == 6 ? 0.70710678118654752 : 0.38268343236508977;
+}
+// a W_16^e (forward, W_16 = e^{-2 pi i/16}) or a conj(W_16^e) (inverse);
+// e is a constant after unrolling, so the trivial cases cost nothing
+template <bool INV>
+__device__ __forceinline__ double2 w16mul(double2 a, int e) {
+    if (e == 0) return a;
+    if (e == 4) return INV ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
+    const double c = w16c(e), s = INV ? w16s(e) : -w16s(e);
+    return make_double2(a.x * c - a.y * s, a.x * s + a.y * c);
+}
+
+// In-register radix-2 decimation in time over 2^Q points: input in
+// bit-reversed order, output natural, unnormalised.
+template <int Q, bool INV>
+__device__ __forceinline__ void dit_regs(double2* x) {
+#pragma unroll
+    for (int s = 0; s < Q; ++s) {
+        const int half = 1 << s;
+#pragma unroll
+        for (int b = 0; b < (1 << Q); b += 2 * half) {
+#pragma unroll
+            for (int p = 0; p < half; ++p) {
+                const double2 u = x[b + p], v = w16mul<INV>(x[b + p + half], p << (3 - s));
+                x[b + p] = cadd(u, v);
+                x[b + p + half] = csub(u, v);
+            }
+        }
+    }
+}
+
+// Inverse input fold: Z_n = E_n + i O_n from the half spectrum F (natural
+// order, F_M in the imaginary part of slot 0), E_n = (F_n + conj F_{M-n})/2,
+// O_n = conj(W^n) (F_n - conj F_{M-n})/2.
+__device__ __forceinline__ double2 ut_fold(const double2* a, int n, int M, const double2* W) {
+    if (n == 0) {
+        const double2 f = a[0];
+        return make_double2(0.5 * (f.x + f.y), 0.5 * (f.x - f.y));
+    }
+    const double2 fm = a[pad16(n)], fc = conj2(a[pad16(M - n)]);
+    const double2 E = cscale(cadd(fm, fc), 0.5);
+    const double2 O = cmul(conj2(W[n]), cscale(csub(fm, fc), 0.5));
+    return make_double2(E.x - O.y, E.y + O.x);
+}
+
+// First pass: Q0 stages, 2^(Q-Q0) groups per thread.  Group g reads the
+// natural-order points g + j M/2^Q0 and, after a barrier (the writes land
+// where other groups read), writes its outputs to base + j, base =
+// bitrev(g) 2^Q0.
+template <int Q, int Q0, bool INV>
+__device__ __forceinline__ void ut_pass0(double2* a, int t, int T, int mlog, const double2* W) {
+    constexpr int R0 = 1 << (Q - Q0), P0 = 1 << Q0;
+    const int M = 1 << mlog, G0 = M >> Q0;
+    double2 x[1 << Q];
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+        const int g = t + r * T;
+#pragma unroll
+        for (int j = 0; j < P0; ++j) {
+            const int n = g + j * G0;
+            x[r * P0 + brev_c(j, Q0)] = INV ? ut_fold(a, n, M, W) : a[pad16(n)];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+        dit_regs<Q0, INV>(x + r * P0);
+        const int base = bitrev(t + r * T, mlog - Q0) << Q0;
+#pragma unroll
+        for (int j = 0; j < P0; ++j) a[pad16(base + j)] = x[r * P0 + j];
+    }
+    __syncthreads();
+}
+
+// Later passes (UT_Q stages from span 2^h): one group per thread, read and
+// written in place.
+template <bool INV>
+__device__ __forceinline__ void ut_passk(double2* a, int t, int mlog, int h, const double2* W) {
+    constexpr int Q = UT_Q, P = 1 << Q;
+    const int blo = t & ((1 << h) - 1);
+    const int base = blo | ((t >> h) << (h + Q));
+    const int idx1 = blo << (mlog + 1 - h - Q);  // W_{2^(h+Q)}^blo = W_N^idx1
+    double2 tw[P];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const double2 w = W[idx1 << i];  // idx1 << (Q-1) < M
+        tw[1 << i] = INV ? conj2(w) : w;
+    }
+#pragma unroll
+    for (int k = 3; k < P; ++k)
+        if (k & (k - 1)) {
+            const int hb = 1 << (31 - __builtin_clz(k));
+            tw[k] = cmul(tw[hb], tw[k - hb]);
+        }
+    double2 x[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) x[k] = a[pad16(base + (k << h))];
+#pragma unroll
+    for (int k = 1; k < P; ++k) x[k] = cmul(x[k], tw[brev_c(k, Q)]);
+    dit_regs<Q, INV>(x);
+#pragma unroll
+    for (int j = 0; j < P; ++j) a[pad16(base + (j << h))] = x[j];
+    __syncthreads();
+}
+
+// Complex FFT of the block's lines in LDS, natural order in and out.  Every
+// thread of the block takes part (the passes hold barriers); INV folds the
+// half spectrum on the first read and uses conjugate twiddles.
+template <bool INV>
+__device__ __forceinline__ void ut_cfft(double2* lds, int ls, int mlog, const double2* W) {
+    const int Q = mlog < UT_Q ? mlog : UT_Q;
+    const int tlog = mlog - Q, T = 1 << tlog;
+    const int l = threadIdx.x >> tlog, t = threadIdx.x & (T - 1);
+    double2* a = lds + (size_t)l * ls;
+    const int npass = (mlog + Q - 1) / Q, q0 = mlog - (npass - 1) * Q;
+    if (Q < UT_Q) {  // short lines: one pass of mlog = Q stages
+        if (Q == 2) ut_pass0<2, 2, INV>(a, t, T, mlog, W);
+        else if constexpr (UT_Q > 3) ut_pass0<3, 3, INV>(a, t, T, mlog, W);
+    } else if (q0 == 1) ut_pass0<UT_Q, 1, INV>(a, t, T, mlog, W);
+    else if constexpr (UT_Q == 2) ut_pass0<UT_Q, 2, INV>(a, t, T, mlog, W);
+    else if (q0 == 2) ut_pass0<UT_Q, 2, INV>(a, t, T, mlog, W);
+    else if constexpr (UT_Q == 3) ut_pass0<UT_Q, 3, INV>(a, t, T, mlog, W);
+    else if (q0 == 3) ut_pass0<UT_Q, 3, INV>(a, t, T, mlog, W);
+    else ut_pass0<UT_Q, 4, INV>(a, t, T, mlog, W);
+    for (int h = q0; h < mlog; h += UT_Q) ut_passk<INV>(a, t, mlog, h, W);
+}
+
 // Block geometry.  All sizes are powers of two, so work items map to (line,
 // index) with shifts and masks.  Strided (y) lines: a thread always serves
-// the same line (lpb divides the block size), whose start is computed once.
+// the same line in the load and store phases (lpb divides the block size),
+// whose start is computed once.
 struct UtGeom {
-    int N, M, nlog, mlog, lpb, llog;
+    int N, M, nlog, mlog, lpb, llog, nt, ls;
     long long line0;
     int ly;          // y lines: this thread's line in the block
     long long ybase; // y lines: offset of element 0 of that line
@@ -75,10 +238,12 @@ __device__ __forceinline__ UtGeom ut_geom(const FftDesc& d, long long blk) {
     UtGeom g;
     g.N = d.n;
     g.M = d.n >> 1;
-    g.nlog = ilog2(g.N);
+    g.nlog = ut_log2(g.N);
     g.mlog = g.nlog - 1;
-    g.lpb = ut_lines_per_block(g.N, d.ylines);
-    g.llog = ilog2(g.lpb);
+    g.lpb = ut_lines_per_block(g.N);
+    g.llog = ut_log2(g.lpb);
+    g.nt = ut_threads(g.N);
+    g.ls = ut_line_stride(g.N);
     g.line0 = blk << g.llog;
     g.ly = threadIdx.x & (g.lpb - 1);
     g.ybase = 0;
@@ -121,164 +286,131 @@ __device__ __forceinline__ int ut_vpos(int kind, int n, int e) {
     if (kind == UT_FOURIER) return e;
     return (e & 1) ? n - 1 - (e >> 1) : (e >> 1);
 }
-
-// Forward decimation in time over M points per line (bit-reversed in,
-// natural out).  Radix-2 stages are taken in pairs: a thread owns the four
-// points that stages L and 2L combine (one LDS round trip and one barrier per
-// pair); an odd stage count starts with one plain radix-2 stage (L = 2,
-// twiddle 1).
-__device__ __forceinline__ void ut_dit(double2* lds, const UtGeom& g, const double2* __restrict__ W) {
-    const int glog = 8 - g.llog;  // threads per line: 256 / lpb
-    const int l = threadIdx.x >> glog, t = threadIdx.x & ((1 << glog) - 1);
-    double2* a = lds + ((size_t)l << g.mlog);
-    int hlog = 0;
-    if (g.mlog & 1) {
-#pragma unroll 4
-        for (int b = t; b < (g.M >> 1); b += (1 << glog)) {
-            const double2 u = a[2 * b], v = a[2 * b + 1];
-            a[2 * b] = cadd(u, v);
-            a[2 * b + 1] = csub(u, v);
-        }
-        __syncthreads();
-        hlog = 1;
-    }
-    for (; hlog < g.mlog; hlog += 2) {
-        const int half = 1 << hlog, L = half << 1;
-        const int s1 = g.nlog - hlog - 1;  // twiddle stride N / L
-        const int s2 = s1 - 1;             // N / 2L
-#pragma unroll 2
-        for (int b = t; b < (g.M >> 2); b += (1 << glog)) {
-            const int p = b & (half - 1);
-            const int i0 = ((b >> hlog) << (hlog + 2)) + p, i1 = i0 + half, i2 = i0 + L, i3 = i2 + half;
-            double2 x0 = a[i0], x1 = a[i1], x2 = a[i2], x3 = a[i3];
-            const double2 w1 = W[p << s1], w2 = W[p << s2], w3 = W[(p + half) << s2];
-            double2 u = cmul(x1, w1);
-            x1 = csub(x0, u);
-            x0 = cadd(x0, u);
-            u = cmul(x3, w1);
-            x3 = csub(x2, u);
-            x2 = cadd(x2, u);
-            u = cmul(x2, w2);
-            x2 = csub(x0, u);
-            x0 = cadd(x0, u);
-            u = cmul(x3, w3);
-            x3 = csub(x1, u);
-            x1 = cadd(x1, u);
-            a[i0] = x0;
-            a[i1] = x1;
-            a[i2] = x2;
-            a[i3] = x3;
-        }
-        __syncthreads();
-    }
-}
-
-// Inverse complex FFT (conjugate twiddles), decimation in frequency: natural
-// in, bit-reversed out, unnormalised.  Stages L and L/2 taken in pairs as in
-// ut_dit; an odd stage count ends with one radix-2 stage (L = 2).
-__device__ __forceinline__ void ut_dif_inv(double2* lds, const UtGeom& g, const double2* __restrict__ W) {
-    const int glog = 8 - g.llog;
-    const int l = threadIdx.x >> glog, t = threadIdx.x & ((1 << glog) - 1);
-    double2* a = lds + ((size_t)l << g.mlog);
-    int hlog = g.mlog - 1;  // stage span L = 2^(hlog + 1)
-    for (; hlog >= 1; hlog -= 2) {
-        const int q4 = 1 << (hlog - 1);    // L / 4
-        const int sa = g.nlog - hlog - 1;  // twiddle stride N / L
-        const int sc = sa + 1;             // 2N / L
-#pragma unroll 2
-        for (int b = t; b < (g.M >> 2); b += (1 << glog)) {
-            const int p = b & (q4 - 1);
-            const int i0 = ((b >> (hlog - 1)) << (hlog + 1)) + p, i1 = i0 + q4, i2 = i1 + q4, i3 = i2 + q4;
-            double2 x0 = a[i0], x1 = a[i1], x2 = a[i2], x3 = a[i3];
-            const double2 wa = conj2(W[p << sa]), wb = conj2(W[(p + q4) << sa]), wc = conj2(W[p << sc]);
-            double2 d = csub(x0, x2);
-            x0 = cadd(x0, x2);
-            x2 = cmul(d, wa);
-            d = csub(x1, x3);
-            x1 = cadd(x1, x3);
-            x3 = cmul(d, wb);
-            d = csub(x0, x1);
-            x0 = cadd(x0, x1);
-            x1 = cmul(d, wc);
-            d = csub(x2, x3);
-            x2 = cadd(x2, x3);
-            x3 = cmul(d, wc);
-            a[i0] = x0;
-            a[i1] = x1;
-            a[i2] = x2;
-            a[i3] = x3;
-        }
-        __syncthreads();
-    }
-    if (hlog == 0) {
-#pragma unroll 4
-        for (int b = t; b < (g.M >> 1); b += (1 << glog)) {
-            const double2 u = a[2 * b], v = a[2 * b + 1];
-            a[2 * b] = cadd(u, v);
-            a[2 * b + 1] = csub(u, v);
-        }
-        __syncthreads();
-    }
+// LDS double index of v_j in line l (v_j is part j%2 of complex point j/2)
+__device__ __forceinline__ int ut_vslot(const UtGeom& g, int l, int j) {
+    return 2 * (l * g.ls + pad16(j >> 1)) + (j & 1);
 }
 
 // Copy the twiddle tables of the descriptor into LDS (after the line data):
 // W^k (k < N/2) and, for the cosine and sine transforms, e^{-i pi k/2N}
-// (k <= N/2).  Returns the LDS copies; the caller synchronises.
+// (k <= N/2).  The caller synchronises.
 __device__ __forceinline__ void ut_tables(const FftDesc& d, const UtGeom& g, double2* lds, double2*& W,
                                           double2*& Q) {
-    W = lds + ((size_t)g.lpb << g.mlog);
+    W = lds + (size_t)g.lpb * g.ls;
     Q = W + g.M;
-    for (int k = threadIdx.x; k < g.M; k += UT_NT) W[k] = d.twiddle[k];
+    for (int k = threadIdx.x; k < g.M; k += g.nt) W[k] = d.twiddle[k];
     if (d.kind != UT_FOURIER)
-        for (int k = threadIdx.x; k <= g.M; k += UT_NT) Q[k] = d.qtw[k];
+        for (int k = threadIdx.x; k <= g.M; k += g.nt) Q[k] = d.qtw[k];
 }
+
+template <typename T> struct Pair2;
+template <> struct Pair2<double> { typedef double2 type; };
+template <> struct Pair2<float> { typedef float2 type; };
 
 template <typename TI, typename TO>
 __device__ __forceinline__ void ut_forward(const FftDesc& d, long long blk, double2* lds) {
     const UtGeom g = ut_geom(d, blk);
     double2 *W, *Q;
     ut_tables(d, g, lds, W, Q);
-    const int N = g.N, M = g.M, bits = g.mlog, kind = d.kind;
+    const int N = g.N, M = g.M, kind = d.kind;
     const TI* in = (const TI*)d.in;
     TO* out = (TO*)d.out;
     double* ldsd = (double*)lds;
-    // 1) load into bit-reversed complex slots (v_j -> slot j/2, part j%2);
-    //    up to sixteen loads in flight per thread before the LDS stores
-    constexpr int UL = 16;
-    const int total = g.lpb << g.nlog;
-    for (int base = 0; base < total; base += UL * UT_NT) {
-        double v[UL];
-        int pos[UL];
+    // 1) load v in natural order (DST: (-1)^e f_e)
+    if (!d.ylines) {
+        // contiguous lines: element pairs (2c, 2c+1), 16 (FP64) or 8 (FP32)
+        // bytes per lane when the line data is aligned to it
+        constexpr int UL = 1 << UT_Q;
+        const int total = g.lpb << g.mlog;  // pairs in the block
+        const bool vec = ((uintptr_t)in % sizeof(typename Pair2<TI>::type)) == 0;
+        for (int base = 0; base < total; base += UL * g.nt) {
+            double2 v[UL];
 #pragma unroll
-        for (int u = 0; u < UL; ++u) {
-            const int idx = base + u * UT_NT + (int)threadIdx.x;
-            int l, e;
-            ut_item(d, g, g.nlog, idx, l, e);
-            pos[u] = -1;
-            v[u] = 0.0;
-            if (idx < total && ut_valid(d, g, l)) {
-                double x = (double)in[ut_off(d, g, l, e)];
-                if (kind == UT_DST && (e & 1)) x = -x;
-                const int j = ut_vpos(kind, N, e);
-                pos[u] = (l << g.nlog) + 2 * bitrev(j >> 1, bits) + (j & 1);
-                v[u] = x;
+            for (int u = 0; u < UL; ++u) {
+                const int idx = base + u * g.nt + (int)threadIdx.x;
+                const int l = idx >> g.mlog, c = idx & (M - 1);
+                v[u] = make_double2(0.0, 0.0);
+                if (idx < total && g.line0 + l < d.lines) {
+                    const long long o = ((g.line0 + l) << g.nlog) + 2 * c;
+                    if (vec) {
+                        const typename Pair2<TI>::type p = *(const typename Pair2<TI>::type*)(in + o);
+                        v[u] = make_double2((double)p.x, (double)p.y);
+                    } else {
+                        v[u] = make_double2((double)in[o], (double)in[o + 1]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < UL; ++u) {
+                const int idx = base + u * g.nt + (int)threadIdx.x;
+                if (idx >= total) continue;
+                const int l = idx >> g.mlog, c = idx & (M - 1);
+                if (kind == UT_FOURIER) {
+                    lds[l * g.ls + pad16(c)] = v[u];
+                } else {
+                    // v_c = f_2c, v_{N-1-c} = f_2c+1 (negated for DST)
+                    ldsd[ut_vslot(g, l, c)] = v[u].x;
+                    ldsd[ut_vslot(g, l, N - 1 - c)] = kind == UT_DST ? -v[u].y : v[u].y;
+                }
             }
         }
+    } else {
+        constexpr int UL = 16;
+        const int total = g.lpb << g.nlog;
+        for (int base = 0; base < total; base += UL * g.nt) {
+            double v[UL];
 #pragma unroll
-        for (int u = 0; u < UL; ++u)
-            if (pos[u] >= 0) ldsd[pos[u]] = v[u];
+            for (int u = 0; u < UL; ++u) {
+                const int idx = base + u * g.nt + (int)threadIdx.x;
+                const int e = idx >> g.llog;
+                v[u] = 0.0;
+                if (idx < total && g.yvalid) v[u] = (double)in[g.ybase + (long long)e * d.s_elem];
+            }
+#pragma unroll
+            for (int u = 0; u < UL; ++u) {
+                const int idx = base + u * g.nt + (int)threadIdx.x;
+                if (idx >= total) continue;
+                const int e = idx >> g.llog;
+                const double x = (kind == UT_DST && (e & 1)) ? -v[u] : v[u];
+                ldsd[ut_vslot(g, g.ly, ut_vpos(kind, N, e))] = x;
+            }
+        }
     }
     __syncthreads();
-    // 2) complex FFT
-    ut_dit(lds, g, W);
-    // 3) half spectrum and outputs, from LDS straight to memory; item m = 0
-    //    also writes the output of V_M
+    // 2) complex FFT of z_n = v_2n + i v_2n+1
+    ut_cfft<false>(lds, g.ls, g.mlog, W);
+    // 3) half spectrum and outputs, from LDS straight to memory
     const double s = d.scale;
-    for (int idx = threadIdx.x; idx < (g.lpb << g.mlog); idx += UT_NT) {
+    if (kind == UT_FOURIER && !d.ylines && ((uintptr_t)out % sizeof(typename Pair2<TO>::type)) == 0) {
+        // contiguous lines: item p writes the output pair (2p, 2p+1) =
+        // (-Im V_p, Re V_{p+1}) scaled, with V_0 and V_M at the two ends
+        const double c0 = s / sqrt((double)N), c1 = s * sqrt(2.0 / N);
+        for (int idx = threadIdx.x; idx < (g.lpb << g.mlog); idx += g.nt) {
+            const int l = idx >> g.mlog, p = idx & (M - 1);
+            if (g.line0 + l >= d.lines) continue;
+            const double2* a = lds + (size_t)l * g.ls;
+            auto vm = [&](int m) {  // V_m, 0 < m < M
+                const double2 zm = a[pad16(m)], zc = conj2(a[pad16(M - m)]);
+                const double2 e = cscale(cadd(zm, zc), 0.5);
+                const double2 t = cmul(W[m], cscale(csub(zm, zc), 0.5));
+                return make_double2(e.x + t.y, e.y - t.x);
+            };
+            const double2 z0 = a[0];
+            const double lo = p == 0 ? c0 * (z0.x + z0.y) : -c1 * vm(p).y;
+            const double hi = p == M - 1 ? c0 * (z0.x - z0.y) : c1 * vm(p + 1).x;
+            typename Pair2<TO>::type o;
+            o.x = (TO)lo;
+            o.y = (TO)hi;
+            *(typename Pair2<TO>::type*)(out + ((g.line0 + l) << g.nlog) + 2 * p) = o;
+        }
+        return;
+    }
+    // item m = 0 also writes the output of V_M
+    for (int idx = threadIdx.x; idx < (g.lpb << g.mlog); idx += g.nt) {
         int l, m;
         ut_item(d, g, g.mlog, idx, l, m);
         if (!ut_valid(d, g, l)) continue;
-        const double2* a = lds + ((size_t)l << g.mlog);
+        const double2* a = lds + (size_t)l * g.ls;
         if (kind == UT_FOURIER) {
             const double c0 = s / sqrt((double)N), c1 = s * sqrt(2.0 / N);
             if (m == 0) {
@@ -286,7 +418,7 @@ __device__ __forceinline__ void ut_forward(const FftDesc& d, long long blk, doub
                 out[ut_off(d, g, l, 0)] = (TO)(c0 * (z0.x + z0.y));      // V_0 = Re Z_0 + Im Z_0
                 out[ut_off(d, g, l, N - 1)] = (TO)(c0 * (z0.x - z0.y));  // V_M = Re Z_0 - Im Z_0
             } else {
-                const double2 zm = a[m], zc = conj2(a[M - m]);
+                const double2 zm = a[pad16(m)], zc = conj2(a[pad16(M - m)]);
                 const double2 e = cscale(cadd(zm, zc), 0.5);
                 const double2 t = cmul(W[m], cscale(csub(zm, zc), 0.5));
                 // V_m = e - i t; column 2m-1 takes Re V_m, column 2m takes -Im V_m
@@ -302,7 +434,7 @@ __device__ __forceinline__ void ut_forward(const FftDesc& d, long long blk, doub
                 // X_M = cos(pi/4) V_M
                 out[ut_off(d, g, l, rev ? N - 1 - M : M)] = (TO)(cb * sqrt(0.5) * (z0.x - z0.y));
             } else {
-                const double2 zm = a[m], zc = conj2(a[M - m]);
+                const double2 zm = a[pad16(m)], zc = conj2(a[pad16(M - m)]);
                 const double2 e = cscale(cadd(zm, zc), 0.5);
                 const double2 t = cmul(W[m], cscale(csub(zm, zc), 0.5));
                 const double2 r = cmul(Q[m], make_double2(e.x + t.y, e.y - t.x));  // e^{-i pi m/2N} V_m
@@ -313,85 +445,161 @@ __device__ __forceinline__ void ut_forward(const FftDesc& d, long long blk, doub
     }
 }
 
+// Sum (a, b) over a block of nt threads (a multiple of 64, at most 128) in a
+// fixed order; thread 0 gets the result.
+__device__ __forceinline__ void ut_block_sum2(double& a, double& b, double* red, int nt) {
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+    __syncthreads();
+    if (l == 0) {
+        red[2 * w] = a;
+        red[2 * w + 1] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sa = 0.0, sb = 0.0;
+        for (int i = 0; i < nt / 64; ++i) {
+            sa += red[2 * i];
+            sb += red[2 * i + 1];
+        }
+        a = sa;
+        b = sb;
+    }
+}
+
 template <typename TI, typename TO, int EPI>
 __device__ __forceinline__ void ut_inverse(const FftDesc& d, long long blk, double2* lds, double* red) {
     const UtGeom g = ut_geom(d, blk);
     double2 *W, *Q;
     ut_tables(d, g, lds, W, Q);
     __syncthreads();
-    const int N = g.N, M = g.M, bits = g.mlog, kind = d.kind;
+    const int N = g.N, M = g.M, kind = d.kind;
     const TI* in = (const TI*)d.in;
     const double s = d.scale;  // 1 / sqrt(h)
     // 1) half spectrum F_m, m = 0 .. M-1, in natural order; F_0 and F_M are
-    //    real, and F_M rides in the imaginary part of slot 0
-    for (int idx = threadIdx.x; idx < (g.lpb << g.mlog); idx += UT_NT) {
-        int l, m;
-        ut_item(d, g, g.mlog, idx, l, m);
-        double2 F = make_double2(0.0, 0.0);
-        if (ut_valid(d, g, l)) {
+    //    real, and F_M rides in the imaginary part of slot 0.  Inputs of up
+    //    to eight items are loaded before they are combined.
+    constexpr int UL = 1 << UT_Q;
+    const int total = g.lpb << g.mlog;
+    if (kind == UT_FOURIER && !d.ylines && ((uintptr_t)in % sizeof(typename Pair2<TI>::type)) == 0) {
+        // contiguous lines: item p loads the input pair (2p, 2p+1); 2p is
+        // -Im F_p / cH (Re F_0 / cN for p = 0) and 2p+1 is Re F_{p+1} / cH
+        // (Im F_0 / cN for p = M-1: F_M rides in slot 0)
+        const double cN = s * sqrt((double)N), cH = s * sqrt(0.5 * N);
+        double* ldsd = (double*)lds;
+        for (int base = 0; base < total; base += UL * g.nt) {
+            double2 v[UL];
+#pragma unroll
+            for (int u = 0; u < UL; ++u) {
+                const int idx = base + u * g.nt + (int)threadIdx.x;
+                const int l = idx >> g.mlog, p = idx & (M - 1);
+                v[u] = make_double2(0.0, 0.0);
+                if (idx < total && g.line0 + l < d.lines) {
+                    const typename Pair2<TI>::type q =
+                        *(const typename Pair2<TI>::type*)(in + ((g.line0 + l) << g.nlog) + 2 * p);
+                    v[u] = make_double2((double)q.x, (double)q.y);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < UL; ++u) {
+                const int idx = base + u * g.nt + (int)threadIdx.x;
+                if (idx >= total) continue;
+                const int l = idx >> g.mlog, p = idx & (M - 1);
+                const int row = 2 * l * g.ls;
+                if (p == 0) ldsd[row] = cN * v[u].x;
+                else ldsd[row + 2 * pad16(p) + 1] = -cH * v[u].x;
+                if (p == M - 1) ldsd[row + 1] = cN * v[u].y;
+                else ldsd[row + 2 * pad16(p + 1)] = cH * v[u].y;
+            }
+        }
+    } else
+    for (int base = 0; base < total; base += UL * g.nt) {
+        double p0[UL], p1[UL];
+#pragma unroll
+        for (int u = 0; u < UL; ++u) {
+            const int idx = base + u * g.nt + (int)threadIdx.x;
+            int l, m;
+            ut_item(d, g, g.mlog, idx, l, m);
+            p0[u] = 0.0;
+            p1[u] = 0.0;
+            if (idx < total && ut_valid(d, g, l)) {
+                int k0, k1;
+                if (kind == UT_FOURIER) {
+                    k0 = m == 0 ? 0 : 2 * m - 1;
+                    k1 = m == 0 ? N - 1 : 2 * m;
+                } else {
+                    // X_k at k = m and N - m (m = 0: X_0 and X_M); DST reads reversed
+                    k0 = m;
+                    k1 = m == 0 ? M : N - m;
+                    if (kind == UT_DST) {
+                        k0 = N - 1 - k0;
+                        k1 = N - 1 - k1;
+                    }
+                }
+                p0[u] = (double)in[ut_off(d, g, l, k0)];
+                p1[u] = (double)in[ut_off(d, g, l, k1)];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < UL; ++u) {
+            const int idx = base + u * g.nt + (int)threadIdx.x;
+            if (idx >= total) continue;
+            int l, m;
+            ut_item(d, g, g.mlog, idx, l, m);
+            double2 F;
             if (kind == UT_FOURIER) {
                 const double cN = s * sqrt((double)N), cH = s * sqrt(0.5 * N);
-                if (m == 0)
-                    F = make_double2(cN * (double)in[ut_off(d, g, l, 0)], cN * (double)in[ut_off(d, g, l, N - 1)]);
-                else
-                    F = make_double2(cH * (double)in[ut_off(d, g, l, 2 * m - 1)],
-                                     -cH * (double)in[ut_off(d, g, l, 2 * m)]);
+                F = m == 0 ? make_double2(cN * p0[u], cN * p1[u]) : make_double2(cH * p0[u], -cH * p1[u]);
             } else {
-                // X_k = s c_k phihat_k (DST: phihat read in reverse), X_0 doubled
-                const bool rev = kind == UT_DST;
+                // X_k = s c_k phihat_k, X_0 doubled; V_0 = X_0, V_M = sqrt(2) X_M,
+                // V_m = e^{i pi m/2N} (X_m - i X_{N-m})
                 const double ca = s * sqrt(1.0 / N), cb = s * sqrt(2.0 / N);
-                auto X = [&](int k) -> double {
-                    return (k == 0 ? 2.0 * ca : cb) * (double)in[ut_off(d, g, l, rev ? N - 1 - k : k)];
-                };
-                if (m == 0)
-                    F = make_double2(X(0), sqrt(2.0) * X(M));  // V_0 = X_0, V_M = sqrt(2) X_M
-                else
-                    F = cmul(conj2(Q[m]), make_double2(X(m), -X(N - m)));  // e^{i pi m/2N}(X_m - i X_{N-m})
+                F = m == 0 ? make_double2(2.0 * ca * p0[u], sqrt(2.0) * cb * p1[u])
+                           : cmul(conj2(Q[m]), make_double2(cb * p0[u], -cb * p1[u]));
             }
-        }
-        lds[((size_t)l << g.mlog) + m] = F;
-    }
-    __syncthreads();
-    // 2) fold the pairs (m, M-m) into Z_m = E_m + i O_m in place, with
-    //    E_m = (F_m + conj F_{M-m})/2 and O_m = conj(W^m) (F_m - conj F_{M-m})/2;
-    //    item 0 folds slot 0 and the self-paired slot M/2
-    for (int idx = threadIdx.x; idx < (g.lpb << (g.mlog - 1)); idx += UT_NT) {
-        const int l = idx >> (g.mlog - 1), m0 = idx & ((M >> 1) - 1);
-        double2* a = lds + ((size_t)l << g.mlog);
-        for (int rep = 0; rep < (m0 == 0 ? 2 : 1); ++rep) {
-            const int m = rep == 0 ? m0 : (M >> 1);
-            if (m == 0) {
-                const double f0 = a[0].x, fM = a[0].y;
-                a[0] = make_double2(0.5 * (f0 + fM), 0.5 * (f0 - fM));
-                continue;
-            }
-            const int mc = M - m;
-            const double2 fm = a[m], fc = a[mc];
-            const double2 Em = cscale(cadd(fm, conj2(fc)), 0.5);
-            const double2 Om = cmul(conj2(W[m]), cscale(csub(fm, conj2(fc)), 0.5));
-            if (mc != m) {
-                // E_{M-m} = conj E_m and conj(W^{M-m}) = -W^m
-                const double2 Ec = conj2(Em);
-                const double2 Oc = cmul(cscale(W[m], -1.0), cscale(csub(fc, conj2(fm)), 0.5));
-                a[mc] = make_double2(Ec.x - Oc.y, Ec.y + Oc.x);
-            }
-            a[m] = make_double2(Em.x - Om.y, Em.y + Om.x);
+            lds[(size_t)l * g.ls + pad16(m)] = F;
         }
     }
     __syncthreads();
-    // 3) inverse complex FFT, natural in, bit-reversed out
-    ut_dif_inv(lds, g, W);
-    // 4) unpack and store
+    // 2) fold into Z and inverse complex FFT, natural order out
+    ut_cfft<true>(lds, g.ls, g.mlog, W);
+    // 3) unpack and store
     const double* ldsd = (const double*)lds;
     const double post = (kind == UT_FOURIER) ? 1.0 / M : 1.0;
     TO* out = (TO*)d.out;
     double se = 0.0, sx = 0.0;
-    for (int idx = threadIdx.x; idx < (g.lpb << g.nlog); idx += UT_NT) {
+    if (!d.ylines && ((uintptr_t)out % sizeof(typename Pair2<TO>::type)) == 0) {
+        // contiguous lines: item c stores the output pair (2c, 2c+1)
+        for (int idx = threadIdx.x; idx < (g.lpb << g.mlog); idx += g.nt) {
+            const int l = idx >> g.mlog, c = idx & (M - 1);
+            if (g.line0 + l >= d.lines) continue;
+            double v0 = ldsd[ut_vslot(g, l, ut_vpos(kind, N, 2 * c))] * post;
+            double v1 = ldsd[ut_vslot(g, l, ut_vpos(kind, N, 2 * c + 1))] * post;
+            if (kind == UT_DST) v1 = -v1;
+            typename Pair2<TO>::type* o = (typename Pair2<TO>::type*)(out + ((g.line0 + l) << g.nlog) + 2 * c);
+            if constexpr (EPI == EPI_ACCUM_F64) {
+                const typename Pair2<TO>::type prev = *o;
+                const double x0 = (double)prev.x + v0, x1 = (double)prev.y + v1;
+                typename Pair2<TO>::type r;
+                r.x = (TO)x0;
+                r.y = (TO)x1;
+                *o = r;
+                se += v0 * v0 + v1 * v1;
+                sx += x0 * x0 + x1 * x1;
+            } else {
+                typename Pair2<TO>::type r;
+                r.x = (TO)v0;
+                r.y = (TO)v1;
+                *o = r;
+            }
+        }
+    } else
+    for (int idx = threadIdx.x; idx < (g.lpb << g.nlog); idx += g.nt) {
         int l, e;
         ut_item(d, g, g.nlog, idx, l, e);
         if (!ut_valid(d, g, l)) continue;
-        const int j = ut_vpos(kind, N, e);
-        double v = ldsd[(l << g.nlog) + 2 * bitrev(j >> 1, bits) + (j & 1)] * post;
+        double v = ldsd[ut_vslot(g, l, ut_vpos(kind, N, e))] * post;
         if (kind == UT_DST && (e & 1)) v = -v;
         const long long o = ut_off(d, g, l, e);
         if constexpr (EPI == EPI_ACCUM_F64) {
@@ -404,7 +612,7 @@ __device__ __forceinline__ void ut_inverse(const FftDesc& d, long long blk, doub
         }
     }
     if constexpr (EPI == EPI_ACCUM_F64) {
-        block_sum2<UT_NT>(se, sx, red);
+        ut_block_sum2(se, sx, red, g.nt);
         if (threadIdx.x == 0) {
             d.partials[2 * blk] = se;
             d.partials[2 * blk + 1] = sx;
@@ -446,14 +654,14 @@ __global__ __launch_bounds__(UT_NT) void ut_multi_kernel(const FftDesc* __restri
 
 template <typename TI, typename TO, int EPI, bool INV>
 hipError_t launch_ut_t(const FftDesc& d, const FftDesc* d_work, int nwork, long long blocks, hipStream_t s) {
-    // line data, then W (N/2 entries) and the quarter-wave table (N/2 + 1)
-    const size_t sm = (size_t)ut_lines_per_block(d.n, d.ylines) * d.n * sizeof(double) + (size_t)(d.n + 1) * sizeof(double2);
+    const size_t sm = ut_lds_bytes(d.n);
+    const dim3 nt(ut_threads(d.n));
     if (d_work)
         TPT_KLAUNCH((ut_multi_kernel<TI, TO, EPI, INV>),
                            dim3((unsigned)(blocks < 4 * PERSISTENT_BLOCKS ? blocks : 4 * PERSISTENT_BLOCKS)),
-                           dim3(UT_NT), sm, s, d_work, nwork, blocks);
+                           nt, sm, s, d_work, nwork, blocks);
     else
-        TPT_KLAUNCH((ut_kernel<TI, TO, EPI, INV>), dim3((unsigned)blocks), dim3(UT_NT), sm, s, d, blocks);
+        TPT_KLAUNCH((ut_kernel<TI, TO, EPI, INV>), dim3((unsigned)blocks), nt, sm, s, d, blocks);
     return hipGetLastError();
 }
 
@@ -462,10 +670,9 @@ hipError_t launch_ut_t(const FftDesc& d, const FftDesc* d_work, int nwork, long 
 bool fft_supported(int n) { return n >= 8 && n <= 2048 && (n & (n - 1)) == 0; }
 
 long long fft_blocks(const FftDesc& d) {
-    const int lpb = ut_lines_per_block(d.n, d.ylines);
+    const int lpb = ut_lines_per_block(d.n);
     return (d.lines + lpb - 1) / lpb;
 }
-
 // rep: a representative descriptor (types, direction, epilogue, line length);
 // every descriptor of a work list has the same line length n, since the
 // block's line count and LDS size depend on it.
