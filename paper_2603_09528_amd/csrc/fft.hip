@@ -34,7 +34,8 @@
 // is where the bit-reversed order of the usual in-place algorithm puts a
 // group, so no separate reordering is needed and the output comes out in
 // natural order.  LDS positions are padded by one complex per sixteen, which
-// keeps the power-of-two strides of the passes off a single bank.
+// keeps the power-of-two strides of the passes off a single bank, and lines
+// are an odd number of points apart.
 //
 // Lines are either contiguous (x direction, element stride 1) or strided (y
 // direction: the lines of one z slab are its Nx columns, element stride Nx).
@@ -65,8 +66,10 @@ __host__ __device__ inline int ut_log2(int v) {
 __host__ __device__ inline int ut_tpl(int n) { return (n >> 1) > (1 << UT_Q) ? (n >> 1) >> UT_Q : 1; }
 __host__ __device__ inline int ut_lines_per_block(int n) { return n >= 2048 ? 1 : UT_NT / ut_tpl(n); }
 __host__ __device__ inline int ut_threads(int n) { return ut_lines_per_block(n) * ut_tpl(n); }
-// LDS line stride in complex points: M plus one pad slot per sixteen
-__host__ __device__ inline int ut_line_stride(int n) { return (n >> 1) + (n >> 5); }
+// LDS line stride in complex points: M plus one pad slot per sixteen, plus
+// three, so that the lanes of strided (y) lines, which run across lines,
+// fall in different banks
+__host__ __device__ inline int ut_line_stride(int n) { return (n >> 1) + (n >> 5) + 3; }
 __host__ __device__ inline size_t ut_lds_bytes(int n) {
     // line data, then W (N/2 entries) and the quarter-wave table (N/2 + 1)
     return ((size_t)ut_lines_per_block(n) * ut_line_stride(n) + (size_t)n + 1) * sizeof(double2);
