@@ -39,7 +39,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--modes", default="fp64,fp64_gg,fp32,bf16x3",
-                    help="precisions; a _gg suffix applies the x basis by dense GEMM instead of the FFT")
+                    help="precisions; a _gg suffix applies the x basis by dense GEMM instead of the FFT, "
+                         "_fused runs the x FFT inside the y GEMM's loads (one pass each way)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--n", type=int, default=256, help="cells per direction (default: the 256^3 workload)")
@@ -59,7 +60,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-KERNEL_SOURCES = ("kernels.hip", "fft.hip", "gemm_f64.hip", "gemm_f32.hip", "gemm_bf16.hip", "gemm_impl.h",
+KERNEL_SOURCES = ("kernels.hip", "fft.hip", "fft_core.h", "xgemm.hip", "gemm_f64.hip", "gemm_f32.hip", "gemm_bf16.hip", "gemm_impl.h",
                   "device_common.h", "kernels.h")
 
 
@@ -277,7 +278,7 @@ def main():
         prec, _, xform = mode.partition("_")
         dense_x = xform == "gg"
         if prec == "fp64":
-            plan = T.Plan.from_problem(prob, dense_x=dense_x)
+            plan = T.Plan.from_problem(prob, dense_x=dense_x, fuse_xy=xform == "fused")
             iters = 0
         else:
             # calibrate the number of corrections with the adaptive stop rule
@@ -399,7 +400,9 @@ def main():
     launches = r["kernel_launches"][kname] / args.steps
     per_launch_ms = kms / launches
     nalpha = n
-    if kname.startswith("gemm"):
+    if kname.startswith("gemm") or kname.startswith("xgemm"):
+        # GEMM flops of the y (or x) contraction; a fused kernel's x transform
+        # (about 2.5 log2(Nx) + 6 flops per unknown) runs on the vector ALUs
         dt = kname.rsplit("_", 1)[1]
         mult = 3 if dt == "bf16x3" else 1
         flops = 2.0 * nalpha * dof * mult

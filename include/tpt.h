@@ -77,7 +77,14 @@ enum {
                                plan can be inspected but not solved */
     TPT_FLAG_DENSE_X = 2,   /* apply the x eigenbasis by dense GEMM even where a
                                fast transform applies (see tpt_plan_transforms) */
-    TPT_FLAG_DENSE_Y = 4    /* the same for y */
+    TPT_FLAG_DENSE_Y = 4,   /* the same for y */
+    TPT_FLAG_FUSE_XY = 8    /* FP64 plans whose x is a fast transform and y a
+                               GEMM: run the two as one fused pass per
+                               direction (tpt_plan_fused).  Reads and writes
+                               the field once instead of twice, but on gfx950
+                               it is slower than the separate passes (the
+                               row transforms inside the GEMM are not hidden
+                               behind its MFMAs), so it is not the default */
 };
 
 /* How a plan applies the eigenbasis of x or y (tpt_plan_transforms). */
@@ -158,6 +165,13 @@ int tpt_plan_operator(tpt_plan plan, int dir, double *a, double *b, double *c, d
  * analytic basis is one of the three listed, its unknown count is a power of
  * two in 8..2048, and its TPT_FLAG_DENSE_* flag is not set; otherwise GEMM. */
 int tpt_plan_transforms(tpt_plan plan, int kinds[2]);
+
+/* *fused = 1 when an FP64 solve of the plan applies the x fast transform
+ * inside the y GEMM's operand loads (steps 2.1 + 2.2 and 2.4 + 2.5 of §2.2.2
+ * as one pass each: the field is read and written once instead of twice);
+ * this needs TPT_FLAG_FUSE_XY, x a fast transform with N_x = 128 or 256 and
+ * y a GEMM with N_y a multiple of 128 (0 for host-only plans). */
+int tpt_plan_fused(tpt_plan plan, int *fused);
 
 /* Solve A x = rhs for the plan's nrhs right-hand sides.  rhs, out: device
  * FP64 fields (nrhs * Nz*Ny*Nx each); rhs is read only and must not overlap

@@ -85,6 +85,7 @@ def lib():
             "tpt_plan_eigen": (i, [vp, i, dp, dp]),
             "tpt_plan_operator": (i, [vp, i, dp, dp, dp, dp]),
             "tpt_plan_transforms": (i, [vp, ctypes.POINTER(ctypes.c_int)]),
+            "tpt_plan_fused": (i, [vp, ctypes.POINTER(ctypes.c_int)]),
             "tpt_solve": (i, [vp, vp, vp, vp, sz, vp]),
             "tpt_solve_info": (i, [vp, ctypes.POINTER(Info)]),
             "tpt_batch_create": (i, [i, ctypes.POINTER(vp), ctypes.POINTER(vp)]),
@@ -117,7 +118,7 @@ def lib():
 
 
 EXPORTED = ("tpt_plan_desc_init", "tpt_plan_create", "tpt_plan_destroy", "tpt_plan_shape",
-            "tpt_plan_workspace_bytes", "tpt_plan_eigen", "tpt_plan_operator", "tpt_plan_transforms", "tpt_solve",
+            "tpt_plan_workspace_bytes", "tpt_plan_eigen", "tpt_plan_operator", "tpt_plan_transforms", "tpt_plan_fused", "tpt_solve",
             "tpt_solve_info", "tpt_batch_create", "tpt_batch_destroy", "tpt_batch_workspace_bytes",
             "tpt_batch_solve", "tpt_autotune", "tpt_autotune_save", "tpt_autotune_load",
             "tpt_server_create", "tpt_server_submit", "tpt_server_poll", "tpt_server_drain",
@@ -161,12 +162,15 @@ class Plan:
     'helmholtz' with alpha; precision 'fp64', 'fp32' or 'bf16x3';
     fixed_refine >= 0 runs that many corrections without host synchronisation;
     dense_x / dense_y force the dense GEMM for a direction where a fast
-    transform (FFT, DCT-II, DST-II of a uniform direction) would apply.
+    transform (FFT, DCT-II, DST-II of a uniform direction) would apply;
+    fuse_xy runs the x fast transform and the y GEMM of an FP64 solve as
+    one fused pass per direction (see `fused`; slower on gfx950 than the
+    separate passes, so off by default).
     """
 
     def __init__(self, n, faces, bc, loc=("C", "C", "C"), kind="poisson", alpha=0.0, precision="fp64",
                  rtol=1e-12, max_refine=8, fixed_refine=-1, nrhs=1, host_only=False, dense_x=False,
-                 dense_y=False):
+                 dense_y=False, fuse_xy=False):
         L = lib()
         d = _Desc()
         L.tpt_plan_desc_init(ctypes.byref(d))
@@ -184,7 +188,8 @@ class Plan:
         d.max_refine = int(max_refine)
         d.fixed_refine = int(fixed_refine)
         d.nrhs = int(nrhs)
-        d.flags = (1 if host_only else 0) | (2 if dense_x else 0) | (4 if dense_y else 0)
+        d.flags = ((1 if host_only else 0) | (2 if dense_x else 0) | (4 if dense_y else 0)
+                   | (8 if fuse_xy else 0))
         h = ctypes.c_void_p()
         _check(L.tpt_plan_create(ctypes.byref(d), ctypes.byref(h)))
         self._h = h
@@ -221,6 +226,14 @@ class Plan:
         _check(lib().tpt_plan_transforms(self._h, v))
         names = ("gemm", "fft", "dct", "dst")
         return names[v[0]], names[v[1]]
+
+    @property
+    def fused(self):
+        """True when an FP64 solve runs the x fast transform inside the y
+        GEMM's loads (one pass each way instead of two)."""
+        v = ctypes.c_int()
+        _check(lib().tpt_plan_fused(self._h, ctypes.byref(v)))
+        return bool(v.value)
 
     @property
     def x_fft(self) -> bool:

@@ -86,6 +86,7 @@ struct tpt_plan_s {
     tpt_info info{};
     int gemm_variant[4] = {-1, -1, -1, -1};  // per stage (x fwd, y fwd, y inv, x inv); -1 = table
     int fast[2] = {-1, -1};          // x, y: XformKind of the fast transform, -1 = GEMM
+    bool fuse_xy = false;            // FP64: x transform fused into the y GEMM's loads
     ~tpt_plan_s();
 };
 

@@ -112,6 +112,12 @@ bool fft_supported(int n);
 long long fft_blocks(const FftDesc& d);
 hipError_t launch_fft(const FftDesc& rep, const FftDesc* d_work, int nwork, long long blocks, hipStream_t s);
 
+// y GEMM of one problem (descriptor of the y pass) whose B rows are first
+// transformed along x (descriptor of the x pass: kind, direction, scale,
+// tables); FP64, N = n_x = 128 or 256, M a multiple of 128, K of 16.
+bool xgemm_supported(const GemmDesc& g, const FftDesc& xf);
+hipError_t launch_xgemm(const GemmDesc& g, const FftDesc& xf, hipStream_t s);
+
 // Thomas solve along z (§2.2.2 step 2.3) for nsys systems of nx*ny lines.
 struct ThomasDesc {
     int nx, ny, nz, nsys;

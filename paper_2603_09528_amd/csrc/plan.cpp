@@ -308,6 +308,10 @@ int tpt_plan_create(const tpt_plan_desc* desc, tpt_plan* out) {
     if (!p->host_only) {
         if (p->bx->fast_kind >= 0 && !(desc->flags & TPT_FLAG_DENSE_X)) p->fast[0] = p->bx->fast_kind;
         if (p->by->fast_kind >= 0 && !(desc->flags & TPT_FLAG_DENSE_Y)) p->fast[1] = p->by->fast_kind;
+        // one pass for the x transform and the y GEMM (FP64; x rows of 128 or
+        // 256 points, whole 128-row tiles of y)
+        p->fuse_xy = desc->precision == TPT_FP64 && (desc->flags & TPT_FLAG_FUSE_XY) && p->fast[0] >= 0 &&
+                     p->fast[1] < 0 && (p->N[0] == 128 || p->N[0] == 256) && p->N[1] % 128 == 0;
     }
     p->info.rel_residual = -1.0;
     if (!p->host_only) {
@@ -382,6 +386,12 @@ int tpt_plan_operator(tpt_plan p, int dir, double* a, double* b, double* c, doub
 int tpt_plan_transforms(tpt_plan p, int kinds[2]) {
     if (!p || !kinds) return fail(TPT_ERR_INVALID, "NULL argument");
     for (int d = 0; d < 2; ++d) kinds[d] = p->fast[d] < 0 ? TPT_XFORM_GEMM : TPT_XFORM_FFT + p->fast[d];
+    return TPT_OK;
+}
+
+int tpt_plan_fused(tpt_plan p, int* fused) {
+    if (!p || !fused) return fail(TPT_ERR_INVALID, "NULL argument");
+    *fused = p->fuse_xy ? 1 : 0;
     return TPT_OK;
 }
 

@@ -356,10 +356,42 @@ long long plan_residual_blocks(const tpt_plan_s* p) {
     return residual_blocks(st);
 }
 
+// Fused x transform + y GEMM (FP64): forward rhs -> w2 (2.1 + 2.2), inverse
+// w2 -> out (2.5 + 2.4: the x inverse is applied first, in the loads).
+// Returns 1 when the operands do not fit the fused kernel (the caller runs
+// the separate passes).
+static int run_fused(const tpt_plan_s* p, bool inverse, const double* in, double* out, int nrhs, hipStream_t s) {
+    const GemmDesc g = stage_gemm(p, inverse ? ST_YI : ST_YF, GP_F64, in, DT_F64, out, DT_F64, EPI_STORE, nullptr, nrhs);
+    const FftDesc xf = stage_fft(p, inverse ? ST_XI : ST_XF, nullptr, DT_F64, nullptr, DT_F64, EPI_STORE, nullptr, nrhs);
+    if (!xgemm_supported(g, xf)) return 1;
+    TimedScope ts(inverse ? "xgemm_inv_f64" : "xgemm_fwd_f64", s);
+    hipError_t e = launch_xgemm(g, xf, s);
+    if (e != hipSuccess) return fail(TPT_ERR_HIP, std::string("fused transform launch: ") + hipGetErrorString(e));
+    return TPT_OK;
+}
+
 // FP64 path: 2.1 x forward, 2.2 y forward, 2.3 Thomas, 2.4 y inverse, 2.5 x inverse.
 static int solve_fp64(tpt_plan_s* p, const double* rhs, double* out, const Ws& w, hipStream_t s) {
     const int R = p->desc.nrhs;
     int rc;
+    if (p->fuse_xy && (rc = run_fused(p, false, rhs, (double*)w.w2, R, s)) <= 0) {
+        if (rc) return rc;
+        if ((rc = run_thomas(p, w.w2, DT_F64, w.w2, DT_F64, w.scratch, R, s))) return rc;
+        if ((rc = run_fused(p, true, (const double*)w.w2, out, R, s)) < 0) return rc;
+        if (rc == 0) {
+            p->info.iters = 0;
+            p->info.rel_correction = 0.0;
+            p->info.rel_residual = -1.0;
+            return TPT_OK;
+        }
+        // output not aligned for the fused kernel: separate passes for the inverse
+        if ((rc = run_stage(p, ST_YI, GP_F64, w.w2, DT_F64, w.w1, DT_F64, EPI_STORE, nullptr, R, s))) return rc;
+        if ((rc = run_stage(p, ST_XI, GP_F64, w.w1, DT_F64, out, DT_F64, EPI_STORE, nullptr, R, s))) return rc;
+        p->info.iters = 0;
+        p->info.rel_correction = 0.0;
+        p->info.rel_residual = -1.0;
+        return TPT_OK;
+    }
     if ((rc = run_stage(p, ST_XF, GP_F64, rhs, DT_F64, w.w1, DT_F64, EPI_STORE, nullptr, R, s))) return rc;
     if ((rc = run_stage(p, ST_YF, GP_F64, w.w1, DT_F64, w.w2, DT_F64, EPI_STORE, nullptr, R, s))) return rc;
     if ((rc = run_thomas(p, w.w2, DT_F64, w.w2, DT_F64, w.scratch, R, s))) return rc;
