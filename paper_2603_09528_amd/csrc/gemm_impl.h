@@ -202,11 +202,12 @@ __device__ __forceinline__ void gemm_tile_f(const GemmDesc& g, long long lb, TM*
             for (int i = 0; i < C::MI; ++i)
 #pragma unroll
                 for (int j = 0; j < C::NI; ++j) acc[i][j] = MM::mma(fa[i], fb[j], acc[i][j]);
+            // stage the next K tile before the last MFMA group (see the
+            // persistent form)
+            if constexpr (NBUF == 2)
+                if (kk == BK / 4 - 2 && kt + 1 < nk) sstore(cur ^ 1);
         }
-        if constexpr (NBUF == 2) {
-            if (kt + 1 < nk) sstore(cur ^ 1);
-            __syncthreads();
-        }
+        if constexpr (NBUF == 2) __syncthreads();
     }
     };
     if (full) kloop(std::true_type{});
@@ -249,6 +250,10 @@ __device__ __forceinline__ void gemm_tile_f(const GemmDesc& g, long long lb, TM*
 // read and results written through buffer resources (base in scalar
 // registers, 32-bit per-thread offsets, block-uniform K steps as scalar
 // offsets), which keeps the address state small enough for two blocks per CU.
+// Within a K step the next K tile is written to the free LDS buffer before the
+// last group of MFMAs rather than after all of them: the wait for its loads
+// and the LDS writes then overlap MFMAs still in the queue (measured 7-8 %
+// faster at 256^3 x 256, 512^3 x 64 and 768 x 1024 x 768 x 64).
 // ---------------------------------------------------------------------------
 typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
 constexpr int BUF_RSRC_WORD3 = 0x00020000;  // raw 32-bit buffer (gfx9 family)
@@ -370,6 +375,7 @@ __device__ __forceinline__ void gemm_tiles_persist_f(const GemmDesc& g, long lon
             }
             const TM* a = As + buf * S::A_ELEMS + (wm * C::WM + lr) * S::PA + lg;
             const TM* bb = Bs + buf * S::B_ELEMS;
+            const bool stage = kt + 1 < nk || more;
 #pragma unroll
             for (int kk = 0; kk < BK / 4; ++kk) {
                 TM fa[C::MI], fb[C::NI];
@@ -384,16 +390,16 @@ __device__ __forceinline__ void gemm_tiles_persist_f(const GemmDesc& g, long lon
                 for (int i = 0; i < C::MI; ++i)
 #pragma unroll
                     for (int j = 0; j < C::NI; ++j) acc[i][j] = MM::mma(fa[i], fb[j], acc[i][j]);
+                // stage the next K tile (or the next tile's first) into the
+                // other buffer before the last MFMA group, so that waiting for
+                // its loads and writing it overlap the MFMAs still queued
+                if (kk == BK / 4 - 2 && stage) sstore(buf ^ 1);
             }
             if (kt + 1 < nk) {
-                sstore(buf ^ 1);
                 __syncthreads();
                 buf ^= 1;
             }
         }
-        // the next tile's first K tile goes to the other buffer (last read
-        // before the latest barrier, or by the previous tile)
-        if (more) sstore(buf ^ 1);
         double se = 0.0, sx = 0.0;
 #pragma unroll
         for (int i = 0; i < C::MI; ++i) {
