@@ -299,13 +299,36 @@ def main():
             plan.solve(f, out, ws)
         torch.cuda.synchronize()
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-        # throughput: the timed solves back to back
+        # throughput: the timed solves back to back, issued from the host
         torch.cuda.synchronize()
         t_start = time.perf_counter()
         for k in range(args.steps):
             plan.solve(f, out, ws)
+        t_issue = time.perf_counter() - t_start
         torch.cuda.synchronize()
         wall = time.perf_counter() - t_start
+        # the same solve captured once into a HIP graph and replayed: one
+        # launch per solve instead of one per kernel (the solve neither
+        # allocates nor synchronises, so it can be captured)
+        gms = None
+        try:
+            graph = torch.cuda.CUDAGraph()
+            gs = torch.cuda.Stream()
+            gs.wait_stream(stream)
+            with torch.cuda.stream(gs):
+                with torch.cuda.graph(graph, stream=gs):
+                    plan.solve(f, out, ws)
+            stream.wait_stream(gs)
+            graph.replay()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(args.steps):
+                graph.replay()
+            torch.cuda.synchronize()
+            gms = (time.perf_counter() - t0) * 1e3 / args.steps
+            del graph
+        except Exception as e:  # capture is an optimisation; the stream timing stands
+            log(f"{mode}: graph capture failed ({e})")
         # latency: the same solves one at a time between events (an event
         # record between solves costs about 10 us of idle GPU, so these are
         # kept out of the throughput pass)
@@ -324,9 +347,15 @@ def main():
         T.timing_enable(False)
         kern = T.timing_collect()
         lat = np.array([a.elapsed_time(b) for a, b in evs])
-        ms = wall * 1e3 / args.steps
+        ms_stream = wall * 1e3 / args.steps
+        launch = "graph" if gms is not None and gms < ms_stream else "stream"
+        ms = gms if launch == "graph" else ms_stream
         results[mode] = {
             "ms_per_solve": ms,
+            "launch": launch,
+            "ms_per_solve_stream": ms_stream,
+            "ms_per_solve_graph": gms,
+            "host_issue_ms_per_solve": t_issue * 1e3 / args.steps,
             "gdofs": dof / (ms * 1e-3) / 1e9,
             "p50_ms": float(np.percentile(lat, 50)),
             "p99_ms": float(np.percentile(lat, 99)),
@@ -336,7 +365,9 @@ def main():
             "kernel_launches": {k: int(v[1]) for k, v in kern.items()},
         }
         outs[mode] = out.detach().cpu().numpy()
-        log(f"{mode}: {ms:.3f} ms/solve, {results[mode]['gdofs']:.2f} GDOF/s")
+        log(f"{mode}: {ms:.3f} ms/solve ({launch}; stream {ms_stream:.3f}, graph "
+            f"{'-' if gms is None else f'{gms:.3f}'}, host issue {t_issue * 1e3 / args.steps:.3f}), "
+            f"{results[mode]['gdofs']:.2f} GDOF/s")
         del plan
 
     # tile variants the autotuner chose (precision, pass, M, N, K -> tile)
@@ -450,7 +481,7 @@ def main():
         "data": "synthetic (seeded Gaussian RHS, volume-weighted mean removed)",
         "config": {"workload": f"channel{n}: {n}^3 Poisson, x periodic uniform (Fourier basis by {xdesc}), "
                                f"y,z Neumann tanh beta=2 (y by GEMM, z by Thomas)",
-                   "dof": dof, "mode": best},
+                   "dof": dof, "mode": best, "launch": r["launch"]},
         "p50_ms": r["p50_ms"],
         "p99_ms": r["p99_ms"],
         "modes": results,

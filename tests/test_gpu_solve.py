@@ -144,3 +144,38 @@ def test_channel256_fp64_and_mixed_match_oracle():
         err = O.relative_error(p, got, ref)
         say("  iters", plan.info().iters, "err", err)
         assert err <= MIXED_TOL
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_solve_captured_in_graph(prec):
+    """One solve captured into a HIP graph (FP64; mixed with a fixed
+    correction count, which never synchronises the host) and replayed three
+    times, with eager solves and synchronisation in between: every replay
+    equals the eager result bitwise."""
+    import torch
+    T = _T()
+    p = W.make_problem((64, 48, 40), (0.0, 1.5, 1.5), (W.PP, W.NN, W.NN))
+    kw = {} if prec == "fp64" else dict(precision=prec, fixed_refine=2)
+    plan = T.Plan.from_problem(p, **kw)
+    f = cuda(W.rhs(p, 61))
+    ws = plan.workspace()
+    out = torch.empty_like(f)
+    plan.solve(f, out, ws)
+    torch.cuda.synchronize()
+    eager = host(out)
+    g = torch.cuda.CUDAGraph()
+    gout = torch.empty_like(f)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            plan.solve(f, gout, ws)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        gout.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(gout), eager), f"replay {rep}"
+        plan.solve(f, out, ws)  # eager work between the replays
+        torch.cuda.synchronize()
+        assert np.array_equal(host(out), eager)
