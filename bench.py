@@ -131,6 +131,14 @@ def run_variants(args, T, W):
     f = torch.from_numpy(W.rhs(prob, 7)).to("cuda")
     out = torch.empty_like(f)
     ref = None
+
+    def gdiff(o):
+        # relative difference after removing the mean (the problem is singular:
+        # solutions are defined up to a constant; uniform grid, so the
+        # volume-weighted mean is the plain mean)
+        d = (o - o.mean()) - (ref - ref.mean())
+        return float(np.linalg.norm(d) / np.linalg.norm(ref - ref.mean()))
+
     res = {"workload": f"{n}^3 Poisson, periodic x, Neumann y and z, uniform, FP64", "dof": prob.dof,
            "paper_gb200_s": PAPER_1024_VARIANT_S if n == 1024 else None}
     for name, dx, dy in (("FF", False, False), ("FG", False, True), ("GF", True, False), ("GG", True, True)):
@@ -154,7 +162,7 @@ def run_variants(args, T, W):
             ref = o
             diff = 0.0
         else:
-            diff = float(np.linalg.norm(o - ref) / np.linalg.norm(ref))
+            diff = gdiff(o)
         res[name] = {"ms_per_solve": ms, "gdofs": prob.dof / (ms * 1e-3) / 1e9, "transforms": plan.transforms,
                      "rel_diff_vs_FF": diff,
                      "kernels_ms_per_solve": {k: v[0] / args.variants_steps for k, v in kern.items()}}
@@ -162,24 +170,34 @@ def run_variants(args, T, W):
         del plan, ws
         torch.cuda.empty_cache()
     res["GG_over_FF"] = res["GG"]["ms_per_solve"] / res["FF"]["ms_per_solve"]
-    # the dense-GEMM variant with split-BF16x3 transforms and FP64 refinement
-    # (corrections calibrated with the adaptive rule, then timed at that count)
+    # the dense-GEMM variant in the mixed modes with FP64 refinement, timed at
+    # the smallest correction count whose solution is within 1e-10 of the FP64
+    # solve above after gauge normalisation (the refinement cannot see the
+    # constant: the pinned gauge of the low-precision first solve is off by
+    # about 1e-9 / 4e-8 of the solution in FP32 / BF16x3, which the raw
+    # difference reports)
     for prec in ("fp32", "bf16x3"):
         name = f"GG_{prec}"
-        t0 = time.time()
-        cal = T.Plan.from_problem(prob, dense_x=True, dense_y=True, precision=prec, rtol=1e-11, max_refine=12)
-        try:
-            cal.solve(f, out)
+        iters = None
+        plan = ws = None
+        for it in range(1, 13):
+            plan = T.Plan.from_problem(prob, dense_x=True, dense_y=True, precision=prec, fixed_refine=it)
+            ws = plan.workspace()
+            plan.solve(f, out, ws)
             torch.cuda.synchronize()
-            iters = cal.info().iters
-        except T.TptError as e:
-            log(f"variants {name}: refinement did not converge ({e})")
+            o = out.detach().cpu().numpy()
+            diff = gdiff(o)
+            raw = float(np.linalg.norm(o - ref) / np.linalg.norm(ref))
+            log(f"variants {name}: {it} corrections, diff vs FF {diff:.2e} (without gauge normalisation {raw:.2e})")
+            if diff <= 1e-10:
+                iters = it
+                break
+            del plan, ws
+            plan = ws = None
+            torch.cuda.empty_cache()
+        if iters is None:
+            res[name] = {"corrections": None, "note": "not within 1e-10 of FP64 after 12 corrections"}
             continue
-        del cal
-        plan = T.Plan.from_problem(prob, dense_x=True, dense_y=True, precision=prec, fixed_refine=iters)
-        ws = plan.workspace()
-        plan.solve(f, out, ws)
-        torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.variants_steps):
             plan.solve(f, out, ws)
@@ -191,10 +209,8 @@ def run_variants(args, T, W):
         torch.cuda.synchronize()
         T.timing_enable(False)
         kern = T.timing_collect()
-        o = out.detach().cpu().numpy()
-        diff = float(np.linalg.norm(o - ref) / np.linalg.norm(ref))
         res[name] = {"ms_per_solve": ms, "gdofs": prob.dof / (ms * 1e-3) / 1e9, "corrections": iters,
-                     "rel_diff_vs_FF": diff,
+                     "rel_diff_vs_FF": diff, "rel_diff_vs_FF_raw": raw,
                      "kernels_ms_per_solve": {k: v[0] for k, v in kern.items()}}
         log(f"variants {name}: {ms:.2f} ms/solve, {res[name]['gdofs']:.2f} GDOF/s, corrections {iters}, "
             f"diff vs FF {diff:.2e}")
