@@ -15,7 +15,9 @@ def _T():
     return T
 
 
-@pytest.mark.parametrize("nx,ny,nz,nsys", [(37, 5, 11, 1), (64, 64, 33, 2), (3, 2, 2, 1), (1, 1, 1, 1), (130, 7, 64, 1)])
+# long lines: a partial top chunk (131) and whole chunks with two systems (256)
+@pytest.mark.parametrize("nx,ny,nz,nsys", [(37, 5, 11, 1), (64, 64, 33, 2), (3, 2, 2, 1), (1, 1, 1, 1), (130, 7, 64, 1),
+                                           (33, 9, 131, 1), (16, 8, 256, 2)])
 @pytest.mark.parametrize("sigma,tau", [(0.0, 1.0), (1.0, -3e-3)])
 def test_thomas_matches_oracle(nx, ny, nz, nsys, sigma, tau):
     import torch
@@ -43,10 +45,11 @@ def test_thomas_matches_oracle(nx, ny, nz, nsys, sigma, tau):
     del w
 
 
-def test_thomas_pinned_line_in_place():
+@pytest.mark.parametrize("nz", [17, 150])
+def test_thomas_pinned_line_in_place(nz):
     import torch
     T = _T()
-    nx, ny, nz = 9, 4, 17
+    nx, ny = 9, 4
     rng = np.random.default_rng(5)
     faces = np.cumsum(np.concatenate([[0.0], rng.uniform(0.5, 1.5, nz)]))
     az, bz, cz, _ = O.operator_1d(faces, ("N", "N"), "C")
