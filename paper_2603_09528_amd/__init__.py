@@ -302,19 +302,6 @@ class Batch:
         self._h = h
         self._ws = None
 
-    @property
-    def transforms(self):
-        """How x and y are transformed: each of 'gemm', 'fft', 'dct', 'dst'."""
-        v = (ctypes.c_int * 2)()
-        _check(lib().tpt_plan_transforms(self._h, v))
-        names = ("gemm", "fft", "dct", "dst")
-        return names[v[0]], names[v[1]]
-
-    @property
-    def x_fft(self) -> bool:
-        """True if the x eigenbasis is applied by a fast transform."""
-        return self.transforms[0] != "gemm"
-
     def workspace_bytes(self) -> int:
         b = ctypes.c_size_t()
         _check(lib().tpt_batch_workspace_bytes(self._h, ctypes.byref(b)))
