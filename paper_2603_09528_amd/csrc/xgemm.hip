@@ -18,7 +18,7 @@
 // once per K step.
 //
 // Measured on gfx950 (256^3, N_x = N_y = 256) the fused pass takes longer than
-// the two separate passes (about 0.22 against 0.055 + 0.148 ms): the matrix
+// the two separate passes (about 0.22 against 0.05 + 0.14 ms): the matrix
 // unit is busy about half the time, as the row transforms' chains of LDS round
 // trips are not hidden behind the MFMAs with eight waves per CU (the
 // stand-alone transform kernel runs sixteen).  Plans use it only on request.
