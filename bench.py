@@ -62,7 +62,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-KERNEL_SOURCES = ("kernels.hip", "fft.hip", "fft_core.h", "xgemm.hip", "gemm_f64.hip", "gemm_f32.hip", "gemm_bf16.hip", "gemm_impl.h",
+KERNEL_SOURCES = ("kernels.hip", "thomas_part.hip", "fft.hip", "fft_core.h", "xgemm.hip", "gemm_f64.hip", "gemm_f32.hip", "gemm_bf16.hip", "gemm_impl.h",
                   "device_common.h", "kernels.h")
 
 

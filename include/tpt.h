@@ -245,11 +245,19 @@ int tpt_server_destroy(tpt_server server);
  * [nsys][nz][ny][nx]; scratch: device FP64 of at least
  * 4 * nx * ny * nsys * ceil(nz / 16) elements (chunk checkpoints).
  * pin_line >= 0 sets the last unknown of that line to zero and drops its
- * last equation (§3 gauge).  f may equal x. */
+ * last equation (§3 gauge).  f may equal x.
+ * variant: -1 automatic (what plans use); 0 sequential (one lane per line,
+ * the only kernel for cyclic lines); 1..17 partitioned (each line cut into
+ * P segments of L planes solved in parallel and joined by a P-row interface
+ * system, LB lines per block), (LB, P, L) = (64,4,8) (64,8,8) (32,8,8)
+ * (64,8,16) (32,8,16) (16,8,16) (64,16,16) (32,16,16) (16,16,16) (64,8,32)
+ * (32,8,32) (16,8,32) (16,32,16) (32,16,32) (16,16,32) (16,64,16)
+ * (16,32,32), needing P*L >= nz and non-cyclic lines, else
+ * TPT_ERR_INVALID.  The partitioned kernels use no scratch. */
 int tpt_thomas(int nx, int ny, int nz, int nsys, const double *lamx, const double *lamy,
                const double *az, const double *bz, const double *cz, int periodic_z,
                double sigma, double tau, int pin_line, const double *f, double *x,
-               double *scratch, void *stream);
+               double *scratch, int variant, void *stream);
 
 /* Strided-batched GEMM with the library's MFMA kernels (the transform
  * kernels of §2.2.2 on explicit operands).  A is M x K row-major (lda = K);

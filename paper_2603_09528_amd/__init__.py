@@ -100,7 +100,7 @@ def lib():
             "tpt_server_poll": (i, [vp, ctypes.c_ulonglong, ctypes.POINTER(Info), dp, dp, dp]),
             "tpt_server_drain": (i, [vp]),
             "tpt_server_destroy": (i, [vp]),
-            "tpt_thomas": (i, [i, i, i, i, vp, vp, vp, vp, vp, i, d, d, i, vp, vp, vp, vp]),
+            "tpt_thomas": (i, [i, i, i, i, vp, vp, vp, vp, vp, i, d, d, i, vp, vp, vp, i, vp]),
             "tpt_gemm": (i, [i, i, i, i, i, i, i, vp, ctypes.c_longlong, vp, ctypes.c_longlong, vp,
                              ctypes.c_longlong, vp]),
             "tpt_timing_enable": (i, [i]),
@@ -383,13 +383,21 @@ class Server:
             self._h = None
 
 
+# partitioned Thomas configurations (lines per block, segments, planes per
+# segment), variants 1..
+THOMAS_PARTS = ((64, 4, 8), (64, 8, 8), (32, 8, 8), (64, 8, 16), (32, 8, 16), (16, 8, 16), (64, 16, 16),
+                (32, 16, 16), (16, 16, 16), (64, 8, 32), (32, 8, 32), (16, 8, 32), (16, 32, 16), (32, 16, 32),
+                (16, 16, 32), (16, 64, 16), (16, 32, 32))
+
+
 def thomas(nx, ny, nz, nsys, lamx, lamy, az, bz, cz, sigma, tau, pin_line, f, x, scratch, stream=None,
-           periodic_z=False):
+           periodic_z=False, variant=-1):
     """Kernel-level batched Thomas solve on explicit device inputs (cyclic
-    lines with periodic_z)."""
+    lines with periodic_z); variant -1 automatic, 0 sequential, 1.. the
+    partitioned configurations THOMAS_PARTS."""
     _check(lib().tpt_thomas(nx, ny, nz, nsys, _ptr(lamx), _ptr(lamy), _ptr(az), _ptr(bz), _ptr(cz),
                             1 if periodic_z else 0, float(sigma), float(tau), int(pin_line), _ptr(f), _ptr(x),
-                            _ptr(scratch), _stream(stream)))
+                            _ptr(scratch), int(variant), _stream(stream)))
     return x
 
 

@@ -28,6 +28,17 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 
+// 1/d from the hardware reciprocal and two Newton steps (about 1 ulp): the
+// Thomas recurrence is a chain of dependent operations, so a short chain is
+// what matters here (Thomas kernels).
+__device__ __forceinline__ double recip(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    double e = __builtin_fma(-d, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-d, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+
 // ---------------------------------------------------------------------------
 // Wave-level helpers
 // ---------------------------------------------------------------------------

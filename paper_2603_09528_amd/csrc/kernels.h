@@ -134,7 +134,22 @@ struct ThomasDesc {
     double* scratch;       // thomas_scratch_doubles() doubles
     int tf, tx;            // DType of f and x
     long long block_begin; // multi-problem: first block of this problem
+    int variant;           // THOMAS_AUTO, THOMAS_SEQ or THOMAS_PART + configuration
 };
+// Thomas kernels: sequential (one lane per line, checkpointed chunks; the
+// only one for periodic lines and mixed storage types) or partitioned (P
+// segments of L planes per line, one lane per segment, LB lines per block)
+// in one of THOMAS_NPART configurations.
+enum { THOMAS_AUTO = 0, THOMAS_SEQ = 1, THOMAS_PART = 2, THOMAS_NPART = 17 };
+// the variant launch_thomas runs for t (-1: t.variant does not fit t)
+int thomas_variant(const ThomasDesc& t);
+void thomas_part_shape(int v, int* lb, int* p, int* l);
+long long thomas_part_blocks(const ThomasDesc& t, int v);
+hipError_t launch_thomas_part(const ThomasDesc& t, int v, hipStream_t s);
+// every problem of the list in configuration v with storage type dtype (f
+// and x alike); block_begin counts blocks of that configuration's LB lines
+hipError_t launch_thomas_part_multi(const ThomasDesc* d_work, int nwork, long long total_blocks, int v, int dtype,
+                                    hipStream_t s);
 hipError_t launch_thomas(const ThomasDesc& t, hipStream_t s);
 long long thomas_blocks(const ThomasDesc& t);
 // Scratch the Thomas kernel needs: (c', d') checkpoints, one per line every

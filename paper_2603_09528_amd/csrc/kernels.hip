@@ -103,17 +103,6 @@ long long thomas_scratch_doubles(int nx, int ny, int nz, int nsys, int periodic)
     return (periodic ? 4 : 2) * lines * nck;
 }
 
-// 1/d from the hardware reciprocal and two Newton steps (about 1 ulp): the
-// Thomas recurrence is a chain of dependent operations, so a short chain is
-// what matters here.
-__device__ __forceinline__ double recip(double d) {
-    double r = __builtin_amdgcn_rcp(d);
-    double e = __builtin_fma(-d, r, 1.0);
-    r = __builtin_fma(r, e, r);
-    e = __builtin_fma(-d, r, 1.0);
-    return __builtin_fma(r, e, r);
-}
-
 // Stage the coefficients of one problem in LDS as planes of nz doubles:
 // A_k (0 at k = 0), D_k, C_k (0 at k = nz-1) and AC_k = A_{k+1} C_k (the
 // coupling of pivot k+1 to pivot k; 0 at k = nz-1).
@@ -452,6 +441,9 @@ long long thomas_blocks(const ThomasDesc& t) {
 hipError_t launch_thomas(const ThomasDesc& t, hipStream_t s) {
     const long long n = (long long)t.nx * t.ny * t.nsys;
     if (n <= 0) return hipSuccess;
+    const int variant = thomas_variant(t);
+    if (variant < 0) return hipErrorInvalidValue;
+    if (variant >= THOMAS_PART) return launch_thomas_part(t, variant - THOMAS_PART, s);
     const long long blocks = thomas_blocks(t);
     const dim3 gr((unsigned)blocks), bl(THOMAS_NT);
     const size_t sm = THOMAS_LDS_PLANES * sizeof(double) * (size_t)t.nz;

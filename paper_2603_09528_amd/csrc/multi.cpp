@@ -163,22 +163,39 @@ int MultiExec::build(const double* const* rhs, double* const* out, void* ws) {
         std::vector<long long> nb(n);
         stage(ST_XF, from_rhs ? rhsv : resv, from_rhs ? DT_F64 : DT_F32, w1, tmid, EPI_STORE, nullptr);
         stage(ST_YF, w1c, tmid, w2, tmid, EPI_STORE, nullptr);
-        std::vector<ThomasDesc> t(n);
-        long long blocks = 0;
-        int nz_max = 1;
+        // one launch per Thomas kernel: each problem runs the variant its
+        // single-problem solve runs, so batch and single results agree bit
+        // for bit
+        std::vector<ThomasDesc> all(n);
+        std::vector<int> var(n);
         for (int i = 0; i < n; ++i) {
-            t[i] = plan_thomas(plans_[i], w[i].w2, tmid, w[i].w2, tmid, w[i].scratch, 1);
-            t[i].block_begin = blocks;
-            blocks += thomas_blocks(t[i]);
-            nz_max = std::max(nz_max, t[i].nz);
+            all[i] = plan_thomas(plans_[i], w[i].w2, tmid, w[i].w2, tmid, w[i].scratch, 1);
+            var[i] = thomas_variant(all[i]);
         }
-        Launch L{};
-        L.kind = 1;
-        L.off = append(blob_, t);
-        L.nwork = n;
-        L.total = blocks;
-        L.variant = nz_max;
-        seq_.push_back(L);
+        std::vector<int> kinds(var);
+        std::sort(kinds.begin(), kinds.end());
+        kinds.erase(std::unique(kinds.begin(), kinds.end()), kinds.end());
+        for (int v : kinds) {
+            std::vector<ThomasDesc> t;
+            long long blocks = 0;
+            int nz_max = 1;
+            for (int i = 0; i < n; ++i) {
+                if (var[i] != v) continue;
+                ThomasDesc d = all[i];
+                d.block_begin = blocks;
+                blocks += v == THOMAS_SEQ ? thomas_blocks(d) : thomas_part_blocks(d, v - THOMAS_PART);
+                nz_max = std::max(nz_max, d.nz);
+                t.push_back(d);
+            }
+            Launch L{};
+            L.kind = v == THOMAS_SEQ ? 1 : 5;
+            L.off = append(blob_, t);
+            L.nwork = (int)t.size();
+            L.total = blocks;
+            L.variant = v == THOMAS_SEQ ? nz_max : v - THOMAS_PART;
+            L.prec = tmid;
+            seq_.push_back(L);
+        }
         stage(ST_YI, w2c, tmid, w1, tmid, EPI_STORE, nullptr);
         stage(ST_XI, w1c, tmid, outv, DT_F64, epi, &nb);
         return nb;
@@ -252,6 +269,12 @@ int MultiExec::enqueue(hipStream_t s) const {
             case 1: {
                 TimedScope ts("multi_thomas", s);
                 e = launch_thomas_multi((const ThomasDesc*)(d_desc_ + L.off), L.nwork, L.total, L.variant, s);
+                break;
+            }
+            case 5: {
+                TimedScope ts("multi_thomas", s);
+                e = launch_thomas_part_multi((const ThomasDesc*)(d_desc_ + L.off), L.nwork, L.total, L.variant,
+                                             L.prec, s);
                 break;
             }
             case 2: {

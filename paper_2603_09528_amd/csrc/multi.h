@@ -32,8 +32,10 @@ class MultiExec {
 
    private:
     struct Launch {
-        int kind;     // 0 gemm, 1 thomas, 2 residual, 3 reduce, 4 x-line FFT
-        int prec, variant, b_nk;  // thomas: variant holds the largest nz
+        int kind;     // 0 gemm, 1 sequential Thomas, 2 residual, 3 reduce, 4 x-line FFT, 5 partitioned Thomas
+        // sequential Thomas: variant holds the largest nz; partitioned: the
+        // configuration, prec the storage type
+        int prec, variant, b_nk;
         size_t off;   // byte offset of the first descriptor in the blob
         int nwork;
         long long total;

@@ -541,8 +541,9 @@ int tpt_solve_info(tpt_plan plan, tpt_info* info) {
 
 int tpt_thomas(int nx, int ny, int nz, int nsys, const double* lamx, const double* lamy, const double* az,
                const double* bz, const double* cz, int periodic_z, double sigma, double tau, int pin_line,
-               const double* f, double* x, double* scratch, void* stream) {
+               const double* f, double* x, double* scratch, int variant, void* stream) {
     if (nx < 1 || ny < 1 || nz < 1 || nsys < 1) return fail(TPT_ERR_INVALID, "bad sizes");
+    if (variant < -1 || variant > THOMAS_NPART) return fail(TPT_ERR_INVALID, "bad Thomas variant");
     if (periodic_z && nz < 2) return fail(TPT_ERR_INVALID, "cyclic lines need nz >= 2");
     if (!lamx || !lamy || !az || !bz || !cz || !f || !x || !scratch) return fail(TPT_ERR_INVALID, "NULL pointer");
     if (pin_line >= nx * ny) return fail(TPT_ERR_INVALID, "pin_line out of range");
@@ -551,6 +552,9 @@ int tpt_thomas(int nx, int ny, int nz, int nsys, const double* lamx, const doubl
     t.lamx = lamx; t.lamy = lamy; t.az = az; t.bz = bz; t.cz = cz;
     t.sigma = sigma; t.tau = tau; t.pin_line = pin_line; t.periodic = periodic_z ? 1 : 0;
     t.f = f; t.tf = DT_F64; t.x = x; t.tx = DT_F64; t.scratch = scratch;
+    t.variant = variant < 0 ? THOMAS_AUTO : variant == 0 ? THOMAS_SEQ : THOMAS_PART + variant - 1;
+    if (thomas_variant(t) < 0)
+        return fail(TPT_ERR_INVALID, "Thomas variant does not fit (cyclic lines, or P*L < nz)");
     TimedScope ts("thomas_f64", (hipStream_t)stream);
     hipError_t e = launch_thomas(t, (hipStream_t)stream);
     if (e != hipSuccess) return fail(TPT_ERR_HIP, hipGetErrorString(e));

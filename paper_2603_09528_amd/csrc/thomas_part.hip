@@ -1,0 +1,340 @@
+// Partitioned batched Thomas along z (§2.2.2 step 2.3) for non-periodic
+// lines: single- and multi-problem launches over a table of (lines per
+// block, segments, planes per segment) configurations.
+#include "device_common.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+namespace tpt {
+
+// ---------------------------------------------------------------------------
+// Partitioned Thomas (non-periodic lines): each line is split into P
+// segments of L planes, one lane per (line, segment), LB lines per block
+// (lane t holds segment t / LB of line t % LB, so every load and store of a
+// plane touches LB consecutive lines).  The segment's planes stay in
+// registers: f is read once and x written once (16 B per unknown against 24 B
+// for the sequential kernel), and the dependent chain per lane is P times
+// shorter.
+//
+// Segment s owns rows k0 = sL .. k0+L-1; rows k0 .. k0+L-2 are its interior,
+// row k0+L-1 its interface unknown z_s.  With the neighbouring interface
+// values Xl = z_{s-1} and Xr = z_s taken as known, every interior unknown is
+// affine in them, x_r = U_r + V_r Xr + W_r Xl.  Pass 1 finds these responses
+// at the two ends of the interior: a downward elimination gives the last
+// interior row (U, V, W at r = L-2), an upward one the first (r = 0), no
+// back substitution needed.  Substituted into the interface rows they give a
+// tridiagonal system of P unknowns per line,
+//   (D + A Vd_s + C Wu_{s+1}) z_s + A Wd_s z_{s-1} + C Vu_{s+1} z_{s+1}
+//       = f - A Ud_s - C Uu_{s+1},
+// (A, D, C, f of row k0+L-1; Ud.. of segment s at its last interior row, Uu..
+// of segment s+1 at its first), which one lane per line solves from LDS.
+// Pass 2 folds Xl and Xr into the interior's first and last right-hand side
+// and runs the interior Thomas with the pivots kept from pass 1.
+//
+// Rows k >= nz are identity rows (f = 0), so P L may exceed nz.  The pinned
+// line (singular Poisson) has its row nz-1 replaced by the identity with
+// f = 0: x_{nz-1} = 0 and rows 0..nz-2 unchanged, the gauge of §3.  Without
+// pivoting the elimination relies, as the sequential one does, on the
+// diagonal dominance of D + tau lambda.
+// ---------------------------------------------------------------------------
+template <int LB, int P, int L>
+struct ThomasPartLds {
+    static constexpr int NT = LB * P, CS = L + 1;  // CS: segment stride of cf (one row of bank padding)
+    // (A, C, D, E) per row, E = 1 where the line shift applies (0 on identity
+    // rows); segment s at s CS, then the pinned line's copy of segment
+    // (nz-1)/L with row nz-1 made the identity
+    double4 cf[(P + 1) * CS];
+    double ex[7][NT];  // responses (Ud, Vd, Wd, Uu, Vu, Wu) and the interface f
+    double zz[P][LB];  // interface solution
+};
+
+// One block of LB lines (block index blk of the problem t with nlines lines).
+template <int LB, int P, int L, typename TF, typename TX>
+__device__ __forceinline__ void thomas_part_block(const ThomasDesc& t, long long nlines, long long blk,
+                                                  ThomasPartLds<LB, P, L>& sh) {
+    constexpr int NT = LB * P, M = L - 1, CS = L + 1, PIN = P * CS;
+    static_assert(L >= 4, "segments need interior rows");
+    const int nz = t.nz;
+    const int sp = (nz - 1) / L;  // segment of row nz-1
+    for (int e = threadIdx.x; e < (P + 1) * L; e += NT) {
+        const int seg = e / L, r = e - seg * L;
+        const int k = (seg < P ? seg : sp) * L + r;
+        double4 v = make_double4(0.0, 0.0, 1.0, 0.0);
+        if (k < nz && !(seg == P && k == nz - 1)) {
+            v.x = k > 0 ? t.tau * t.az[k] : 0.0;
+            v.y = k < nz - 1 ? t.tau * t.cz[k] : 0.0;
+            v.z = t.sigma + t.tau * t.bz[k];
+            v.w = 1.0;
+        }
+        sh.cf[seg * CS + r] = v;
+    }
+
+    const int l = threadIdx.x % LB, s = threadIdx.x / LB;
+    const long long S = (long long)t.nx * t.ny;
+    const long long glr = blk * LB + l;
+    const bool live = glr < nlines;
+    const long long gl = live ? glr : nlines - 1;
+    const int sys = (int)(gl / S);
+    const long long line = gl - (long long)sys * S;
+    const int i = (int)(line % t.nx), j = (int)(line / t.nx);
+    const double tl = t.tau * (t.lamx[i] + t.lamy[j]);
+    const bool pinned = line == t.pin_line;
+    const int k0 = s * L;
+    const long long base = (long long)sys * S * nz + line;
+    const TF* f = (const TF*)t.f + base;
+    TX* x = (TX*)t.x + base;
+    const bool full = k0 + L <= nz;
+
+    double fv[L];
+    if (live && full) {
+#pragma unroll
+        for (int r = 0; r < L; ++r) fv[r] = (double)f[(long long)(k0 + r) * S];
+    } else {
+#pragma unroll
+        for (int r = 0; r < L; ++r) fv[r] = live && k0 + r < nz ? (double)f[(long long)(k0 + r) * S] : 0.0;
+    }
+    if (pinned && s == sp) {
+#pragma unroll
+        for (int r = 0; r < L; ++r)
+            if (k0 + r == nz - 1) fv[r] = 0.0;
+    }
+    __syncthreads();
+    const double4* cb = sh.cf + ((pinned && s == sp) ? PIN : s * CS);
+
+    // ---- pass 1: end responses of the interior rows 0 .. M-1 ----
+    double ip[M];
+    double Ud, Vd, Wd, Uu, Vu, Wu;
+    {
+        double4 v = cb[0];
+        ip[0] = recip(__builtin_fma(v.w, tl, v.z));
+        double Fd = fv[0] * ip[0], Gd = v.x * ip[0], cprev = v.y;
+#pragma unroll
+        for (int r = 1; r < M; ++r) {
+            v = cb[r];
+            ip[r] = recip(__builtin_fma(v.w, tl, v.z) - v.x * cprev * ip[r - 1]);
+            Fd = (fv[r] - v.x * Fd) * ip[r];
+            Gd = -v.x * Gd * ip[r];
+            cprev = v.y;
+        }
+        Ud = Fd;
+        Vd = -cprev * ip[M - 1];
+        Wd = -Gd;
+        // re-read the coefficients rather than keep the down sweep's in
+        // registers
+        asm volatile("" ::: "memory");
+        v = cb[M - 1];
+        double jp = recip(__builtin_fma(v.w, tl, v.z));
+        double Fu = fv[M - 1] * jp, Hu = v.y * jp, anext = v.x;
+#pragma unroll
+        for (int r = M - 2; r >= 0; --r) {
+            v = cb[r];
+            jp = recip(__builtin_fma(v.w, tl, v.z) - v.y * anext * jp);
+            Fu = (fv[r] - v.y * Fu) * jp;
+            Hu = -v.y * Hu * jp;
+            anext = v.x;
+        }
+        Uu = Fu;
+        Vu = -Hu;
+        Wu = -anext * jp;
+    }
+    sh.ex[0][threadIdx.x] = Ud;
+    sh.ex[1][threadIdx.x] = Vd;
+    sh.ex[2][threadIdx.x] = Wd;
+    sh.ex[3][threadIdx.x] = Uu;
+    sh.ex[4][threadIdx.x] = Vu;
+    sh.ex[5][threadIdx.x] = Wu;
+    sh.ex[6][threadIdx.x] = fv[M];
+    __syncthreads();
+
+    // ---- interface system, one lane per line ----
+    // (c', d') of the elimination go to LDS slots already read: c' to ex[1]
+    // of the row, d' to zz, so the lane keeps no arrays beside fv, ip.  The
+    // loops are not unrolled: unrolled, their LDS reads are all hoisted into
+    // registers while fv and ip are live.
+    if (s == 0) {
+        double cprev = 0.0, dprev = 0.0;
+#pragma unroll 1
+        for (int q = 0; q < P; ++q) {
+            const double4 v = sh.cf[(pinned && q == sp) ? PIN + M : q * CS + M];
+            const double a = v.x, c = v.y, d = __builtin_fma(v.w, tl, v.z);
+            const int me = q * LB + l;
+            double rd = d + a * sh.ex[1][me];
+            const double ra = a * sh.ex[2][me];
+            double rf = sh.ex[6][me] - a * sh.ex[0][me], rc = 0.0;
+            if (q + 1 < P) {
+                const int nb = me + LB;
+                rd += c * sh.ex[5][nb];
+                rc = c * sh.ex[4][nb];
+                rf -= c * sh.ex[3][nb];
+            }
+            const double iq = recip(rd - ra * cprev);
+            cprev = rc * iq;
+            dprev = (rf - ra * dprev) * iq;
+            sh.ex[1][me] = cprev;
+            sh.zz[q][l] = dprev;
+        }
+        double z = dprev;
+#pragma unroll 1
+        for (int q = P - 2; q >= 0; --q) {
+            z = sh.zz[q][l] - sh.ex[1][q * LB + l] * z;
+            sh.zz[q][l] = z;
+        }
+    }
+    __syncthreads();
+
+    // ---- pass 2: interior Thomas with the interface values folded in ----
+    const double Xr = sh.zz[s][l], Xl = s > 0 ? sh.zz[s - 1][l] : 0.0;
+    fv[0] -= cb[0].x * Xl;
+    fv[M - 1] -= cb[M - 1].y * Xr;
+    fv[0] *= ip[0];
+#pragma unroll
+    for (int r = 1; r < M; ++r) fv[r] = (fv[r] - cb[r].x * fv[r - 1]) * ip[r];
+#pragma unroll
+    for (int r = M - 2; r >= 0; --r) fv[r] -= cb[r].y * ip[r] * fv[r + 1];
+    fv[M] = Xr;
+    if (live && full) {
+#pragma unroll
+        for (int r = 0; r < L; ++r) x[(long long)(k0 + r) * S] = (TX)fv[r];
+    } else if (live) {
+#pragma unroll
+        for (int r = 0; r < L; ++r)
+            if (k0 + r < nz) x[(long long)(k0 + r) * S] = (TX)fv[r];
+    }
+}
+
+template <int LB, int P, int L, typename TF, typename TX>
+__global__ __launch_bounds__(LB * P) void thomas_part_kernel(ThomasDesc t, long long nlines) {
+    __shared__ ThomasPartLds<LB, P, L> sh;
+    thomas_part_block<LB, P, L, TF, TX>(t, nlines, blockIdx.x, sh);
+}
+
+// Multi-problem: block_begin counts blocks of LB lines per problem; every
+// problem of the list has the same storage types and P L >= nz.
+template <int LB, int P, int L, typename TF, typename TX>
+__global__ __launch_bounds__(LB * P) void thomas_part_multi_kernel(const ThomasDesc* __restrict__ work, int nwork,
+                                                                   long long total_blocks) {
+    __shared__ ThomasPartLds<LB, P, L> sh;
+    for (long long blk = blockIdx.x; blk < total_blocks; blk += gridDim.x) {
+        int lo = 0, hi = nwork - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if (work[mid].block_begin <= blk) lo = mid;
+            else hi = mid - 1;
+        }
+        const ThomasDesc t = work[lo];
+        thomas_part_block<LB, P, L, TF, TX>(t, (long long)t.nx * t.ny * t.nsys, blk - t.block_begin, sh);
+        __syncthreads();
+    }
+}
+
+// Configurations (lines per block LB, segments P, planes per segment L); a
+// line of nz planes needs P L >= nz.  Blocks of LB P lanes; the register
+// count grows with L (about 122 at L = 16, 246 at L = 32), which with the
+// block size sets how many blocks share a compute unit.
+struct ThomasPart {
+    int LB, P, L;
+};
+#define TPT_THOMAS_PARTS(X) \
+    X(64, 4, 8)             \
+    X(64, 8, 8)             \
+    X(32, 8, 8)             \
+    X(64, 8, 16)            \
+    X(32, 8, 16)            \
+    X(16, 8, 16)            \
+    X(64, 16, 16)           \
+    X(32, 16, 16)           \
+    X(16, 16, 16)           \
+    X(64, 8, 32)            \
+    X(32, 8, 32)            \
+    X(16, 8, 32)            \
+    X(16, 32, 16)           \
+    X(32, 16, 32)           \
+    X(16, 16, 32)           \
+    X(16, 64, 16)           \
+    X(16, 32, 32)
+#define TPT_TP_ROW(XLB, XP, XL) {XLB, XP, XL},
+constexpr ThomasPart THOMAS_PARTS[] = {TPT_THOMAS_PARTS(TPT_TP_ROW)};
+#undef TPT_TP_ROW
+static_assert(sizeof(THOMAS_PARTS) / sizeof(THOMAS_PARTS[0]) == THOMAS_NPART, "configuration count");
+
+void thomas_part_shape(int v, int* lb, int* p, int* l) {
+    *lb = THOMAS_PARTS[v].LB;
+    *p = THOMAS_PARTS[v].P;
+    *l = THOMAS_PARTS[v].L;
+}
+
+// Automatic choice by nz: the configuration measured fastest on lines of
+// 32, 64, 128, 256, 512 and 1024 planes (FP64, 0.25-1 M lines).  Small blocks
+// win: with three barriers per block, several blocks per compute unit keep
+// its loads going while one block computes.
+static int thomas_part_auto(int nz) {
+    const int want[][2] = {{32, 0}, {64, 2}, {128, 4}, {256, 8}, {512, 12}, {1024, 16}};
+    for (const auto& w : want)
+        if (nz <= w[0]) return w[1];
+    return -1;
+}
+
+int thomas_variant(const ThomasDesc& t) {
+    const bool same = t.tf == t.tx;
+    if (t.variant == THOMAS_SEQ) return THOMAS_SEQ;
+    if (t.variant == THOMAS_AUTO) {
+        if (t.periodic || !same || t.nz < 16) return THOMAS_SEQ;
+        const int v = thomas_part_auto(t.nz);
+        return v < 0 ? THOMAS_SEQ : THOMAS_PART + v;
+    }
+    const int v = t.variant - THOMAS_PART;
+    if (v < 0 || v >= THOMAS_NPART || t.periodic || !same || THOMAS_PARTS[v].P * THOMAS_PARTS[v].L < t.nz)
+        return -1;
+    return t.variant;
+}
+
+long long thomas_part_blocks(const ThomasDesc& t, int v) {
+    const long long lb = THOMAS_PARTS[v].LB;
+    return ((long long)t.nx * t.ny * t.nsys + lb - 1) / lb;
+}
+
+template <typename T>
+static hipError_t launch_part_t(const ThomasDesc& t, int v, hipStream_t s) {
+    const long long n = (long long)t.nx * t.ny * t.nsys;
+    const dim3 gr((unsigned)thomas_part_blocks(t, v));
+#define TPT_TP_CASE(XLB, XP, XL)                                                           \
+    if (THOMAS_PARTS[v].LB == XLB && THOMAS_PARTS[v].P == XP && THOMAS_PARTS[v].L == XL) { \
+        TPT_KLAUNCH((thomas_part_kernel<XLB, XP, XL, T, T>), gr, dim3(XLB * XP), 0, s, t, n); \
+        return hipGetLastError();                                                       \
+    }
+    TPT_THOMAS_PARTS(TPT_TP_CASE)
+#undef TPT_TP_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_thomas_part(const ThomasDesc& t, int v, hipStream_t s) {
+    if (v < 0 || v >= THOMAS_NPART || t.tf != t.tx) return hipErrorInvalidValue;
+    return t.tf == DT_F64 ? launch_part_t<double>(t, v, s) : launch_part_t<float>(t, v, s);
+}
+
+template <typename T>
+static hipError_t launch_part_multi_t(const ThomasDesc* d_work, int nwork, long long total_blocks, int v,
+                                      hipStream_t s) {
+    const dim3 gr((unsigned)std::min(total_blocks, 8 * PERSISTENT_BLOCKS));
+#define TPT_TP_CASE(XLB, XP, XL)                                                                          \
+    if (THOMAS_PARTS[v].LB == XLB && THOMAS_PARTS[v].P == XP && THOMAS_PARTS[v].L == XL) {                \
+        TPT_KLAUNCH((thomas_part_multi_kernel<XLB, XP, XL, T, T>), gr, dim3(XLB * XP), 0, s, d_work, nwork, \
+                    total_blocks);                                                                     \
+        return hipGetLastError();                                                                      \
+    }
+    TPT_THOMAS_PARTS(TPT_TP_CASE)
+#undef TPT_TP_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_thomas_part_multi(const ThomasDesc* d_work, int nwork, long long total_blocks, int v, int dtype,
+                                    hipStream_t s) {
+    if (total_blocks <= 0) return hipSuccess;
+    if (v < 0 || v >= THOMAS_NPART) return hipErrorInvalidValue;
+    return dtype == DT_F64 ? launch_part_multi_t<double>(d_work, nwork, total_blocks, v, s)
+                           : launch_part_multi_t<float>(d_work, nwork, total_blocks, v, s);
+}
+
+}  // namespace tpt

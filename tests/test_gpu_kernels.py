@@ -15,9 +15,22 @@ def _T():
     return T
 
 
-# long lines: a partial top chunk (131) and whole chunks with two systems (256)
+def _thomas_variants(nz):
+    """(variant, fits) for the automatic, sequential and partitioned kernels."""
+    T = _T()
+    out = [(-1, True), (0, True)]
+    for v, (_, P, L) in enumerate(T.THOMAS_PARTS, start=1):
+        out.append((v, P * L >= nz))
+    return out
+
+
+# long lines: a partial top chunk (131) and whole chunks with two systems
+# (256); for the partitioned kernels: a line count that is not a multiple of
+# the 64 lines of a block (210, 65 per system with blocks straddling systems),
+# nz = P L exactly (64, 256), one plane short of it (255), padded segments
 @pytest.mark.parametrize("nx,ny,nz,nsys", [(37, 5, 11, 1), (64, 64, 33, 2), (3, 2, 2, 1), (1, 1, 1, 1), (130, 7, 64, 1),
-                                           (33, 9, 131, 1), (16, 8, 256, 2)])
+                                           (33, 9, 131, 1), (16, 8, 256, 2), (70, 3, 64, 1), (64, 2, 255, 1),
+                                           (5, 13, 100, 3)])
 @pytest.mark.parametrize("sigma,tau", [(0.0, 1.0), (1.0, -3e-3)])
 def test_thomas_matches_oracle(nx, ny, nz, nsys, sigma, tau):
     import torch
@@ -37,15 +50,24 @@ def test_thomas_matches_oracle(nx, ny, nz, nsys, sigma, tau):
     ref = np.stack([O.thomas_lines(az, bz, cz, lam, sigma, tau, f[s])[0] for s in range(nsys)])
     x = torch.empty(f.shape, dtype=torch.float64, device="cuda")
     scratch = torch.empty((2,) + f.shape, dtype=torch.float64, device="cuda")
-    T.thomas(nx, ny, nz, nsys, cuda(lamx), cuda(lamy), cuda(az), cuda(bz), cuda(cz), sigma, tau, -1,
-             cuda(f), x, scratch)
-    torch.cuda.synchronize()
-    got = host(x)
-    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+    fd = cuda(f)
+    for variant, fits in _thomas_variants(nz):
+        args = (nx, ny, nz, nsys, cuda(lamx), cuda(lamy), cuda(az), cuda(bz), cuda(cz), sigma, tau, -1, fd, x, scratch)
+        if not fits:
+            with pytest.raises(T.TptError):
+                T.thomas(*args, variant=variant)
+            continue
+        x.fill_(float("nan"))
+        T.thomas(*args, variant=variant)
+        torch.cuda.synchronize()
+        got = host(x)
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max(), variant
     del w
 
 
-@pytest.mark.parametrize("nz", [17, 150])
+# the pinned row (nz-1) inside a segment (17, 150) and as the interface row
+# of the last segment (64 = 8 x 8, 128 = 8 x 16, 256 = 16 x 16)
+@pytest.mark.parametrize("nz", [17, 64, 128, 150, 256])
 def test_thomas_pinned_line_in_place(nz):
     import torch
     T = _T()
@@ -60,15 +82,18 @@ def test_thomas_pinned_line_in_place(nz):
     f = rng.standard_normal((nz, ny, nx))
     lam = lamy[:, None] + lamx[None, :]
     ref, _ = O.thomas_lines(az, bz, cz, lam, 0.0, 1.0, f, pin=(2, 3))
-    xf = cuda(f)
     scratch = torch.empty((2, nz, ny, nx), dtype=torch.float64, device="cuda")
-    T.thomas(nx, ny, nz, 1, cuda(lamx), cuda(lamy), cuda(az), cuda(bz), cuda(cz), 0.0, 1.0, 3 + nx * 2,
-             xf, xf, scratch)
-    torch.cuda.synchronize()
-    got = host(xf)
-    assert got[-1, 2, 3] == 0.0
-    assert np.isfinite(got).all()
-    assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
+    for variant, fits in _thomas_variants(nz):
+        if not fits:
+            continue
+        xf = cuda(f)
+        T.thomas(nx, ny, nz, 1, cuda(lamx), cuda(lamy), cuda(az), cuda(bz), cuda(cz), 0.0, 1.0, 3 + nx * 2,
+                 xf, xf, scratch, variant=variant)
+        torch.cuda.synchronize()
+        got = host(xf)
+        assert got[-1, 2, 3] == 0.0, variant
+        assert np.isfinite(got).all(), variant
+        assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max(), variant
 
 
 GEMM_SHAPES = [(1, 1, 1, 1), (16, 16, 16, 1), (37, 53, 29, 3), (128, 128, 128, 1), (200, 131, 77, 2),

@@ -42,6 +42,9 @@ def test_cyclic_thomas_matches_oracle(nx, ny, nz, nsys, sigma, tau):
     torch.cuda.synchronize()
     got = host(x)
     assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+    with pytest.raises(T.TptError):  # the partitioned kernels take non-cyclic lines only
+        T.thomas(nx, ny, nz, nsys, cuda(lamx), cuda(lamy), cuda(az), cuda(bz), cuda(cz), sigma, tau, -1,
+                 cuda(f), x, scratch, periodic_z=True, variant=5)
 
 
 @pytest.mark.parametrize("nz", [2, 17, 40])

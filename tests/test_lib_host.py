@@ -119,6 +119,25 @@ def test_invalid_arguments_rejected():
         T.Plan((8, 8, 8), (f, f, f), (W.NN, W.NN, W.NN), loc=("F", "C", "C"), host_only=True)
 
 
+def test_thomas_variant_rejected_before_launch():
+    """Bad or unfitting Thomas variants fail in the host checks (the dummy,
+    never dereferenced pointers only get past the NULL checks)."""
+    T = _lib()
+    lib = T.lib()
+    p = [4096 + 64 * k for k in range(8)]
+
+    def call(nz, periodic, variant):
+        return lib.tpt_thomas(4, 4, nz, 1, p[0], p[1], p[2], p[3], p[4], periodic, 0.0, 1.0, -1,
+                              p[5], p[6], p[7], variant, 0)
+
+    assert call(32, 0, 18) == -1       # no such variant
+    assert call(32, 0, -2) == -1
+    assert call(33, 0, 1) == -1        # 4 x 8 planes < 33
+    assert call(1025, 0, 16) == -1     # 64 x 16 planes < 1025
+    assert call(300, 0, 10) == -1      # 8 x 32 planes < 300
+    assert call(32, 1, 2) == -1        # cyclic lines: sequential kernel only
+
+
 def test_workspace_size_reported():
     T = _lib()
     p = W.make_problem((10, 9, 8), (1.0, 1.0, 1.0), (W.NN, W.NN, W.NN))
