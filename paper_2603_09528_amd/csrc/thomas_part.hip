@@ -29,7 +29,8 @@ namespace tpt {
 //   (D + A Vd_s + C Wu_{s+1}) z_s + A Wd_s z_{s-1} + C Vu_{s+1} z_{s+1}
 //       = f - A Ud_s - C Uu_{s+1},
 // (A, D, C, f of row k0+L-1; Ud.. of segment s at its last interior row, Uu..
-// of segment s+1 at its first), which one lane per line solves from LDS.
+// of segment s+1 at its first), which the P lanes of the line solve by
+// parallel cyclic reduction through LDS.
 // Pass 2 folds Xl and Xr into the interior's first and last right-hand side
 // and runs the interior Thomas with the pivots kept from pass 1.
 //
@@ -46,8 +47,8 @@ struct ThomasPartLds {
     // rows); segment s at s CS, then the pinned line's copy of segment
     // (nz-1)/L with row nz-1 made the identity
     double4 cf[(P + 1) * CS];
-    double ex[7][NT];  // responses (Ud, Vd, Wd, Uu, Vu, Wu) and the interface f
-    double zz[P][LB];  // interface solution
+    double pcr[2][4][NT];  // interface rows (a, c, d, 1/b) by level; first the up-sweep responses
+    double zz[P][LB];      // interface solution
 };
 
 // One block of LB lines (block index blk of the problem t with nlines lines).
@@ -139,49 +140,68 @@ __device__ __forceinline__ void thomas_part_block(const ThomasDesc& t, long long
         Vu = -Hu;
         Wu = -anext * jp;
     }
-    sh.ex[0][threadIdx.x] = Ud;
-    sh.ex[1][threadIdx.x] = Vd;
-    sh.ex[2][threadIdx.x] = Wd;
-    sh.ex[3][threadIdx.x] = Uu;
-    sh.ex[4][threadIdx.x] = Vu;
-    sh.ex[5][threadIdx.x] = Wu;
-    sh.ex[6][threadIdx.x] = fv[M];
+    // materialise the responses here: left to the compiler, the products
+    // behind Wd and Vd sink past the barrier below with every factor kept
+    // in registers
+    asm volatile("" : "+v"(Ud), "+v"(Vd), "+v"(Wd), "+v"(Uu), "+v"(Vu), "+v"(Wu));
+    // ---- interface system: parallel cyclic reduction over the P rows ----
+    // Lane s forms row s (a z_{s-1} + b z_s + c z_{s+1} = d) from its own
+    // down-sweep responses and the up-sweep responses of segment s+1; each
+    // level h = 1, 2, 4, .. eliminates the couplings to rows s -+ h with the
+    // rows there, so after log2 P levels row s reads b z_s = d.  Rows are
+    // exchanged through two LDS buffers used alternately (one barrier per
+    // level); rows outside 0..P-1 are the identity.
+    const int me = threadIdx.x;
+    sh.pcr[1][0][me] = Uu;
+    sh.pcr[1][1][me] = Vu;
+    sh.pcr[1][2][me] = Wu;
     __syncthreads();
-
-    // ---- interface system, one lane per line ----
-    // (c', d') of the elimination go to LDS slots already read: c' to ex[1]
-    // of the row, d' to zz, so the lane keeps no arrays beside fv, ip.  The
-    // loops are not unrolled: unrolled, their LDS reads are all hoisted into
-    // registers while fv and ip are live.
-    if (s == 0) {
-        double cprev = 0.0, dprev = 0.0;
-#pragma unroll 1
-        for (int q = 0; q < P; ++q) {
-            const double4 v = sh.cf[(pinned && q == sp) ? PIN + M : q * CS + M];
-            const double a = v.x, c = v.y, d = __builtin_fma(v.w, tl, v.z);
-            const int me = q * LB + l;
-            double rd = d + a * sh.ex[1][me];
-            const double ra = a * sh.ex[2][me];
-            double rf = sh.ex[6][me] - a * sh.ex[0][me], rc = 0.0;
-            if (q + 1 < P) {
-                const int nb = me + LB;
-                rd += c * sh.ex[5][nb];
-                rc = c * sh.ex[4][nb];
-                rf -= c * sh.ex[3][nb];
-            }
-            const double iq = recip(rd - ra * cprev);
-            cprev = rc * iq;
-            dprev = (rf - ra * dprev) * iq;
-            sh.ex[1][me] = cprev;
-            sh.zz[q][l] = dprev;
-        }
-        double z = dprev;
-#pragma unroll 1
-        for (int q = P - 2; q >= 0; --q) {
-            z = sh.zz[q][l] - sh.ex[1][q * LB + l] * z;
-            sh.zz[q][l] = z;
+    double ra, rb, rc, rd;
+    {
+        const double4 v = cb[M];  // the interface row (pinned copy on the pinned line)
+        const double A = v.x, C = v.y;
+        ra = A * Wd;
+        rb = __builtin_fma(v.w, tl, v.z) + A * Vd;
+        rc = 0.0;
+        rd = fv[M] - A * Ud;
+        if (s + 1 < P) {
+            const int nb = me + LB;
+            rb += C * sh.pcr[1][2][nb];
+            rc = C * sh.pcr[1][1][nb];
+            rd -= C * sh.pcr[1][0][nb];
         }
     }
+    double ib = recip(rb);
+#pragma unroll 1
+    for (int h = 1, lvl = 0; h < P; h *= 2, ++lvl) {
+        double (*R)[NT] = sh.pcr[lvl & 1];
+        R[0][me] = ra;
+        R[1][me] = rc;
+        R[2][me] = rd;
+        R[3][me] = ib;
+        __syncthreads();
+        double na = 0.0, nc = 0.0, nb = rb, nd = rd;
+        if (s >= h) {
+            const int u = me - h * LB;
+            const double k1 = ra * R[3][u];
+            na = -R[0][u] * k1;
+            nb -= R[1][u] * k1;
+            nd -= R[2][u] * k1;
+        }
+        if (s + h < P) {
+            const int u = me + h * LB;
+            const double k2 = rc * R[3][u];
+            nc = -R[1][u] * k2;
+            nb -= R[0][u] * k2;
+            nd -= R[2][u] * k2;
+        }
+        ra = na;
+        rb = nb;
+        rc = nc;
+        rd = nd;
+        ib = recip(rb);
+    }
+    sh.zz[s][l] = rd * ib;
     __syncthreads();
 
     // ---- pass 2: interior Thomas with the interface values folded in ----
@@ -270,7 +290,7 @@ void thomas_part_shape(int v, int* lb, int* p, int* l) {
 // win: with three barriers per block, several blocks per compute unit keep
 // its loads going while one block computes.
 static int thomas_part_auto(int nz) {
-    const int want[][2] = {{32, 0}, {64, 2}, {128, 4}, {256, 8}, {512, 12}, {1024, 16}};
+    const int want[][2] = {{32, 0}, {64, 2}, {128, 4}, {256, 8}, {512, 12}, {1024, 15}};
     for (const auto& w : want)
         if (nz <= w[0]) return w[1];
     return -1;
