@@ -78,13 +78,17 @@ enum {
     TPT_FLAG_DENSE_X = 2,   /* apply the x eigenbasis by dense GEMM even where a
                                fast transform applies (see tpt_plan_transforms) */
     TPT_FLAG_DENSE_Y = 4,   /* the same for y */
-    TPT_FLAG_FUSE_XY = 8    /* FP64 plans whose x is a fast transform and y a
+    TPT_FLAG_FUSE_XY = 8,   /* FP64 plans whose x is a fast transform and y a
                                GEMM: run the two as one fused pass per
                                direction (tpt_plan_fused).  Reads and writes
                                the field once instead of twice, but on gfx950
                                it is slower than the separate passes (the
                                row transforms inside the GEMM are not hidden
                                behind its MFMAs), so it is not the default */
+    TPT_FLAG_SEQ_THOMAS = 16 /* solve the z lines with the sequential kernel
+                               (one lane per line) instead of the partitioned
+                               one (segments joined by an interface system);
+                               periodic z always uses the sequential kernel */
 };
 
 /* How a plan applies the eigenbasis of x or y (tpt_plan_transforms). */

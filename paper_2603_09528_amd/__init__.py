@@ -165,12 +165,13 @@ class Plan:
     transform (FFT, DCT-II, DST-II of a uniform direction) would apply;
     fuse_xy runs the x fast transform and the y GEMM of an FP64 solve as
     one fused pass per direction (see `fused`; slower on gfx950 than the
-    separate passes, so off by default).
+    separate passes, so off by default); seq_thomas solves the z lines with
+    the sequential kernel instead of the partitioned one.
     """
 
     def __init__(self, n, faces, bc, loc=("C", "C", "C"), kind="poisson", alpha=0.0, precision="fp64",
                  rtol=1e-12, max_refine=8, fixed_refine=-1, nrhs=1, host_only=False, dense_x=False,
-                 dense_y=False, fuse_xy=False):
+                 dense_y=False, fuse_xy=False, seq_thomas=False):
         L = lib()
         d = _Desc()
         L.tpt_plan_desc_init(ctypes.byref(d))
@@ -189,7 +190,7 @@ class Plan:
         d.fixed_refine = int(fixed_refine)
         d.nrhs = int(nrhs)
         d.flags = ((1 if host_only else 0) | (2 if dense_x else 0) | (4 if dense_y else 0)
-                   | (8 if fuse_xy else 0))
+                   | (8 if fuse_xy else 0) | (16 if seq_thomas else 0))
         h = ctypes.c_void_p()
         _check(L.tpt_plan_create(ctypes.byref(d), ctypes.byref(h)))
         self._h = h

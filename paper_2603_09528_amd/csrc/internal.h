@@ -87,6 +87,7 @@ struct tpt_plan_s {
     int gemm_variant[4] = {-1, -1, -1, -1};  // per stage (x fwd, y fwd, y inv, x inv); -1 = table
     int fast[2] = {-1, -1};          // x, y: XformKind of the fast transform, -1 = GEMM
     bool fuse_xy = false;            // FP64: x transform fused into the y GEMM's loads
+    bool seq_thomas = false;         // z lines by the sequential Thomas kernel
     ~tpt_plan_s();
 };
 

@@ -275,6 +275,7 @@ int tpt_plan_create(const tpt_plan_desc* desc, tpt_plan* out) {
     if (p->desc.rtol <= 0.0) p->desc.rtol = 1e-12;
     if (p->desc.max_refine <= 0) p->desc.max_refine = 8;
     p->host_only = (desc->flags & TPT_FLAG_HOST_ONLY) != 0;
+    p->seq_thomas = (desc->flags & TPT_FLAG_SEQ_THOMAS) != 0;
     if (!p->host_only && hipGetDevice(&p->device) != hipSuccess)
         return fail(TPT_ERR_HIP, "no HIP device");
     for (int d = 0; d < 3; ++d) {

@@ -242,6 +242,7 @@ ThomasDesc plan_thomas(const tpt_plan_s* p, const void* f, int tf, void* x, int 
     t.x = x;
     t.tx = tx;
     t.scratch = scratch;
+    t.variant = p->seq_thomas ? THOMAS_SEQ : THOMAS_AUTO;
     return t;
 }
 

@@ -285,11 +285,16 @@ void thomas_part_shape(int v, int* lb, int* p, int* l) {
     *l = THOMAS_PARTS[v].L;
 }
 
-// Automatic choice by nz: the configuration measured fastest on lines of
-// 32, 64, 128, 256, 512 and 1024 planes (FP64, 0.25-1 M lines).  Small blocks
-// win: with three barriers per block, several blocks per compute unit keep
-// its loads going while one block computes.
-static int thomas_part_auto(int nz) {
+// Automatic choice by nz and line count: the configuration measured fastest
+// on lines of 32, 64, 128, 256, 512 and 1024 planes (FP64, 32 K - 1 M
+// lines).  Small blocks win: with the barriers of each block, several blocks
+// per compute unit keep its loads going while one block computes.  Lines of
+// more than 512 planes need 1024-lane blocks (one per compute unit); with
+// many lines the sequential kernel then has parallelism enough and is faster
+// (1024^3: 5.2 against 6.9 ms), with few it is not (32 K lines of 1024
+// planes: 0.24 against 0.17 ms).
+static int thomas_part_auto(int nz, long long lines) {
+    if (nz > 512 && lines >= 131072) return -1;
     const int want[][2] = {{32, 0}, {64, 2}, {128, 4}, {256, 8}, {512, 12}, {1024, 15}};
     for (const auto& w : want)
         if (nz <= w[0]) return w[1];
@@ -301,7 +306,7 @@ int thomas_variant(const ThomasDesc& t) {
     if (t.variant == THOMAS_SEQ) return THOMAS_SEQ;
     if (t.variant == THOMAS_AUTO) {
         if (t.periodic || !same || t.nz < 16) return THOMAS_SEQ;
-        const int v = thomas_part_auto(t.nz);
+        const int v = thomas_part_auto(t.nz, (long long)t.nx * t.ny * t.nsys);
         return v < 0 ? THOMAS_SEQ : THOMAS_PART + v;
     }
     const int v = t.variant - THOMAS_PART;

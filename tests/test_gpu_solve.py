@@ -80,6 +80,18 @@ def test_small_fp64_matches_oracle(case):
 
 
 @pytest.mark.parametrize("case", SMALL, ids=lambda c: f"{c[0][0]}x{c[0][1]}x{c[0][2]}-{c[4]}")
+def test_small_fp64_sequential_thomas_matches_oracle(case):
+    """The same solves with the z lines on the sequential kernel."""
+    p = _small_problem(case)
+    f = W.rhs(p, 11)
+    say("small fp64 seq thomas", p.n, p.bc, p.loc, p.kind)
+    got, _ = _solve(p, f, seq_thomas=True)
+    ref = O.solve(p, f)
+    err = O.relative_error(p, got, ref)
+    assert err <= FP64_TOL, err
+
+
+@pytest.mark.parametrize("case", SMALL, ids=lambda c: f"{c[0][0]}x{c[0][1]}x{c[0][2]}-{c[4]}")
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 def test_small_mixed_matches_oracle(case, prec):
     p = _small_problem(case)
