@@ -507,6 +507,10 @@ def main():
                 if ln.startswith("#") or not ln.strip():
                     continue
                 pr, kind, M, N, K, v = (int(t) for t in ln.split())
+                if kind == 2:  # Thomas kernel: 1 sequential, 2.. partitioned (lines/block, segments, planes)
+                    key = f"{precs[pr]} thomas lines={M} nz={N}"
+                    tiles[key] = "sequential" if v == 1 else f"partitioned {T.THOMAS_PARTS[v - 2]}"
+                    continue
                 key = f"{precs[pr]} {'x' if kind == 0 else 'y'} M={M or 'any'} N={N} K={K}"
                 tiles[key] = names[v] if 0 <= v < len(names) else str(v)
     except Exception as e:  # the table is informative only

@@ -207,13 +207,18 @@ int tpt_batch_workspace_bytes(tpt_batch batch, size_t *bytes);
 int tpt_batch_solve(tpt_batch batch, const double *const *rhs, double *const *out,
                     void *workspace, size_t workspace_bytes, void *stream, int use_graph);
 
-/* ---- autotuning of GEMM tiles --------------------------------------------- */
+/* ---- autotuning of GEMM tiles and the Thomas kernel ------------------------ */
 
 /* Time every compiled tile variant for the GEMM shapes of the given plans and
- * record the fastest per (shape class, precision) in the process-wide table.
- * Needs the GPU; synchronous. */
+ * record the fastest per (shape class, precision) in the process-wide table;
+ * for non-periodic z, likewise time the sequential and the partitioned Thomas
+ * kernels (variants of tpt_thomas) on the plan's lines and record the fastest
+ * per (precision, line count, line length).  Plans created before or after
+ * use the table; plans with TPT_FLAG_SEQ_THOMAS keep the sequential kernel.
+ * Needs the GPU; synchronous; allocates temporary device buffers. */
 int tpt_autotune(int count, const tpt_plan *plans, void *stream);
-/* Save / load the table as text (one "kind prec M N K variant" line per entry). */
+/* Save / load the table as text (one "prec kind M N K variant" line per
+ * entry; kind 0 x GEMM, 1 y GEMM, 2 Thomas with M = lines, N = nz). */
 int tpt_autotune_save(const char *path);
 int tpt_autotune_load(const char *path);
 

@@ -111,6 +111,11 @@ int plan_gemm_prec(const tpt_plan_s* p);
 // Tile selection: autotuned table lookup (falls back to a size heuristic).
 int choose_variant(int prec, int stage_kind, int M, int N, int K);
 void autotune_record(int prec, int stage_kind, int M, int N, int K, int variant);
+// tuning-table kind of the Thomas kernel entries: (prec, TUNE_THOMAS, lines,
+// nz, 0) -> THOMAS_SEQ or THOMAS_PART + configuration
+constexpr int TUNE_THOMAS = 2;
+// the recorded Thomas variant for that key, or THOMAS_AUTO
+int tuned_thomas(int prec, long long lines, int nz);
 // stage_kind: 0 = x pass (B = basis), 1 = y pass (A = basis)
 
 // ---- kernel timing ------------------------------------------------------------

@@ -412,7 +412,8 @@ int tpt_batch_solve(tpt_batch b, const double* const* rhs, double* const* out, v
 
 // ---------------------------------------------------------------------------
 // Autotuner: time every tile variant on the plan's own GEMM shapes and keep
-// the fastest per (precision, pass, shape).
+// the fastest per (precision, pass, shape); likewise the Thomas kernel per
+// (precision, line count, line length).
 // ---------------------------------------------------------------------------
 int tpt_autotune(int count, const tpt_plan* plans, void* stream) {
     if (count < 1 || !plans) return fail(TPT_ERR_INVALID, "bad autotune arguments");
@@ -469,6 +470,44 @@ int tpt_autotune(int count, const tpt_plan* plans, void* stream) {
                 }
             }
             if (best >= 0) autotune_record(prec, kind, g.M, g.N, g.K, best);
+        }
+        // Thomas kernel: the sequential one and every partitioned
+        // configuration that fits, on the plan's own lines (one system)
+        if (!p->op[2].periodic && !p->seq_thomas) {
+            const int dt = prec == GP_F64 ? DT_F64 : DT_F32;
+            const long long lines = (long long)p->N[0] * p->N[1];
+            auto key = std::make_tuple(prec, TUNE_THOMAS, (int)lines, p->N[2], 0);
+            void* scratch = nullptr;
+            const size_t sbytes = 8 * (size_t)thomas_scratch_doubles(p->N[0], p->N[1], p->N[2], 1, 0) + 256;
+            if (std::find(done.begin(), done.end(), key) == done.end() && hipMalloc(&scratch, sbytes) == hipSuccess) {
+                done.push_back(key);
+                ThomasDesc t = plan_thomas(p, in, dt, outb, dt, (double*)scratch, 1);
+                int best = -1;
+                float best_ms = 1e30f;
+                for (int v = THOMAS_SEQ; v < THOMAS_PART + THOMAS_NPART; ++v) {
+                    t.variant = v;
+                    if (thomas_variant(t) != v || launch_thomas(t, s) != hipSuccess) continue;  // warm-up
+                    float ms_min = 1e30f;
+                    for (int r = 0; r < 5; ++r) {
+                        (void)hipEventRecord(e0, s);
+                        (void)launch_thomas(t, s);
+                        (void)hipEventRecord(e1, s);
+                        (void)hipEventSynchronize(e1);
+                        float ms = 0.f;
+                        (void)hipEventElapsedTime(&ms, e0, e1);
+                        ms_min = std::min(ms_min, ms);
+                    }
+                    if (ms_min < best_ms) {
+                        best_ms = ms_min;
+                        best = v;
+                    }
+                }
+                if (best >= 0) autotune_record(prec, TUNE_THOMAS, (int)lines, p->N[2], 0, best);
+                (void)hipStreamSynchronize(s);
+                (void)hipFree(scratch);
+            } else {
+                (void)hipGetLastError();
+            }
         }
         (void)hipStreamSynchronize(s);
         (void)hipFree(in);

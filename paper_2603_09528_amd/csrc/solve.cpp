@@ -95,6 +95,13 @@ void autotune_record(int prec, int kind, int M, int N, int K, int variant) {
     g_tune[tune_key(prec, kind, M, N, K)] = variant;
 }
 
+int tuned_thomas(int prec, long long lines, int nz) {
+    if (lines > 0x7fffffffLL) return THOMAS_AUTO;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tune.find(tune_key(prec, TUNE_THOMAS, (int)lines, nz, 0));
+    return it != g_tune.end() ? it->second : THOMAS_AUTO;
+}
+
 int choose_variant(int prec, int kind, int M, int N, int K) {
     {
         std::lock_guard<std::mutex> lock(g_tune_mu);
@@ -242,7 +249,10 @@ ThomasDesc plan_thomas(const tpt_plan_s* p, const void* f, int tf, void* x, int 
     t.x = x;
     t.tx = tx;
     t.scratch = scratch;
-    t.variant = p->seq_thomas ? THOMAS_SEQ : THOMAS_AUTO;
+    // the sequential kernel if asked for, else what the autotuner recorded
+    // for these lines, else the automatic choice
+    t.variant = p->seq_thomas ? THOMAS_SEQ : tuned_thomas(plan_gemm_prec(p), (long long)t.nx * t.ny * nrhs, t.nz);
+    if (thomas_variant(t) < 0) t.variant = THOMAS_AUTO;
     return t;
 }
 
@@ -680,7 +690,9 @@ int tpt_autotune_load(const char* path) {
         std::istringstream is(line);
         int prec, kind, M, N, K, v;
         if (!(is >> prec >> kind >> M >> N >> K >> v)) continue;
-        if (v < 0 || v >= TV_COUNT) continue;
+        if (prec < GP_F64 || prec > GP_BF16X3 || kind < 0 || kind > TUNE_THOMAS) continue;
+        if (kind == TUNE_THOMAS ? (v < THOMAS_SEQ || v >= THOMAS_PART + THOMAS_NPART) : (v < 0 || v >= TV_COUNT))
+            continue;
         g_tune[tune_key(prec, kind, M, N, K)] = v;
     }
     return TPT_OK;

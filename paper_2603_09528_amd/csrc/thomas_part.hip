@@ -285,17 +285,21 @@ void thomas_part_shape(int v, int* lb, int* p, int* l) {
     *l = THOMAS_PARTS[v].L;
 }
 
-// Automatic choice by nz and line count: the configuration measured fastest
-// on lines of 32, 64, 128, 256, 512 and 1024 planes (FP64, 32 K - 1 M
-// lines).  Small blocks win: with the barriers of each block, several blocks
-// per compute unit keep its loads going while one block computes.  Lines of
+// Automatic choice by nz and line count (the autotuner's measurement on the
+// plan's own lines takes precedence): the configuration measured fastest on
+// lines of 32, 64, 128, 256, 512 and 1024 planes (FP64, 16 K - 1 M lines).
+// Small blocks win: with the barriers of each block, several blocks per
+// compute unit keep its loads going while one block computes; from about
+// 256 K lines, 32-line blocks (256-byte plane segments) overtake 16-line ones
+// (1024^2 x 256: 0.98 against 1.22 ms; 256^3: 55 against 54 us).  Lines of
 // more than 512 planes need 1024-lane blocks (one per compute unit); with
 // many lines the sequential kernel then has parallelism enough and is faster
 // (1024^3: 5.2 against 6.9 ms), with few it is not (32 K lines of 1024
 // planes: 0.24 against 0.17 ms).
 static int thomas_part_auto(int nz, long long lines) {
     if (nz > 512 && lines >= 131072) return -1;
-    const int want[][2] = {{32, 0}, {64, 2}, {128, 4}, {256, 8}, {512, 12}, {1024, 15}};
+    const bool many = lines >= 262144;
+    const int want[][2] = {{32, 0}, {64, 2}, {128, 4}, {256, many ? 7 : 8}, {512, many ? 13 : 12}, {1024, 15}};
     for (const auto& w : want)
         if (nz <= w[0]) return w[1];
     return -1;

@@ -91,6 +91,24 @@ def test_small_fp64_sequential_thomas_matches_oracle(case):
     assert err <= FP64_TOL, err
 
 
+def test_autotune_records_thomas_kernel(tmp_path):
+    """The autotuner times the Thomas kernels on the plan's lines, records the
+    fastest (table kind 2), and solves with it still match the oracle."""
+    T = _T()
+    p = W.make_problem((48, 40, 100), (1.5, 2.0, 1.0), (W.NN, W.NN, W.NN))
+    f = W.rhs(p, 13)
+    plan = T.Plan.from_problem(p)
+    T.autotune([plan])
+    path = tmp_path / "tune.txt"
+    T.autotune_save(str(path))
+    rows = [tuple(int(t) for t in ln.split()) for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    thomas = [r for r in rows if r[1] == 2 and r[2] == 48 * 40 and r[3] == 100]
+    assert len(thomas) == 1 and 1 <= thomas[0][5] <= 1 + len(T.THOMAS_PARTS), rows
+    got, _ = _solve(p, f)
+    err = O.relative_error(p, got, O.solve(p, f))
+    assert err <= FP64_TOL, err
+
+
 @pytest.mark.parametrize("case", SMALL, ids=lambda c: f"{c[0][0]}x{c[0][1]}x{c[0][2]}-{c[4]}")
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 def test_small_mixed_matches_oracle(case, prec):

@@ -148,7 +148,8 @@ def test_workspace_size_reported():
 def test_autotune_table_roundtrip(tmp_path):
     T = _lib()
     src = tmp_path / "table.txt"
-    src.write_text("# prec kind M N K variant\n0 0 0 256 256 5\n2 1 96 96 96 3\nbogus line\n1 0 0 48 48 9\n")
+    src.write_text("# prec kind M N K variant\n0 0 0 256 256 5\n2 1 96 96 96 3\nbogus line\n1 0 0 48 48 9\n"
+                   "0 2 65536 256 0 10\n1 2 4096 64 0 30\n")
     T.autotune_load(str(src))
     out = tmp_path / "out.txt"
     T.autotune_save(str(out))
@@ -156,6 +157,8 @@ def test_autotune_table_roundtrip(tmp_path):
     assert "0 0 0 256 256 5" in lines
     assert "2 1 96 96 96 3" in lines
     assert not any(l.endswith(" 9") for l in lines)  # out-of-range variant ignored
+    assert "0 2 65536 256 0 10" in lines              # Thomas entry (kind 2)
+    assert not any(l.endswith(" 30") for l in lines)  # no such Thomas variant
 
 
 def test_timing_collect_empty():
