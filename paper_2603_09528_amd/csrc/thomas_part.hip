@@ -56,22 +56,55 @@ template <int LB, int P, int L, typename TF, typename TX>
 __device__ __forceinline__ void thomas_part_block(const ThomasDesc& t, long long nlines, long long blk,
                                                   ThomasPartLds<LB, P, L>& sh) {
     constexpr int NT = LB * P, M = L - 1, CS = L + 1, PIN = P * CS;
+    constexpr int NE = (P + 1) * L, SI = (NE + NT - 1) / NT;  // staged rows, per thread
     static_assert(L >= 4, "segments need interior rows");
     const int nz = t.nz;
     const int sp = (nz - 1) / L;  // segment of row nz-1
-    for (int e = threadIdx.x; e < (P + 1) * L; e += NT) {
+
+    // Prologue, two forms.  EAGER: every global load of the block is issued
+    // before any is waited for (at clamped, valid addresses, without
+    // branches): the raw coefficients of its staged rows, the lambdas, the
+    // segment's planes of f; the block then waits one memory latency and
+    // pass 1 can start as the first planes arrive.  Otherwise the staging
+    // loop waits for its coefficient loads before the planes are requested
+    // (up to three latencies in a row), but the block needs about ten fewer
+    // registers.  With L = 16 those ten registers cross the 128 that keep
+    // four waves per SIMD, and the lazy form measured faster there (32-line
+    // blocks at 1024^2 x 256: 0.98 against 1.06 ms); at L = 8 and 32 the
+    // occupancy does not change and the eager form is faster (1024^2 x 512:
+    // 2.19 against 2.34 ms; 1024^2 x 64: 0.214 against 0.228 ms).
+    constexpr bool EAGER = L != 16;
+    [[maybe_unused]] double za[SI], zb[SI], zc[SI];
+    // (A, C, D, E) of staged row e; the pinned copy (seg == P) has its row
+    // nz-1 as the identity
+    auto stage_row = [&](int e, double a, double b, double c) {
         const int seg = e / L, r = e - seg * L;
         const int k = (seg < P ? seg : sp) * L + r;
         double4 v = make_double4(0.0, 0.0, 1.0, 0.0);
         if (k < nz && !(seg == P && k == nz - 1)) {
-            v.x = k > 0 ? t.tau * t.az[k] : 0.0;
-            v.y = k < nz - 1 ? t.tau * t.cz[k] : 0.0;
-            v.z = t.sigma + t.tau * t.bz[k];
+            v.x = k > 0 ? t.tau * a : 0.0;
+            v.y = k < nz - 1 ? t.tau * c : 0.0;
+            v.z = t.sigma + t.tau * b;
             v.w = 1.0;
         }
         sh.cf[seg * CS + r] = v;
+    };
+    if constexpr (EAGER) {
+#pragma unroll
+        for (int q = 0; q < SI; ++q) {
+            const int e = threadIdx.x + q * NT, seg = e / L;
+            const int k = min((seg < P ? seg : sp) * L + (e - seg * L), nz - 1);
+            za[q] = t.az[k];
+            zb[q] = t.bz[k];
+            zc[q] = t.cz[k];
+        }
+    } else {
+        for (int e = threadIdx.x; e < NE; e += NT) {
+            const int seg = e / L;
+            const int k = min((seg < P ? seg : sp) * L + (e - seg * L), nz - 1);
+            stage_row(e, t.az[k], t.bz[k], t.cz[k]);
+        }
     }
-
     const int l = threadIdx.x % LB, s = threadIdx.x / LB;
     const long long S = (long long)t.nx * t.ny;
     const long long glr = blk * LB + l;
@@ -89,20 +122,35 @@ __device__ __forceinline__ void thomas_part_block(const ThomasDesc& t, long long
     const bool full = k0 + L <= nz;
 
     double fv[L];
-    if (live && full) {
+    if constexpr (EAGER) {
 #pragma unroll
-        for (int r = 0; r < L; ++r) fv[r] = (double)f[(long long)(k0 + r) * S];
+        for (int r = 0; r < L; ++r) fv[r] = (double)f[(long long)min(k0 + r, nz - 1) * S];
+#pragma unroll
+        for (int q = 0; q < SI; ++q)
+            if (threadIdx.x + q * NT < NE) stage_row(threadIdx.x + q * NT, za[q], zb[q], zc[q]);
     } else {
+        if (live && full) {
 #pragma unroll
-        for (int r = 0; r < L; ++r) fv[r] = live && k0 + r < nz ? (double)f[(long long)(k0 + r) * S] : 0.0;
-    }
-    if (pinned && s == sp) {
+            for (int r = 0; r < L; ++r) fv[r] = (double)f[(long long)(k0 + r) * S];
+        } else {
 #pragma unroll
-        for (int r = 0; r < L; ++r)
-            if (k0 + r == nz - 1) fv[r] = 0.0;
+            for (int r = 0; r < L; ++r) fv[r] = live && k0 + r < nz ? (double)f[(long long)(k0 + r) * S] : 0.0;
+        }
+        if (pinned && s == sp) {
+#pragma unroll
+            for (int r = 0; r < L; ++r)
+                if (k0 + r == nz - 1) fv[r] = 0.0;
+        }
     }
     __syncthreads();
     const double4* cb = sh.cf + ((pinned && s == sp) ? PIN : s * CS);
+    if constexpr (EAGER) {
+        // identity rows (beyond nz, and the pinned row) carry no data: E = 0
+        // there and 1 elsewhere.  (A select on the row index instead was
+        // scheduled before the barrier, making it wait for the loads.)
+#pragma unroll
+        for (int r = 0; r < L; ++r) fv[r] *= cb[r].w;
+    }
 
     // ---- pass 1: end responses of the interior rows 0 .. M-1 ----
     double ip[M];
