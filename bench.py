@@ -367,8 +367,8 @@ def run_batch(args, T, W):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only (--gpus 1); "
-                          "multi-GPU sharding is a design in DESIGN.md, not part of this build"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only (--gpus 1): a solve is not "
+                          "sharded across GPUs"}))
         sys.exit(2)
     import torch
     import paper_2603_09528_amd as T

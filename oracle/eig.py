@@ -16,8 +16,8 @@ operator, which carry the solution, are only determined to eps ||T|| / gap
 Null mode (periodic or Neumann-Neumann): T 1 = 0, so T~ has the exact null
 vector D^{1/2} 1 / ||D^{1/2} 1||.  The eigenvalue of smallest magnitude is set
 to exactly 0, its eigenvector to that exact null vector, and the remaining
-eigenvectors are re-orthogonalised against it (reading listed in the design doc:
-the paper treats the null mode through the final-pivot gauge of §3, which
+eigenvectors are re-orthogonalised against it (a reading of the paper:
+it treats the null mode through the final-pivot gauge of §3, which
 needs the null line to be identified exactly).
 """
 from __future__ import annotations

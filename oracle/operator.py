@@ -8,7 +8,7 @@ between unknowns i and i+1, so that (Eq. tridiagonal-coefficients)
     a_i = 1/(dx_i dx_{i-1/2}),  c_i = 1/(dx_i dx_{i+1/2}),  b_i = -(a_i + c_i).
 The paper only says the first and last rows are modified by the boundary
 conditions and that periodic boundaries add cyclic corner entries; the rows
-used here are the ghost-cell rows (reading listed in the design doc):
+used here are the ghost-cell rows (a reading of the paper, not its text):
 
 * cell-centred unknowns, Neumann wall: zero flux through the wall face, the
   wall coupling is dropped and b_1 = -c_1;
