@@ -11,8 +11,8 @@ forward transforms, Thomas, inverse transforms, and for the mixed modes the
 FP64 residual/refinement loop) with the input already resident in HBM; the
 eigendecomposition (plan) is one-time initialization and is not timed.
 
-Prints one JSON line.  ``--gpus`` above 1 is refused: this build measures one
-GPU.
+Prints one JSON line.  ``--gpus`` above 1 is refused: the benchmark measures
+one GPU.
 """
 from __future__ import annotations
 
