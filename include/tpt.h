@@ -276,8 +276,11 @@ int tpt_thomas(int nx, int ny, int nz, int nsys, const double *lamx, const doubl
  * (float) or TPT_MIXED_BF16X3 (float operands; the basis-side operand — B for
  * b_nk = 1, A for b_nk = 0 — is split once into bf16 planes in a temporary
  * device buffer, the other on the fly).  variant: tile shape 0..4 (128x128,
- * 64x128, 128x64, 64x64, 32x64) or -1 for the tile table.  Batch strides in
- * elements (0 = shared).  Synchronises the stream for TPT_MIXED_BF16X3. */
+ * 64x128, 128x64, 64x64, 32x64); FP64 / FP32 only: 5 (128x128 with a 32-deep
+ * K tile), 6 (128x128 persistent, four 64x64 waves), 7 (128x128 persistent,
+ * eight 64x32 waves) — 6 and 7 need M, N multiples of 128 and K of 16; or -1
+ * for the tile table.  Batch strides in elements (0 = shared).  Synchronises
+ * the stream for TPT_MIXED_BF16X3. */
 int tpt_gemm(int prec, int b_nk, int variant, int M, int N, int K, int batch, const void *A,
              long long strideA, const void *B, long long strideB, void *C, long long strideC,
              void *stream);

@@ -33,9 +33,9 @@ template <> struct Mfma<float> {
 };
 
 // Work decomposition of a BM x BN tile: waves of WM x WN.
-template <int BM, int BN> struct TileCfg {
-    static constexpr int WM = BM >= 64 ? 64 : 32;
-    static constexpr int WN = BN >= 64 ? 64 : BN;
+template <int BM, int BN, int WM_ = (BM >= 64 ? 64 : 32), int WN_ = (BN >= 64 ? 64 : BN)> struct TileCfg {
+    static constexpr int WM = WM_;
+    static constexpr int WN = WN_;
     static constexpr int WAVES_M = BM / WM;
     static constexpr int WAVES_N = BN / WN;
     static constexpr int NT = WAVES_M * WAVES_N * 64;
@@ -279,10 +279,10 @@ template <> struct BufIO<float> {
     }
 };
 
-template <typename TM, typename TA, typename TB, typename TC, int EPI, bool BNK>
+template <typename TM, typename TA, typename TB, typename TC, int EPI, bool BNK, int WN = 64>
 __device__ __forceinline__ void gemm_tiles_persist_f(const GemmDesc& g, long long ntiles, TM* smem, double* red) {
     constexpr int BM = 128, BN = 128, BK = 16;
-    typedef TileCfg<BM, BN> C;
+    typedef TileCfg<BM, BN, 64, WN> C;
     typedef SmemF<TM, BM, BN, BNK, BK, 2> S;
     typedef Mfma<TM> MM;
     constexpr int NT = C::NT;
@@ -727,13 +727,14 @@ __global__ TPT_GEMM_ATTR void gemm_kernel(GemmDesc g) {
     GemmKernel<PREC, TA, TB, TC, EPI, BM, BN, BNK, DEEP>::tile(g, xcd_block(blockIdx.x, gridDim.x));
 }
 
-// Persistent single-problem kernel (interior tiles only, FP64 / FP32).
-template <int PREC, typename TA, typename TB, typename TC, int EPI, bool BNK>
-__global__ __launch_bounds__(256) void gemm_persist_kernel(GemmDesc g, long long ntiles) {
+// Persistent single-problem kernel (interior tiles only, FP64 / FP32): four
+// waves of 64 x 64 (WN = 64, 256 threads) or eight of 64 x 32 (WN = 32).
+template <int PREC, typename TA, typename TB, typename TC, int EPI, bool BNK, int WN = 64>
+__global__ __launch_bounds__((TileCfg<128, 128, 64, WN>::NT)) void gemm_persist_kernel(GemmDesc g, long long ntiles) {
     typedef typename std::conditional<PREC == GP_F64, double, float>::type T;
     __shared__ __attribute__((aligned(16))) T smem[SmemF<T, 128, 128, BNK, 16, 2>::TOTAL];
-    __shared__ double red[2 * 4];
-    gemm_tiles_persist_f<T, TA, TB, TC, EPI, BNK>(g, ntiles, smem, red);
+    __shared__ double red[2 * (TileCfg<128, 128, 64, WN>::NT / 64)];
+    gemm_tiles_persist_f<T, TA, TB, TC, EPI, BNK, WN>(g, ntiles, smem, red);
 }
 
 template <int PREC, typename TA, typename TB, typename TC, int EPI, int BM, int BN, bool BNK, int DEEP>
@@ -779,6 +780,7 @@ hipError_t launch_gemm_typed(const GemmDesc& g, const GemmDesc* d_work, int nwor
             else TPT_LAUNCH(128, 128, 1);
             break;
         case TV_128x128_P:
+        case TV_128x128_P8:
             if constexpr (PREC == GP_BF16X3) {
                 return hipErrorInvalidValue;
             } else {
@@ -788,8 +790,12 @@ hipError_t launch_gemm_typed(const GemmDesc& g, const GemmDesc* d_work, int nwor
                 }
                 if (g.M % 128 || g.N % 128 || g.K % 16 || g.K < 16) return hipErrorInvalidValue;
                 const long long grid = persistent_gemm_grid(blocks);
-                TPT_KLAUNCH((gemm_persist_kernel<PREC, TA, TB, TC, EPI, BNK>), dim3((unsigned)grid), dim3(256),
-                                   0, s, g, blocks);
+                if (variant == TV_128x128_P)
+                    TPT_KLAUNCH((gemm_persist_kernel<PREC, TA, TB, TC, EPI, BNK, 64>), dim3((unsigned)grid),
+                                dim3(TileCfg<128, 128, 64, 64>::NT), 0, s, g, blocks);
+                else
+                    TPT_KLAUNCH((gemm_persist_kernel<PREC, TA, TB, TC, EPI, BNK, 32>), dim3((unsigned)grid),
+                                dim3(TileCfg<128, 128, 64, 32>::NT), 0, s, g, blocks);
             }
             break;
         default: return hipErrorInvalidValue;

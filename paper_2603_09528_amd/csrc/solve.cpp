@@ -284,7 +284,7 @@ int stage_variant(const tpt_plan_s* p, int stage, const GemmDesc& g, int prec) {
     }
     // the persistent tile needs interior tiles; the x-pass table entry is
     // shared by every row count, so check this problem's own shape
-    if (v == TV_128x128_P && (prec == GP_BF16X3 || g.M % 128 || g.N % 128 || g.K % 16)) v = TV_128x128;
+    if (tv_persistent(v) && (prec == GP_BF16X3 || g.M % 128 || g.N % 128 || g.K % 16)) v = TV_128x128;
     return v;
 }
 
@@ -611,7 +611,7 @@ int tpt_gemm(int prec, int b_nk, int variant, int M, int N, int K, int batch, co
         g.basis_is_A = b_nk ? 0 : 1;
     }
     int v = variant >= 0 ? variant : choose_variant(gp, b_nk ? 0 : 1, M, N, K);
-    if (variant < 0 && v == TV_128x128_P && (gp == GP_BF16X3 || M % 128 || N % 128 || K % 16)) v = TV_128x128;
+    if (variant < 0 && tv_persistent(v) && (gp == GP_BF16X3 || M % 128 || N % 128 || K % 16)) v = TV_128x128;
     hipError_t e;
     {
         TimedScope ts("gemm_test", s);

@@ -91,6 +91,31 @@ def test_small_fp64_sequential_thomas_matches_oracle(case):
     assert err <= FP64_TOL, err
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_persistent_tiles_match_oracle(tmp_path, prec):
+    """Dense x and y passes on each persistent 128 x 128 tile (four 64 x 64
+    waves, eight 64 x 32 waves), forced through the tuning table; the FP32
+    mode also runs the accumulating epilogue with its norm partials."""
+    T = _T()
+    p = W.make_problem((128, 128, 12), (1.5, 2.0, 1.0), (W.NN, W.DD, W.NN))
+    f = W.rhs(p, 14)
+    ref = O.solve(p, f)
+    gp = {"fp64": 0, "fp32": 1}[prec]
+    table = tmp_path / "tiles.txt"
+    try:
+        for v in (6, 7):
+            table.write_text(f"{gp} 0 0 128 128 {v}\n{gp} 1 128 128 128 {v}\n")
+            T.autotune_load(str(table))
+            kw = {} if prec == "fp64" else {"precision": prec, "rtol": 1e-13, "max_refine": 12}
+            got, _ = _solve(p, f, dense_x=True, **kw)
+            err = O.relative_error(p, got, ref)
+            assert err <= (FP64_TOL if prec == "fp64" else MIXED_TOL), (v, err)
+    finally:
+        # back to the persistent four-wave tile, the choice without a table entry
+        table.write_text(f"{gp} 0 0 128 128 6\n{gp} 1 128 128 128 6\n")
+        T.autotune_load(str(table))
+
+
 def test_autotune_records_thomas_kernel(tmp_path):
     """The autotuner times the Thomas kernels on the plan's lines, records the
     fastest (table kind 2), and solves with it still match the oracle."""
