@@ -261,9 +261,22 @@ int MultiExec::enqueue(hipStream_t s) const {
         hipError_t e = hipSuccess;
         switch (L.kind) {
             case 0: {
-                TimedScope ts("multi_gemm", s);
-                const GemmDesc& rep = *(const GemmDesc*)(blob_.data() + L.off);
-                e = launch_gemm_multi(rep, (const GemmDesc*)(d_desc_ + L.off), L.nwork, L.total, L.prec, L.variant, s);
+                const GemmDesc* hd = (const GemmDesc*)(blob_.data() + L.off);
+                if (tv_persistent(L.variant) && L.nwork <= 4) {
+                    // a few problems on a persistent tile: one launch each.  A
+                    // work list runs the plain 128 x 128 tile instead (the
+                    // persistent one prefetches the next tile of the same
+                    // problem), about 10 % slower on large K; every output sees
+                    // the same MFMA sequence either way, so results are the same
+                    for (int k = 0; k < L.nwork && e == hipSuccess; ++k) {
+                        TimedScope ts("multi_gemm", s);
+                        e = launch_gemm(hd[k], L.prec, L.variant, s);
+                    }
+                } else {
+                    TimedScope ts("multi_gemm", s);
+                    e = launch_gemm_multi(hd[0], (const GemmDesc*)(d_desc_ + L.off), L.nwork, L.total, L.prec,
+                                          L.variant, s);
+                }
                 break;
             }
             case 1: {

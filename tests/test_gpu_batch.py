@@ -51,6 +51,31 @@ def test_batch_matches_single_and_oracle(prec, fixed):
             assert np.array_equal(host(outs[i]), singles[i]), f"graph replay {rep}, problem {i}"
 
 
+@pytest.mark.parametrize("prec,fixed", [("fp64", -1), ("fp32", 2)])
+def test_small_batch_of_interior_problems_matches_single(prec, fixed):
+    """Up to four problems whose GEMMs take a persistent tile run one launch per
+    problem instead of one work list; results stay bitwise those of the single
+    solves."""
+    import torch
+    T = _T()
+    probs = [(W.make_problem((128, 128, 12), (1.5, 2.0, 1.0), (W.NN, W.DD, W.NN)), 41),
+             (W.make_problem((128, 256, 10), (2.0, 1.0, 1.5), (W.DD, W.NN, W.DD), kind="helmholtz", alpha=1e-3), 42),
+             (W.make_problem((256, 128, 9), (1.0, 1.5, 2.0), (W.NN, W.NN, W.NN)), 43)]
+    plans = [T.Plan.from_problem(p, precision=prec, fixed_refine=fixed, dense_x=True) for p, _ in probs]
+    rhs = [cuda(W.rhs(p, s)) for p, s in probs]
+    singles = [host(pl.solve(r)) for pl, r in zip(plans, rhs)]
+    b = T.Batch(plans)
+    outs = [torch.empty_like(r) for r in rhs]
+    for use_graph in (False, True):
+        b.solve(rhs, outs, use_graph=use_graph)
+        torch.cuda.synchronize()
+        for i, (p, s) in enumerate(probs):
+            assert np.array_equal(host(outs[i]), singles[i]), (i, use_graph)
+    for i, (p, s) in enumerate(probs):
+        err = O.relative_error(p, singles[i], O.solve(p, W.rhs(p, s)))
+        assert err <= (1e-12 if prec == "fp64" else 1e-10), (i, err)
+
+
 def test_batch_rejects_mixed_precisions_and_nrhs():
     T = _T()
     (p, _), (q, _) = _problems(2, 8, 12, seed=3)
