@@ -501,7 +501,8 @@ def main():
         import tempfile
         with tempfile.NamedTemporaryFile("r", suffix=".txt") as tf:
             T.autotune_save(tf.name)
-            names = ("128x128", "64x128", "128x64", "64x64", "32x64", "128x128k32", "128x128p", "128x128p8")
+            names = ("128x128", "64x128", "128x64", "64x64", "32x64", "128x128k32", "128x128p", "128x128p8",
+                     "128x128w8")
             precs = ("fp64", "fp32", "bf16x3")
             for ln in open(tf.name):
                 if ln.startswith("#") or not ln.strip():

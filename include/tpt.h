@@ -278,8 +278,8 @@ int tpt_thomas(int nx, int ny, int nz, int nsys, const double *lamx, const doubl
  * device buffer, the other on the fly).  variant: tile shape 0..4 (128x128,
  * 64x128, 128x64, 64x64, 32x64); FP64 / FP32 only: 5 (128x128 with a 32-deep
  * K tile), 6 (128x128 persistent, four 64x64 waves), 7 (128x128 persistent,
- * eight 64x32 waves) — 6 and 7 need M, N multiples of 128 and K of 16; or -1
- * for the tile table.  Batch strides in elements (0 = shared).  Synchronises
+ * eight 64x32 waves) — 6 and 7 need M, N multiples of 128 and K of 16; 8
+ * (128x128 over eight 64x32 waves, any shape); or -1 for the tile table.  Batch strides in elements (0 = shared).  Synchronises
  * the stream for TPT_MIXED_BF16X3. */
 int tpt_gemm(int prec, int b_nk, int variant, int M, int N, int K, int batch, const void *A,
              long long strideA, const void *B, long long strideB, void *C, long long strideC,

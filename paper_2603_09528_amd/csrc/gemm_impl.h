@@ -79,9 +79,9 @@ __device__ __forceinline__ void epi_store(TC* __restrict__ C, long long idx, dou
 }
 
 template <typename TM, typename TA, typename TB, typename TC, int EPI, int BM, int BN, bool BNK, int BK_ = 16,
-          int NBUF = 2>
+          int NBUF = 2, int WN_ = (BN >= 64 ? 64 : BN)>
 __device__ __forceinline__ void gemm_tile_f(const GemmDesc& g, long long lb, TM* smem, double* red) {
-    typedef TileCfg<BM, BN> C;
+    typedef TileCfg<BM, BN, (BM >= 64 ? 64 : 32), WN_> C;
     typedef SmemF<TM, BM, BN, BNK, BK_, NBUF> S;
     typedef Mfma<TM> MM;
     constexpr int BK = S::BK;
@@ -700,6 +700,13 @@ __device__ __forceinline__ void gemm_tile_b(const GemmDesc& g, long long lb, uin
 // PREC: GP_F64 / GP_F32 / GP_BF16X3; TA: data type of the x-pass A (or of A
 // for a plain GEMM), TB: data type of the y-pass B, TC output type.
 // DEEP = 1: K tile of 32 with a single LDS buffer (FP64/FP32 only).
+// Threads of the plain tile kernels: DEEP 2 splits the tile over waves of
+// 64 x 32 (FP64 / FP32 only).
+template <int BM, int BN, int DEEP>
+struct GemmThreads {
+    static constexpr int NT = TileCfg<BM, BN, (BM >= 64 ? 64 : 32), (DEEP == 2 ? 32 : (BN >= 64 ? 64 : BN))>::NT;
+};
+
 template <int PREC, typename TA, typename TB, typename TC, int EPI, int BM, int BN, bool BNK, int DEEP>
 struct GemmKernel {
     static __device__ __forceinline__ void tile(const GemmDesc& g, long long lb) {
@@ -710,15 +717,17 @@ struct GemmKernel {
             else gemm_tile_b<TB, TC, EPI, BM, BN, false>(g, lb, smem, red);
         } else {
             typedef typename std::conditional<PREC == GP_F64, double, float>::type T;
-            constexpr int BKd = DEEP ? 32 : 16, NB = DEEP ? 1 : 2;
+            // DEEP 1: 32-deep K tile, single buffer; DEEP 2: waves of 64 x 32
+            constexpr int BKd = DEEP == 1 ? 32 : 16, NB = DEEP == 1 ? 1 : 2;
+            constexpr int WNd = DEEP == 2 ? 32 : (BN >= 64 ? 64 : BN);
             __shared__ __attribute__((aligned(16))) T smem[SmemF<T, BM, BN, BNK, BKd, NB>::TOTAL];
-            __shared__ double red[2 * TileCfg<BM, BN>::NT / 64];
-            gemm_tile_f<T, TA, TB, TC, EPI, BM, BN, BNK, BKd, NB>(g, lb, smem, red);
+            __shared__ double red[2 * GemmThreads<BM, BN, DEEP>::NT / 64];
+            gemm_tile_f<T, TA, TB, TC, EPI, BM, BN, BNK, BKd, NB, WNd>(g, lb, smem, red);
         }
     }
 };
 
-#define TPT_GEMM_ATTR __launch_bounds__((TileCfg<BM, BN>::NT))
+#define TPT_GEMM_ATTR __launch_bounds__((GemmThreads<BM, BN, DEEP>::NT))
 
 template <int PREC, typename TA, typename TB, typename TC, int EPI, int BM, int BN, bool BNK, int DEEP>
 __global__ TPT_GEMM_ATTR void gemm_kernel(GemmDesc g) {
@@ -760,7 +769,7 @@ hipError_t launch_gemm_typed(const GemmDesc& g, const GemmDesc* d_work, int nwor
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
 #define TPT_LAUNCH(BM_, BN_, DEEP_)                                                                              \
     do {                                                                                                         \
-        constexpr int NT_ = TileCfg<BM_, BN_>::NT;                                                               \
+        constexpr int NT_ = GemmThreads<BM_, BN_, DEEP_>::NT;                                                    \
         if (d_work)                                                                                              \
             TPT_KLAUNCH((gemm_multi_kernel<PREC, TA, TB, TC, EPI, BM_, BN_, BNK, DEEP_>),                 \
                                dim3((unsigned)(blocks < PERSISTENT_BLOCKS ? blocks : PERSISTENT_BLOCKS)),        \
@@ -770,7 +779,19 @@ hipError_t launch_gemm_typed(const GemmDesc& g, const GemmDesc* d_work, int nwor
                                dim3((unsigned)blocks), dim3(NT_), 0, s, g);                                      \
     } while (0)
     switch (variant) {
-        case TV_128x128: TPT_LAUNCH(128, 128, 0); break;
+        case TV_128x128:
+            // work lists (FP64 / FP32) run the 128 x 128 tile over eight waves:
+            // the work-list kernel's extra registers leave the four-wave form
+            // one wave per SIMD; every output sees the same MFMA sequence, so
+            // the results are those of the single-problem launch
+            if constexpr (PREC != GP_BF16X3) {
+                if (d_work) {
+                    TPT_LAUNCH(128, 128, 2);
+                    break;
+                }
+            }
+            TPT_LAUNCH(128, 128, 0);
+            break;
         case TV_64x128: TPT_LAUNCH(64, 128, 0); break;
         case TV_128x64: TPT_LAUNCH(128, 64, 0); break;
         case TV_64x64: TPT_LAUNCH(64, 64, 0); break;
@@ -779,13 +800,17 @@ hipError_t launch_gemm_typed(const GemmDesc& g, const GemmDesc* d_work, int nwor
             if constexpr (PREC == GP_BF16X3) return hipErrorInvalidValue;
             else TPT_LAUNCH(128, 128, 1);
             break;
+        case TV_128x128_W8:
+            if constexpr (PREC == GP_BF16X3) return hipErrorInvalidValue;
+            else TPT_LAUNCH(128, 128, 2);
+            break;
         case TV_128x128_P:
         case TV_128x128_P8:
             if constexpr (PREC == GP_BF16X3) {
                 return hipErrorInvalidValue;
             } else {
-                if (d_work) {  // work lists run the plain 128 x 128 tile
-                    TPT_LAUNCH(128, 128, 0);
+                if (d_work) {  // work lists run the plain 128 x 128 tile (eight waves)
+                    TPT_LAUNCH(128, 128, 2);
                     break;
                 }
                 if (g.M % 128 || g.N % 128 || g.K % 16 || g.K < 16) return hipErrorInvalidValue;

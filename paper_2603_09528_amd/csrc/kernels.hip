@@ -16,13 +16,13 @@ namespace tpt {
 
 const char* tile_variant_name(int v) {
     static const char* names[TV_COUNT] = {"128x128", "64x128", "128x64", "64x64", "32x64", "128x128k32", "128x128p",
-                                          "128x128p8"};
+                                          "128x128p8", "128x128w8"};
     return (v >= 0 && v < TV_COUNT) ? names[v] : "?";
 }
 
 void tile_variant_shape(int v, int* bm, int* bn) {
     static const int s[TV_COUNT][2] = {{128, 128}, {64, 128}, {128, 64}, {64, 64}, {32, 64}, {128, 128}, {128, 128},
-                                       {128, 128}};
+                                       {128, 128}, {128, 128}};
     *bm = s[v][0];
     *bn = s[v][1];
 }

@@ -123,7 +123,7 @@ def test_gemm_matches_numpy(prec, M, N, K, batch, b_nk):
     C = torch.empty((batch, M, N), dtype=dt, device="cuda")
     scale = np.abs(A).max() * np.abs(B).max() * K
     interior = M % 128 == 0 and N % 128 == 0 and K % 16 == 0
-    for variant in range(8 if prec != "bf16x3" else 5):
+    for variant in range(9 if prec != "bf16x3" else 5):
         C.fill_(float("nan"))
         if variant in (6, 7) and not interior:
             # the persistent tiles take interior-only problems
