@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--variants-n", type=int, default=1024,
                     help="cells per direction of the FF/FG/GF/GG comparison (0 disables it)")
     ap.add_argument("--variants-steps", type=int, default=3)
+    ap.add_argument("--stretch-steps", type=int, default=20,
+                    help="timed solves per stretching parameter of the beta comparison (0 disables it)")
     ap.add_argument("--preheat", type=float, default=0.15,
                     help="seconds of untimed solves before each timed section's warmup: after idle "
                          "periods (plan set-up, autotuning) the GPU runs ~13%% slower for ~25 ms")
@@ -109,32 +111,63 @@ def load_traffic(kernel_name):
     return None if ent is None else ent.get("hbm_bytes_per_launch")
 
 
-def run_serving(args, T, W):
-    """Serving on the ten grid families: closed-loop FP64 throughput, then open
-    loop at 0.7x that rate for FP64 and split-BF16x3 (fixed correction count,
-    the largest the adaptive rule needs over the families)."""
+def run_serving(args, T, W, check_oracle=True):
+    """Serving on the ten grid families: closed-loop throughput of FP64 and of
+    split-BF16x3 (fixed correction count: the largest the adaptive rule needs
+    over the families), then open loop (Poisson arrivals) for each mode at
+    0.7x its own closed-loop rate, and both modes at one common rate, 0.7x the
+    slower mode's closed-loop rate.  The last served result of the four
+    smallest families and of the 256^3 family is checked against the oracle."""
     import torch
     from paper_2603_09528_amd import loadgen
     fams = W.serving_families()
-    rhs = [torch.from_numpy(W.rhs(p, 50 + i)).to("cuda") for i, p in enumerate(fams)]
+    rhs_host = [W.rhs(p, 50 + i) for i, p in enumerate(fams)]
+    rhs = [torch.from_numpy(f).to("cuda") for f in rhs_host]
     t0 = time.time()
-    plans64 = [T.Plan.from_problem(p) for p in fams]
+    plans = {"fp64": [T.Plan.from_problem(p) for p in fams]}
     log(f"serving: {len(fams)} fp64 plans in {time.time() - t0:.1f}s")
-    nreq, warm = args.serve_requests, max(20, args.serve_requests // 10)
-    closed = loadgen.run(fams, rhs, plans64, n_requests=nreq, warmup=warm, rate=None)
-    rate = 0.7 * closed["solves_per_s"]
-    log(f"serving: closed loop {closed['solves_per_s']:.1f} solves/s; open loop at {rate:.1f}/s")
-    open64 = loadgen.run(fams, rhs, plans64, n_requests=nreq, warmup=warm, rate=rate)
     iters = 0
     for p, f in zip(fams, rhs):
-        cal = T.Plan.from_problem(p, precision="bf16x3", rtol=1e-11, max_refine=12)
+        cal = T.Plan.from_problem(p, precision="bf16x3", max_refine=12)
         cal.solve(f)
         iters = max(iters, cal.info().iters)
-    plansb = [T.Plan.from_problem(p, precision="bf16x3", fixed_refine=iters) for p in fams]
-    openb = loadgen.run(fams, rhs, plansb, n_requests=nreq, warmup=warm, rate=rate)
-    openb["corrections"] = iters
-    return {"families": [p.name + f" {p.n[0]}^3 {''.join(b[0] + b[1] for b in p.bc)}" for p in fams],
-            "closed_loop_fp64": closed, "open_loop_fp64": open64, "open_loop_bf16x3": openb}
+    plans["bf16x3"] = [T.Plan.from_problem(p, precision="bf16x3", fixed_refine=iters) for p in fams]
+    nreq, warm = args.serve_requests, max(20, args.serve_requests // 10)
+    res = {"families": [p.name + f" {p.n[0]}^3 {''.join(b[0] + b[1] for b in p.bc)}" for p in fams],
+           "bf16x3_corrections": iters}
+    check = [0, 1, 2, 3, 5]
+    refs = {}
+    if check_oracle:
+        import oracle as O
+        for i in check:
+            refs[i] = O.solve(fams[i], rhs_host[i])
+
+    def served(key, prec, rate):
+        r = loadgen.run(fams, rhs, plans[prec], n_requests=nreq, warmup=warm, rate=rate,
+                        keep_outputs=bool(refs))
+        outs = r.pop("_outputs", {})
+        if refs:
+            import oracle as O
+            errs = {}
+            for i in check:
+                if i in outs:
+                    o = outs[i].detach().cpu().numpy()
+                    errs[fams[i].name] = max(O.relative_error(fams[i], o, refs[i]),
+                                             O.relative_error(fams[i], o, refs[i], norm="max"))
+            r["rel_err_vs_oracle"] = errs
+        res[key] = r
+        log(f"serving {key}: {r['solves_per_s']:.1f} solves/s, p50 {r['p50_ms']:.2f} ms, "
+            f"p99 {r['p99_ms']:.2f} ms" + (f", max error vs oracle {max(r['rel_err_vs_oracle'].values()):.2e}"
+                                           if r.get("rel_err_vs_oracle") else ""))
+        return r
+
+    closed = {prec: served(f"closed_loop_{prec}", prec, None) for prec in ("fp64", "bf16x3")}
+    for prec in ("fp64", "bf16x3"):
+        served(f"open_loop_{prec}", prec, 0.7 * closed[prec]["solves_per_s"])
+    common = 0.7 * min(c["solves_per_s"] for c in closed.values())
+    for prec in ("fp64", "bf16x3"):
+        served(f"open_loop_common_{prec}", prec, common)
+    return res
 
 
 # single-GPU FP64 Poisson solve times of the paper (§4.2.2: 1024^3, periodic x,
@@ -211,7 +244,7 @@ def run_variants(args, T, W):
             diff = gdiff(o)
             raw = float(np.linalg.norm(o - ref) / np.linalg.norm(ref))
             log(f"variants {name}: {it} corrections, diff vs FF {diff:.2e} (without gauge normalisation {raw:.2e})")
-            if diff <= 1e-10:
+            if diff <= TOL / 10:
                 iters = it
                 break
             del plan, ws
@@ -286,7 +319,7 @@ def run_helmholtz(args, T, W):
                 diff = max(float(np.linalg.norm(o.detach().cpu().numpy() - r) / np.linalg.norm(r))
                            for o, r in zip(outs, ref))
                 log(f"helmholtz {prec}: {it} corrections, max relative difference vs FP64 {diff:.2e}")
-                if diff <= 1e-10:
+                if diff <= TOL / 10:
                     iters = it
                     break
                 del b, plans
@@ -342,7 +375,7 @@ def run_batch(args, T, W):
             diff = max(float(np.linalg.norm(gnorm(p, g) - r) / np.linalg.norm(r))
                        for (p, _), g, r in zip(probs, got, ref))
             log(f"batch64 {prec}: {it} corrections, max difference vs FP64 {diff:.2e}")
-            if diff <= 1e-10:
+            if diff <= TOL / 10:
                 used = it
                 break
         if used is None:
@@ -361,6 +394,37 @@ def run_batch(args, T, W):
         log(f"batch64 {prec}: {ms:.2f} ms per batch of {len(probs)}, {res[prec]['gdofs']:.2f} GDOF/s")
         del b, plans
         torch.cuda.empty_cache()
+    return res
+
+
+def run_stretching(args, T, W):
+    """Cost against stretching at fixed N: the 256^3 channel problem with y
+    applied by dense GEMM whatever its spacing (uniform y would otherwise take
+    the DCT), FP64, tanh beta = 0, 2 and 4 in y and z.  The eigenbasis of a
+    stretched direction is as dense as a uniform one's, so the solve time
+    should not depend on beta."""
+    import torch
+    n = args.n
+    res = {"workload": f"{n}^3 Poisson, x periodic uniform (FFT), y and z Neumann tanh beta (y by GEMM), FP64"}
+    for beta in (0.0, 2.0, 4.0):
+        prob = W.make_problem((n, n, n), (0.0, beta, beta), (W.PP, W.NN, W.NN), name=f"channel{n}_b{beta:g}")
+        f = torch.from_numpy(W.rhs(prob, 2)).to("cuda")
+        out = torch.empty_like(f)
+        plan = T.Plan.from_problem(prob, dense_y=True)
+        T.autotune([plan])
+        ws = plan.workspace()
+        preheat(lambda: plan.solve(f, out, ws), args.preheat)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.stretch_steps):
+            plan.solve(f, out, ws)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.stretch_steps
+        res[f"beta{beta:g}"] = {"ms_per_solve": ms, "gdofs": prob.dof / (ms * 1e-3) / 1e9}
+        log(f"stretching beta={beta:g}: {ms:.3f} ms/solve")
+        del plan, ws
+    t = [v["ms_per_solve"] for k, v in res.items() if k.startswith("beta")]
+    res["max_over_min"] = max(t) / min(t)
     return res
 
 
@@ -395,6 +459,18 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    # the oracle's solution of the timed problem: the error check of every
+    # mode, and the reference the mixed modes' correction counts are set by
+    import oracle as O
+    t0 = time.time()
+    oplan = O.solver.Plan(prob)
+    t_oplan = time.time() - t0
+    ref = oplan.solve(f_host)
+    log(f"oracle: plan {t_oplan:.1f}s, one solve {time.time() - t0 - t_oplan:.1f}s")
+
+    def err_vs_oracle(o):
+        return max(O.relative_error(prob, o, ref), O.relative_error(prob, o, ref, norm="max"))
+
     results = {}
     outs = {}
     for mode in modes:
@@ -405,16 +481,28 @@ def main():
             plan = T.Plan.from_problem(prob, dense_x=dense_x, fuse_xy=xform == "fused")
             iters = 0
         else:
-            # calibrate the number of corrections with the adaptive stop rule
-            # (||e||/||x|| <= 1e-11), then time that count with no host syncs
-            cal = T.Plan.from_problem(prob, precision=prec, rtol=1e-11, max_refine=12, dense_x=dense_x)
+            # the correction count: what the adaptive stop rule takes at its
+            # default rtol, raised until the solution is within a tenth of the
+            # 1e-10 target of the oracle's (2-norm and max-norm); that count
+            # is timed with no host synchronisation
+            cal = T.Plan.from_problem(prob, precision=prec, max_refine=12, dense_x=dense_x)
             try:
                 cal.solve(f)
-                iters = cal.info().iters
+                iters_adaptive = cal.info().iters
             except T.TptError as e:
                 log(f"{mode}: refinement did not converge ({e}); skipped")
                 continue
-            plan = T.Plan.from_problem(prob, precision=prec, fixed_refine=iters, dense_x=dense_x)
+            del cal
+            iters = iters_adaptive
+            while True:
+                plan = T.Plan.from_problem(prob, precision=prec, fixed_refine=iters, dense_x=dense_x)
+                o = plan.solve(f)
+                torch.cuda.synchronize()
+                e = err_vs_oracle(o.detach().cpu().numpy())
+                log(f"{mode}: {iters} corrections (adaptive rule: {iters_adaptive}), error vs oracle {e:.2e}")
+                if e <= TOL / 10 or iters >= 12:
+                    break
+                iters += 1
         T.autotune([plan])  # tile variant per GEMM shape, timed on this GPU
         log(f"{mode}: plan + autotune {time.time() - t0:.2f}s, corrections {iters}, transforms {plan.transforms}")
         out = torch.empty_like(f)
@@ -485,6 +573,7 @@ def main():
             "p50_ms": float(np.percentile(lat, 50)),
             "p99_ms": float(np.percentile(lat, 99)),
             "corrections": iters,
+            "corrections_adaptive_rule": None if prec == "fp64" else iters_adaptive,
             "x_transform": "fft" if plan.x_fft else "gemm",
             "kernels_ms_per_solve": {k: v[0] / args.steps for k, v in kern.items()},
             "kernel_launches": {k: int(v[1]) for k, v in kern.items()},
@@ -519,22 +608,23 @@ def main():
     log(f"autotuned tiles: {tiles}")
 
     # ---- CPU oracle: baseline timing on a bounded sample, and the error check ----
+    for mode, out in outs.items():
+        results[mode]["rel_err_vs_oracle"] = O.relative_error(prob, out, ref)
+        results[mode]["max_err_vs_oracle"] = O.relative_error(prob, out, ref, norm="max")
+        log(f"{mode}: error vs oracle {results[mode]['rel_err_vs_oracle']:.3e} (2-norm), "
+            f"{results[mode]['max_err_vs_oracle']:.3e} (max-norm)")
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle as O
         try:
             from threadpoolctl import threadpool_info
             cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
         except Exception:
             cores = os.cpu_count()
-        t0 = time.time()
-        oplan = O.solver.Plan(prob)
-        t_plan = time.time() - t0
+        t_plan = t_oplan
         solves = 0
         t0 = time.time()
-        ref = None
         while True:
-            ref = oplan.solve(f_host)
+            oplan.solve(f_host)
             solves += 1
             if time.time() - t0 >= args.cpu_seconds or solves >= 50:
                 break
@@ -542,9 +632,6 @@ def main():
         cpu = {"value": dof / t_cpu / 1e9, "unit": "GDOF/s", "cores": int(cores), "kind": "oracle",
                "sample": f"{solves} full {n}^3 FP64 oracle solves ({t_cpu:.2f} s each; "
                          f"Jacobi eigendecomposition {t_plan:.1f} s, untimed)"}
-        for mode, out in outs.items():
-            results[mode]["rel_err_vs_oracle"] = O.relative_error(prob, out, ref)
-            log(f"{mode}: rel err vs oracle {results[mode]['rel_err_vs_oracle']:.3e}")
 
     helm = None
     if args.helmholtz_steps > 0:
@@ -563,8 +650,16 @@ def main():
     if args.serve_requests > 0:
         serving = run_serving(args, T, W)
 
-    # ---- headline: fastest mode that meets the 1e-10 bar -------------------------
-    ok = [m for m in results if results[m].get("rel_err_vs_oracle", 0.0) <= TOL]
+    stretching = None
+    if args.stretch_steps > 0:
+        stretching = run_stretching(args, T, W)
+
+    # ---- headline: fastest mode that meets its bar against the oracle ----------
+    # (FP64 1e-12, mixed 1e-10; 2-norm and max-norm)
+    def meets(m):
+        e = max(results[m]["rel_err_vs_oracle"], results[m]["max_err_vs_oracle"])
+        return e <= (1e-12 if m.startswith("fp64") else TOL)
+    ok = [m for m in results if meets(m)]
     best = max(ok or list(results), key=lambda m: results[m]["gdofs"])
     r = results[best]
     # dominant kernel of the headline mode and its roofline
@@ -626,6 +721,7 @@ def main():
         "helmholtz_1024x768x512_3rhs": helm,
         "batch64": batch,
         "transform_variants": variants,
+        "stretching": stretching,
         "gemm_tiles": tiles,
     }
     print(json.dumps(line))

@@ -85,10 +85,14 @@ enum {
                                it is slower than the separate passes (the
                                row transforms inside the GEMM are not hidden
                                behind its MFMAs), so it is not the default */
-    TPT_FLAG_SEQ_THOMAS = 16 /* solve the z lines with the sequential kernel
+    TPT_FLAG_SEQ_THOMAS = 16, /* solve the z lines with the sequential kernel
                                (one lane per line) instead of the partitioned
                                one (segments joined by an interface system);
                                periodic z always uses the sequential kernel */
+    TPT_FLAG_NO_CHECK = 32  /* skip the right-hand-side check of every solve
+                               (one extra read of rhs on the device); the
+                               compat_defect and nonfinite fields of tpt_info
+                               are then -1 */
 };
 
 /* How a plan applies the eigenbasis of x or y (tpt_plan_transforms). */
@@ -115,9 +119,11 @@ typedef struct {
     int kind;               /* TPT_POISSON or TPT_HELMHOLTZ */
     double alpha;           /* Helmholtz coefficient (> 0), ignored for Poisson */
     int precision;          /* TPT_FP64, TPT_MIXED_FP32, TPT_MIXED_BF16X3 */
-    double rtol;            /* mixed modes (adaptive): stop when the estimated remaining error
-                               ||e_k|| min(1, ||e_k|| / ||e_{k-1}||) / ||x|| <= rtol, where e_k is
-                               the k-th correction and e_0 = x (default 1e-12 if <= 0) */
+    double rtol;            /* mixed modes (adaptive): stop after correction k when, for every
+                               right-hand side, c_k = ||e_k|| / ||x_k|| <= rtol, or k >= 2 and the
+                               observed contraction rho = c_k / c_{k-1} < 1 gives an estimated
+                               remaining error c_k rho / (1 - rho) <= rtol (e_k: the k-th
+                               correction, x_k: the iterate after it; default 1e-12 if <= 0) */
     int max_refine;         /* mixed modes: cap on corrections (default 8 if <= 0) */
     int fixed_refine;       /* mixed modes: >= 0 runs exactly this many corrections with
                                no host synchronisation (stream-ordered, capturable);
@@ -127,12 +133,20 @@ typedef struct {
 } tpt_plan_desc;
 
 /* Result of the last solve of a plan (valid after the stream has been
- * synchronised). */
+ * synchronised).  With several right-hand sides each ratio is the largest
+ * over them. */
 typedef struct {
     int iters;              /* corrections applied (0 for FP64) */
     double rel_correction;  /* ||e_last||_2 / ||x||_2 (mixed modes), 0 for FP64 */
     double rel_residual;    /* ||f - A x||_2 / ||f||_2 at the last refinement residual (mixed), or -1 */
     int null_line;          /* index i + Nx*j of the pinned modal line, or -1 */
+    double compat_defect;   /* singular Poisson plans (null_line >= 0): |sum dV f| / sum dV |f|
+                               over the finite values of rhs, dV the control volumes (the left
+                               null vector of the operator, §2.2.1: D T is symmetric).  The
+                               share of f that the §3 pin absorbs; 0 for a compatible f up to
+                               rounding, 0 for non-singular plans, -1 with TPT_FLAG_NO_CHECK */
+    int nonfinite;          /* number of NaN / Inf values in rhs (the output is then not
+                               meaningful), -1 with TPT_FLAG_NO_CHECK */
 } tpt_info;
 
 /* Fill a descriptor with defaults (FP64 Poisson, centre-located, Neumann, nrhs 1). */
@@ -184,7 +198,10 @@ int tpt_plan_fused(tpt_plan plan, int *fused);
  * (allocated on first use).  Stream-ordered; the adaptive mixed mode
  * (fixed_refine = -1) synchronises `stream` once per correction.  A singular
  * Poisson right-hand side is solved with the gauge of §3 (pinned final
- * modal unknown); an incompatible component is absorbed by that pin. */
+ * modal unknown); an incompatible component is absorbed by that pin and
+ * reported as tpt_info.compat_defect.  Unless TPT_FLAG_NO_CHECK, every solve
+ * first reads rhs once on the device for that defect and for NaN / Inf
+ * values (tpt_info.nonfinite); the solve itself proceeds either way. */
 int tpt_solve(tpt_plan plan, const double *rhs, double *out, void *workspace,
               size_t workspace_bytes, void *stream);
 
@@ -206,6 +223,12 @@ int tpt_batch_workspace_bytes(tpt_batch batch, size_t *bytes);
  * (adaptive ones are rejected with TPT_ERR_UNSUPPORTED). */
 int tpt_batch_solve(tpt_batch batch, const double *const *rhs, double *const *out,
                     void *workspace, size_t workspace_bytes, void *stream, int use_graph);
+/* Info of problem `index` of the batch's last solve (call after synchronising
+ * its stream; reads a few bytes of the workspace, which must still hold them):
+ * corrections, the last correction and residual ratios of mixed plans, and
+ * the right-hand-side check (compat_defect, nonfinite) as for tpt_solve_info.
+ * TPT_ERR_INVALID before the first solve or for an index out of range. */
+int tpt_batch_info(tpt_batch batch, int index, tpt_info *info);
 
 /* ---- autotuning of GEMM tiles and the Thomas kernel ------------------------ */
 
@@ -236,7 +259,9 @@ int tpt_server_create(size_t hbm_budget_bytes, int max_slots, tpt_server *out);
 int tpt_server_submit(tpt_server server, tpt_plan plan, const double *rhs, double *out,
                       unsigned long long *ticket);
 /* TPT_OK when done (times in seconds on a process-wide monotonic clock:
- * submit, admitted to a slot, finished on the GPU), TPT_PENDING if not yet. */
+ * submit, admitted to a slot, finished on the GPU), TPT_PENDING if not yet.
+ * info: corrections, the last correction and residual ratios of mixed plans,
+ * and the right-hand-side check (compat_defect, nonfinite) of the request. */
 int tpt_server_poll(tpt_server server, unsigned long long ticket, tpt_info *info,
                     double *t_submit, double *t_start, double *t_done);
 /* Block until every submitted request has finished. */

@@ -58,6 +58,8 @@ class Info(ctypes.Structure):
         ("rel_correction", ctypes.c_double),
         ("rel_residual", ctypes.c_double),
         ("null_line", ctypes.c_int),
+        ("compat_defect", ctypes.c_double),
+        ("nonfinite", ctypes.c_int),
     ]
 
     def as_dict(self):
@@ -92,6 +94,7 @@ def lib():
             "tpt_batch_destroy": (i, [vp]),
             "tpt_batch_workspace_bytes": (i, [vp, ctypes.POINTER(sz)]),
             "tpt_batch_solve": (i, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, sz, vp, i]),
+            "tpt_batch_info": (i, [vp, i, ctypes.POINTER(Info)]),
             "tpt_autotune": (i, [i, ctypes.POINTER(vp), vp]),
             "tpt_autotune_save": (i, [ctypes.c_char_p]),
             "tpt_autotune_load": (i, [ctypes.c_char_p]),
@@ -120,7 +123,7 @@ def lib():
 EXPORTED = ("tpt_plan_desc_init", "tpt_plan_create", "tpt_plan_destroy", "tpt_plan_shape",
             "tpt_plan_workspace_bytes", "tpt_plan_eigen", "tpt_plan_operator", "tpt_plan_transforms", "tpt_plan_fused", "tpt_solve",
             "tpt_solve_info", "tpt_batch_create", "tpt_batch_destroy", "tpt_batch_workspace_bytes",
-            "tpt_batch_solve", "tpt_autotune", "tpt_autotune_save", "tpt_autotune_load",
+            "tpt_batch_solve", "tpt_batch_info", "tpt_autotune", "tpt_autotune_save", "tpt_autotune_load",
             "tpt_server_create", "tpt_server_submit", "tpt_server_poll", "tpt_server_drain",
             "tpt_server_destroy", "tpt_thomas", "tpt_gemm", "tpt_timing_enable", "tpt_timing_collect",
             "tpt_last_error", "tpt_version")
@@ -166,12 +169,13 @@ class Plan:
     fuse_xy runs the x fast transform and the y GEMM of an FP64 solve as
     one fused pass per direction (see `fused`; slower on gfx950 than the
     separate passes, so off by default); seq_thomas solves the z lines with
-    the sequential kernel instead of the partitioned one.
+    the sequential kernel instead of the partitioned one; check=False skips
+    the right-hand-side check (Info.compat_defect, Info.nonfinite).
     """
 
     def __init__(self, n, faces, bc, loc=("C", "C", "C"), kind="poisson", alpha=0.0, precision="fp64",
                  rtol=1e-12, max_refine=8, fixed_refine=-1, nrhs=1, host_only=False, dense_x=False,
-                 dense_y=False, fuse_xy=False, seq_thomas=False):
+                 dense_y=False, fuse_xy=False, seq_thomas=False, check=True):
         L = lib()
         d = _Desc()
         L.tpt_plan_desc_init(ctypes.byref(d))
@@ -190,7 +194,7 @@ class Plan:
         d.fixed_refine = int(fixed_refine)
         d.nrhs = int(nrhs)
         d.flags = ((1 if host_only else 0) | (2 if dense_x else 0) | (4 if dense_y else 0)
-                   | (8 if fuse_xy else 0) | (16 if seq_thomas else 0))
+                   | (8 if fuse_xy else 0) | (16 if seq_thomas else 0) | (0 if check else 32))
         h = ctypes.c_void_p()
         _check(L.tpt_plan_create(ctypes.byref(d), ctypes.byref(h)))
         self._h = h
@@ -325,6 +329,12 @@ class Batch:
         _check(lib().tpt_batch_solve(self._h, ra, oa, _ptr(workspace), workspace.numel(), _stream(stream),
                                      1 if use_graph else 0))
         return outs
+
+    def info(self, index: int) -> Info:
+        """Info of problem `index` of the last solve (after synchronising)."""
+        inf = Info()
+        _check(lib().tpt_batch_info(self._h, int(index), ctypes.byref(inf)))
+        return inf
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -62,9 +62,17 @@ struct PlanBuffers {  // per-plan small device arrays
     double* ax = nullptr; double* bx = nullptr; double* cx = nullptr;
     double* ay = nullptr; double* by = nullptr; double* cy = nullptr;
     double* az = nullptr; double* bz = nullptr; double* cz = nullptr;
-    double* norms = nullptr;     // device scratch for reduced sums
+    double* vx = nullptr; double* vy = nullptr; double* vz = nullptr;  // control volumes
+    double* norms = nullptr;     // device sums, TPT_STATS doubles per rhs (StatSlot)
     void* block = nullptr;
 };
+
+// Reduced sums of one right-hand side, TPT_STATS doubles: refinement norms
+// (||r||^2, ||f||^2 of the last residual; ||e||^2, ||x||^2 of the last
+// correction and iterate) and the right-hand-side check (sum dV f,
+// sum dV |f|, non-finite count).
+enum StatSlot { SS_R2 = 0, SS_F2 = 1, SS_E2 = 2, SS_X2 = 3, SS_WF = 4, SS_WABS = 5, SS_BAD = 6 };
+constexpr int TPT_STATS = 8;
 
 }  // namespace tpt
 
@@ -84,6 +92,11 @@ struct tpt_plan_s {
     size_t own_ws_bytes = 0;
     double* h_norms = nullptr;       // pinned host copy of norms (adaptive mode)
     tpt_info info{};
+    bool info_on_device = false;     // info fields still to be read from buf.norms
+    bool check = true;               // right-hand-side check reported in tpt_info
+    bool run_check = true;           // check kernel runs (also for mixed singular plans,
+                                     // whose residuals use its weighted sum)
+    double last_area_inv = 0.0;      // 1 / sum dV over the last z plane
     int gemm_variant[4] = {-1, -1, -1, -1};  // per stage (x fwd, y fwd, y inv, x inv); -1 = table
     int fast[2] = {-1, -1};          // x, y: XformKind of the fast transform, -1 = GEMM
     bool fuse_xy = false;            // FP64: x transform fused into the y GEMM's loads
@@ -105,7 +118,9 @@ bool stage_is_fast(const tpt_plan_s* p, int stage);
 FftDesc stage_fft(const tpt_plan_s* p, int stage, const void* in, int tin, void* out, int tout, int epi,
                   double* partials, int nrhs);
 ThomasDesc plan_thomas(const tpt_plan_s* p, const void* f, int tf, void* x, int tx, double* scratch, int nrhs);
-StencilDesc plan_stencil(const tpt_plan_s* p, const double* x, const double* f, float* r, double* partials);
+// stats: the rhs's TPT_STATS sums (after the right-hand-side check), or NULL
+StencilDesc plan_stencil(const tpt_plan_s* p, const double* x, const double* f, float* r, double* partials,
+                         const double* stats);
 int plan_gemm_prec(const tpt_plan_s* p);
 
 // Tile selection: autotuned table lookup (falls back to a size heuristic).
@@ -134,6 +149,10 @@ struct TimedScope {
 };
 
 int solve_one(tpt_plan_s* p, const double* rhs, double* out, void* ws, size_t ws_bytes, hipStream_t s);
+// tpt_info fields of plan p from its reduced per-rhs sums h (TPT_STATS
+// doubles per rhs): the refinement norms when `norms`, the check fields when
+// the plan checks its right-hand sides; other fields are left as they are.
+void stats_to_info(const tpt_plan_s* p, const double* h, bool norms, tpt_info* info);
 
 // Workspace carve-up of one plan's solve (see plan_workspace_bytes).
 struct Ws {

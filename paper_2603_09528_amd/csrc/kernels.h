@@ -179,6 +179,11 @@ struct StencilDesc {
     const double* f;
     float* r;
     double* partials;
+    // singular problems: f on the last z plane is read as f - S * wscale, with
+    // S = *wsum = sum dV f (the right-hand-side check) and wscale = 1 / (the
+    // area sum dV of that plane), so that sum dV r = 0 (null = no change)
+    const double* wsum;
+    double wscale;
     long long block_begin;  // multi-problem
 };
 int residual_blocks(const StencilDesc& st);
@@ -193,6 +198,29 @@ struct ReduceDesc {
     double* out;
 };
 hipError_t launch_reduce_pairs_multi(const ReduceDesc* d_work, int nwork, hipStream_t s);
+
+// Right-hand-side check of one solve (tpt_info compat_defect and nonfinite):
+// per field, the weighted sums S = sum w f and A = sum w |f| over the finite
+// values, w = vx_i vy_j vz_k (the control volumes: the left null vector of a
+// singular operator), and the count of NaN / Inf values.  Blocks write
+// partials (4 doubles each); one block per field then folds them in a fixed
+// order into out + sys * out_stride: [S, A, count].
+struct CheckDesc {
+    int nx, ny, nz;
+    int nsys;               // fields back to back at f
+    const double* f;
+    const double* vx;
+    const double* vy;
+    const double* vz;
+    double* partials;       // 4 doubles per block, nsys * check_blocks(c) blocks
+    double* out;
+    int out_stride;
+    long long block_begin;  // multi-problem: first block of this problem
+};
+long long check_blocks(const CheckDesc& c);  // blocks per field
+hipError_t launch_check(const CheckDesc& c, hipStream_t s);
+// every problem of the list (one field each); then one reduction block each
+hipError_t launch_check_multi(const CheckDesc* d_work, int nwork, long long total_blocks, hipStream_t s);
 
 // Split float -> bf16 hi/lo planes (round to nearest even), n elements.
 hipError_t launch_split_bf16(const float* x, uint16_t* hi, uint16_t* lo, long long n, hipStream_t s);

@@ -511,6 +511,8 @@ __device__ __forceinline__ void residual_block(const StencilDesc& st, long long 
         if (j < ny - 1) { oyp = nx; ayp = st.cy[j]; } else if (st.pery) { oyp = -(long long)(ny - 1) * nx; ayp = st.cy[ny - 1]; }
         const double bxy = st.bx[i] + st.by[j];
         const int k0 = (int)zc * RES_RZ, k1 = min(nz, k0 + RES_RZ);
+        // the incompatible part of f, removed from the last plane
+        const double fshift = (st.wsum && k1 == nz) ? *st.wsum * st.wscale : 0.0;
         // z window: the value below k0 (or its periodic image) and at k0
         double xm = 0.0;
         if (k0 > 0) xm = x[(long long)(k0 - 1) * sxy + c];
@@ -526,7 +528,7 @@ __device__ __forceinline__ void residual_block(const StencilDesc& st, long long 
             double lap = (bxy + st.bz[k]) * xc + azk * xm + czk * xp;
             lap += axm * x[idx + oxm] + axp * x[idx + oxp] + aym * x[idx + oym] + ayp * x[idx + oyp];
             const double ax = st.helmholtz ? xc - st.alpha * lap : lap;
-            const double fv = st.f[idx];
+            const double fv = st.f[idx] - (k == nz - 1 ? fshift : 0.0);
             const double r = fv - ax;
             st.r[idx] = (float)r;
             sr += r * r;
@@ -616,6 +618,134 @@ hipError_t launch_reduce_pairs(const double* partials, int n, double* out, hipSt
 hipError_t launch_reduce_pairs_multi(const ReduceDesc* d_work, int nwork, hipStream_t s) {
     if (nwork <= 0) return hipSuccess;
     TPT_KLAUNCH(reduce_pairs_multi_kernel, dim3(nwork), dim3(RED_NT), 0, s, d_work, nwork);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Right-hand-side check: volume-weighted sums (for the compatibility defect
+// of a singular problem) and the count of non-finite values.  A block covers
+// CHK_NT * CHK_PT consecutive unknowns of one field; each thread walks them
+// at stride CHK_NT, carrying (i, j, k) by increments instead of divisions.
+// ---------------------------------------------------------------------------
+constexpr int CHK_NT = 256;
+constexpr int CHK_PT = 32;
+
+__host__ __device__ inline long long check_blocks_of(const CheckDesc& c) {
+    const long long dof = (long long)c.nx * c.ny * c.nz;
+    return (dof + (long long)CHK_NT * CHK_PT - 1) / ((long long)CHK_NT * CHK_PT);
+}
+long long check_blocks(const CheckDesc& c) { return check_blocks_of(c); }
+
+__device__ __forceinline__ void check_block(const CheckDesc& c, int sys, long long lb, long long nb, double* red) {
+    const int nx = c.nx, ny = c.ny;
+    const long long dof = (long long)nx * ny * c.nz;
+    const double* __restrict__ f = c.f + (long long)sys * dof;
+    long long e = lb * (CHK_NT * CHK_PT) + threadIdx.x;
+    long long row = e / nx;
+    int i = (int)(e - row * nx);
+    int j = (int)(row % ny);
+    int k = (int)(row / ny);
+    double s = 0.0, a = 0.0, bad = 0.0;
+#pragma unroll 8
+    for (int m = 0; m < CHK_PT; ++m) {
+        if (e < dof) {
+            const double v = f[e];
+            const double w = c.vx[i] * c.vy[j] * c.vz[k];
+            const bool fin = __builtin_isfinite(v);
+            s += fin ? w * v : 0.0;
+            a += fin ? w * __builtin_fabs(v) : 0.0;
+            bad += fin ? 0.0 : 1.0;
+        }
+        e += CHK_NT;
+        i += CHK_NT;
+        while (i >= nx) {
+            i -= nx;
+            if (++j == ny) {
+                j = 0;
+                ++k;
+            }
+        }
+    }
+    double zero = 0.0;
+    block_sum2<CHK_NT>(s, a, red);
+    block_sum2<CHK_NT>(bad, zero, red);
+    if (threadIdx.x == 0) {
+        double* p = c.partials + 4 * ((long long)sys * nb + lb);
+        p[0] = s;
+        p[1] = a;
+        p[2] = bad;
+        p[3] = 0.0;
+    }
+}
+
+__global__ __launch_bounds__(CHK_NT) void check_kernel(CheckDesc c, long long nb) {
+    __shared__ double red[2 * CHK_NT / 64];
+    check_block(c, blockIdx.y, blockIdx.x, nb, red);
+}
+
+__global__ __launch_bounds__(CHK_NT) void check_multi_kernel(const CheckDesc* __restrict__ work, int nwork,
+                                                             long long total) {
+    __shared__ double red[2 * CHK_NT / 64];
+    for (long long blk = blockIdx.x; blk < total; blk += gridDim.x) {
+        int lo = 0, hi = nwork - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if (work[mid].block_begin <= blk) lo = mid;
+            else hi = mid - 1;
+        }
+        const CheckDesc c = work[lo];
+        check_block(c, 0, blk - c.block_begin, check_blocks_of(c), red);
+        __syncthreads();
+    }
+}
+
+// Fold the nb partials of field `sys` in a fixed order.
+__device__ __forceinline__ void check_reduce_block(const CheckDesc& c, int sys, long long nb, double* red) {
+    const double* p = c.partials + 4 * (long long)sys * nb;
+    double s = 0.0, a = 0.0, bad = 0.0, zero = 0.0;
+    for (long long b = threadIdx.x; b < nb; b += RED_NT) {
+        s += p[4 * b];
+        a += p[4 * b + 1];
+        bad += p[4 * b + 2];
+    }
+    block_sum2<RED_NT>(s, a, red);
+    block_sum2<RED_NT>(bad, zero, red);
+    if (threadIdx.x == 0) {
+        double* o = c.out + (long long)sys * c.out_stride;
+        o[0] = s;
+        o[1] = a;
+        o[2] = bad;
+    }
+}
+
+__global__ __launch_bounds__(RED_NT) void check_reduce_kernel(CheckDesc c, long long nb) {
+    __shared__ double red[2 * RED_NT / 64];
+    check_reduce_block(c, blockIdx.x, nb, red);
+}
+
+__global__ __launch_bounds__(RED_NT) void check_reduce_multi_kernel(const CheckDesc* __restrict__ work) {
+    __shared__ double red[2 * RED_NT / 64];
+    const CheckDesc c = work[blockIdx.x];
+    check_reduce_block(c, 0, check_blocks_of(c), red);
+}
+
+hipError_t launch_check(const CheckDesc& c, hipStream_t s) {
+    const long long nb = check_blocks(c);
+    if (nb <= 0 || c.nsys < 1) return hipSuccess;
+    TPT_KLAUNCH(check_kernel, dim3((unsigned)nb, (unsigned)c.nsys), dim3(CHK_NT), 0, s, c, nb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    TPT_KLAUNCH(check_reduce_kernel, dim3((unsigned)c.nsys), dim3(RED_NT), 0, s, c, nb);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_multi(const CheckDesc* d_work, int nwork, long long total_blocks, hipStream_t s) {
+    if (nwork <= 0 || total_blocks <= 0) return hipSuccess;
+    TPT_KLAUNCH(check_multi_kernel, dim3((unsigned)std::min(total_blocks, 4 * PERSISTENT_BLOCKS)), dim3(CHK_NT), 0,
+                s, d_work, nwork, total_blocks);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    TPT_KLAUNCH(check_reduce_multi_kernel, dim3((unsigned)nwork), dim3(RED_NT), 0, s, d_work);
     return hipGetLastError();
 }
 

@@ -38,8 +38,11 @@ int MultiExec::init(const std::vector<tpt_plan_s*>& plans) {
     for (auto* p : plans) {
         ws_off_.push_back(off);
         off += al256(plan_workspace_bytes(p));
+    }
+    // the per-problem sums back to back at the end, so one copy reads them all
+    for (size_t i = 0; i < plans.size(); ++i) {
         norm_off_.push_back(off);
-        off += 256;
+        off += STATS_BYTES;
     }
     ws_total_ = off;
     return TPT_OK;
@@ -200,13 +203,45 @@ int MultiExec::build(const double* const* rhs, double* const* out, void* ws) {
         stage(ST_XI, w1c, tmid, outv, DT_F64, epi, &nb);
         return nb;
     };
+    // right-hand-side checks of the plans that ask for them
+    {
+        std::vector<CheckDesc> cd;
+        long long blocks = 0;
+        for (int i = 0; i < n; ++i) {
+            if (!plans_[i]->run_check) continue;
+            CheckDesc c{};
+            c.nx = plans_[i]->N[0];
+            c.ny = plans_[i]->N[1];
+            c.nz = plans_[i]->N[2];
+            c.nsys = 1;
+            c.f = rhs[i];
+            c.vx = plans_[i]->buf.vx;
+            c.vy = plans_[i]->buf.vy;
+            c.vz = plans_[i]->buf.vz;
+            c.partials = w[i].partials;
+            c.out = (double*)((char*)ws + norm_off_[i]) + SS_WF;
+            c.out_stride = TPT_STATS;
+            c.block_begin = blocks;
+            blocks += check_blocks(c);
+            cd.push_back(c);
+        }
+        if (!cd.empty()) {
+            Launch L{};
+            L.kind = 6;
+            L.off = append(blob_, cd);
+            L.nwork = (int)cd.size();
+            L.total = blocks;
+            seq_.push_back(L);
+        }
+    }
     std::vector<long long> xi = minv(true, EPI_STORE);
     for (int it = 0; it < iters_; ++it) {
         std::vector<StencilDesc> st(n);
         std::vector<ReduceDesc> rd(n);
         long long blocks = 0;
         for (int i = 0; i < n; ++i) {
-            st[i] = plan_stencil(plans_[i], out[i], rhs[i], w[i].r, w[i].partials);
+            st[i] = plan_stencil(plans_[i], out[i], rhs[i], w[i].r, w[i].partials,
+                                 (const double*)((char*)ws + norm_off_[i]));
             st[i].block_begin = blocks;
             const int nb = residual_blocks(st[i]);
             blocks += nb;
@@ -300,6 +335,11 @@ int MultiExec::enqueue(hipStream_t s) const {
                 e = launch_reduce_pairs_multi((const ReduceDesc*)(d_desc_ + L.off), L.nwork, s);
                 break;
             }
+            case 6: {
+                TimedScope ts("multi_check", s);
+                e = launch_check_multi((const CheckDesc*)(d_desc_ + L.off), L.nwork, L.total, s);
+                break;
+            }
             case 4: {
                 TimedScope ts("multi_fft", s);
                 const FftDesc& rep = *(const FftDesc*)(blob_.data() + L.off);
@@ -358,6 +398,25 @@ int tpt_batch_destroy(tpt_batch b) {
 int tpt_batch_workspace_bytes(tpt_batch b, size_t* bytes) {
     if (!b || !bytes) return fail(TPT_ERR_INVALID, "NULL argument");
     *bytes = b->exec.workspace_bytes();
+    return TPT_OK;
+}
+
+int tpt_batch_info(tpt_batch b, int index, tpt_info* info) {
+    if (!b || !info) return fail(TPT_ERR_INVALID, "NULL argument");
+    if (index < 0 || index >= b->exec.count()) return fail(TPT_ERR_INVALID, "problem index out of range");
+    if (!b->built) return fail(TPT_ERR_INVALID, "the batch has not been solved");
+    tpt_plan_s* p = b->exec.plan(index);
+    double h[TPT_STATS];
+    TPT_HIP(hipMemcpy(h, b->exec.norms(index), sizeof(h), hipMemcpyDeviceToHost));
+    tpt_info inf{};
+    inf.iters = b->exec.iterations();
+    inf.null_line = p->null_line;
+    inf.rel_correction = 0.0;
+    inf.rel_residual = -1.0;
+    inf.compat_defect = -1.0;
+    inf.nonfinite = -1;
+    stats_to_info(p, h, inf.iters > 0, &inf);
+    *info = inf;
     return TPT_OK;
 }
 

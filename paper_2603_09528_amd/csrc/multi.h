@@ -26,13 +26,17 @@ class MultiExec {
     int enqueue(hipStream_t s) const;
     int count() const { return (int)plans_.size(); }
     int iterations() const { return iters_; }
-    // per-problem device norms (4 doubles: r^2, f^2, e^2, x^2)
+    // per-problem device sums (TPT_STATS doubles, StatSlot order), STATS_BYTES
+    // apart and back to back from norms(0)
     const double* norms(int i) const { return (const double*)((const char*)ws_ + norm_off_[i]); }
+    static constexpr size_t STATS_BYTES = 256;
+    tpt_plan_s* plan(int i) const { return plans_[i]; }
     ~MultiExec();
 
    private:
     struct Launch {
-        int kind;     // 0 gemm, 1 sequential Thomas, 2 residual, 3 reduce, 4 x-line FFT, 5 partitioned Thomas
+        int kind;     // 0 gemm, 1 sequential Thomas, 2 residual, 3 reduce, 4 x-line FFT, 5 partitioned Thomas,
+                      // 6 right-hand-side check
         // sequential Thomas: variant holds the largest nz; partitioned: the
         // configuration, prec the storage type
         int prec, variant, b_nk;

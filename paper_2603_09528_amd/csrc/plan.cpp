@@ -211,8 +211,14 @@ static size_t partial_slots(const tpt_plan_s* p) {
     long long xi = ((long long)p->N[1] * p->N[2] * p->desc.nrhs + 31) / 32 * ((p->N[0] + 63) / 64);
     // the x-inverse fast transform: at most one block per x line
     const long long fx = (long long)p->N[1] * p->N[2] * p->desc.nrhs;
+    // the right-hand-side check: 4 doubles (two slots) per block
+    CheckDesc c{};
+    c.nx = p->N[0];
+    c.ny = p->N[1];
+    c.nz = p->N[2];
+    const long long chk = 2 * check_blocks(c) * p->desc.nrhs;
     (void)dof;
-    return (size_t)std::max(std::max(res, xi), fx) + 8;
+    return (size_t)std::max(std::max(std::max(res, xi), fx), chk) + 8;
 }
 
 size_t plan_workspace_bytes(const tpt_plan_s* p) {
@@ -276,6 +282,7 @@ int tpt_plan_create(const tpt_plan_desc* desc, tpt_plan* out) {
     if (p->desc.max_refine <= 0) p->desc.max_refine = 8;
     p->host_only = (desc->flags & TPT_FLAG_HOST_ONLY) != 0;
     p->seq_thomas = (desc->flags & TPT_FLAG_SEQ_THOMAS) != 0;
+    p->check = (desc->flags & TPT_FLAG_NO_CHECK) == 0;
     if (!p->host_only && hipGetDevice(&p->device) != hipSuccess)
         return fail(TPT_ERR_HIP, "no HIP device");
     for (int d = 0; d < 3; ++d) {
@@ -306,6 +313,13 @@ int tpt_plan_create(const tpt_plan_desc* desc, tpt_plan* out) {
         p->op[2].null_mode)
         p->null_line = p->bx->eig.null_index + p->N[0] * p->by->eig.null_index;
     p->info.null_line = p->null_line;
+    p->run_check = p->check || (desc->precision != TPT_FP64 && p->null_line >= 0);
+    {
+        double ax = 0.0, ay = 0.0;
+        for (double v : p->op[0].vol) ax += v;
+        for (double v : p->op[1].vol) ay += v;
+        p->last_area_inv = 1.0 / (ax * ay * p->op[2].vol[p->N[2] - 1]);
+    }
     if (!p->host_only) {
         if (p->bx->fast_kind >= 0 && !(desc->flags & TPT_FLAG_DENSE_X)) p->fast[0] = p->bx->fast_kind;
         if (p->by->fast_kind >= 0 && !(desc->flags & TPT_FLAG_DENSE_Y)) p->fast[1] = p->by->fast_kind;
@@ -315,9 +329,12 @@ int tpt_plan_create(const tpt_plan_desc* desc, tpt_plan* out) {
                      p->fast[1] < 0 && (p->N[0] == 128 || p->N[0] == 256) && p->N[1] % 128 == 0;
     }
     p->info.rel_residual = -1.0;
+    p->info.compat_defect = p->check ? 0.0 : -1.0;
+    p->info.nonfinite = p->check ? 0 : -1;
     if (!p->host_only) {
         const size_t nx = p->N[0], ny = p->N[1], nz = p->N[2];
-        const size_t doubles = 3 * (nx + ny + nz) + 64;
+        const size_t nstat = (size_t)TPT_STATS * p->desc.nrhs;
+        const size_t doubles = 4 * (nx + ny + nz) + nstat + 64;
         void* blk = nullptr;
         if (hipMalloc(&blk, doubles * 8) != hipSuccess) {
             (void)hipGetLastError();
@@ -333,13 +350,15 @@ int tpt_plan_create(const tpt_plan_desc* desc, tpt_plan* out) {
         put(p->op[0].a); put(p->op[0].b); put(p->op[0].c);
         put(p->op[1].a); put(p->op[1].b); put(p->op[1].c);
         put(p->op[2].a); put(p->op[2].b); put(p->op[2].c);
+        put(p->op[0].vol); put(p->op[1].vol); put(p->op[2].vol);
         TPT_HIP(hipMemcpy(blk, h.data(), doubles * 8, hipMemcpyHostToDevice));
         double* d = (double*)blk;
         p->buf.ax = d; d += nx; p->buf.bx = d; d += nx; p->buf.cx = d; d += nx;
         p->buf.ay = d; d += ny; p->buf.by = d; d += ny; p->buf.cy = d; d += ny;
         p->buf.az = d; d += nz; p->buf.bz = d; d += nz; p->buf.cz = d; d += nz;
+        p->buf.vx = d; d += nx; p->buf.vy = d; d += ny; p->buf.vz = d; d += nz;
         p->buf.norms = d;
-        if (hipHostMalloc((void**)&p->h_norms, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        if (hipHostMalloc((void**)&p->h_norms, (nstat + 8) * sizeof(double), hipHostMallocDefault) != hipSuccess) {
             p->h_norms = nullptr;
             return fail(TPT_ERR_OOM, "pinned host allocation failed");
         }

@@ -99,6 +99,7 @@ struct Request {
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
+    double* h_stats = nullptr;  // pinned copy of the group's per-request sums
     MultiExec exec;
     void* d_desc = nullptr;
     size_t d_desc_bytes = 0;
@@ -138,10 +139,13 @@ bool tpt_server_s::complete_locked() {
         hipError_t q = hipEventQuery(s.done);
         if (q == hipErrorNotReady) continue;
         const double t = now_seconds();
-        for (Request* r : s.reqs) {
+        for (size_t i = 0; i < s.reqs.size(); ++i) {
+            Request* r = s.reqs[i];
             r->t_done = t;
             if (q == hipSuccess) {
                 r->state = 2;
+                stats_to_info(r->plan, s.h_stats + i * (MultiExec::STATS_BYTES / sizeof(double)),
+                              r->info.iters > 0, &r->info);
             } else {
                 r->state = TPT_ERR_HIP;
                 r->error = hipGetErrorString(q);
@@ -232,6 +236,9 @@ bool tpt_server_s::admit_locked() {
         if (rc == TPT_OK) rc = s.exec.upload(s.d_desc, s.stream);
         const double t = now_seconds();
         if (rc == TPT_OK) rc = s.exec.enqueue(s.stream);
+        if (rc == TPT_OK && hipMemcpyAsync(s.h_stats, s.exec.norms(0), grp.size() * MultiExec::STATS_BYTES,
+                                           hipMemcpyDeviceToHost, s.stream) != hipSuccess)
+            rc = fail(TPT_ERR_HIP, "copy of request sums");
         if (rc == TPT_OK && hipEventRecord(s.done, s.stream) != hipSuccess) rc = TPT_ERR_HIP;
         if (rc != TPT_OK) {
             const std::string msg = tpt_last_error();
@@ -250,8 +257,10 @@ bool tpt_server_s::admit_locked() {
             r->t_start = t;
             r->info.iters = s.exec.iterations();
             r->info.null_line = r->plan->null_line;
-            r->info.rel_correction = -1.0;
+            r->info.rel_correction = 0.0;
             r->info.rel_residual = -1.0;
+            r->info.compat_defect = -1.0;
+            r->info.nonfinite = -1;
         }
         s.reqs = grp;
         s.arena_off = off;
@@ -300,6 +309,7 @@ int tpt_server_create(size_t budget, int max_slots, tpt_server* out) {
         auto sl = std::make_unique<Slot>();
         TPT_HIP(hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking));
         TPT_HIP(hipEventCreateWithFlags(&sl->done, hipEventDisableTiming));
+        TPT_HIP(hipHostMalloc((void**)&sl->h_stats, s->max_group * MultiExec::STATS_BYTES, hipHostMallocDefault));
         s->slots.push_back(std::move(sl));
     }
     tpt_server_s* raw = s.get();
@@ -369,6 +379,7 @@ int tpt_server_destroy(tpt_server s) {
         if (sl->stream) (void)hipStreamSynchronize(sl->stream);
         if (sl->d_desc) (void)hipFree(sl->d_desc);
         if (sl->done) (void)hipEventDestroy(sl->done);
+        if (sl->h_stats) (void)hipHostFree(sl->h_stats);
         if (sl->stream) (void)hipStreamDestroy(sl->stream);
     }
     delete s;

@@ -256,7 +256,8 @@ ThomasDesc plan_thomas(const tpt_plan_s* p, const void* f, int tf, void* x, int 
     return t;
 }
 
-StencilDesc plan_stencil(const tpt_plan_s* p, const double* x, const double* f, float* r, double* partials) {
+StencilDesc plan_stencil(const tpt_plan_s* p, const double* x, const double* f, float* r, double* partials,
+                         const double* stats) {
     StencilDesc st{};
     st.nx = p->N[0];
     st.ny = p->N[1];
@@ -273,6 +274,14 @@ StencilDesc plan_stencil(const tpt_plan_s* p, const double* x, const double* f, 
     st.f = f;
     st.r = r;
     st.partials = partials;
+    // singular problems: the residual drops the incompatible part of f (the
+    // constant on the last z plane that the pin of §3 absorbs, whose image in
+    // modal space is the dropped last equation of the null line), so the
+    // low-precision corrections see a compatible residual
+    if (p->null_line >= 0 && stats) {
+        st.wsum = stats + SS_WF;
+        st.wscale = p->last_area_inv;
+    }
     return st;
 }
 
@@ -338,6 +347,67 @@ static int run_thomas(const tpt_plan_s* p, const void* f, int tf, void* x, int t
     return TPT_OK;
 }
 
+// Right-hand-side check of every rhs (weighted sums and non-finite count)
+// into the plan's stats; its partials use the workspace's partial slots,
+// which are free until the first refinement residual.
+static int run_check(const tpt_plan_s* p, const double* rhs, double* partials, hipStream_t s) {
+    if (!p->run_check) return TPT_OK;
+    CheckDesc c{};
+    c.nx = p->N[0];
+    c.ny = p->N[1];
+    c.nz = p->N[2];
+    c.nsys = p->desc.nrhs;
+    c.f = rhs;
+    c.vx = p->buf.vx;
+    c.vy = p->buf.vy;
+    c.vz = p->buf.vz;
+    c.partials = partials;
+    c.out = p->buf.norms + SS_WF;
+    c.out_stride = TPT_STATS;
+    TimedScope ts("check", s);
+    hipError_t e = launch_check(c, s);
+    if (e != hipSuccess) return fail(TPT_ERR_HIP, std::string("check launch: ") + hipGetErrorString(e));
+    return TPT_OK;
+}
+
+// sqrt(a / b) of two sums of squares: 0 when both vanish, NaN when either is
+// not finite
+static double ratio(double a, double b) {
+    if (!std::isfinite(a) || !std::isfinite(b)) return NAN;
+    if (b > 0) return std::sqrt(a / b);
+    return a > 0 ? INFINITY : 0.0;
+}
+
+// Info fields from the reduced per-rhs sums h (TPT_STATS doubles per rhs):
+// the refinement norms when `norms`, the check fields when the plan checks.
+void stats_to_info(const tpt_plan_s* p, const double* h, bool norms, tpt_info* info) {
+    const int R = p->desc.nrhs;
+    if (norms) {
+        double rc = 0.0, rr = 0.0;
+        for (int r = 0; r < R; ++r) {
+            const double* q = h + (size_t)TPT_STATS * r;
+            const double c = ratio(q[SS_E2], q[SS_X2]);
+            const double e = ratio(q[SS_R2], q[SS_F2]);
+            rc = (c == c && rc == rc) ? std::max(rc, c) : NAN;
+            rr = (e == e && rr == rr) ? std::max(rr, e) : NAN;
+        }
+        info->rel_correction = rc;
+        info->rel_residual = rr;
+    }
+    if (p->check) {
+        double defect = 0.0, bad = 0.0;
+        for (int r = 0; r < R; ++r) {
+            const double* q = h + (size_t)TPT_STATS * r;
+            bad += q[SS_BAD];
+            if (p->null_line >= 0 && q[SS_WABS] > 0) defect = std::max(defect, std::fabs(q[SS_WF]) / q[SS_WABS]);
+        }
+        info->compat_defect = defect;
+        info->nonfinite = bad > 2147483647.0 ? 2147483647 : (int)bad;
+    }
+}
+
+static void info_from_stats(tpt_plan_s* p, const double* h, bool norms) { stats_to_info(p, h, norms, &p->info); }
+
 static inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 Ws carve(const tpt_plan_s* p, void* ws) {
@@ -363,7 +433,7 @@ Ws carve(const tpt_plan_s* p, void* ws) {
 }
 
 long long plan_residual_blocks(const tpt_plan_s* p) {
-    StencilDesc st = plan_stencil(p, nullptr, nullptr, nullptr, nullptr);
+    StencilDesc st = plan_stencil(p, nullptr, nullptr, nullptr, nullptr, nullptr);
     return residual_blocks(st);
 }
 
@@ -385,6 +455,8 @@ static int run_fused(const tpt_plan_s* p, bool inverse, const double* in, double
 static int solve_fp64(tpt_plan_s* p, const double* rhs, double* out, const Ws& w, hipStream_t s) {
     const int R = p->desc.nrhs;
     int rc;
+    if ((rc = run_check(p, rhs, w.partials, s))) return rc;
+    p->info_on_device = p->check;
     if (p->fuse_xy && (rc = run_fused(p, false, rhs, (double*)w.w2, R, s)) <= 0) {
         if (rc) return rc;
         if ((rc = run_thomas(p, w.w2, DT_F64, w.w2, DT_F64, w.scratch, R, s))) return rc;
@@ -415,78 +487,111 @@ static int solve_fp64(tpt_plan_s* p, const double* rhs, double* out, const Ws& w
 }
 
 // Low-precision application of M^{-1} to `in` (FP64 rhs or FP32 residual):
-// result stored into out (epi STORE) or added to out (epi ACCUM, with norm
-// partials of the correction and the updated iterate).
+// result stored into out (epi STORE) or added to out (epi ACCUM).  An
+// accumulating application runs its last pass once per right-hand side, so
+// that the norm partials of the correction and the updated iterate of each
+// rhs are reduced into that rhs's stats.
 static int apply_minv(tpt_plan_s* p, int prec, const void* in, int tin, double* out, int epi, const Ws& w,
-                      hipStream_t s, long long* xi_blocks) {
+                      hipStream_t s) {
     const int R = p->desc.nrhs;
     int rc;
     if ((rc = run_stage(p, ST_XF, prec, in, tin, w.w1, DT_F32, EPI_STORE, nullptr, R, s))) return rc;
     if ((rc = run_stage(p, ST_YF, prec, w.w1, DT_F32, w.w2, DT_F32, EPI_STORE, nullptr, R, s))) return rc;
     if ((rc = run_thomas(p, w.w2, DT_F32, w.w2, DT_F32, w.scratch, R, s))) return rc;
     if ((rc = run_stage(p, ST_YI, prec, w.w2, DT_F32, w.w1, DT_F32, EPI_STORE, nullptr, R, s))) return rc;
-    if ((rc = run_stage(p, ST_XI, prec, w.w1, DT_F32, out, DT_F64, epi, w.partials, R, s, xi_blocks))) return rc;
+    if (epi != EPI_ACCUM_F64)
+        return run_stage(p, ST_XI, prec, w.w1, DT_F32, out, DT_F64, epi, nullptr, R, s);
+    for (int r = 0; r < R; ++r) {
+        const size_t off = (size_t)r * p->dof;
+        long long nb = 0;
+        if ((rc = run_stage(p, ST_XI, prec, (const float*)w.w1 + off, DT_F32, out + off, DT_F64, epi, w.partials, 1,
+                            s, &nb)))
+            return rc;
+        TimedScope ts("reduce", s);
+        hipError_t e = launch_reduce_pairs(w.partials, (int)nb, p->buf.norms + (size_t)TPT_STATS * r + SS_E2, s);
+        if (e != hipSuccess) return fail(TPT_ERR_HIP, hipGetErrorString(e));
+    }
     return TPT_OK;
 }
 
 // Mixed path: x0 = M^{-1} f; then repeat r = f - A x (FP64), x += M^{-1} r.
+// Adaptive stop (per rhs, all must pass): c_k = ||e_k|| / ||x_k|| is the
+// size of correction k, i.e. about the error left by iterate k-1, so
+// c_k <= rtol meets the target; from the second correction on, the observed
+// contraction rho = c_k / c_{k-1} < 1 bounds the error after x_k by the
+// geometric tail c_k rho / (1 - rho).  The first correction alone gives no
+// rate, so it stops only on c_1 <= rtol.
 static int solve_mixed(tpt_plan_s* p, const double* rhs, double* out, const Ws& w, hipStream_t s) {
     const int prec = plan_gemm_prec(p);
     const int R = p->desc.nrhs;
     int rc;
-    long long xi_blocks = 0;
-    if ((rc = apply_minv(p, prec, rhs, DT_F64, out, EPI_STORE, w, s, &xi_blocks))) return rc;
+    if ((rc = run_check(p, rhs, w.partials, s))) return rc;
+    if ((rc = apply_minv(p, prec, rhs, DT_F64, out, EPI_STORE, w, s))) return rc;
     const bool adaptive = p->desc.fixed_refine < 0;
     const int max_it = adaptive ? p->desc.max_refine : p->desc.fixed_refine;
-    double* dn = p->buf.norms;  // [0,1] = (r^2, f^2), [2,3] = (e^2, x^2)
+    double* dn = p->buf.norms;
+    std::vector<double> prev(R, -1.0);
     int it = 0;
-    double rel_e = 0.0, rel_r = -1.0, prev_e = 1.0, est = 1.0;  // the first solve counts as a correction of size ||x||
+    double est = 1.0;
     for (it = 0; it < max_it;) {
-        // residual of every rhs, partials packed back to back
-        long long pb = 0;
+        // residual of every rhs and its norms
         for (int r = 0; r < R; ++r) {
             StencilDesc st = plan_stencil(p, out + (size_t)r * p->dof, rhs + (size_t)r * p->dof,
-                                          w.r + (size_t)r * p->dof, w.partials + 2 * pb);
-            TimedScope ts("residual_f64", s);
-            hipError_t e = launch_residual(st, s);
-            if (e != hipSuccess) return fail(TPT_ERR_HIP, std::string("residual launch: ") + hipGetErrorString(e));
-            pb += residual_blocks(st);
-        }
-        {
+                                          w.r + (size_t)r * p->dof, w.partials, dn + (size_t)TPT_STATS * r);
+            {
+                TimedScope ts("residual_f64", s);
+                hipError_t e = launch_residual(st, s);
+                if (e != hipSuccess) return fail(TPT_ERR_HIP, std::string("residual launch: ") + hipGetErrorString(e));
+            }
             TimedScope ts("reduce", s);
-            hipError_t e = launch_reduce_pairs(w.partials, (int)pb, dn, s);
+            hipError_t e = launch_reduce_pairs(w.partials, residual_blocks(st), dn + (size_t)TPT_STATS * r + SS_R2, s);
             if (e != hipSuccess) return fail(TPT_ERR_HIP, hipGetErrorString(e));
         }
-        if ((rc = apply_minv(p, prec, w.r, DT_F32, out, EPI_ACCUM_F64, w, s, &xi_blocks))) return rc;
-        {
-            TimedScope ts("reduce", s);
-            hipError_t e = launch_reduce_pairs(w.partials, (int)xi_blocks, dn + 2, s);
-            if (e != hipSuccess) return fail(TPT_ERR_HIP, hipGetErrorString(e));
-        }
+        if ((rc = apply_minv(p, prec, w.r, DT_F32, out, EPI_ACCUM_F64, w, s))) return rc;
         ++it;
         if (adaptive) {
-            TPT_HIP(hipMemcpyAsync(p->h_norms, dn, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+            const size_t nst = (size_t)TPT_STATS * R;
+            TPT_HIP(hipMemcpyAsync(p->h_norms, dn, nst * sizeof(double), hipMemcpyDeviceToHost, s));
             TPT_HIP(hipStreamSynchronize(s));
             const double* h = p->h_norms;
-            rel_r = h[1] > 0 ? std::sqrt(h[0] / h[1]) : 0.0;
-            rel_e = h[3] > 0 ? std::sqrt(h[2] / h[3]) : 0.0;
-            if (!(rel_e == rel_e)) return fail(TPT_ERR_NOT_CONVERGED, "non-finite correction");
-            // error left after this correction ~ contraction rate * ||e_k||, with
-            // the rate estimated from two successive corrections
-            est = rel_e * std::min(1.0, rel_e / prev_e);
-            prev_e = rel_e;
+            info_from_stats(p, h, true);
+            est = 0.0;
+            for (int r = 0; r < R; ++r) {
+                const double* q = h + (size_t)TPT_STATS * r;
+                const double c = ratio(q[SS_E2], q[SS_X2]);
+                if (!std::isfinite(c) || (p->check && p->info.nonfinite > 0)) {
+                    p->info.iters = it;
+                    return fail(TPT_ERR_NOT_CONVERGED,
+                                p->check && p->info.nonfinite > 0
+                                    ? "right-hand side holds " + std::to_string(p->info.nonfinite) + " non-finite values"
+                                    : std::string("non-finite correction"));
+                }
+                double est_r = c;
+                if (c > p->desc.rtol && prev[r] > 0.0) {
+                    const double rho = c / prev[r];
+                    if (rho < 1.0) est_r = c * rho / (1.0 - rho);
+                }
+                prev[r] = c;
+                est = std::max(est, est_r);
+            }
             if (est <= p->desc.rtol) break;
         }
     }
     p->info.iters = it;
     if (!adaptive) {
-        // norms are read back lazily by tpt_solve_info
-        p->info.rel_correction = -2.0;
-        p->info.rel_residual = -2.0;
+        // norms and check results are read back lazily by tpt_solve_info
+        p->info.rel_correction = it > 0 ? -2.0 : 0.0;
+        p->info.rel_residual = -1.0;
+        p->info_on_device = it > 0 || p->check;
     } else {
-        p->info.rel_correction = rel_e;
-        p->info.rel_residual = rel_r;
-        if (est > p->desc.rtol && it >= max_it)
+        if (it == 0) {
+            p->info.rel_correction = 0.0;
+            p->info.rel_residual = -1.0;
+            p->info_on_device = p->check;
+        } else {
+            p->info_on_device = false;
+        }
+        if (it > 0 && est > p->desc.rtol && it >= max_it)
             return fail(TPT_ERR_NOT_CONVERGED, "refinement stopped with estimated error " + std::to_string(est));
     }
     return TPT_OK;
@@ -535,16 +640,12 @@ int tpt_solve(tpt_plan plan, const double* rhs, double* out, void* workspace, si
 
 int tpt_solve_info(tpt_plan plan, tpt_info* info) {
     if (!plan || !info) return fail(TPT_ERR_INVALID, "NULL argument");
-    if (plan->info.rel_correction == -2.0) {
-        // fixed-refinement mode: the norms of the last correction are on the device
-        double h[4];
-        TPT_HIP(hipMemcpy(h, plan->buf.norms, sizeof(h), hipMemcpyDeviceToHost));
-        plan->info.rel_residual = h[1] > 0 ? std::sqrt(h[0] / h[1]) : 0.0;
-        plan->info.rel_correction = h[3] > 0 ? std::sqrt(h[2] / h[3]) : 0.0;
-        if (plan->info.iters == 0) {
-            plan->info.rel_residual = -1.0;
-            plan->info.rel_correction = 0.0;
-        }
+    if (plan->info_on_device) {
+        // fixed-refinement norms and the check sums of the last solve are on the device
+        std::vector<double> h((size_t)TPT_STATS * plan->desc.nrhs);
+        TPT_HIP(hipMemcpy(h.data(), plan->buf.norms, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+        info_from_stats(plan, h.data(), plan->info.rel_correction == -2.0);
+        plan->info_on_device = false;
     }
     *info = plan->info;
     return TPT_OK;

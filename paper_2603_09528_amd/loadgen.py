@@ -25,12 +25,15 @@ def _pools(families, rhs_list, per_family):
 
 def run(families: Sequence, rhs_list: Sequence, plans: Sequence, *, n_requests: int, warmup: int,
         rate: float | None, seed: int = 5, max_slots: int = 4, per_family: int = 6,
-        budget_bytes: int = 0, weights: Sequence[float] | None = None) -> Dict:
+        budget_bytes: int = 0, weights: Sequence[float] | None = None, keep_outputs: bool = False) -> Dict:
     """Serve n_requests (+ warmup) requests over the families.
 
     rate None: closed loop (keep max_slots*2 requests in flight) -> throughput.
     rate > 0: open loop with exponential inter-arrival times (Poisson process).
-    Returns a dict with solves/s, GDOF/s, p50/p99/max latency in ms.
+    Returns a dict with solves/s, GDOF/s, p50/p99/max latency in ms; with
+    keep_outputs also "_outputs": {family index: the output tensor of that
+    family's last completed request} (every request of a family solves the
+    same right-hand side).
     """
     import paper_2603_09528_amd as T
     rng = np.random.default_rng(seed)
@@ -43,6 +46,7 @@ def run(families: Sequence, rhs_list: Sequence, plans: Sequence, *, n_requests: 
     pools = _pools(families, rhs_list, per_family)
     srv = T.Server(hbm_budget_bytes=budget_bytes, max_slots=max_slots)
     inflight: Dict[int, tuple] = {}
+    last_slot: Dict[int, int] = {}
     lat: List[float] = []
     dofs = 0
     t_first = None
@@ -62,6 +66,7 @@ def run(families: Sequence, rhs_list: Sequence, plans: Sequence, *, n_requests: 
                 info, ts, tstart, tdone = r
                 idx, fam, slot = inflight.pop(t)
                 pools[fam]["free"].append(slot)
+                last_slot[fam] = slot
                 done_any = True
                 if idx >= warmup:
                     lat.append((tdone - ts) * 1e3)
@@ -109,5 +114,7 @@ def run(families: Sequence, rhs_list: Sequence, plans: Sequence, *, n_requests: 
         "mean_ms": float(lat_a.mean()),
         "slots": max_slots,
     }
+    if keep_outputs:
+        out["_outputs"] = {fam: pools[fam]["outs"][slot] for fam, slot in last_slot.items()}
     del srv
     return out

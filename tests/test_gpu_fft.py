@@ -7,7 +7,7 @@ import pytest
 
 import oracle as O
 import workloads as W
-from tests.gpu_util import cuda, host, say
+from tests.gpu_util import cuda, host, say, parity_error
 
 pytestmark = pytest.mark.gpu
 
@@ -62,7 +62,7 @@ def test_fft_solve_matches_oracle(case):
     got, plan = _solve(p, f)
     assert plan.x_fft
     ref = O.solve(p, f)
-    err = O.relative_error(p, got, ref)
+    err = parity_error(p, got, ref)
     assert err <= FP64_TOL, err
 
 
@@ -75,7 +75,7 @@ def test_fft_mixed_matches_oracle(case, prec):
     say("fft mixed", prec, p.n)
     got, plan = _solve(p, f, precision=prec, rtol=1e-13, max_refine=12)
     assert plan.x_fft
-    err = O.relative_error(p, got, O.solve(p, f))
+    err = parity_error(p, got, O.solve(p, f))
     say("  iters", plan.info().iters, "err", err)
     assert err <= MIXED_TOL, err
 
@@ -133,7 +133,7 @@ def test_fft_nrhs_and_repeat():
     o3b = host(plan3.solve(cuda(fs)))
     assert np.array_equal(o3, o3b)
     for i in range(3):
-        assert O.relative_error(p, o3[i], O.solve(p, fs[i])) <= FP64_TOL
+        assert parity_error(p, o3[i], O.solve(p, fs[i])) <= FP64_TOL
     torch.cuda.synchronize()
 
 
@@ -158,7 +158,7 @@ def test_batch_mixing_fft_and_gemm_plans(prec, fixed):
         for i, p in enumerate(probs):
             single = host(plans[i].solve(rhs[i]))
             assert np.array_equal(host(outs[i]), single), (i, use_graph)
-            err = O.relative_error(p, single, O.solve(p, fs[i]))
+            err = parity_error(p, single, O.solve(p, fs[i]))
             assert err <= (FP64_TOL if prec == "fp64" else MIXED_TOL), (i, err)
 
 
@@ -195,7 +195,7 @@ def test_transform_kinds_match_oracle(case):
     got, plan = _solve(p, f)
     assert plan.transforms == case[5]
     ref = O.solve(p, f)
-    err = O.relative_error(p, got, ref)
+    err = parity_error(p, got, ref)
     assert err <= FP64_TOL, err
 
 
@@ -207,7 +207,7 @@ def test_transform_kinds_mixed_match_oracle(case, prec):
     say("kinds mixed", prec, p.n, case[5])
     got, plan = _solve(p, f, precision=prec, rtol=1e-13, max_refine=12)
     assert plan.transforms == case[5]
-    err = O.relative_error(p, got, O.solve(p, f))
+    err = parity_error(p, got, O.solve(p, f))
     say("  iters", plan.info().iters, "err", err)
     assert err <= MIXED_TOL, err
 
@@ -247,5 +247,5 @@ def test_batch_mixing_all_transform_kinds(prec, fixed):
         for i, p in enumerate(probs):
             single = host(plans[i].solve(rhs[i]))
             assert np.array_equal(host(outs[i]), single), (i, use_graph)
-            err = O.relative_error(p, single, O.solve(p, fs[i]))
+            err = parity_error(p, single, O.solve(p, fs[i]))
             assert err <= (FP64_TOL if prec == "fp64" else MIXED_TOL), (i, err)

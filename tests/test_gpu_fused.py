@@ -7,7 +7,7 @@ import pytest
 
 import oracle as O
 import workloads as W
-from tests.gpu_util import cuda, host, say
+from tests.gpu_util import cuda, host, say, parity_error
 
 pytestmark = pytest.mark.gpu
 
@@ -52,7 +52,7 @@ def test_fused_matches_oracle_and_separate(case):
     assert not sep.fused
     ref_sep = host(sep.solve(cuda(f)))
     torch.cuda.synchronize()
-    err = O.relative_error(p, got, O.solve(p, f))
+    err = parity_error(p, got, O.solve(p, f))
     d = float(np.linalg.norm(got - ref_sep) / np.linalg.norm(ref_sep))
     say("  err vs oracle", err, "vs separate", d)
     assert err <= FP64_TOL, err
@@ -69,7 +69,7 @@ def test_fused_several_rhs():
     got = host(plan.solve(cuda(fs)))
     torch.cuda.synchronize()
     for r in range(2):
-        err = O.relative_error(p, got[r], O.solve(p, fs[r]))
+        err = parity_error(p, got[r], O.solve(p, fs[r]))
         assert err <= FP64_TOL, (r, err)
 
 

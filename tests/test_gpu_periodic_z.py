@@ -7,7 +7,7 @@ import pytest
 
 import oracle as O
 import workloads as W
-from tests.gpu_util import cuda, host, say
+from tests.gpu_util import cuda, host, say, parity_error
 
 pytestmark = pytest.mark.gpu
 
@@ -100,7 +100,7 @@ def test_periodic_z_solve_matches_oracle(case, prec):
     plan = T.Plan.from_problem(p, **kw)
     got = host(plan.solve(cuda(f)))
     torch.cuda.synchronize()
-    err = O.relative_error(p, got, O.solve(p, f))
+    err = parity_error(p, got, O.solve(p, f))
     say("  err", err, "iters", plan.info().iters)
     assert err <= (FP64_TOL if prec == "fp64" else MIXED_TOL), err
 
@@ -122,4 +122,4 @@ def test_periodic_z_in_batch():
         for i, p in enumerate(probs):
             single = host(plans[i].solve(rhs[i]))
             assert np.array_equal(host(outs[i]), single), (i, use_graph)
-            assert O.relative_error(p, single, O.solve(p, fs[i])) <= FP64_TOL, i
+            assert parity_error(p, single, O.solve(p, fs[i])) <= FP64_TOL, i

@@ -7,7 +7,7 @@ import pytest
 
 import oracle as O
 import workloads as W
-from tests.gpu_util import cuda, host, say
+from tests.gpu_util import cuda, host, say, parity_error
 
 pytestmark = pytest.mark.gpu
 
@@ -57,7 +57,7 @@ def test_server_mix_equals_alone(prec, fixed):
         assert np.array_equal(host(outs[k]), alone[k]), f"request {k} differs from its solve alone"
     i, s = reqs[0]
     ref = O.solve(fams[i], W.rhs(fams[i], s))
-    assert O.relative_error(fams[i], host(outs[0]), ref) <= (1e-12 if prec == "fp64" else 1e-10)
+    assert parity_error(fams[i], host(outs[0]), ref) <= (1e-12 if prec == "fp64" else 1e-10)
     del srv
 
 
@@ -88,3 +88,32 @@ def test_server_memory_admission_and_oversize_rejection():
     assert ei.value.code == -3
     del srv
     say("admission ok")
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("prec,fixed", [("fp64", -1), ("bf16x3", 3)])
+def test_served_full_size_families_match_oracle(prec, fixed):
+    """Requests of the 64^3, 256^3 and 512^3 serving families, served
+    together, each against the oracle (FP64 at 1e-12, refined BF16x3 at
+    1e-10, 2-norm and max-norm)."""
+    import torch
+    T = _T()
+    fams = W.serving_families()
+    pick = [fams[0], fams[5], fams[9]]
+    assert [p.n[0] for p in pick] == [64, 256, 512]
+    plans = [T.Plan.from_problem(p, precision=prec, fixed_refine=fixed) for p in pick]
+    rhs = [cuda(W.rhs(p, 700 + k)) for k, p in enumerate(pick)]
+    outs = [torch.empty_like(r) for r in rhs]
+    srv = T.Server(hbm_budget_bytes=0, max_slots=3)
+    tickets = [srv.submit(pl, r, o) for pl, r, o in zip(plans, rhs, outs)]
+    done = _wait(srv, tickets, timeout=120.0)
+    srv.drain()
+    del srv
+    for k, (p, t) in enumerate(zip(pick, tickets)):
+        info = done[t][0]
+        assert info.nonfinite == 0
+        say("oracle", p.name, p.bc)
+        ref = O.solve(p, W.rhs(p, 700 + k))
+        err = parity_error(p, host(outs[k]), ref)
+        say(f"  {prec}: {err:.3e}")
+        assert err <= (1e-12 if prec == "fp64" else 1e-10), (p.name, err)

@@ -6,7 +6,7 @@ import pytest
 
 import oracle as O
 import workloads as W
-from tests.gpu_util import cuda, host, say
+from tests.gpu_util import cuda, host, say, parity_error
 
 pytestmark = pytest.mark.gpu
 
@@ -34,7 +34,7 @@ def test_cavity32_fp64_matches_oracle():
     say("cavity32", p.shape)
     got, plan = _solve(p, f)
     ref = O.solve(p, f)
-    err = O.relative_error(p, got, ref)
+    err = parity_error(p, got, ref)
     assert err <= FP64_TOL, err
     r = O.residual(p, f, got)
     assert np.linalg.norm(r) / np.linalg.norm(f) <= 1e-12
@@ -45,7 +45,7 @@ def test_cavity32_mms():
     p, f, u = W.cavity32_mms()
     got, _ = _solve(p, f)
     ref = O.solve(p, f)
-    err = O.relative_error(p, got, ref)
+    err = parity_error(p, got, ref)
     assert err <= FP64_TOL, err
     # discretisation error of the manufactured case, as the oracle's
     assert abs(O.relative_error(p, got, u) - O.relative_error(p, ref, u)) <= 1e-9
@@ -75,7 +75,7 @@ def test_small_fp64_matches_oracle(case):
     say("small fp64", p.n, p.bc, p.loc, p.kind)
     got, _ = _solve(p, f)
     ref = O.solve(p, f)
-    err = O.relative_error(p, got, ref)
+    err = parity_error(p, got, ref)
     assert err <= FP64_TOL, err
 
 
@@ -87,7 +87,7 @@ def test_small_fp64_sequential_thomas_matches_oracle(case):
     say("small fp64 seq thomas", p.n, p.bc, p.loc, p.kind)
     got, _ = _solve(p, f, seq_thomas=True)
     ref = O.solve(p, f)
-    err = O.relative_error(p, got, ref)
+    err = parity_error(p, got, ref)
     assert err <= FP64_TOL, err
 
 
@@ -108,7 +108,7 @@ def test_persistent_tiles_match_oracle(tmp_path, prec):
             T.autotune_load(str(table))
             kw = {} if prec == "fp64" else {"precision": prec, "rtol": 1e-13, "max_refine": 12}
             got, _ = _solve(p, f, dense_x=True, **kw)
-            err = O.relative_error(p, got, ref)
+            err = parity_error(p, got, ref)
             assert err <= (FP64_TOL if prec == "fp64" else MIXED_TOL), (v, err)
     finally:
         # back to the persistent four-wave tile, the choice without a table entry
@@ -130,7 +130,7 @@ def test_autotune_records_thomas_kernel(tmp_path):
     thomas = [r for r in rows if r[1] == 2 and r[2] == 48 * 40 and r[3] == 100]
     assert len(thomas) == 1 and 1 <= thomas[0][5] <= 1 + len(T.THOMAS_PARTS), rows
     got, _ = _solve(p, f)
-    err = O.relative_error(p, got, O.solve(p, f))
+    err = parity_error(p, got, O.solve(p, f))
     assert err <= FP64_TOL, err
 
 
@@ -142,7 +142,7 @@ def test_small_mixed_matches_oracle(case, prec):
     say("small mixed", prec, p.n, p.bc, p.loc, p.kind)
     got, plan = _solve(p, f, precision=prec, rtol=1e-13, max_refine=12)
     ref = O.solve(p, f)
-    err = O.relative_error(p, got, ref)
+    err = parity_error(p, got, ref)
     say("  iters", plan.info().iters, "err", err)
     assert err <= MIXED_TOL
 
@@ -158,8 +158,8 @@ def test_nrhs_batch_equals_single():
     for i in range(3):
         o1 = host(plan1.solve(cuda(fs[i])))
         ref = O.solve(p, fs[i])
-        assert O.relative_error(p, out3[i], ref) <= FP64_TOL
-        assert O.relative_error(p, o1, ref) <= FP64_TOL
+        assert parity_error(p, out3[i], ref) <= FP64_TOL
+        assert parity_error(p, o1, ref) <= FP64_TOL
     torch.cuda.synchronize()
 
 
@@ -191,12 +191,12 @@ def test_channel256_fp64_and_mixed_match_oracle():
     ref = O.solve(p, f)
     say("channel256 fp64")
     got, _ = _solve(p, f)
-    err = O.relative_error(p, got, ref)
+    err = parity_error(p, got, ref)
     assert err <= FP64_TOL, err
     for prec in ("fp32", "bf16x3"):
         say("channel256", prec)
         got, plan = _solve(p, f, precision=prec, rtol=1e-12, max_refine=12)
-        err = O.relative_error(p, got, ref)
+        err = parity_error(p, got, ref)
         say("  iters", plan.info().iters, "err", err)
         assert err <= MIXED_TOL
 
@@ -234,3 +234,19 @@ def test_solve_captured_in_graph(prec):
         plan.solve(f, out, ws)  # eager work between the replays
         torch.cuda.synchronize()
         assert np.array_equal(host(out), eager)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_channel256_adaptive_default_rtol_meets_target_with_margin(prec):
+    """The adaptive refinement at its default rtol (1e-12) on the 256^3
+    channel: the solve it returns is within 1e-11 of the oracle, a tenth of
+    the 1e-10 target (2-norm and max-norm)."""
+    p = W.channel256()
+    f = W.rhs(p, 2)
+    got, plan = _solve(p, f, precision=prec)
+    inf = plan.info()
+    ref = O.solve(p, f)
+    err = parity_error(p, got, ref)
+    say(prec, "corrections", inf.iters, "last correction", inf.rel_correction, "error", err)
+    assert err <= 1e-11, err
