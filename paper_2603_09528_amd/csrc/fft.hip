@@ -168,12 +168,61 @@ __device__ __forceinline__ void ut_tables(const FftDesc& d, const UtGeom& g, dou
         for (int k = threadIdx.x; k <= g.M; k += g.nt) Q[k] = d.qtw[k];
 }
 
+// Sum (a, b) over a block of nt threads (a multiple of 64, at most UT_NT) in a
+// fixed order; thread 0 gets the result.
+__device__ __forceinline__ void ut_block_sum2(double& a, double& b, double* red, int nt) {
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+    __syncthreads();
+    if (l == 0) {
+        red[2 * w] = a;
+        red[2 * w + 1] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sa = 0.0, sb = 0.0;
+        for (int i = 0; i < nt / 64; ++i) {
+            sa += red[2 * i];
+            sb += red[2 * i + 1];
+        }
+        a = sa;
+        b = sb;
+    }
+}
+
+// The same for three values (red holds 3 nt / 64 doubles).
+__device__ __forceinline__ void ut_block_sum3(double& a, double& b, double& c, double* red, int nt) {
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
+    const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+    __syncthreads();
+    if (l == 0) {
+        red[3 * w] = a;
+        red[3 * w + 1] = b;
+        red[3 * w + 2] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sa = 0.0, sb = 0.0, sc = 0.0;
+        for (int i = 0; i < nt / 64; ++i) {
+            sa += red[3 * i];
+            sb += red[3 * i + 1];
+            sc += red[3 * i + 2];
+        }
+        a = sa;
+        b = sb;
+        c = sc;
+    }
+}
+
 template <typename T> struct Pair2;
 template <> struct Pair2<double> { typedef double2 type; };
 template <> struct Pair2<float> { typedef float2 type; };
 
 template <typename TI, typename TO>
-__device__ __forceinline__ void ut_forward(const FftDesc& d, long long blk, double2* lds) {
+__device__ __forceinline__ void ut_forward_body(const FftDesc& d, long long blk, double2* lds, double* chk) {
     const UtGeom g = ut_geom(d, blk);
     double2 *W, *Q;
     ut_tables(d, g, lds, W, Q);
@@ -188,14 +237,32 @@ __device__ __forceinline__ void ut_forward(const FftDesc& d, long long blk, doub
         constexpr int UL = 1 << UT_Q;
         const int total = g.lpb << g.mlog;  // pairs in the block
         const bool vec = ((uintptr_t)in % sizeof(typename Pair2<TI>::type)) == 0;
+        // fused right-hand-side check: volume-weighted sums of the finite
+        // values and the count of the others.  Where the block size is a
+        // multiple of M (N <= 512) a thread's items share one pair position
+        // c, so its x weights are loaded once; the block's lines lie in one
+        // rhs, so the (j, k) of line l follow from those of its first line.
+        double cs = 0.0, ca = 0.0, cbad = 0.0;
+        double cwx0 = 0.0, cwx1 = 0.0;
+        unsigned crr0 = 0;
+        const bool cfix = (g.nt & (M - 1)) == 0;
+        if (d.cpart) {
+            const int c = (int)threadIdx.x & (M - 1);
+            cwx0 = d.cvx[2 * c];
+            cwx1 = d.cvx[2 * c + 1];
+            crr0 = (unsigned)g.line0 % d.crows;
+        }
         for (int base = 0; base < total; base += UL * g.nt) {
             double2 v[UL];
+            double wyz[UL];
 #pragma unroll
             for (int u = 0; u < UL; ++u) {
                 const int idx = base + u * g.nt + (int)threadIdx.x;
                 const int l = idx >> g.mlog, c = idx & (M - 1);
                 v[u] = make_double2(0.0, 0.0);
+                wyz[u] = 0.0;
                 if (idx < total && g.line0 + l < d.lines) {
+                    if (d.cpart) wyz[u] = d.cvyz[crr0 + (unsigned)l];
                     const long long o = ((g.line0 + l) << g.nlog) + 2 * c;
                     if (vec) {
                         const typename Pair2<TI>::type p = *(const typename Pair2<TI>::type*)(in + o);
@@ -210,6 +277,15 @@ __device__ __forceinline__ void ut_forward(const FftDesc& d, long long blk, doub
                 const int idx = base + u * g.nt + (int)threadIdx.x;
                 if (idx >= total) continue;
                 const int l = idx >> g.mlog, c = idx & (M - 1);
+                if (d.cpart) {
+                    // items past the last line hold zeros (finite, weight 0)
+                    const double wx0 = cfix ? cwx0 : d.cvx[2 * c], wx1 = cfix ? cwx1 : d.cvx[2 * c + 1];
+                    const bool f0 = __builtin_isfinite(v[u].x), f1 = __builtin_isfinite(v[u].y);
+                    const double x0 = f0 ? v[u].x : 0.0, x1 = f1 ? v[u].y : 0.0;
+                    cs += wyz[u] * (wx0 * x0 + wx1 * x1);
+                    ca += wyz[u] * (wx0 * __builtin_fabs(x0) + wx1 * __builtin_fabs(x1));
+                    cbad += (f0 ? 0.0 : 1.0) + (f1 ? 0.0 : 1.0);
+                }
                 if (kind == UT_FOURIER) {
                     lds[l * g.ls + pad16(c)] = v[u];
                 } else {
@@ -219,6 +295,9 @@ __device__ __forceinline__ void ut_forward(const FftDesc& d, long long blk, doub
                 }
             }
         }
+        chk[0] = cs;
+        chk[1] = ca;
+        chk[2] = cbad;
     } else {
         constexpr int UL = 16;
         const int total = g.lpb << g.nlog;
@@ -310,26 +389,22 @@ __device__ __forceinline__ void ut_forward(const FftDesc& d, long long blk, doub
     }
 }
 
-// Sum (a, b) over a block of nt threads (a multiple of 64, at most 128) in a
-// fixed order; thread 0 gets the result.
-__device__ __forceinline__ void ut_block_sum2(double& a, double& b, double* red, int nt) {
-    a = wave_sum(a);
-    b = wave_sum(b);
-    const int w = threadIdx.x / 64, l = threadIdx.x % 64;
-    __syncthreads();
-    if (l == 0) {
-        red[2 * w] = a;
-        red[2 * w + 1] = b;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double sa = 0.0, sb = 0.0;
-        for (int i = 0; i < nt / 64; ++i) {
-            sa += red[2 * i];
-            sb += red[2 * i + 1];
+// The forward transform; with a fused right-hand-side check (x lines) the
+// block's sums are reduced after its stores, where the barriers cost least,
+// into one partial record per block.
+template <typename TI, typename TO>
+__device__ __forceinline__ void ut_forward(const FftDesc& d, long long blk, double2* lds, double* red) {
+    double chk[3] = {0.0, 0.0, 0.0};
+    ut_forward_body<TI, TO>(d, blk, lds, chk);
+    if (d.cpart && !d.ylines) {
+        ut_block_sum3(chk[0], chk[1], chk[2], red, ut_threads(d.n));
+        if (threadIdx.x == 0) {
+            double* q = d.cpart + 4 * blk;
+            q[0] = chk[0];
+            q[1] = chk[1];
+            q[2] = chk[2];
+            q[3] = 0.0;
         }
-        a = sa;
-        b = sb;
     }
 }
 
@@ -488,9 +563,9 @@ __device__ __forceinline__ void ut_inverse(const FftDesc& d, long long blk, doub
 template <typename TI, typename TO, int EPI, bool INV>
 __device__ __forceinline__ void ut_block(const FftDesc& d, long long blk) {
     extern __shared__ double2 ut_smem[];
-    __shared__ double red[2 * (UT_NT / 64)];
+    __shared__ double red[3 * (UT_NT / 64)];
     if constexpr (INV) ut_inverse<TI, TO, EPI>(d, blk, ut_smem, red);
-    else ut_forward<TI, TO>(d, blk, ut_smem);
+    else ut_forward<TI, TO>(d, blk, ut_smem, red);
 }
 
 // Consecutive blocks of strided lines share cache lines: y launches number
@@ -533,6 +608,8 @@ hipError_t launch_ut_t(const FftDesc& d, const FftDesc* d_work, int nwork, long 
 }  // namespace
 
 bool fft_supported(int n) { return n >= 8 && n <= 2048 && (n & (n - 1)) == 0; }
+
+int fft_lines_per_block(int n) { return ut_lines_per_block(n); }
 
 long long fft_blocks(const FftDesc& d) {
     const int lpb = ut_lines_per_block(d.n);

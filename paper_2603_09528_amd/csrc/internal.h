@@ -63,6 +63,7 @@ struct PlanBuffers {  // per-plan small device arrays
     double* ay = nullptr; double* by = nullptr; double* cy = nullptr;
     double* az = nullptr; double* bz = nullptr; double* cz = nullptr;
     double* vx = nullptr; double* vy = nullptr; double* vz = nullptr;  // control volumes
+    double* vyz = nullptr;       // vy_j vz_k at j + Ny k
     double* norms = nullptr;     // device sums, TPT_STATS doubles per rhs (StatSlot)
     void* block = nullptr;
 };
@@ -149,6 +150,14 @@ struct TimedScope {
 };
 
 int solve_one(tpt_plan_s* p, const double* rhs, double* out, void* ws, size_t ws_bytes, hipStream_t s);
+// Right-hand-side check of a solve: its descriptor (stats into the plan's
+// buffer), whether it rides in the x forward fast transform's loads (x lines
+// by FFT, whole blocks of lines per rhs), the partials per rhs it then
+// writes, and the descriptor fields of that transform.
+CheckDesc check_desc(const tpt_plan_s* p, const double* rhs, double* partials);
+bool check_fused(const tpt_plan_s* p);
+long long check_fused_blocks(const tpt_plan_s* p);
+void attach_check(const tpt_plan_s* p, const CheckDesc& c, FftDesc& f);
 // tpt_info fields of plan p from its reduced per-rhs sums h (TPT_STATS
 // doubles per rhs): the refinement norms when `norms`, the check fields when
 // the plan checks its right-hand sides; other fields are left as they are.

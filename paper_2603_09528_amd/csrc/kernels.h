@@ -113,9 +113,19 @@ struct FftDesc {
     const double2* qtw;     // e^{-i pi k / 2n}, k <= n/2 (DCT, DST)
     double* partials;       // EPI_ACCUM_F64: 2 doubles per block
     long long block_begin;  // multi-problem
+    // forward x lines only: the right-hand-side check fused into the loads
+    // (cpart non-null): per block the partials of CheckDesc (4 doubles at
+    // cpart + 4 blk) over its lines, line = row of rhs
+    // line / crows, crows = Ny Nz a multiple of the lines per block; weights
+    // vx_i cvyz[row] (cvyz[j + Ny k] = vy_j vz_k)
+    const double* cvx;
+    const double* cvyz;
+    double* cpart;
+    unsigned crows;
 };
 bool fft_supported(int n);
 long long fft_blocks(const FftDesc& d);
+int fft_lines_per_block(int n);
 hipError_t launch_fft(const FftDesc& rep, const FftDesc* d_work, int nwork, long long blocks, hipStream_t s);
 
 // y GEMM of one problem (descriptor of the y pass) whose B rows are first
@@ -212,13 +222,20 @@ struct CheckDesc {
     const double* vx;
     const double* vy;
     const double* vz;
+    const double* vyz;      // vy_j vz_k at j + Ny k
     double* partials;       // 4 doubles per block, nsys * check_blocks(c) blocks
     double* out;
     int out_stride;
     long long block_begin;  // multi-problem: first block of this problem
+    long long nblk;         // partials per field when written by another kernel
+                            // (the fused x-forward check), else 0
 };
 long long check_blocks(const CheckDesc& c);  // blocks per field
 hipError_t launch_check(const CheckDesc& c, hipStream_t s);
+// only the folding of partials written elsewhere (nb blocks per field)
+hipError_t launch_check_reduce(const CheckDesc& c, long long nb, hipStream_t s);
+// the same for a list (one field each, c.nblk partials each)
+hipError_t launch_check_reduce_multi(const CheckDesc* d_work, int nwork, hipStream_t s);
 // every problem of the list (one field each); then one reduction block each
 hipError_t launch_check_multi(const CheckDesc* d_work, int nwork, long long total_blocks, hipStream_t s);
 

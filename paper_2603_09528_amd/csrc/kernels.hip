@@ -624,46 +624,53 @@ hipError_t launch_reduce_pairs_multi(const ReduceDesc* d_work, int nwork, hipStr
 // ---------------------------------------------------------------------------
 // Right-hand-side check: volume-weighted sums (for the compatibility defect
 // of a singular problem) and the count of non-finite values.  A block covers
-// CHK_NT * CHK_PT consecutive unknowns of one field; each thread walks them
-// at stride CHK_NT, carrying (i, j, k) by increments instead of divisions.
+// CHK_ROWS consecutive x-lines (rows (j, k)) of one field as 64 columns x 4
+// row lanes: lane (c, r) visits columns i = c + 64 a and rows r + 4 b, so a
+// wave reads 512 contiguous bytes of one row per access, holds vx_i in a
+// register across its rows and forms vy_j vz_k once per row; the CHK_ROWS / 4
+// loads of a column are independent and issued together.
 // ---------------------------------------------------------------------------
 constexpr int CHK_NT = 256;
-constexpr int CHK_PT = 32;
+constexpr int CHK_ROWS = 32;
 
 __host__ __device__ inline long long check_blocks_of(const CheckDesc& c) {
-    const long long dof = (long long)c.nx * c.ny * c.nz;
-    return (dof + (long long)CHK_NT * CHK_PT - 1) / ((long long)CHK_NT * CHK_PT);
+    const long long rows = (long long)c.ny * c.nz;
+    return (rows + CHK_ROWS - 1) / CHK_ROWS;
 }
 long long check_blocks(const CheckDesc& c) { return check_blocks_of(c); }
 
 __device__ __forceinline__ void check_block(const CheckDesc& c, int sys, long long lb, long long nb, double* red) {
     const int nx = c.nx, ny = c.ny;
-    const long long dof = (long long)nx * ny * c.nz;
-    const double* __restrict__ f = c.f + (long long)sys * dof;
-    long long e = lb * (CHK_NT * CHK_PT) + threadIdx.x;
-    long long row = e / nx;
-    int i = (int)(e - row * nx);
-    int j = (int)(row % ny);
-    int k = (int)(row / ny);
+    const long long rows = (long long)ny * c.nz;
+    const double* __restrict__ f = c.f + (long long)sys * rows * nx;
+    const int col = threadIdx.x & 63, rl = threadIdx.x >> 6;
+    const long long r0 = lb * CHK_ROWS + rl;
+    // the rows of this lane and their y-z weights (0 past the last row)
+    double wyz[CHK_ROWS / 4];
+    long long roff[CHK_ROWS / 4];
+#pragma unroll
+    for (int b = 0; b < CHK_ROWS / 4; ++b) {
+        const long long row = r0 + 4 * b;
+        const bool in = row < rows;
+        const long long rr = in ? row : 0;
+        const int k = (int)(rr / ny), j = (int)(rr - (long long)k * ny);
+        wyz[b] = in ? c.vy[j] * c.vz[k] : 0.0;
+        roff[b] = rr * nx;
+    }
     double s = 0.0, a = 0.0, bad = 0.0;
-#pragma unroll 8
-    for (int m = 0; m < CHK_PT; ++m) {
-        if (e < dof) {
-            const double v = f[e];
-            const double w = c.vx[i] * c.vy[j] * c.vz[k];
-            const bool fin = __builtin_isfinite(v);
-            s += fin ? w * v : 0.0;
-            a += fin ? w * __builtin_fabs(v) : 0.0;
-            bad += fin ? 0.0 : 1.0;
-        }
-        e += CHK_NT;
-        i += CHK_NT;
-        while (i >= nx) {
-            i -= nx;
-            if (++j == ny) {
-                j = 0;
-                ++k;
-            }
+    for (int i = col; i < nx; i += 64) {
+        const double wx = c.vx[i];
+        double v[CHK_ROWS / 4];
+#pragma unroll
+        for (int b = 0; b < CHK_ROWS / 4; ++b) v[b] = f[roff[b] + i];
+#pragma unroll
+        for (int b = 0; b < CHK_ROWS / 4; ++b) {
+            const bool live = wyz[b] != 0.0;
+            const bool fin = __builtin_isfinite(v[b]);
+            const double w = wx * wyz[b];
+            s += fin ? w * v[b] : 0.0;
+            a += fin ? w * __builtin_fabs(v[b]) : 0.0;
+            bad += (live && !fin) ? 1.0 : 0.0;
         }
     }
     double zero = 0.0;
@@ -726,7 +733,7 @@ __global__ __launch_bounds__(RED_NT) void check_reduce_kernel(CheckDesc c, long 
 __global__ __launch_bounds__(RED_NT) void check_reduce_multi_kernel(const CheckDesc* __restrict__ work) {
     __shared__ double red[2 * RED_NT / 64];
     const CheckDesc c = work[blockIdx.x];
-    check_reduce_block(c, 0, check_blocks_of(c), red);
+    check_reduce_block(c, 0, c.nblk > 0 ? c.nblk : check_blocks_of(c), red);
 }
 
 hipError_t launch_check(const CheckDesc& c, hipStream_t s) {
@@ -736,6 +743,18 @@ hipError_t launch_check(const CheckDesc& c, hipStream_t s) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     TPT_KLAUNCH(check_reduce_kernel, dim3((unsigned)c.nsys), dim3(RED_NT), 0, s, c, nb);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_reduce(const CheckDesc& c, long long nb, hipStream_t s) {
+    if (nb <= 0 || c.nsys < 1) return hipSuccess;
+    TPT_KLAUNCH(check_reduce_kernel, dim3((unsigned)c.nsys), dim3(RED_NT), 0, s, c, nb);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_reduce_multi(const CheckDesc* d_work, int nwork, hipStream_t s) {
+    if (nwork <= 0) return hipSuccess;
+    TPT_KLAUNCH(check_reduce_multi_kernel, dim3((unsigned)nwork), dim3(RED_NT), 0, s, d_work);
     return hipGetLastError();
 }
 

@@ -123,6 +123,11 @@ int MultiExec::build(const double* const* rhs, double* const* out, void* ws) {
         if (!rhs[i] || !out[i]) return fail(TPT_ERR_INVALID, "NULL rhs/out in batch");
         w[i] = carve(plans_[i], (char*)ws + ws_off_[i]);
     }
+    // right-hand-side checks (filled below): descriptors, and which ride in
+    // the first x forward pass
+    std::vector<CheckDesc> chk(n);
+    std::vector<char> fused(n, 0);
+    std::vector<CheckDesc> fused_list;
     // per stage: which problems take the fast transform, which the GEMM
     auto fast_mask = [&](int stage, bool fast) {
         std::vector<char> m(n);
@@ -132,13 +137,14 @@ int MultiExec::build(const double* const* rhs, double* const* out, void* ws) {
     // one transform stage of every problem: GEMM launches grouped by tile
     // variant, fast-transform launches grouped by line length
     auto stage = [&](int st, const std::vector<const void*>& in, int tin, const std::vector<void*>& outp, int tout,
-                     int epi, std::vector<long long>* nb) {
+                     int epi, std::vector<long long>* nb, bool with_check = false) {
         std::vector<GemmDesc> g(n);
         std::vector<FftDesc> f(n);
         for (int i = 0; i < n; ++i) {
             double* part = epi == EPI_ACCUM_F64 ? w[i].partials : nullptr;
             if (stage_is_fast(plans_[i], st)) {
                 f[i] = stage_fft(plans_[i], st, in[i], tin, outp[i], tout, epi, part, 1);
+                if (with_check && fused[i]) attach_check(plans_[i], chk[i], f[i]);
                 if (nb) (*nb)[i] = fft_blocks(f[i]);
             } else {
                 g[i] = stage_gemm(plans_[i], st, prec_, in[i], tin, outp[i], tout, epi, part, 1);
@@ -164,7 +170,14 @@ int MultiExec::build(const double* const* rhs, double* const* out, void* ws) {
     auto minv = [&](bool from_rhs, int epi) {
         const int tmid = mixed_ ? DT_F32 : DT_F64;
         std::vector<long long> nb(n);
-        stage(ST_XF, from_rhs ? rhsv : resv, from_rhs ? DT_F64 : DT_F32, w1, tmid, EPI_STORE, nullptr);
+        stage(ST_XF, from_rhs ? rhsv : resv, from_rhs ? DT_F64 : DT_F32, w1, tmid, EPI_STORE, nullptr, from_rhs);
+        if (from_rhs && !fused_list.empty()) {
+            Launch L{};
+            L.kind = 7;
+            L.off = append(blob_, fused_list);
+            L.nwork = (int)fused_list.size();
+            seq_.push_back(L);
+        }
         stage(ST_YF, w1c, tmid, w2, tmid, EPI_STORE, nullptr);
         // one launch per Thomas kernel: each problem runs the variant its
         // single-problem solve runs, so batch and single results agree bit
@@ -203,24 +216,24 @@ int MultiExec::build(const double* const* rhs, double* const* out, void* ws) {
         stage(ST_XI, w1c, tmid, outv, DT_F64, epi, &nb);
         return nb;
     };
-    // right-hand-side checks of the plans that ask for them
+    // right-hand-side checks of the plans that ask for them: in the loads of
+    // the first x forward pass where a single solve fuses it (the same
+    // partials, so batch and single results stay bitwise equal), else a
+    // separate pass first
     {
         std::vector<CheckDesc> cd;
         long long blocks = 0;
         for (int i = 0; i < n; ++i) {
             if (!plans_[i]->run_check) continue;
-            CheckDesc c{};
-            c.nx = plans_[i]->N[0];
-            c.ny = plans_[i]->N[1];
-            c.nz = plans_[i]->N[2];
-            c.nsys = 1;
-            c.f = rhs[i];
-            c.vx = plans_[i]->buf.vx;
-            c.vy = plans_[i]->buf.vy;
-            c.vz = plans_[i]->buf.vz;
-            c.partials = w[i].partials;
+            CheckDesc c = check_desc(plans_[i], rhs[i], w[i].partials);
             c.out = (double*)((char*)ws + norm_off_[i]) + SS_WF;
-            c.out_stride = TPT_STATS;
+            chk[i] = c;
+            if (check_fused(plans_[i])) {
+                fused[i] = 1;
+                c.nblk = check_fused_blocks(plans_[i]);
+                fused_list.push_back(c);
+                continue;
+            }
             c.block_begin = blocks;
             blocks += check_blocks(c);
             cd.push_back(c);
@@ -338,6 +351,11 @@ int MultiExec::enqueue(hipStream_t s) const {
             case 6: {
                 TimedScope ts("multi_check", s);
                 e = launch_check_multi((const CheckDesc*)(d_desc_ + L.off), L.nwork, L.total, s);
+                break;
+            }
+            case 7: {
+                TimedScope ts("multi_check_reduce", s);
+                e = launch_check_reduce_multi((const CheckDesc*)(d_desc_ + L.off), L.nwork, s);
                 break;
             }
             case 4: {

@@ -36,7 +36,7 @@ class MultiExec {
    private:
     struct Launch {
         int kind;     // 0 gemm, 1 sequential Thomas, 2 residual, 3 reduce, 4 x-line FFT, 5 partitioned Thomas,
-                      // 6 right-hand-side check
+                      // 6 right-hand-side check, 7 folding of fused-check partials
         // sequential Thomas: variant holds the largest nz; partitioned: the
         // configuration, prec the storage type
         int prec, variant, b_nk;

@@ -216,7 +216,8 @@ static size_t partial_slots(const tpt_plan_s* p) {
     c.nx = p->N[0];
     c.ny = p->N[1];
     c.nz = p->N[2];
-    const long long chk = 2 * check_blocks(c) * p->desc.nrhs;
+    long long chk = 2 * check_blocks(c) * p->desc.nrhs;
+    if (fft_supported(p->N[0])) chk = std::max(chk, 2 * check_fused_blocks(p) * p->desc.nrhs);
     (void)dof;
     return (size_t)std::max(std::max(std::max(res, xi), fx), chk) + 8;
 }
@@ -334,7 +335,7 @@ int tpt_plan_create(const tpt_plan_desc* desc, tpt_plan* out) {
     if (!p->host_only) {
         const size_t nx = p->N[0], ny = p->N[1], nz = p->N[2];
         const size_t nstat = (size_t)TPT_STATS * p->desc.nrhs;
-        const size_t doubles = 4 * (nx + ny + nz) + nstat + 64;
+        const size_t doubles = 4 * (nx + ny + nz) + ny * nz + nstat + 64;
         void* blk = nullptr;
         if (hipMalloc(&blk, doubles * 8) != hipSuccess) {
             (void)hipGetLastError();
@@ -351,12 +352,15 @@ int tpt_plan_create(const tpt_plan_desc* desc, tpt_plan* out) {
         put(p->op[1].a); put(p->op[1].b); put(p->op[1].c);
         put(p->op[2].a); put(p->op[2].b); put(p->op[2].c);
         put(p->op[0].vol); put(p->op[1].vol); put(p->op[2].vol);
+        for (size_t k = 0; k < nz; ++k)
+            for (size_t j = 0; j < ny; ++j) *w++ = p->op[1].vol[j] * p->op[2].vol[k];
         TPT_HIP(hipMemcpy(blk, h.data(), doubles * 8, hipMemcpyHostToDevice));
         double* d = (double*)blk;
         p->buf.ax = d; d += nx; p->buf.bx = d; d += nx; p->buf.cx = d; d += nx;
         p->buf.ay = d; d += ny; p->buf.by = d; d += ny; p->buf.cy = d; d += ny;
         p->buf.az = d; d += nz; p->buf.bz = d; d += nz; p->buf.cz = d; d += nz;
         p->buf.vx = d; d += nx; p->buf.vy = d; d += ny; p->buf.vz = d; d += nz;
+        p->buf.vyz = d; d += ny * nz;
         p->buf.norms = d;
         if (hipHostMalloc((void**)&p->h_norms, (nstat + 8) * sizeof(double), hipHostMallocDefault) != hipSuccess) {
             p->h_norms = nullptr;

@@ -325,11 +325,14 @@ static const char* fast_name(int stage, int tin, int tout) {
 }
 
 // One transform stage: the fast transform where the plan uses one for that
-// direction, else the GEMM.
+// direction, else the GEMM.  chk (x forward by fast transform only): the
+// right-hand-side check fused into its loads.
 static int run_stage(const tpt_plan_s* p, int stage, int prec, const void* in, int tin, void* out, int tout,
-                     int epi, double* partials, int nrhs, hipStream_t s, long long* nblocks = nullptr) {
+                     int epi, double* partials, int nrhs, hipStream_t s, long long* nblocks = nullptr,
+                     const CheckDesc* chk = nullptr) {
     if (!stage_is_fast(p, stage)) return run_gemm(p, stage, prec, in, tin, out, tout, epi, partials, nrhs, s, nblocks);
     FftDesc f = stage_fft(p, stage, in, tin, out, tout, epi, partials, nrhs);
+    if (chk) attach_check(p, *chk, f);
     const long long nb = fft_blocks(f);
     if (nblocks) *nblocks = nb;
     TimedScope ts(fast_name(stage, tin, tout), s);
@@ -347,11 +350,10 @@ static int run_thomas(const tpt_plan_s* p, const void* f, int tf, void* x, int t
     return TPT_OK;
 }
 
-// Right-hand-side check of every rhs (weighted sums and non-finite count)
-// into the plan's stats; its partials use the workspace's partial slots,
-// which are free until the first refinement residual.
-static int run_check(const tpt_plan_s* p, const double* rhs, double* partials, hipStream_t s) {
-    if (!p->run_check) return TPT_OK;
+// The right-hand-side check of a solve (weighted sums and non-finite count of
+// every rhs, into the plan's stats; partials in the workspace's partial
+// slots, which are free until the first refinement residual).
+CheckDesc check_desc(const tpt_plan_s* p, const double* rhs, double* partials) {
     CheckDesc c{};
     c.nx = p->N[0];
     c.ny = p->N[1];
@@ -361,9 +363,44 @@ static int run_check(const tpt_plan_s* p, const double* rhs, double* partials, h
     c.vx = p->buf.vx;
     c.vy = p->buf.vy;
     c.vz = p->buf.vz;
+    c.vyz = p->buf.vyz;
     c.partials = partials;
     c.out = p->buf.norms + SS_WF;
     c.out_stride = TPT_STATS;
+    return c;
+}
+
+// Whether the check rides in the loads of the x forward pass: x by fast
+// transform on FP64 input, and no block of x lines spans two right-hand sides.
+bool check_fused(const tpt_plan_s* p) {
+    if (!p->run_check || !stage_is_fast(p, ST_XF) || p->fuse_xy) return false;
+    const long long rows = (long long)p->N[1] * p->N[2];
+    return rows * p->desc.nrhs < 0xffffffffLL && rows % fft_lines_per_block(p->N[0]) == 0;
+}
+
+long long check_fused_blocks(const tpt_plan_s* p) {
+    return (long long)p->N[1] * p->N[2] / fft_lines_per_block(p->N[0]);
+}
+
+void attach_check(const tpt_plan_s* p, const CheckDesc& c, FftDesc& f) {
+    f.cvx = c.vx;
+    f.cvyz = c.vyz;
+    f.cpart = c.partials;
+    f.crows = (unsigned)((long long)p->N[1] * p->N[2]);
+}
+
+// Fold the partials the fused check wrote in the x forward pass.
+static int finish_fused_check(const tpt_plan_s* p, const CheckDesc& c, hipStream_t s) {
+    const long long nb = check_fused_blocks(p);
+    TimedScope ts("check_reduce", s);
+    hipError_t e = launch_check_reduce(c, nb, s);
+    if (e != hipSuccess) return fail(TPT_ERR_HIP, std::string("check launch: ") + hipGetErrorString(e));
+    return TPT_OK;
+}
+
+static int run_check(const tpt_plan_s* p, const double* rhs, double* partials, hipStream_t s) {
+    if (!p->run_check || check_fused(p)) return TPT_OK;
+    const CheckDesc c = check_desc(p, rhs, partials);
     TimedScope ts("check", s);
     hipError_t e = launch_check(c, s);
     if (e != hipSuccess) return fail(TPT_ERR_HIP, std::string("check launch: ") + hipGetErrorString(e));
@@ -475,7 +512,12 @@ static int solve_fp64(tpt_plan_s* p, const double* rhs, double* out, const Ws& w
         p->info.rel_residual = -1.0;
         return TPT_OK;
     }
-    if ((rc = run_stage(p, ST_XF, GP_F64, rhs, DT_F64, w.w1, DT_F64, EPI_STORE, nullptr, R, s))) return rc;
+    const bool fchk = check_fused(p);
+    const CheckDesc chk = check_desc(p, rhs, w.partials);
+    if ((rc = run_stage(p, ST_XF, GP_F64, rhs, DT_F64, w.w1, DT_F64, EPI_STORE, nullptr, R, s, nullptr,
+                        fchk ? &chk : nullptr)))
+        return rc;
+    if (fchk && (rc = finish_fused_check(p, chk, s))) return rc;
     if ((rc = run_stage(p, ST_YF, GP_F64, w.w1, DT_F64, w.w2, DT_F64, EPI_STORE, nullptr, R, s))) return rc;
     if ((rc = run_thomas(p, w.w2, DT_F64, w.w2, DT_F64, w.scratch, R, s))) return rc;
     if ((rc = run_stage(p, ST_YI, GP_F64, w.w2, DT_F64, w.w1, DT_F64, EPI_STORE, nullptr, R, s))) return rc;
@@ -495,7 +537,13 @@ static int apply_minv(tpt_plan_s* p, int prec, const void* in, int tin, double* 
                       hipStream_t s) {
     const int R = p->desc.nrhs;
     int rc;
-    if ((rc = run_stage(p, ST_XF, prec, in, tin, w.w1, DT_F32, EPI_STORE, nullptr, R, s))) return rc;
+    // the first application reads the rhs: its check may ride in the x pass
+    const bool fchk = tin == DT_F64 && check_fused(p);
+    const CheckDesc chk = check_desc(p, (const double*)in, w.partials);
+    if ((rc = run_stage(p, ST_XF, prec, in, tin, w.w1, DT_F32, EPI_STORE, nullptr, R, s, nullptr,
+                        fchk ? &chk : nullptr)))
+        return rc;
+    if (fchk && (rc = finish_fused_check(p, chk, s))) return rc;
     if ((rc = run_stage(p, ST_YF, prec, w.w1, DT_F32, w.w2, DT_F32, EPI_STORE, nullptr, R, s))) return rc;
     if ((rc = run_thomas(p, w.w2, DT_F32, w.w2, DT_F32, w.scratch, R, s))) return rc;
     if ((rc = run_stage(p, ST_YI, prec, w.w2, DT_F32, w.w1, DT_F32, EPI_STORE, nullptr, R, s))) return rc;

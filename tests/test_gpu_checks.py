@@ -30,10 +30,18 @@ def _defect(p, f):
 SINGULAR = W.make_problem((24, 20, 16), (1.5, 2.0, 1.0), (W.NN, W.NN, W.NN))
 PERIODIC = W.make_problem((32, 16, 12), (0.0, 2.0, 1.5), (W.PP, W.NN, W.NN))
 REGULAR = W.make_problem((20, 18, 14), (1.0, 1.5, 2.0), (W.DD, W.NN, ("N", "D")))
+# x by FFT with whole blocks of x lines per right-hand side: the check rides
+# in the loads of the x forward transform
+PERIODIC_F = W.make_problem((64, 32, 16), (0.0, 2.0, 1.5), (W.PP, W.NN, W.NN))
+REGULAR_F = W.make_problem((64, 32, 16), (0.0, 2.0, 1.5), (W.PP, W.NN, W.DD))
+# long x lines (a block holds fewer threads than pairs per line)
+PERIODIC_L1 = W.make_problem((1024, 8, 4), (0.0, 1.5, 1.0), (W.PP, W.NN, W.NN))
+PERIODIC_L2 = W.make_problem((2048, 4, 3), (0.0, 1.5, 1.0), (W.PP, W.NN, W.NN))
 
 
 @pytest.mark.parametrize("prec,fixed", [("fp64", -1), ("fp32", 2), ("bf16x3", -1)])
-@pytest.mark.parametrize("p", [SINGULAR, PERIODIC], ids=["nnn", "pnn"])
+@pytest.mark.parametrize("p", [SINGULAR, PERIODIC, PERIODIC_F, PERIODIC_L1, PERIODIC_L2],
+                         ids=["nnn", "pnn", "pnn-fused", "pnn-fused-1024", "pnn-fused-2048"])
 def test_compat_defect_of_incompatible_rhs(p, prec, fixed):
     import torch
     T = _T()
@@ -69,10 +77,10 @@ def test_regular_problem_reports_no_defect(prec, fixed):
 
 
 @pytest.mark.parametrize("prec,fixed", [("fp64", -1), ("fp32", 2), ("bf16x3", 2)])
-def test_nonfinite_rhs_is_counted(prec, fixed):
+@pytest.mark.parametrize("p", [REGULAR, REGULAR_F], ids=["gemm-x", "fused"])
+def test_nonfinite_rhs_is_counted(p, prec, fixed):
     import torch
     T = _T()
-    p = REGULAR
     f = W.rhs(p, 5)
     f[3, 4, 5] = np.nan
     f[0, 0, 0] = np.inf
@@ -101,10 +109,10 @@ def test_nonfinite_rhs_stops_adaptive_refinement():
     assert plan.info().nonfinite == 1
 
 
-def test_nrhs_checks_report_the_worst_rhs():
+@pytest.mark.parametrize("p", [SINGULAR, PERIODIC_F], ids=["gemm-x", "fused"])
+def test_nrhs_checks_report_the_worst_rhs(p):
     import torch
     T = _T()
-    p = SINGULAR
     fs = np.stack([W.rhs(p, 10), W.rhs(p, 11) + 0.1, W.rhs(p, 12)])
     fs[2, 1, 1, 1] = np.nan
     plan = T.Plan.from_problem(p, nrhs=3)
