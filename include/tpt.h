@@ -208,6 +208,19 @@ int tpt_solve(tpt_plan plan, const double *rhs, double *out, void *workspace,
 /* Info of the plan's last solve (call after synchronising its stream). */
 int tpt_solve_info(tpt_plan plan, tpt_info *info);
 
+/* tpt_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * workspace is a static device array of tpt_static_workspace_capacity()
+ * bytes (64 MiB) in the library's code object, one per GPU, held until the
+ * process ends; the call allocates nothing (the caller still passes rhs and
+ * out).  Same arguments, results and info as tpt_solve with workspace.
+ * A plan whose tpt_plan_workspace_bytes exceeds the capacity is rejected
+ * with TPT_ERR_WORKSPACE.  Every call on one GPU shares that GPU's array:
+ * calls that overlap on a GPU (other streams or threads) race on it, so the
+ * caller serialises them. */
+int tpt_solve_noalloc(tpt_plan plan, const double *rhs, double *out, void *stream);
+size_t tpt_static_workspace_capacity(void);
+
 /* ---- multi-problem batches (independent problems, uneven sizes) ---------- */
 
 /* Group `count` plans (any sizes, same precision) into a batch whose solve

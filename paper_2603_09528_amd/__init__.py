@@ -90,6 +90,8 @@ def lib():
             "tpt_plan_fused": (i, [vp, ctypes.POINTER(ctypes.c_int)]),
             "tpt_solve": (i, [vp, vp, vp, vp, sz, vp]),
             "tpt_solve_info": (i, [vp, ctypes.POINTER(Info)]),
+            "tpt_solve_noalloc": (i, [vp, vp, vp, vp]),
+            "tpt_static_workspace_capacity": (sz, []),
             "tpt_batch_create": (i, [i, ctypes.POINTER(vp), ctypes.POINTER(vp)]),
             "tpt_batch_destroy": (i, [vp]),
             "tpt_batch_workspace_bytes": (i, [vp, ctypes.POINTER(sz)]),
@@ -122,7 +124,7 @@ def lib():
 
 EXPORTED = ("tpt_plan_desc_init", "tpt_plan_create", "tpt_plan_destroy", "tpt_plan_shape",
             "tpt_plan_workspace_bytes", "tpt_plan_eigen", "tpt_plan_operator", "tpt_plan_transforms", "tpt_plan_fused", "tpt_solve",
-            "tpt_solve_info", "tpt_batch_create", "tpt_batch_destroy", "tpt_batch_workspace_bytes",
+            "tpt_solve_info", "tpt_solve_noalloc", "tpt_static_workspace_capacity", "tpt_batch_create", "tpt_batch_destroy", "tpt_batch_workspace_bytes",
             "tpt_batch_solve", "tpt_batch_info", "tpt_autotune", "tpt_autotune_save", "tpt_autotune_load",
             "tpt_server_create", "tpt_server_submit", "tpt_server_poll", "tpt_server_drain",
             "tpt_server_destroy", "tpt_thomas", "tpt_gemm", "tpt_timing_enable", "tpt_timing_collect",
@@ -282,6 +284,14 @@ class Plan:
         ws = self.workspace() if workspace is None else workspace
         _check(lib().tpt_solve(self._h, _ptr(rhs), _ptr(out), _ptr(ws), ws.numel() * ws.element_size(),
                                _stream(stream)))
+        return out
+
+    def solve_noalloc(self, rhs, out, stream=None):
+        """Solve with the library's static device workspace (no allocation;
+        see tpt_solve_noalloc); out must be given."""
+        _require_f64_cuda(rhs, self.shape, "rhs")
+        _require_f64_cuda(out, self.shape, "out")
+        _check(lib().tpt_solve_noalloc(self._h, _ptr(rhs), _ptr(out), _stream(stream)))
         return out
 
     def info(self) -> Info:
