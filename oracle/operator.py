@@ -23,6 +23,10 @@ used here are the ghost-cell rows (a reading of the paper, not its text):
 
 §2.2.2: T = T_x (x) I_y (x) I_z + I_x (x) T_y (x) I_z + I_x (x) I_y (x) T_z.
 Arrays here are (Nz, Ny, Nx) with x fastest.
+
+§2.1: the implicit diffusion operator L_I of the Helmholtz step may hold all
+three directions (xyz), only y and z (yz) or only z (z); the terms of the
+other directions are dropped from the Kronecker sum.
 """
 from __future__ import annotations
 
@@ -134,12 +138,19 @@ def _apply_1d(x, a, b, c, periodic, axis):
     return np.moveaxis(y, -1, axis)
 
 
+def implicit_dirs(p):
+    """Directions (0 = x, 1 = y, 2 = z) in the operator of problem p."""
+    return {"xyz": (0, 1, 2), "yz": (1, 2), "z": (2,)}[getattr(p, "implicit", "xyz")]
+
+
 def apply_operator(p, phi: np.ndarray) -> np.ndarray:
     """A phi for problem p: the Kronecker-sum Laplacian of §2.2.2, or
-    (I - alpha L) phi for a Helmholtz problem."""
+    (I - alpha L_I) phi for a Helmholtz problem."""
     ops = _ops(p)
     lap = np.zeros_like(phi)
     for d, axis in ((0, 2), (1, 1), (2, 0)):
+        if d not in implicit_dirs(p):
+            continue
         a, b, c, _, per = ops[d]
         lap += _apply_1d(phi, a, b, c, per, axis)
     if p.kind == "helmholtz":
@@ -159,6 +170,8 @@ def assemble_3d(p) -> np.ndarray:
     ops = _ops(p)
     Ts = [dense_1d(a, b, c, per) for (a, b, c, _, per) in ops]
     Ix, Iy, Iz = (np.eye(T.shape[0]) for T in Ts)
+    # a direction outside L_I contributes nothing to the sum
+    Ts = [T if d in implicit_dirs(p) else np.zeros_like(T) for d, T in enumerate(Ts)]
     T = (np.kron(Iz, np.kron(Iy, Ts[0])) + np.kron(Iz, np.kron(Ts[1], Ix))
          + np.kron(Ts[2], np.kron(Iy, Ix)))
     if p.kind == "helmholtz":

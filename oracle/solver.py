@@ -16,6 +16,11 @@ modal shift (end of §2.2.2): line (i, j) solves
 (sigma + tau (lambda_ij + T_z)) u^ = f^ with sigma = 1, tau = -alpha;
 Poisson is sigma = 0, tau = 1.
 
+Implicit directions (§2.1, L_I of the Helmholtz step; §3: with y and z
+implicit the x transforms are omitted, with only z the solve is the
+tridiagonal one alone): a direction outside L_I is not transformed and adds
+no eigenvalue to the line shift.
+
 Gauge (§3): for a Poisson problem with a constant null mode, the line whose
 shift is lambda_x = lambda_y = 0 has a vanishing final pivot; its last modal
 unknown is set to zero and back substitution proceeds from there.
@@ -105,22 +110,28 @@ class Plan:
 
     def __init__(self, p):
         self.p = p
+        imp = getattr(p, "implicit", "xyz")
+        self.tx = imp == "xyz"             # x transformed
+        self.ty = imp in ("xyz", "yz")     # y transformed
         self.zper = p.bc[2][0] == "P"
-        self.ex = eig_direction(p.faces[0], p.bc[0], p.loc[0])
-        self.ey = eig_direction(p.faces[1], p.bc[1], p.loc[1])
+        self.ex = eig_direction(p.faces[0], p.bc[0], p.loc[0]) if self.tx else None
+        self.ey = eig_direction(p.faces[1], p.bc[1], p.loc[1]) if self.ty else None
         self.az, self.bz, self.cz, _ = operator_1d(p.faces[2], p.bc[2], p.loc[2])
         self.sigma, self.tau = _coeffs(p)
         self.pin = None
-        if (self.sigma == 0.0 and self.ex.null_index >= 0 and self.ey.null_index >= 0
-                and has_null(p.bc[2], p.loc[2])):
+        if (self.tx and self.ty and self.sigma == 0.0 and self.ex.null_index >= 0
+                and self.ey.null_index >= 0 and has_null(p.bc[2], p.loc[2])):
             self.pin = (self.ey.null_index, self.ex.null_index)
 
     def forward(self, f):
-        fx = f @ self.ex.Qinv.T            # 2.1: sum_i Qx^{-1}[p, i] f[k, j, i]
-        return np.matmul(self.ey.Qinv, fx)  # 2.2: sum_j Qy^{-1}[q, j] fx[k, j, p]
+        fx = f @ self.ex.Qinv.T if self.tx else f             # 2.1: sum_i Qx^{-1}[p, i] f[k, j, i]
+        return np.matmul(self.ey.Qinv, fx) if self.ty else fx  # 2.2: sum_j Qy^{-1}[q, j] fx[k, j, p]
 
     def modal(self, fxy):
-        lam = self.ey.lam[:, None] + self.ex.lam[None, :]
+        nz, ny, nx = self.p.shape
+        lx = self.ex.lam if self.tx else np.zeros(nx)
+        ly = self.ey.lam if self.ty else np.zeros(ny)
+        lam = ly[:, None] + lx[None, :]
         if self.zper:
             return cyclic_lines(self.az, self.bz, self.cz, lam, self.sigma, self.tau, fxy, self.pin)
         x, piv = thomas_lines(self.az, self.bz, self.cz, lam, self.sigma, self.tau, fxy, self.pin)
@@ -128,8 +139,8 @@ class Plan:
         return x
 
     def inverse(self, phixy):
-        phix = np.matmul(self.ey.Q, phixy)  # 2.4
-        return phix @ self.ex.Q.T           # 2.5: sum_p Qx[i, p] phix[k, j, p]
+        phix = np.matmul(self.ey.Q, phixy) if self.ty else phixy  # 2.4
+        return phix @ self.ex.Q.T if self.tx else phix            # 2.5: sum_p Qx[i, p] phix[k, j, p]
 
     def solve(self, f):
         f = np.asarray(f, dtype=np.float64)

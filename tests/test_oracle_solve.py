@@ -172,3 +172,86 @@ def test_mms_second_order(make):
     order_max = np.log2(e[:-1, 1] / e[1:, 1])
     assert order_l2[-1] >= 1.9, order_l2
     assert order_max[-1] >= 1.75, order_max
+
+
+# ---- implicit directions of the Helmholtz step (§2.1 L_I; §3) ---------------
+
+IMPLICIT_CASES = [
+    ((6, 5, 7), (1.5, 1.5, 1.5), (W.DD, W.NN, W.DD), ("C", "C", "C")),
+    ((7, 6, 5), (0.0, 2.0, 2.0), (W.PP, W.DD, W.DD), ("F", "C", "F")),
+    ((5, 8, 6), (2.0, 0.0, 1.0), (("N", "D"), W.PP, W.NN), ("C", "C", "C")),
+    ((6, 6, 8), (1.0, 1.5, 0.0), (W.NN, W.NN, W.PP), ("C", "C", "C")),
+]
+
+
+@pytest.mark.parametrize("implicit", ["yz", "z"])
+@pytest.mark.parametrize("case", IMPLICIT_CASES, ids=lambda c: "".join(x[0] + x[1] for x in c[2]) + "".join(c[3]))
+def test_implicit_options_match_dense_lu(case, implicit):
+    n, beta, bc, loc = case
+    p = W.make_problem(n, beta, bc, loc=loc, kind="helmholtz", alpha=0.05, implicit=implicit)
+    f = W.rhs(p, 17)
+    assert O.relative_error(p, O.solve(p, f), O.solve_dense(p, f), norm="max") <= 5e-14
+
+
+def test_z_only_lines_match_banded_solver():
+    """I - alpha T_z on every (i, j) line, against LAPACK's banded solver
+    (scipy.linalg.solve_banded) line by line."""
+    from scipy.linalg import solve_banded
+    p = W.make_problem((5, 4, 11), (1.0, 1.0, 2.0), (W.DD, W.NN, ("N", "D")), kind="helmholtz",
+                       alpha=0.3, implicit="z")
+    f = W.rhs(p, 5)
+    x = O.solve(p, f)
+    az, bz, cz, _ = O.operator_1d(p.faces[2], p.bc[2], p.loc[2])
+    ab = np.zeros((3, len(bz)))
+    ab[0, 1:] = -p.alpha * cz[:-1]
+    ab[1] = 1.0 - p.alpha * bz
+    ab[2, :-1] = -p.alpha * az[1:]
+    for j in range(p.shape[1]):
+        for i in range(p.shape[2]):
+            ref = solve_banded((1, 1), ab, f[:, j, i])
+            assert np.abs(x[:, j, i] - ref).max() <= 1e-14 * np.abs(ref).max()
+
+
+def test_yz_solve_does_not_couple_x():
+    """With x explicit, a right-hand side g(x) h(y, z) has the solution
+    g(x) times the solution for h: every x index is its own 2-D problem."""
+    p = W.make_problem((7, 6, 5), (1.5, 2.0, 1.0), (W.NN, W.DD, W.NN), kind="helmholtz", alpha=0.1,
+                       implicit="yz")
+    rng = np.random.default_rng(8)
+    g = rng.standard_normal(p.shape[2])
+    h = rng.standard_normal(p.shape[:2])
+    x = O.solve(p, h[:, :, None] * g[None, None, :])
+    xh = O.solve(p, np.repeat(h[:, :, None], p.shape[2], axis=2))[:, :, 0]
+    assert np.abs(x - xh[:, :, None] * g[None, None, :]).max() <= 1e-13 * np.abs(x).max()
+
+
+def _mk_yz_helm(n):
+    # u = g(x) sin(pi y) sin(pi z) with an arbitrary g: x is not differentiated,
+    # (I - a (d_yy + d_zz)) u = (1 + 2 a pi^2) u
+    alpha = 0.1
+    p = W.make_problem((n, n, n), (1.5, 1.0, 2.0), (W.NN, W.DD, W.DD), kind="helmholtz", alpha=alpha,
+                       implicit="yz")
+    xs = [W.centres(p.faces[d], p.bc[d], "C") for d in range(3)]
+    g = 1.0 + xs[0] ** 3 - np.cos(5 * xs[0])
+    u = np.sin(np.pi * xs[2])[:, None, None] * np.sin(np.pi * xs[1])[None, :, None] * g[None, None, :]
+    return p, (1 + 2 * alpha * np.pi ** 2) * u, u
+
+
+def _mk_z_helm(n):
+    # u = g(x, y) sin(pi z), (I - a d_zz) u = (1 + a pi^2) u
+    alpha = 0.1
+    p = W.make_problem((n, n, n), (1.5, 1.0, 2.0), (W.PP, W.NN, W.DD), kind="helmholtz", alpha=alpha,
+                       implicit="z")
+    xs = [W.centres(p.faces[d], p.bc[d], "C") for d in range(3)]
+    g = np.exp(xs[1])[:, None] * (2.0 + np.sin(2 * np.pi * xs[0]))[None, :]
+    u = np.sin(np.pi * xs[2])[:, None, None] * g[None, :, :]
+    return p, (1 + alpha * np.pi ** 2) * u, u
+
+
+@pytest.mark.parametrize("make", [_mk_yz_helm, _mk_z_helm], ids=["yz_helm", "z_helm"])
+def test_implicit_mms_second_order(make):
+    e = _mms_errors(make, [16, 32, 64])
+    order_l2 = np.log2(e[:-1, 0] / e[1:, 0])
+    order_max = np.log2(e[:-1, 1] / e[1:, 1])
+    assert order_l2[-1] >= 1.9, order_l2
+    assert order_max[-1] >= 1.75, order_max

@@ -67,7 +67,9 @@ def control_volumes(faces: np.ndarray, bc: BC, loc: str) -> np.ndarray:
 class Problem:
     """One constant-coefficient Poisson or Helmholtz problem on a stretched grid.
 
-    kind 'poisson': L phi = f.  kind 'helmholtz': (I - alpha L) u = f.
+    kind 'poisson': L phi = f.  kind 'helmholtz': (I - alpha L_I) u = f, with
+    L_I the Laplacian restricted to the directions treated implicitly:
+    implicit 'xyz' (L), 'yz' (L_y + L_z) or 'z' (L_z).
     """
 
     n: Tuple[int, int, int]
@@ -77,6 +79,7 @@ class Problem:
     kind: str = "poisson"
     alpha: float = 0.0
     name: str = ""
+    implicit: str = "xyz"
 
     @property
     def shape(self) -> Tuple[int, int, int]:
@@ -104,15 +107,19 @@ class Problem:
 
 
 def make_problem(n, beta, bc, loc=("C", "C", "C"), kind="poisson", alpha=0.0,
-                 length=(1.0, 1.0, 1.0), name="") -> Problem:
+                 length=(1.0, 1.0, 1.0), name="", implicit="xyz") -> Problem:
     """Build a Problem from per-direction cell counts and stretching; a
     periodic direction is always uniform."""
+    if implicit not in ("xyz", "yz", "z"):
+        raise ValueError(f"unknown implicit directions {implicit!r}")
+    if implicit != "xyz" and kind != "helmholtz":
+        raise ValueError("only a Helmholtz problem can leave directions explicit")
     faces = []
     for d in range(3):
         b = 0.0 if bc[d][0] == "P" else float(beta[d])
         faces.append(tanh_faces(int(n[d]), b, float(length[d])))
     return Problem(tuple(int(v) for v in n), tuple(faces), tuple(tuple(b) for b in bc),
-                   tuple(loc), kind, float(alpha), name)
+                   tuple(loc), kind, float(alpha), name, implicit)
 
 
 def project_compatible(p: Problem, f: np.ndarray) -> np.ndarray:
