@@ -63,6 +63,12 @@ enum { TPT_LOC_CENTER = 0, TPT_LOC_FACE = 1 };
 /* Poisson: L phi = f (Eq. poi_ns).  Helmholtz: (I - alpha L) u = f
  * (Eq. helmholtz_ns with alpha = gamma nu dt / 2, implicit in x, y and z). */
 enum { TPT_POISSON = 0, TPT_HELMHOLTZ = 1 };
+/* Directions a Helmholtz plan treats implicitly (§2.1: the implicit diffusion
+ * operator L_I holds all three directions, y and z, or z alone; §3: the same
+ * pipeline serves them, yz without the x transforms, z with the tridiagonal
+ * solve only): (I - alpha L_I) u = f.  Poisson plans are always XYZ; YZ and
+ * Z plans are FP64 only. */
+enum { TPT_IMPLICIT_XYZ = 0, TPT_IMPLICIT_YZ = 1, TPT_IMPLICIT_Z = 2 };
 /* Arithmetic of the transforms.  FP64: everything in double precision.
  * MIXED_FP32: transforms in FP32 MFMA; MIXED_BF16X3: transforms as three
  * BF16 MFMA products (hi*hi + hi*lo + lo*hi) with FP32 accumulation.  Both
@@ -100,7 +106,8 @@ enum {
     TPT_XFORM_GEMM = 0,     /* dense eigenbasis product (MFMA GEMM) */
     TPT_XFORM_FFT = 1,      /* uniform periodic: real Fourier transform */
     TPT_XFORM_DCT = 2,      /* uniform Neumann-Neumann, cell centres: DCT-II */
-    TPT_XFORM_DST = 3       /* uniform Dirichlet-Dirichlet, cell centres: DST-II */
+    TPT_XFORM_DST = 3,      /* uniform Dirichlet-Dirichlet, cell centres: DST-II */
+    TPT_XFORM_NONE = 4      /* not transformed: the direction is explicit (TPT_IMPLICIT_*) */
 };
 
 typedef struct tpt_plan_s *tpt_plan;
@@ -130,6 +137,7 @@ typedef struct {
                                -1 = adaptive, which synchronises the stream once per correction */
     int nrhs;               /* right-hand sides per solve call (>= 1), stored back to back */
     int flags;              /* TPT_FLAG_* */
+    int implicit;           /* TPT_IMPLICIT_* (Helmholtz; default XYZ) */
 } tpt_plan_desc;
 
 /* Result of the last solve of a plan (valid after the stream has been
@@ -178,7 +186,8 @@ int tpt_plan_eigen(tpt_plan plan, int dir, double *lam, double *Qt);
  * periodic direction a[0] and c[N-1] are the cyclic corners). */
 int tpt_plan_operator(tpt_plan plan, int dir, double *a, double *b, double *c, double *vol);
 
-/* kinds[0], kinds[1]: TPT_XFORM_* used for x and y.  A direction gets a fast
+/* kinds[0], kinds[1]: TPT_XFORM_* used for x and y (NONE where the plan
+ * leaves the direction explicit).  A direction gets a fast
  * transform (§3: a uniform direction may use FFT-based transforms) when its
  * analytic basis is one of the three listed, its unknown count is a power of
  * two in 8..2048, and its TPT_FLAG_DENSE_* flag is not set; otherwise GEMM. */

@@ -26,6 +26,7 @@ PRECISIONS = {"fp64": FP64, "fp32": MIXED_FP32, "bf16x3": MIXED_BF16X3}
 _BC = {"P": 0, "N": 1, "D": 2}
 _LOC = {"C": 0, "F": 1}
 _KIND = {"poisson": 0, "helmholtz": 1}
+_IMPLICIT = {"xyz": 0, "yz": 1, "z": 2}
 OK, PENDING = 0, 1
 
 
@@ -49,6 +50,7 @@ class _Desc(ctypes.Structure):
         ("fixed_refine", ctypes.c_int),
         ("nrhs", ctypes.c_int),
         ("flags", ctypes.c_int),
+        ("implicit", ctypes.c_int),
     ]
 
 
@@ -164,7 +166,8 @@ class Plan:
 
     n: cells (nx, ny, nz); faces: three arrays of n+1 face coordinates;
     bc: three (lower, upper) pairs; loc: three of 'C'/'F'; kind 'poisson' or
-    'helmholtz' with alpha; precision 'fp64', 'fp32' or 'bf16x3';
+    'helmholtz' with alpha; implicit 'xyz', 'yz' or 'z' (Helmholtz: the
+    directions in the implicit operator); precision 'fp64', 'fp32' or 'bf16x3';
     fixed_refine >= 0 runs that many corrections without host synchronisation;
     dense_x / dense_y force the dense GEMM for a direction where a fast
     transform (FFT, DCT-II, DST-II of a uniform direction) would apply;
@@ -177,7 +180,7 @@ class Plan:
 
     def __init__(self, n, faces, bc, loc=("C", "C", "C"), kind="poisson", alpha=0.0, precision="fp64",
                  rtol=1e-12, max_refine=8, fixed_refine=-1, nrhs=1, host_only=False, dense_x=False,
-                 dense_y=False, fuse_xy=False, seq_thomas=False, check=True):
+                 dense_y=False, fuse_xy=False, seq_thomas=False, check=True, implicit="xyz"):
         L = lib()
         d = _Desc()
         L.tpt_plan_desc_init(ctypes.byref(d))
@@ -195,6 +198,7 @@ class Plan:
         d.max_refine = int(max_refine)
         d.fixed_refine = int(fixed_refine)
         d.nrhs = int(nrhs)
+        d.implicit = _IMPLICIT[implicit]
         d.flags = ((1 if host_only else 0) | (2 if dense_x else 0) | (4 if dense_y else 0)
                    | (8 if fuse_xy else 0) | (16 if seq_thomas else 0) | (0 if check else 32))
         h = ctypes.c_void_p()
@@ -209,7 +213,9 @@ class Plan:
 
     @classmethod
     def from_problem(cls, p, **kw):
-        """Plan for an object with n, faces, bc, loc, kind, alpha attributes."""
+        """Plan for an object with n, faces, bc, loc, kind, alpha (and
+        optionally implicit) attributes."""
+        kw.setdefault("implicit", getattr(p, "implicit", "xyz"))
         return cls(p.n, p.faces, p.bc, p.loc, p.kind, p.alpha, **kw)
 
     @property
@@ -228,10 +234,11 @@ class Plan:
 
     @property
     def transforms(self):
-        """How x and y are transformed: each of 'gemm', 'fft', 'dct', 'dst'."""
+        """How x and y are transformed: each of 'gemm', 'fft', 'dct', 'dst',
+        or 'none' for a direction the plan leaves explicit."""
         v = (ctypes.c_int * 2)()
         _check(lib().tpt_plan_transforms(self._h, v))
-        names = ("gemm", "fft", "dct", "dst")
+        names = ("gemm", "fft", "dct", "dst", "none")
         return names[v[0]], names[v[1]]
 
     @property
@@ -245,7 +252,7 @@ class Plan:
     @property
     def x_fft(self) -> bool:
         """True if the x eigenbasis is applied by a fast transform."""
-        return self.transforms[0] != "gemm"
+        return self.transforms[0] not in ("gemm", "none")
 
     def workspace_bytes(self) -> int:
         b = ctypes.c_size_t()

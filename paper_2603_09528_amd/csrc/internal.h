@@ -64,6 +64,7 @@ struct PlanBuffers {  // per-plan small device arrays
     double* az = nullptr; double* bz = nullptr; double* cz = nullptr;
     double* vx = nullptr; double* vy = nullptr; double* vz = nullptr;  // control volumes
     double* vyz = nullptr;       // vy_j vz_k at j + Ny k
+    double* zeros = nullptr;     // max(Nx, Ny) zeros: the shift of an explicit direction
     double* norms = nullptr;     // device sums, TPT_STATS doubles per rhs (StatSlot)
     void* block = nullptr;
 };
@@ -102,6 +103,7 @@ struct tpt_plan_s {
     int fast[2] = {-1, -1};          // x, y: XformKind of the fast transform, -1 = GEMM
     bool fuse_xy = false;            // FP64: x transform fused into the y GEMM's loads
     bool seq_thomas = false;         // z lines by the sequential Thomas kernel
+    bool tx = true, ty = true;       // x / y transformed (implicit in the operator)
     ~tpt_plan_s();
 };
 

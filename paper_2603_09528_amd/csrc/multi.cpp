@@ -128,19 +128,25 @@ int MultiExec::build(const double* const* rhs, double* const* out, void* ws) {
     std::vector<CheckDesc> chk(n);
     std::vector<char> fused(n, 0);
     std::vector<CheckDesc> fused_list;
-    // per stage: which problems take the fast transform, which the GEMM
+    // per stage: which problems apply it (a direction the plan leaves
+    // explicit has no transform), and of those which take the fast
+    // transform, which the GEMM
+    auto applies = [&](int i, int stage) {
+        return (stage == ST_XF || stage == ST_XI) ? plans_[i]->tx : plans_[i]->ty;
+    };
     auto fast_mask = [&](int stage, bool fast) {
         std::vector<char> m(n);
-        for (int i = 0; i < n; ++i) m[i] = stage_is_fast(plans_[i], stage) == fast ? 1 : 0;
+        for (int i = 0; i < n; ++i) m[i] = applies(i, stage) && stage_is_fast(plans_[i], stage) == fast ? 1 : 0;
         return m;
     };
-    // one transform stage of every problem: GEMM launches grouped by tile
-    // variant, fast-transform launches grouped by line length
+    // one transform stage of every problem that applies it: GEMM launches
+    // grouped by tile variant, fast-transform launches grouped by line length
     auto stage = [&](int st, const std::vector<const void*>& in, int tin, const std::vector<void*>& outp, int tout,
                      int epi, std::vector<long long>* nb, bool with_check = false) {
         std::vector<GemmDesc> g(n);
         std::vector<FftDesc> f(n);
         for (int i = 0; i < n; ++i) {
+            if (!applies(i, st)) continue;
             double* part = epi == EPI_ACCUM_F64 ? w[i].partials : nullptr;
             if (stage_is_fast(plans_[i], st)) {
                 f[i] = stage_fft(plans_[i], st, in[i], tin, outp[i], tout, epi, part, 1);
@@ -167,10 +173,15 @@ int MultiExec::build(const double* const* rhs, double* const* out, void* ws) {
     }
     // one application of M^{-1}; returns the x-inverse block count of every
     // problem (the number of norm partials it wrote)
+    // Data flow of one problem: rhs (or residual) -> [x fwd -> w1] -> [y fwd
+    // -> w2] -> Thomas -> [y inv] -> [x inv] -> out, the bracketed stages only
+    // for transformed directions (plans with an explicit direction are FP64,
+    // where every buffer has one type).
     auto minv = [&](bool from_rhs, int epi) {
         const int tmid = mixed_ ? DT_F32 : DT_F64;
         std::vector<long long> nb(n);
-        stage(ST_XF, from_rhs ? rhsv : resv, from_rhs ? DT_F64 : DT_F32, w1, tmid, EPI_STORE, nullptr, from_rhs);
+        std::vector<const void*> src(from_rhs ? rhsv : resv);
+        stage(ST_XF, src, from_rhs ? DT_F64 : DT_F32, w1, tmid, EPI_STORE, nullptr, from_rhs);
         if (from_rhs && !fused_list.empty()) {
             Launch L{};
             L.kind = 7;
@@ -178,14 +189,18 @@ int MultiExec::build(const double* const* rhs, double* const* out, void* ws) {
             L.nwork = (int)fused_list.size();
             seq_.push_back(L);
         }
-        stage(ST_YF, w1c, tmid, w2, tmid, EPI_STORE, nullptr);
+        for (int i = 0; i < n; ++i)
+            if (plans_[i]->tx) src[i] = w1c[i];
+        stage(ST_YF, src, tmid, w2, tmid, EPI_STORE, nullptr);
         // one launch per Thomas kernel: each problem runs the variant its
         // single-problem solve runs, so batch and single results agree bit
-        // for bit
+        // for bit; a z-only problem solves straight from rhs into out
         std::vector<ThomasDesc> all(n);
         std::vector<int> var(n);
         for (int i = 0; i < n; ++i) {
-            all[i] = plan_thomas(plans_[i], w[i].w2, tmid, w[i].w2, tmid, w[i].scratch, 1);
+            const bool zonly = !plans_[i]->ty;
+            all[i] = plan_thomas(plans_[i], zonly ? src[i] : w[i].w2, tmid, zonly ? outv[i] : w[i].w2, tmid,
+                                 w[i].scratch, 1);
             var[i] = thomas_variant(all[i]);
         }
         std::vector<int> kinds(var);
@@ -212,7 +227,10 @@ int MultiExec::build(const double* const* rhs, double* const* out, void* ws) {
             L.prec = tmid;
             seq_.push_back(L);
         }
-        stage(ST_YI, w2c, tmid, w1, tmid, EPI_STORE, nullptr);
+        std::vector<void*> yout(w1);
+        for (int i = 0; i < n; ++i)
+            if (!plans_[i]->tx) yout[i] = outv[i];
+        stage(ST_YI, w2c, tmid, yout, tmid, EPI_STORE, nullptr);
         stage(ST_XI, w1c, tmid, outv, DT_F64, epi, &nb);
         return nb;
     };
@@ -534,6 +552,7 @@ int tpt_autotune(int count, const tpt_plan* plans, void* stream) {
         (void)hipMemsetD32Async((hipDeviceptr_t)in, 0x3FF80000u, bytes / 4, s);
         for (int stage : {ST_XF, ST_YF}) {
             if (stage_is_fast(p, stage)) continue;  // no GEMM in this pass
+            if (stage == ST_XF ? !p->tx : !p->ty) continue;  // explicit direction
             const int dt = prec == GP_F64 ? DT_F64 : DT_F32;
             GemmDesc g = stage_gemm(p, stage, prec, in, dt, outb, dt, EPI_STORE, nullptr, 1);
             const int kind = stage == ST_XF ? 0 : 1;

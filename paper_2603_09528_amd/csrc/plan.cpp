@@ -273,6 +273,12 @@ int tpt_plan_create(const tpt_plan_desc* desc, tpt_plan* out) {
         return fail(TPT_ERR_INVALID, "Helmholtz needs alpha > 0");
     if (desc->precision < TPT_FP64 || desc->precision > TPT_MIXED_BF16X3)
         return fail(TPT_ERR_INVALID, "unknown precision");
+    if (desc->implicit < TPT_IMPLICIT_XYZ || desc->implicit > TPT_IMPLICIT_Z)
+        return fail(TPT_ERR_INVALID, "unknown implicit directions");
+    if (desc->implicit != TPT_IMPLICIT_XYZ && desc->kind != TPT_HELMHOLTZ)
+        return fail(TPT_ERR_INVALID, "only a Helmholtz plan can leave directions explicit");
+    if (desc->implicit != TPT_IMPLICIT_XYZ && desc->precision != TPT_FP64)
+        return fail(TPT_ERR_UNSUPPORTED, "yz and z implicit plans are FP64 only");
     for (int d = 0; d < 3; ++d) {
         if (desc->n[d] < 2) return fail(TPT_ERR_INVALID, "need at least 2 cells per direction");
         if (!desc->faces[d]) return fail(TPT_ERR_INVALID, "faces pointer is NULL");
@@ -284,6 +290,8 @@ int tpt_plan_create(const tpt_plan_desc* desc, tpt_plan* out) {
     p->host_only = (desc->flags & TPT_FLAG_HOST_ONLY) != 0;
     p->seq_thomas = (desc->flags & TPT_FLAG_SEQ_THOMAS) != 0;
     p->check = (desc->flags & TPT_FLAG_NO_CHECK) == 0;
+    p->tx = desc->implicit == TPT_IMPLICIT_XYZ;
+    p->ty = desc->implicit != TPT_IMPLICIT_Z;
     if (!p->host_only && hipGetDevice(&p->device) != hipSuccess)
         return fail(TPT_ERR_HIP, "no HIP device");
     for (int d = 0; d < 3; ++d) {
@@ -326,7 +334,7 @@ int tpt_plan_create(const tpt_plan_desc* desc, tpt_plan* out) {
         if (p->by->fast_kind >= 0 && !(desc->flags & TPT_FLAG_DENSE_Y)) p->fast[1] = p->by->fast_kind;
         // one pass for the x transform and the y GEMM (FP64; x rows of 128 or
         // 256 points, whole 128-row tiles of y)
-        p->fuse_xy = desc->precision == TPT_FP64 && (desc->flags & TPT_FLAG_FUSE_XY) && p->fast[0] >= 0 &&
+        p->fuse_xy = p->tx && p->ty && desc->precision == TPT_FP64 && (desc->flags & TPT_FLAG_FUSE_XY) && p->fast[0] >= 0 &&
                      p->fast[1] < 0 && (p->N[0] == 128 || p->N[0] == 256) && p->N[1] % 128 == 0;
     }
     p->info.rel_residual = -1.0;
@@ -335,7 +343,7 @@ int tpt_plan_create(const tpt_plan_desc* desc, tpt_plan* out) {
     if (!p->host_only) {
         const size_t nx = p->N[0], ny = p->N[1], nz = p->N[2];
         const size_t nstat = (size_t)TPT_STATS * p->desc.nrhs;
-        const size_t doubles = 4 * (nx + ny + nz) + ny * nz + nstat + 64;
+        const size_t doubles = 4 * (nx + ny + nz) + ny * nz + std::max(nx, ny) + nstat + 64;
         void* blk = nullptr;
         if (hipMalloc(&blk, doubles * 8) != hipSuccess) {
             (void)hipGetLastError();
@@ -354,6 +362,7 @@ int tpt_plan_create(const tpt_plan_desc* desc, tpt_plan* out) {
         put(p->op[0].vol); put(p->op[1].vol); put(p->op[2].vol);
         for (size_t k = 0; k < nz; ++k)
             for (size_t j = 0; j < ny; ++j) *w++ = p->op[1].vol[j] * p->op[2].vol[k];
+        w += std::max(nx, ny);  // zeros
         TPT_HIP(hipMemcpy(blk, h.data(), doubles * 8, hipMemcpyHostToDevice));
         double* d = (double*)blk;
         p->buf.ax = d; d += nx; p->buf.bx = d; d += nx; p->buf.cx = d; d += nx;
@@ -361,6 +370,7 @@ int tpt_plan_create(const tpt_plan_desc* desc, tpt_plan* out) {
         p->buf.az = d; d += nz; p->buf.bz = d; d += nz; p->buf.cz = d; d += nz;
         p->buf.vx = d; d += nx; p->buf.vy = d; d += ny; p->buf.vz = d; d += nz;
         p->buf.vyz = d; d += ny * nz;
+        p->buf.zeros = d; d += std::max(nx, ny);
         p->buf.norms = d;
         if (hipHostMalloc((void**)&p->h_norms, (nstat + 8) * sizeof(double), hipHostMallocDefault) != hipSuccess) {
             p->h_norms = nullptr;
@@ -410,6 +420,8 @@ int tpt_plan_operator(tpt_plan p, int dir, double* a, double* b, double* c, doub
 int tpt_plan_transforms(tpt_plan p, int kinds[2]) {
     if (!p || !kinds) return fail(TPT_ERR_INVALID, "NULL argument");
     for (int d = 0; d < 2; ++d) kinds[d] = p->fast[d] < 0 ? TPT_XFORM_GEMM : TPT_XFORM_FFT + p->fast[d];
+    if (!p->tx) kinds[0] = TPT_XFORM_NONE;
+    if (!p->ty) kinds[1] = TPT_XFORM_NONE;
     return TPT_OK;
 }
 

@@ -235,8 +235,9 @@ ThomasDesc plan_thomas(const tpt_plan_s* p, const void* f, int tf, void* x, int 
     t.ny = p->N[1];
     t.nz = p->N[2];
     t.nsys = nrhs;
-    t.lamx = p->bx->d_lam;
-    t.lamy = p->by->d_lam;
+    // an explicit direction adds no eigenvalue to the line shift
+    t.lamx = p->tx ? p->bx->d_lam : p->buf.zeros;
+    t.lamy = p->ty ? p->by->d_lam : p->buf.zeros;
     t.az = p->buf.az;
     t.bz = p->buf.bz;
     t.cz = p->buf.cz;
@@ -373,7 +374,7 @@ CheckDesc check_desc(const tpt_plan_s* p, const double* rhs, double* partials) {
 // Whether the check rides in the loads of the x forward pass: x by fast
 // transform on FP64 input, and no block of x lines spans two right-hand sides.
 bool check_fused(const tpt_plan_s* p) {
-    if (!p->run_check || !stage_is_fast(p, ST_XF) || p->fuse_xy) return false;
+    if (!p->run_check || !p->tx || !stage_is_fast(p, ST_XF) || p->fuse_xy) return false;
     const long long rows = (long long)p->N[1] * p->N[2];
     return rows * p->desc.nrhs < 0xffffffffLL && rows % fft_lines_per_block(p->N[0]) == 0;
 }
@@ -494,6 +495,16 @@ static int solve_fp64(tpt_plan_s* p, const double* rhs, double* out, const Ws& w
     int rc;
     if ((rc = run_check(p, rhs, w.partials, s))) return rc;
     p->info_on_device = p->check;
+    p->info.iters = 0;
+    p->info.rel_correction = 0.0;
+    p->info.rel_residual = -1.0;
+    if (!p->tx) {
+        // x explicit: y forward, Thomas, y inverse (yz); Thomas alone (z)
+        if (!p->ty) return run_thomas(p, rhs, DT_F64, out, DT_F64, w.scratch, R, s);
+        if ((rc = run_stage(p, ST_YF, GP_F64, rhs, DT_F64, w.w2, DT_F64, EPI_STORE, nullptr, R, s))) return rc;
+        if ((rc = run_thomas(p, w.w2, DT_F64, w.w2, DT_F64, w.scratch, R, s))) return rc;
+        return run_stage(p, ST_YI, GP_F64, w.w2, DT_F64, out, DT_F64, EPI_STORE, nullptr, R, s);
+    }
     if (p->fuse_xy && (rc = run_fused(p, false, rhs, (double*)w.w2, R, s)) <= 0) {
         if (rc) return rc;
         if ((rc = run_thomas(p, w.w2, DT_F64, w.w2, DT_F64, w.scratch, R, s))) return rc;
