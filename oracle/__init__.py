@@ -20,7 +20,9 @@ Plain, slow, obviously-correct FP64 implementations:
   (Eq. inverse-xy); the gauge of §3 (vanishing final pivot -> modal unknown 0);
 * ``dense``     - the plain definition x = A^{-1} f by dense LU of the
   assembled operator (bordered by the volume-weighted mean for singular
-  problems), for grids of at most a few thousand unknowns.
+  problems), for grids of at most a few thousand unknowns;
+* ``projection`` - the staggered divergence and gradient of §2.1 and the
+  projection step u = u* - G phi with L phi = D u*.
 
 Every function is pinned by ``tests/test_oracle_*.py`` against values the
 paper prints, closed forms, library routines and brute force.
@@ -29,3 +31,4 @@ from .operator import operator_1d, dense_1d, apply_operator, residual, assemble_
 from .eig import eig_direction, jacobi_eigh  # noqa: F401
 from .solver import solve, thomas_lines, relative_error, gauge_normalise  # noqa: F401
 from .dense import solve_dense  # noqa: F401
+from . import projection  # noqa: F401

@@ -252,3 +252,29 @@ def serving_families(seed: int = 5, sizes: Sequence[int] = SERVING_SIZES):
         bcz = Z_BCS[int(rng.integers(len(Z_BCS)))]
         fam.append(make_problem((s, s, s), (beta, beta, beta), (bcx, bcy, bcz), name=f"family{s}"))
     return fam
+
+
+# ---------------------------------------------------------------------------
+# Projection step inputs: velocity components on the faces of a pressure grid.
+# ---------------------------------------------------------------------------
+
+def velocity_shapes(p: Problem):
+    """Shapes of u, v, w on the faces of the cell-centred pressure problem p:
+    a direction carries N face unknowns if periodic (face m between cells m
+    and m+1, the last wrapping) or N - 1 between walls (interior faces)."""
+    nz, ny, nx = p.shape
+    nf = [n if p.bc[d][0] == "P" else n - 1 for d, n in enumerate((nx, ny, nz))]
+    return (nz, ny, nf[0]), (nz, nf[1], nx), (nf[2], ny, nx)
+
+
+def white_noise_velocity(p: Problem, seed: int):
+    """Seeded N(0, 1) values on every face unknown (a white-noise velocity
+    field, as in the divergence test of §4.1)."""
+    rng = np.random.default_rng(seed)
+    return tuple(np.ascontiguousarray(rng.standard_normal(s)) for s in velocity_shapes(p))
+
+
+def channel_pressure(n=(64, 48, 40), beta=2.0) -> Problem:
+    """Pressure grid of a channel: x periodic uniform, walls in y and z
+    (pressure Neumann), tanh-stretched."""
+    return make_problem(n, (0.0, beta, beta), (PP, NN, NN), name=f"channel_p_{n[0]}x{n[1]}x{n[2]}")
