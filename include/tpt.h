@@ -230,6 +230,37 @@ int tpt_solve_info(tpt_plan plan, tpt_info *info);
 int tpt_solve_noalloc(tpt_plan plan, const double *rhs, double *out, void *stream);
 size_t tpt_static_workspace_capacity(void);
 
+/* ---- projection step (§2.1 staggered grid; §4.1 divergence test) ---------- */
+
+/* The plan must be the cell-centred pressure Poisson problem of the grid
+ * (every loc TPT_LOC_CENTER, nrhs 1) with periodic or Neumann boundaries; a
+ * Neumann direction is bounded by walls with no penetration.  Velocity
+ * components live on the faces normal to them (§2.1), x fastest:
+ * u (Nz, Ny, Nux), v (Nz, Nvy, Nx), w (Nwz, Ny, Nx), with N face unknowns
+ * in a periodic direction (face m between cells m and m+1, the last one
+ * wrapping to cell 0) and N - 1 between walls (the interior faces; the wall
+ * faces carry zero normal velocity and are not stored).  Device FP64
+ * arrays; stream-ordered; TPT_ERR_INVALID for another kind of plan. */
+
+/* div = D(u, v, w): the net flux out of each cell over its volume,
+ * (u_{i+1/2} - u_{i-1/2}) / dx_i + (same in y and z), dx_i the cell width
+ * (the finite-volume divergence whose composition with the gradient below
+ * is the operator of Eq. poisson-fd2).  div: (Nz, Ny, Nx). */
+int tpt_divergence(tpt_plan plan, const double *u, const double *v, const double *w, double *div,
+                   void *stream);
+/* (u, v, w) -= G phi in place: on the face between cells m and m+1,
+ * (phi_{m+1} - phi_m) / dx_{m+1/2}, dx_{m+1/2} the distance of the two cell
+ * centres.  phi: (Nz, Ny, Nx). */
+int tpt_gradient_update(tpt_plan plan, const double *phi, double *u, double *v, double *w, void *stream);
+/* The projection: solve L phi = D u* with the plan (§3 gauge), then
+ * u = u* - G phi, so that D u = 0 up to rounding (and, in the mixed modes,
+ * the refinement tolerance).  u, v, w are updated in place; phi receives the
+ * pressure correction.  workspace: device memory of at least
+ * tpt_project_workspace_bytes (the divergence and the solve's workspace). */
+int tpt_project_workspace_bytes(tpt_plan plan, size_t *bytes);
+int tpt_project(tpt_plan plan, double *u, double *v, double *w, double *phi, void *workspace,
+                size_t workspace_bytes, void *stream);
+
 /* ---- multi-problem batches (independent problems, uneven sizes) ---------- */
 
 /* Group `count` plans (any sizes, same precision) into a batch whose solve

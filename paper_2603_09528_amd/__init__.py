@@ -94,6 +94,10 @@ def lib():
             "tpt_solve_info": (i, [vp, ctypes.POINTER(Info)]),
             "tpt_solve_noalloc": (i, [vp, vp, vp, vp]),
             "tpt_static_workspace_capacity": (sz, []),
+            "tpt_divergence": (i, [vp, vp, vp, vp, vp, vp]),
+            "tpt_gradient_update": (i, [vp, vp, vp, vp, vp, vp]),
+            "tpt_project_workspace_bytes": (i, [vp, ctypes.POINTER(sz)]),
+            "tpt_project": (i, [vp, vp, vp, vp, vp, vp, sz, vp]),
             "tpt_batch_create": (i, [i, ctypes.POINTER(vp), ctypes.POINTER(vp)]),
             "tpt_batch_destroy": (i, [vp]),
             "tpt_batch_workspace_bytes": (i, [vp, ctypes.POINTER(sz)]),
@@ -126,7 +130,8 @@ def lib():
 
 EXPORTED = ("tpt_plan_desc_init", "tpt_plan_create", "tpt_plan_destroy", "tpt_plan_shape",
             "tpt_plan_workspace_bytes", "tpt_plan_eigen", "tpt_plan_operator", "tpt_plan_transforms", "tpt_plan_fused", "tpt_solve",
-            "tpt_solve_info", "tpt_solve_noalloc", "tpt_static_workspace_capacity", "tpt_batch_create", "tpt_batch_destroy", "tpt_batch_workspace_bytes",
+            "tpt_solve_info", "tpt_solve_noalloc", "tpt_static_workspace_capacity", "tpt_divergence", "tpt_gradient_update",
+            "tpt_project_workspace_bytes", "tpt_project", "tpt_batch_create", "tpt_batch_destroy", "tpt_batch_workspace_bytes",
             "tpt_batch_solve", "tpt_batch_info", "tpt_autotune", "tpt_autotune_save", "tpt_autotune_load",
             "tpt_server_create", "tpt_server_submit", "tpt_server_poll", "tpt_server_drain",
             "tpt_server_destroy", "tpt_thomas", "tpt_gemm", "tpt_timing_enable", "tpt_timing_collect",
@@ -204,6 +209,7 @@ class Plan:
         h = ctypes.c_void_p()
         _check(L.tpt_plan_create(ctypes.byref(d), ctypes.byref(h)))
         self._h = h
+        self._bc = tuple(tuple(b) for b in bc)
         self.nrhs = int(nrhs)
         self.precision = precision
         s = (ctypes.c_int * 3)()
@@ -305,6 +311,49 @@ class Plan:
         inf = Info()
         _check(lib().tpt_solve_info(self._h, ctypes.byref(inf)))
         return inf
+
+    # ---- projection step (pressure plans: cell-centred, periodic / Neumann) ----
+    def velocity_shapes(self):
+        """Shapes of u, v, w on the faces of this pressure grid."""
+        nx, ny, nz = self.nxyz
+        b = self._bc
+        nf = [n if b[d][0] == "P" else n - 1 for d, n in enumerate((nx, ny, nz))]
+        return (nz, ny, nf[0]), (nz, nf[1], nx), (nf[2], ny, nx)
+
+    def _check_velocity(self, u, v, w):
+        for t, s, name in zip((u, v, w), self.velocity_shapes(), "uvw"):
+            _require_f64_cuda(t, s, name)
+
+    def divergence(self, u, v, w, out=None, stream=None):
+        import torch
+        self._check_velocity(u, v, w)
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float64, device="cuda")
+        _require_f64_cuda(out, self.shape, "div")
+        _check(lib().tpt_divergence(self._h, _ptr(u), _ptr(v), _ptr(w), _ptr(out), _stream(stream)))
+        return out
+
+    def gradient_update(self, phi, u, v, w, stream=None):
+        """(u, v, w) -= G phi in place."""
+        self._check_velocity(u, v, w)
+        _require_f64_cuda(phi, self.shape, "phi")
+        _check(lib().tpt_gradient_update(self._h, _ptr(phi), _ptr(u), _ptr(v), _ptr(w), _stream(stream)))
+
+    def project(self, u, v, w, phi=None, workspace=None, stream=None):
+        """Project (u, v, w) in place onto the divergence-free fields;
+        returns the pressure correction phi."""
+        import torch
+        self._check_velocity(u, v, w)
+        if phi is None:
+            phi = torch.empty(self.shape, dtype=torch.float64, device="cuda")
+        _require_f64_cuda(phi, self.shape, "phi")
+        if workspace is None:
+            b = ctypes.c_size_t()
+            _check(lib().tpt_project_workspace_bytes(self._h, ctypes.byref(b)))
+            workspace = torch.empty(b.value, dtype=torch.uint8, device="cuda")
+        _check(lib().tpt_project(self._h, _ptr(u), _ptr(v), _ptr(w), _ptr(phi), _ptr(workspace),
+                                 workspace.numel(), _stream(stream)))
+        return phi
 
     def __del__(self):
         h = getattr(self, "_h", None)

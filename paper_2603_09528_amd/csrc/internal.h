@@ -65,6 +65,10 @@ struct PlanBuffers {  // per-plan small device arrays
     double* vx = nullptr; double* vy = nullptr; double* vz = nullptr;  // control volumes
     double* vyz = nullptr;       // vy_j vz_k at j + Ny k
     double* zeros = nullptr;     // max(Nx, Ny) zeros: the shift of an explicit direction
+    // distance between the centres of cells m and m+1 (the last one wrapped
+    // for a periodic direction), N per direction: the face spacing of the
+    // projection's gradient
+    double* dcx = nullptr; double* dcy = nullptr; double* dcz = nullptr;
     double* norms = nullptr;     // device sums, TPT_STATS doubles per rhs (StatSlot)
     void* block = nullptr;
 };

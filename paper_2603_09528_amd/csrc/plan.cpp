@@ -343,7 +343,7 @@ int tpt_plan_create(const tpt_plan_desc* desc, tpt_plan* out) {
     if (!p->host_only) {
         const size_t nx = p->N[0], ny = p->N[1], nz = p->N[2];
         const size_t nstat = (size_t)TPT_STATS * p->desc.nrhs;
-        const size_t doubles = 4 * (nx + ny + nz) + ny * nz + std::max(nx, ny) + nstat + 64;
+        const size_t doubles = 5 * (nx + ny + nz) + ny * nz + std::max(nx, ny) + nstat + 64;
         void* blk = nullptr;
         if (hipMalloc(&blk, doubles * 8) != hipSuccess) {
             (void)hipGetLastError();
@@ -363,6 +363,17 @@ int tpt_plan_create(const tpt_plan_desc* desc, tpt_plan* out) {
         for (size_t k = 0; k < nz; ++k)
             for (size_t j = 0; j < ny; ++j) *w++ = p->op[1].vol[j] * p->op[2].vol[k];
         w += std::max(nx, ny);  // zeros
+        for (int d = 0; d < 3; ++d) {
+            // centre distances, half the sum of the two cell widths (as the
+            // operator's couplings use them, so that D G is its Laplacian)
+            const std::vector<double>& fc = p->faces[d];
+            const size_t nc = fc.size() - 1, n = p->N[d];
+            for (size_t m = 0; m < n; ++m) {
+                const double wm = fc[m + 1] - fc[m];
+                const double wn = m + 1 < nc ? fc[m + 2] - fc[m + 1] : fc[1] - fc[0];
+                *w++ = 0.5 * (wm + wn);
+            }
+        }
         TPT_HIP(hipMemcpy(blk, h.data(), doubles * 8, hipMemcpyHostToDevice));
         double* d = (double*)blk;
         p->buf.ax = d; d += nx; p->buf.bx = d; d += nx; p->buf.cx = d; d += nx;
@@ -371,6 +382,7 @@ int tpt_plan_create(const tpt_plan_desc* desc, tpt_plan* out) {
         p->buf.vx = d; d += nx; p->buf.vy = d; d += ny; p->buf.vz = d; d += nz;
         p->buf.vyz = d; d += ny * nz;
         p->buf.zeros = d; d += std::max(nx, ny);
+        p->buf.dcx = d; d += nx; p->buf.dcy = d; d += ny; p->buf.dcz = d; d += nz;
         p->buf.norms = d;
         if (hipHostMalloc((void**)&p->h_norms, (nstat + 8) * sizeof(double), hipHostMallocDefault) != hipSuccess) {
             p->h_norms = nullptr;
