@@ -24,4 +24,22 @@ hipError_t launch_gemm_f32(const GemmDesc& g, const GemmDesc* d_work, int nwork,
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_gemm_worklist_f32(const GemmDesc& g, const GemmDesc* d_work, int nwork, long long tiles,
+                                    hipStream_t s) {
+    if (g.b_nk) {
+        if (g.tA == DT_F64 && g.tC == DT_F32 && g.epi == EPI_STORE)
+            return launch_worklist_typed<GP_F32, double, float, float, EPI_STORE, true>(d_work, nwork, tiles, s);
+        if (g.tA == DT_F32 && g.tC == DT_F32 && g.epi == EPI_STORE)
+            return launch_worklist_typed<GP_F32, float, float, float, EPI_STORE, true>(d_work, nwork, tiles, s);
+        if (g.tA == DT_F32 && g.tC == DT_F64 && g.epi == EPI_STORE)
+            return launch_worklist_typed<GP_F32, float, float, double, EPI_STORE, true>(d_work, nwork, tiles, s);
+        if (g.tA == DT_F32 && g.tC == DT_F64 && g.epi == EPI_ACCUM_F64)
+            return launch_worklist_typed<GP_F32, float, float, double, EPI_ACCUM_F64, true>(d_work, nwork, tiles, s);
+        return hipErrorInvalidValue;
+    }
+    if (g.tB == DT_F32 && g.tC == DT_F32 && g.epi == EPI_STORE)
+        return launch_worklist_typed<GP_F32, float, float, float, EPI_STORE, false>(d_work, nwork, tiles, s);
+    return hipErrorInvalidValue;
+}
+
 }  // namespace tpt

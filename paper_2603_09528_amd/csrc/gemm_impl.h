@@ -437,6 +437,255 @@ __device__ __forceinline__ void gemm_tiles_persist_f(const GemmDesc& g, long lon
 }
 
 // ---------------------------------------------------------------------------
+// Work-list form of the FP64/FP32 tile for many uneven problems (batches,
+// serving): a persistent grid walks the tiles of every problem of the list
+// (tile v = blockIdx.x, + gridDim.x, ...; its problem by binary search on
+// block_begin) and, as the single-problem persistent tile does, loads and
+// stages the first K tile of its next tile during the last K step of the
+// current one, so a short K loop (K = 48..192 in the batches) does not pay a
+// load latency and a store phase per tile.  Uneven shapes are handled without
+// per-element predicates on the loads: operands are read through buffer
+// resources whose range ends at the problem's data, so rows past M (x pass)
+// or columns past the last slab (y pass) read zero, and only the last K step
+// of a K that is not a multiple of 16 masks the elements past K (in both
+// operands, so that no stray value meets a zero).
+//
+// Tile shapes follow the problems: the x pass (M = Ny Nz rows, N = K = Nx)
+// takes 128 x 64 tiles; the y pass folds the z slabs into N (column
+// n' = slab Nx + i, N' = Nz Nx) and takes 64 x 128 tiles over M = Ny, so a
+// small slab does not leave most of a 128-wide tile empty.  Four waves of
+// (BM/2) x (BN/2).  Every output element accumulates its K products in the
+// same order as in the single-problem tiles, so results are bitwise those of
+// the single solves.
+// ---------------------------------------------------------------------------
+template <int BM, int BN> struct WlCfg {
+    static constexpr int BK = 16, NT = 256, WM = BM / 2, WN = BN / 2, MI = WM / 16, NI = WN / 16;
+    static constexpr int LA = BM * BK / NT, LB = BN * BK / NT;
+};
+
+// buffer resource over [base, base + bytes), bytes clamped to the 31-bit range
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc_n(const void* base, long long bytes) {
+    const int n = bytes <= 0 ? 0 : (bytes > 0x7ffffff0LL ? 0x7ffffff0 : (int)bytes);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, n, BUF_RSRC_WORD3);
+}
+
+// One tile of a work list: its problem's operands and its position.
+struct WlTile {
+    const char* A;
+    const char* B;
+    char* C;
+    double* partials;
+    long long sB, sC, Ntot, n0, lb;
+    int M, N, K, lda, ldb, ldc, m0, batch;
+};
+
+template <int BM, int BN, bool BNK>
+__device__ __forceinline__ void wl_find(const GemmDesc* __restrict__ work, int nwork, long long v, WlTile& t) {
+    int lo = 0, hi = nwork - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (work[mid].block_begin <= v) lo = mid;
+        else hi = mid - 1;
+    }
+    const GemmDesc& g = work[lo];
+    t.A = (const char*)g.A;
+    t.B = (const char*)g.B;
+    t.C = (char*)g.C;
+    t.partials = g.partials;
+    t.M = g.M;
+    t.N = g.N;
+    t.K = g.K;
+    t.lda = g.lda;
+    t.ldb = g.ldb;
+    t.ldc = g.ldc;
+    t.sB = g.sB;
+    t.sC = g.sC;
+    t.batch = BNK ? 1 : g.batch;
+    t.Ntot = (long long)g.N * t.batch;
+    t.lb = v - g.block_begin;
+    const long long tm = t.lb / g.tiles_n;
+    t.m0 = (int)(tm * BM);
+    t.n0 = (t.lb - tm * g.tiles_n) * BN;
+}
+
+template <typename TM, typename TA, typename TB, typename TC, int EPI, bool BNK, int BM, int BN>
+__device__ __forceinline__ void gemm_worklist_f(const GemmDesc* __restrict__ work, int nwork, long long total,
+                                                TM* smem, double* red) {
+    typedef WlCfg<BM, BN> W;
+    constexpr int BK = W::BK, NT = W::NT, LA = W::LA, LB = W::LB, MI = W::MI, NI = W::NI;
+    typedef SmemF<TM, BM, BN, BNK, BK, 2> S;
+    typedef Mfma<TM> MM;
+    TM* As = smem;
+    TM* Bs = smem + 2 * S::A_ELEMS;
+    const int tid = threadIdx.x;
+    const int w = tid / 64, l = tid % 64, lr = l % 16, lg = l / 16;
+    const int wm = w / 2, wn = w % 2;
+    const int arow = tid / BK, acol = tid % BK;
+    constexpr int ea = (int)sizeof(TA), eb = (int)sizeof(TB);
+
+    // operand resources of a tile, and (y pass) the column part of each B
+    // load's offset: slab (relative to the tile's first) and index in it
+    auto setup = [&](const WlTile& t, __amdgpu_buffer_rsrc_t& rA, __amdgpu_buffer_rsrc_t& rB, unsigned* boff) {
+        rA = buf_rsrc_n(t.A + (long long)t.m0 * t.lda * ea, (long long)(t.M - t.m0) * t.lda * ea);
+        if constexpr (BNK) {
+            rB = buf_rsrc_n(t.B + t.n0 * t.ldb * eb, (t.N - t.n0) * (long long)t.ldb * eb);
+        } else {
+            // column indices fit 32 bits (the launcher checks N' and the extents)
+            const unsigned N = (unsigned)t.N, b0 = (unsigned)t.n0 / N;
+            rB = buf_rsrc_n(t.B + (long long)b0 * t.sB * eb, (t.batch - (long long)b0) * t.sB * eb);
+#pragma unroll
+            for (int q = 0; q < LB; ++q) {
+                const int e = tid + NT * q;
+                const unsigned nn = (unsigned)t.n0 + (unsigned)(e % BN);
+                const unsigned bq = nn / N;
+                boff[q] = (bq - b0) * (unsigned)t.sB + (nn - bq * N);
+            }
+        }
+    };
+    TM ra[LA], rb[LB];
+    auto gload = [&](const WlTile& t, __amdgpu_buffer_rsrc_t rA, __amdgpu_buffer_rsrc_t rB, const unsigned* boff,
+                     int kt) {
+        const int k0 = kt * BK;
+        const bool tail = k0 + BK > t.K;
+#pragma unroll
+        for (int q = 0; q < LA; ++q) {
+            const unsigned vo = (unsigned)(((arow + q * (NT / BK)) * t.lda + k0 + acol) * ea);
+            ra[q] = (TM)BufIO<TA>::ld(rA, vo, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < LB; ++q) {
+            unsigned vo;
+            if constexpr (BNK) vo = (unsigned)(((arow + q * (NT / BK)) * t.ldb + k0 + acol) * eb);
+            else vo = (boff[q] + (unsigned)((k0 + (tid + NT * q) / BN) * t.ldb)) * (unsigned)eb;
+            rb[q] = (TM)BufIO<TB>::ld(rB, vo, 0);
+        }
+        if (tail) {
+            const bool ka = k0 + acol < t.K;
+#pragma unroll
+            for (int q = 0; q < LA; ++q) ra[q] = ka ? ra[q] : (TM)0;
+#pragma unroll
+            for (int q = 0; q < LB; ++q) {
+                const bool kb = BNK ? ka : (k0 + (tid + NT * q) / BN < t.K);
+                rb[q] = kb ? rb[q] : (TM)0;
+            }
+        }
+    };
+    auto sstore = [&](int buf) {
+        TM* a = As + buf * S::A_ELEMS;
+        TM* bb = Bs + buf * S::B_ELEMS;
+#pragma unroll
+        for (int q = 0; q < LA; ++q) a[(arow + q * (NT / BK)) * S::PA + acol] = ra[q];
+#pragma unroll
+        for (int q = 0; q < LB; ++q) {
+            if constexpr (BNK) {
+                bb[(arow + q * (NT / BK)) * S::PB + acol] = rb[q];
+            } else {
+                const int e = tid + NT * q;
+                bb[(e / BN) * S::PB + (e % BN)] = rb[q];
+            }
+        }
+    };
+
+    const long long grid = gridDim.x;
+    long long v = blockIdx.x;
+    if (v >= total) return;
+    WlTile cur, nxt;
+    __amdgpu_buffer_rsrc_t rA, rB, nA, nB;
+    unsigned boff[BNK ? 1 : LB], nboff[BNK ? 1 : LB];
+    wl_find<BM, BN, BNK>(work, nwork, v, cur);
+    setup(cur, rA, rB, boff);
+    gload(cur, rA, rB, boff, 0);
+    sstore(0);
+    __syncthreads();
+    int buf = 0;
+    for (; v < total; v += grid) {
+        const bool more = v + grid < total;
+        const int nk = (cur.K + BK - 1) / BK;
+        typename MM::acc acc[MI][NI];
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+#pragma unroll
+            for (int j = 0; j < NI; ++j) acc[i][j] = MM::zero();
+        for (int kt = 0; kt < nk; ++kt) {
+            if (kt + 1 < nk) {
+                gload(cur, rA, rB, boff, kt + 1);
+            } else if (more) {
+                wl_find<BM, BN, BNK>(work, nwork, v + grid, nxt);
+                setup(nxt, nA, nB, nboff);
+                gload(nxt, nA, nB, nboff, 0);
+            }
+            const bool stage = kt + 1 < nk || more;
+            const TM* a = As + buf * S::A_ELEMS + (wm * W::WM + lr) * S::PA + lg;
+            const TM* bb = Bs + buf * S::B_ELEMS;
+#pragma unroll
+            for (int kk = 0; kk < BK / 4; ++kk) {
+                TM fa[MI], fb[NI];
+#pragma unroll
+                for (int i = 0; i < MI; ++i) fa[i] = a[i * 16 * S::PA + kk * 4];
+#pragma unroll
+                for (int j = 0; j < NI; ++j) {
+                    if constexpr (BNK) fb[j] = bb[(wn * W::WN + j * 16 + lr) * S::PB + kk * 4 + lg];
+                    else fb[j] = bb[(kk * 4 + lg) * S::PB + wn * W::WN + j * 16 + lr];
+                }
+#pragma unroll
+                for (int i = 0; i < MI; ++i)
+#pragma unroll
+                    for (int j = 0; j < NI; ++j) acc[i][j] = MM::mma(fa[i], fb[j], acc[i][j]);
+                if (kk == BK / 4 - 2 && stage) sstore(buf ^ 1);
+            }
+            if (kt + 1 < nk) {
+                __syncthreads();
+                buf ^= 1;
+            }
+        }
+        // results: rows m < M, columns n' < N' (y pass: slab n' / N, index n' % N)
+        double se = 0.0, sx = 0.0;
+        TC* __restrict__ C = (TC*)cur.C;
+        long long coff[NI];
+        bool cok[NI];
+#pragma unroll
+        for (int j = 0; j < NI; ++j) {
+            const long long nn = cur.n0 + wn * W::WN + j * 16 + lr;
+            cok[j] = nn < cur.Ntot;
+            if constexpr (BNK) {
+                coff[j] = nn;
+            } else {
+                const unsigned bq = (unsigned)nn / (unsigned)cur.N;
+                coff[j] = (long long)bq * cur.sC + ((unsigned)nn - bq * (unsigned)cur.N);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < MI; ++i) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = cur.m0 + wm * W::WM + i * 16 + MM::row(lg, r);
+                const long long ro = (long long)m * cur.ldc;
+#pragma unroll
+                for (int j = 0; j < NI; ++j)
+                    if (m < cur.M && cok[j]) epi_store<TC, EPI>(C, ro + coff[j], (double)acc[i][j][r], se, sx);
+            }
+        }
+        if constexpr (EPI == EPI_ACCUM_F64) {
+            block_sum2<NT>(se, sx, red);
+            if (threadIdx.x == 0) {
+                cur.partials[2 * cur.lb] = se;
+                cur.partials[2 * cur.lb + 1] = sx;
+            }
+        }
+        __syncthreads();
+        buf ^= 1;
+        if (more) {
+            cur = nxt;
+            rA = nA;
+            rB = nB;
+            if constexpr (!BNK)
+#pragma unroll
+                for (int q = 0; q < LB; ++q) boff[q] = nboff[q];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Split-BF16 x3 (v_mfma_f32_16x16x32_bf16, FP32 accumulate): each operand is
 // x = hi + lo (hi = bf16(x), lo = bf16(x - hi), round to nearest even) and
 // C = A_lo B_hi + A_hi B_lo + A_hi B_hi, small products first.  Fragments:
@@ -760,6 +1009,27 @@ __global__ TPT_GEMM_ATTR void gemm_multi_kernel(const GemmDesc* __restrict__ wor
         GemmKernel<PREC, TA, TB, TC, EPI, BM, BN, BNK, DEEP>::tile(g, blk - g.block_begin);
         __syncthreads();
     }
+}
+
+// Work-list kernel (FP64 / FP32): x pass 128 x 64 tiles, y pass 64 x 128
+// tiles over slab-folded columns.
+template <int PREC, typename TA, typename TB, typename TC, int EPI, bool BNK>
+__global__ __launch_bounds__(256) void gemm_worklist_kernel(const GemmDesc* __restrict__ work, int nwork,
+                                                            long long total) {
+    typedef typename std::conditional<PREC == GP_F64, double, float>::type T;
+    constexpr int BM = BNK ? 128 : 64, BN = BNK ? 64 : 128;
+    __shared__ __attribute__((aligned(16))) T smem[SmemF<T, BM, BN, BNK, 16, 2>::TOTAL];
+    __shared__ double red[2 * (256 / 64)];
+    gemm_worklist_f<T, TA, TB, TC, EPI, BNK, BM, BN>(work, nwork, total, smem, red);
+}
+
+template <int PREC, typename TA, typename TB, typename TC, int EPI, bool BNK>
+hipError_t launch_worklist_typed(const GemmDesc* d_work, int nwork, long long tiles, hipStream_t s) {
+    if (tiles <= 0) return hipSuccess;
+    const long long grid = persistent_gemm_grid(tiles);
+    TPT_KLAUNCH((gemm_worklist_kernel<PREC, TA, TB, TC, EPI, BNK>), dim3((unsigned)grid), dim3(256), 0, s, d_work,
+                nwork, tiles);
+    return hipGetLastError();
 }
 
 template <int PREC, typename TA, typename TB, typename TC, int EPI, bool BNK>

@@ -80,6 +80,20 @@ hipError_t launch_gemm(GemmDesc g, int prec, int variant, hipStream_t s);
 // operand types and the epilogue of `rep`).
 hipError_t launch_gemm_multi(const GemmDesc& rep, const GemmDesc* d_work, int nwork, long long total_blocks,
                              int prec, int variant, hipStream_t s);
+// Work-list GEMM (FP64 / FP32, persistent, next tile prefetched): x pass
+// (b_nk = 1) in 128 x 64 tiles, y pass (b_nk = 0) in 64 x 128 tiles over
+// N' = batch N slab-folded columns.  worklist_tiles gives a descriptor's tile
+// count (tiles_m, tiles_n are set by worklist_shape); worklist_ok whether its
+// extents fit the kernel's 32-bit offsets.
+void worklist_shape(GemmDesc& g);
+long long worklist_tiles(const GemmDesc& g);
+bool worklist_ok(const GemmDesc& g, int prec);
+hipError_t launch_gemm_worklist(const GemmDesc& rep, const GemmDesc* d_work, int nwork, long long tiles, int prec,
+                                hipStream_t s);
+hipError_t launch_gemm_worklist_f64(const GemmDesc& g, const GemmDesc* d_work, int nwork, long long tiles,
+                                    hipStream_t s);
+hipError_t launch_gemm_worklist_f32(const GemmDesc& g, const GemmDesc* d_work, int nwork, long long tiles,
+                                    hipStream_t s);
 // Per-precision launchers (gemm_f64.hip, gemm_f32.hip, gemm_bf16.hip).
 hipError_t launch_gemm_f64(const GemmDesc& g, const GemmDesc* d_work, int nwork, long long blocks, int variant,
                            hipStream_t s);

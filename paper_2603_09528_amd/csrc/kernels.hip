@@ -66,6 +66,45 @@ hipError_t launch_gemm(GemmDesc g, int prec, int variant, hipStream_t s) {
     return hipErrorInvalidValue;
 }
 
+void worklist_shape(GemmDesc& g) {
+    if (g.b_nk) {
+        g.tiles_m = cdiv(g.M, 128);
+        g.tiles_n = cdiv((long long)g.N * g.batch, 64);
+    } else {
+        g.tiles_m = cdiv(g.M, 64);
+        g.tiles_n = cdiv((long long)g.N * g.batch, 128);
+    }
+}
+
+long long worklist_tiles(const GemmDesc& g) {
+    GemmDesc t = g;
+    worklist_shape(t);
+    return (long long)t.tiles_m * t.tiles_n;
+}
+
+bool worklist_ok(const GemmDesc& g, int prec) {
+    if (prec == GP_BF16X3) return false;
+    const long long es = prec == GP_F64 ? 8 : 4;
+    const long long lim = 0x7ffffff0LL;
+    if (g.b_nk) {
+        // x pass: one problem, no batch; a tile's A rows and the basis
+        return g.batch == 1 && 128LL * g.lda * 8 < lim && (long long)g.N * g.ldb * es < lim;
+    }
+    // y pass: slab-folded columns and the B offsets of a tile's slabs
+    const long long ntot = (long long)g.N * g.batch;
+    return ntot < 0x7fffffffLL && (long long)g.M * g.lda * es < lim && g.sB * es * (128 / g.N + 3) < lim &&
+           g.sB < 0x7fffffffLL;
+}
+
+hipError_t launch_gemm_worklist(const GemmDesc& rep, const GemmDesc* d_work, int nwork, long long tiles, int prec,
+                                hipStream_t s) {
+    switch (prec) {
+        case GP_F64: return launch_gemm_worklist_f64(rep, d_work, nwork, tiles, s);
+        case GP_F32: return launch_gemm_worklist_f32(rep, d_work, nwork, tiles, s);
+    }
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_gemm_multi(const GemmDesc& rep, const GemmDesc* d_work, int nwork, long long total_blocks,
                              int prec, int variant, hipStream_t s) {
     switch (prec) {

@@ -56,22 +56,61 @@ static size_t append(std::vector<char>& blob, const std::vector<T>& v) {
     return off;
 }
 
-int MultiExec::add_gemm_stage(int stage, int prec, const std::vector<GemmDesc>& gs, const std::vector<char>& use) {
-    // group problems by tile variant; each group is one persistent launch
+int MultiExec::add_gemm_stage(int stage, int prec, const std::vector<GemmDesc>& gs, const std::vector<char>& use,
+                              std::vector<long long>* nb) {
+    // A problem whose tiles are all interior runs the single-problem
+    // persistent tile, one launch per problem, while there are at most four
+    // of them (large grids: each launch fills the GPU); the other FP64 / FP32
+    // problems share one work-list launch of the persistent work-list tile;
+    // anything else (BF16x3, extents past the work-list kernel's 32-bit
+    // offsets) one launch per tile variant of the plain tile kernel.
     std::vector<int> var(gs.size());
-    for (size_t i = 0; i < gs.size(); ++i) var[i] = use[i] ? stage_variant(plans_[i], stage, gs[i], prec) : -1;
+    int npersist = 0;
+    for (size_t i = 0; i < gs.size(); ++i) {
+        var[i] = use[i] ? stage_variant(plans_[i], stage, gs[i], prec) : -1;
+        if (use[i] && tv_persistent(var[i])) ++npersist;
+    }
+    const bool solo_persist = npersist <= 4;
+    std::vector<char> wl(gs.size(), 0);
+    {
+        std::vector<GemmDesc> grp;
+        long long total = 0;
+        for (size_t i = 0; i < gs.size(); ++i) {
+            if (!use[i] || prec == GP_BF16X3 || (solo_persist && tv_persistent(var[i])) || !worklist_ok(gs[i], prec))
+                continue;
+            wl[i] = 1;
+            GemmDesc g = gs[i];
+            worklist_shape(g);
+            g.block_begin = total;
+            const long long t = (long long)g.tiles_m * g.tiles_n;
+            total += t;
+            if (nb) (*nb)[i] = t;
+            grp.push_back(g);
+        }
+        if (!grp.empty()) {
+            Launch L{};
+            L.kind = 8;
+            L.prec = prec;
+            L.b_nk = grp[0].b_nk;
+            L.off = append(blob_, grp);
+            L.nwork = (int)grp.size();
+            L.total = total;
+            seq_.push_back(L);
+        }
+    }
     for (int v = 0; v < TV_COUNT; ++v) {
         std::vector<GemmDesc> grp;
         long long total = 0;
         int bm, bn;
         tile_variant_shape(v, &bm, &bn);
         for (size_t i = 0; i < gs.size(); ++i) {
-            if (var[i] != v) continue;
+            if (var[i] != v || wl[i]) continue;
             GemmDesc g = gs[i];
             g.tiles_m = (g.M + bm - 1) / bm;
             g.tiles_n = (g.N + bn - 1) / bn;
             g.block_begin = total;
             total += (long long)g.tiles_m * g.tiles_n * g.batch;
+            if (nb) (*nb)[i] = gemm_blocks(gs[i], v);
             grp.push_back(g);
         }
         if (grp.empty()) continue;
@@ -154,10 +193,9 @@ int MultiExec::build(const double* const* rhs, double* const* out, void* ws) {
                 if (nb) (*nb)[i] = fft_blocks(f[i]);
             } else {
                 g[i] = stage_gemm(plans_[i], st, prec_, in[i], tin, outp[i], tout, epi, part, 1);
-                if (nb) (*nb)[i] = gemm_blocks(g[i], stage_variant(plans_[i], st, g[i], prec_));
             }
         }
-        add_gemm_stage(st, prec_, g, fast_mask(st, false));
+        add_gemm_stage(st, prec_, g, fast_mask(st, false), nb);
         add_fft_stage(f, fast_mask(st, true));
     };
     std::vector<void*> w1(n), w2(n), outv(n);
@@ -326,6 +364,12 @@ int MultiExec::enqueue(hipStream_t s) const {
     for (const Launch& L : seq_) {
         hipError_t e = hipSuccess;
         switch (L.kind) {
+            case 8: {
+                TimedScope ts("multi_gemm", s);
+                const GemmDesc& rep = *(const GemmDesc*)(blob_.data() + L.off);
+                e = launch_gemm_worklist(rep, (const GemmDesc*)(d_desc_ + L.off), L.nwork, L.total, L.prec, s);
+                break;
+            }
             case 0: {
                 const GemmDesc* hd = (const GemmDesc*)(blob_.data() + L.off);
                 if (tv_persistent(L.variant) && L.nwork <= 4) {

@@ -36,7 +36,8 @@ class MultiExec {
    private:
     struct Launch {
         int kind;     // 0 gemm, 1 sequential Thomas, 2 residual, 3 reduce, 4 x-line FFT, 5 partitioned Thomas,
-                      // 6 right-hand-side check, 7 folding of fused-check partials
+                      // 6 right-hand-side check, 7 folding of fused-check partials,
+                      // 8 work-list GEMM (persistent, all problems of the stage)
         // sequential Thomas: variant holds the largest nz; partitioned: the
         // configuration, prec the storage type
         int prec, variant, b_nk;
@@ -44,7 +45,10 @@ class MultiExec {
         int nwork;
         long long total;
     };
-    int add_gemm_stage(int stage, int prec, const std::vector<GemmDesc>& g, const std::vector<char>& use);
+    // nb (if given): per problem of the stage, the blocks / tiles its GEMM
+    // launch runs (the norm partials an accumulating stage writes)
+    int add_gemm_stage(int stage, int prec, const std::vector<GemmDesc>& g, const std::vector<char>& use,
+                       std::vector<long long>* nb = nullptr);
     int add_fft_stage(const std::vector<FftDesc>& f, const std::vector<char>& use);
     std::vector<tpt_plan_s*> plans_;
     int prec_ = GP_F64;
