@@ -1026,10 +1026,12 @@ __global__ __launch_bounds__(256) void gemm_worklist_kernel(const GemmDesc* __re
 template <int PREC, typename TA, typename TB, typename TC, int EPI, bool BNK>
 hipError_t launch_worklist_typed(const GemmDesc* d_work, int nwork, long long tiles, hipStream_t s) {
     if (tiles <= 0) return hipSuccess;
-    // three blocks per CU (the kernel's registers and 50 KB of LDS allow three)
-    long long grid = persistent_gemm_grid(tiles) / 2 * 3;
+    // three blocks per CU (the kernel's registers and 50 KB of LDS allow
+    // three), a multiple of 8 so a block keeps its XCD, at most the tiles
+    long long grid = persistent_gemm_grid(1LL << 40) / 2 * 3;
     grid -= grid % 8;
     if (grid > tiles) grid = tiles;
+    if (grid < 1) grid = 1;
     TPT_KLAUNCH((gemm_worklist_kernel<PREC, TA, TB, TC, EPI, BNK>), dim3((unsigned)grid), dim3(256), 0, s, d_work,
                 nwork, tiles);
     return hipGetLastError();

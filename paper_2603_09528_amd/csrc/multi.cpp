@@ -65,12 +65,40 @@ int MultiExec::add_gemm_stage(int stage, int prec, const std::vector<GemmDesc>& 
     // anything else (BF16x3, extents past the work-list kernel's 32-bit
     // offsets) one launch per tile variant of the plain tile kernel.
     std::vector<int> var(gs.size());
-    int npersist = 0;
+    int npersist = 0, nuse = 0;
+    bool all_big = true;
     for (size_t i = 0; i < gs.size(); ++i) {
         var[i] = use[i] ? stage_variant(plans_[i], stage, gs[i], prec) : -1;
-        if (use[i] && tv_persistent(var[i])) ++npersist;
+        if (!use[i]) continue;
+        ++nuse;
+        if (tv_persistent(var[i])) ++npersist;
+        if (gemm_blocks(gs[i], TV_128x128) < 1024) all_big = false;
     }
     const bool solo_persist = npersist <= 4;
+    // at most four problems that each fill the GPU (>= 1024 tiles of 128 x
+    // 128): every one its own launch of the tile its single solve runs
+    if (nuse > 0 && nuse <= 4 && all_big) {
+        for (size_t i = 0; i < gs.size(); ++i) {
+            if (!use[i]) continue;
+            int bm, bn;
+            tile_variant_shape(var[i], &bm, &bn);
+            GemmDesc g = gs[i];
+            g.tiles_m = (g.M + bm - 1) / bm;
+            g.tiles_n = (g.N + bn - 1) / bn;
+            g.block_begin = 0;
+            if (nb) (*nb)[i] = gemm_blocks(gs[i], var[i]);
+            Launch L{};
+            L.kind = 9;
+            L.prec = prec;
+            L.variant = var[i];
+            L.b_nk = g.b_nk;
+            L.off = append(blob_, std::vector<GemmDesc>{g});
+            L.nwork = 1;
+            L.total = gemm_blocks(gs[i], var[i]);
+            seq_.push_back(L);
+        }
+        return TPT_OK;
+    }
     std::vector<char> wl(gs.size(), 0);
     {
         std::vector<GemmDesc> grp;
@@ -364,6 +392,12 @@ int MultiExec::enqueue(hipStream_t s) const {
     for (const Launch& L : seq_) {
         hipError_t e = hipSuccess;
         switch (L.kind) {
+            case 9: {
+                // one large problem on its own (its single-solve tile)
+                TimedScope ts("multi_gemm", s);
+                e = launch_gemm(*(const GemmDesc*)(blob_.data() + L.off), L.prec, L.variant, s);
+                break;
+            }
             case 8: {
                 TimedScope ts("multi_gemm", s);
                 const GemmDesc& rep = *(const GemmDesc*)(blob_.data() + L.off);

@@ -37,7 +37,8 @@ class MultiExec {
     struct Launch {
         int kind;     // 0 gemm, 1 sequential Thomas, 2 residual, 3 reduce, 4 x-line FFT, 5 partitioned Thomas,
                       // 6 right-hand-side check, 7 folding of fused-check partials,
-                      // 8 work-list GEMM (persistent, all problems of the stage)
+                      // 8 work-list GEMM (persistent, all problems of the stage),
+                      // 9 one GEMM problem on its own (single-problem kernel)
         // sequential Thomas: variant holds the largest nz; partitioned: the
         // configuration, prec the storage type
         int prec, variant, b_nk;
