@@ -904,14 +904,24 @@ __device__ __forceinline__ void gemm_tile_b(const GemmDesc& g, long long lb, uin
             fbh[j] = __builtin_bit_cast(bf16x8, *(const u16x8*)(bh + row * P + lg * 8));
             fbl[j] = __builtin_bit_cast(bf16x8, *(const u16x8*)(bl + row * P + lg * 8));
         }
+        // each product over every accumulator in turn: an accumulator's
+        // three MFMAs (small products first) are MI x NI instructions apart
+        // instead of back to back, so none waits for the previous result
 #pragma unroll
         for (int i = 0; i < C::MI; ++i)
 #pragma unroll
-            for (int j = 0; j < C::NI; ++j) {
+            for (int j = 0; j < C::NI; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fal[i], fbh[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < C::MI; ++i)
+#pragma unroll
+            for (int j = 0; j < C::NI; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fah[i], fbl[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < C::MI; ++i)
+#pragma unroll
+            for (int j = 0; j < C::NI; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fah[i], fbh[j], acc[i][j], 0, 0, 0);
-            }
     }
     };
     if (full) kloop(std::true_type{});
