@@ -231,7 +231,41 @@ __device__ __forceinline__ void ut_forward_body(const FftDesc& d, long long blk,
     TO* out = (TO*)d.out;
     double* ldsd = (double*)lds;
     // 1) load v in natural order (DST: (-1)^e f_e)
-    if (!d.ylines) {
+    if (!d.ylines && sizeof(TI) == 4 && ((uintptr_t)in % 16) == 0 && !d.cpart) {
+        // FP32 contiguous lines: element quads (4q .. 4q+3), 16 bytes per
+        // lane, so a wave moves as many bytes per load as in FP64; a block
+        // holds 2048 complex points, four quads per thread
+        constexpr int UQ = 4;
+        const int qlog = g.mlog - 1;
+        const int total = g.lpb << qlog;  // quads in the block
+        for (int base = 0; base < total; base += UQ * g.nt) {
+            float4 v[UQ];
+#pragma unroll
+            for (int u = 0; u < UQ; ++u) {
+                const int idx = base + u * g.nt + (int)threadIdx.x;
+                const int l = idx >> qlog, q = idx & ((M >> 1) - 1);
+                v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (idx < total && g.line0 + l < d.lines)
+                    v[u] = *(const float4*)((const float*)in + ((g.line0 + l) << g.nlog) + 4 * q);
+            }
+#pragma unroll
+            for (int u = 0; u < UQ; ++u) {
+                const int idx = base + u * g.nt + (int)threadIdx.x;
+                if (idx >= total) continue;
+                const int l = idx >> qlog, q = idx & ((M >> 1) - 1);
+                const int c0 = 2 * q, c1 = 2 * q + 1;
+                if (kind == UT_FOURIER) {
+                    lds[l * g.ls + pad16(c0)] = make_double2((double)v[u].x, (double)v[u].y);
+                    lds[l * g.ls + pad16(c1)] = make_double2((double)v[u].z, (double)v[u].w);
+                } else {
+                    ldsd[ut_vslot(g, l, c0)] = (double)v[u].x;
+                    ldsd[ut_vslot(g, l, N - 1 - c0)] = kind == UT_DST ? -(double)v[u].y : (double)v[u].y;
+                    ldsd[ut_vslot(g, l, c1)] = (double)v[u].z;
+                    ldsd[ut_vslot(g, l, N - 1 - c1)] = kind == UT_DST ? -(double)v[u].w : (double)v[u].w;
+                }
+            }
+        }
+    } else if (!d.ylines) {
         // contiguous lines: element pairs (2c, 2c+1), 16 (FP64) or 8 (FP32)
         // bytes per lane when the line data is aligned to it
         constexpr int UL = 1 << UT_Q;
@@ -325,6 +359,32 @@ __device__ __forceinline__ void ut_forward_body(const FftDesc& d, long long blk,
     ut_cfft<false>(lds, g.ls, g.mlog, W);
     // 3) half spectrum and outputs, from LDS straight to memory
     const double s = d.scale;
+    if (kind == UT_FOURIER && !d.ylines && sizeof(TO) == 4 && ((uintptr_t)out % 16) == 0) {
+        // FP32 contiguous lines: item q writes the quad (4q .. 4q+3), the
+        // output pairs of p = 2q and 2q + 1 (see below), 16 bytes per lane
+        const double c0 = s / sqrt((double)N), c1 = s * sqrt(2.0 / N);
+        const int qlog = g.mlog - 1;
+        for (int idx = threadIdx.x; idx < (g.lpb << qlog); idx += g.nt) {
+            const int l = idx >> qlog, q = idx & ((M >> 1) - 1);
+            if (g.line0 + l >= d.lines) continue;
+            const double2* a = lds + (size_t)l * g.ls;
+            auto vm = [&](int m) {  // V_m, 0 < m < M
+                const double2 zm = a[pad16(m)], zc = conj2(a[pad16(M - m)]);
+                const double2 e = cscale(cadd(zm, zc), 0.5);
+                const double2 t = cmul(W[m], cscale(csub(zm, zc), 0.5));
+                return make_double2(e.x + t.y, e.y - t.x);
+            };
+            const double2 z0 = a[0];
+            const int p0 = 2 * q, p1 = 2 * q + 1;
+            const double lo0 = p0 == 0 ? c0 * (z0.x + z0.y) : -c1 * vm(p0).y;
+            const double hi0 = c1 * vm(p0 + 1).x;
+            const double lo1 = -c1 * vm(p1).y;
+            const double hi1 = p1 == M - 1 ? c0 * (z0.x - z0.y) : c1 * vm(p1 + 1).x;
+            *(float4*)((float*)out + ((g.line0 + l) << g.nlog) + 4 * q) =
+                make_float4((float)lo0, (float)hi0, (float)lo1, (float)hi1);
+        }
+        return;
+    }
     if (kind == UT_FOURIER && !d.ylines && ((uintptr_t)out % sizeof(typename Pair2<TO>::type)) == 0) {
         // contiguous lines: item p writes the output pair (2p, 2p+1) =
         // (-Im V_p, Re V_{p+1}) scaled, with V_0 and V_M at the two ends
@@ -422,7 +482,40 @@ __device__ __forceinline__ void ut_inverse(const FftDesc& d, long long blk, doub
     //    to eight items are loaded before they are combined.
     constexpr int UL = 1 << UT_Q;
     const int total = g.lpb << g.mlog;
-    if (kind == UT_FOURIER && !d.ylines && ((uintptr_t)in % sizeof(typename Pair2<TI>::type)) == 0) {
+    if (kind == UT_FOURIER && !d.ylines && sizeof(TI) == 4 && ((uintptr_t)in % 16) == 0) {
+        // FP32 contiguous lines: item q loads the quad (4q .. 4q+3), the input
+        // pairs of p = 2q and 2q + 1 (see below), 16 bytes per lane
+        const double cN = s * sqrt((double)N), cH = s * sqrt(0.5 * N);
+        double* ldsd = (double*)lds;
+        constexpr int UQ = 4;
+        const int qlog = g.mlog - 1;
+        const int tq = g.lpb << qlog;
+        for (int base = 0; base < tq; base += UQ * g.nt) {
+            float4 v[UQ];
+#pragma unroll
+            for (int u = 0; u < UQ; ++u) {
+                const int idx = base + u * g.nt + (int)threadIdx.x;
+                const int l = idx >> qlog, q = idx & ((M >> 1) - 1);
+                v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (idx < tq && g.line0 + l < d.lines)
+                    v[u] = *(const float4*)((const float*)in + ((g.line0 + l) << g.nlog) + 4 * q);
+            }
+#pragma unroll
+            for (int u = 0; u < UQ; ++u) {
+                const int idx = base + u * g.nt + (int)threadIdx.x;
+                if (idx >= tq) continue;
+                const int l = idx >> qlog, q = idx & ((M >> 1) - 1);
+                const int row = 2 * l * g.ls;
+                const int p0 = 2 * q, p1 = 2 * q + 1;
+                if (p0 == 0) ldsd[row] = cN * (double)v[u].x;
+                else ldsd[row + 2 * pad16(p0) + 1] = -cH * (double)v[u].x;
+                ldsd[row + 2 * pad16(p0 + 1)] = cH * (double)v[u].y;
+                ldsd[row + 2 * pad16(p1) + 1] = -cH * (double)v[u].z;
+                if (p1 == M - 1) ldsd[row + 1] = cN * (double)v[u].w;
+                else ldsd[row + 2 * pad16(p1 + 1)] = cH * (double)v[u].w;
+            }
+        }
+    } else if (kind == UT_FOURIER && !d.ylines && ((uintptr_t)in % sizeof(typename Pair2<TI>::type)) == 0) {
         // contiguous lines: item p loads the input pair (2p, 2p+1); 2p is
         // -Im F_p / cH (Re F_0 / cN for p = 0) and 2p+1 is Re F_{p+1} / cH
         // (Im F_0 / cN for p = M-1: F_M rides in slot 0)

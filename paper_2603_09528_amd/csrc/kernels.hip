@@ -585,7 +585,9 @@ __device__ __forceinline__ void residual_block(const StencilDesc& st, long long 
 
 __global__ __launch_bounds__(RES_NT) void residual_kernel(StencilDesc st) {
     __shared__ double red[2 * RES_NT / 64];
-    residual_block(st, blockIdx.x, red);
+    // consecutive logical blocks (neighbouring rows of one z chunk, whose y
+    // neighbours they read) share one XCD's L2
+    residual_block(st, xcd_block(blockIdx.x, gridDim.x), red);
 }
 
 __global__ __launch_bounds__(RES_NT) void residual_multi_kernel(const StencilDesc* __restrict__ work, int nwork,

@@ -54,8 +54,10 @@ inline long long proj_blocks(const ProjDesc& d) {
 __global__ __launch_bounds__(PJ_NT) void divergence_kernel(ProjDesc d) {
     const long long sxy = (long long)d.nx * d.ny;
     const long long ncb = (sxy + PJ_NT - 1) / PJ_NT;
-    const long long zc = blockIdx.x / ncb;
-    const long long c = (blockIdx.x - zc * ncb) * PJ_NT + threadIdx.x;
+    // neighbouring rows on one XCD (they read each other's y neighbours)
+    const long long lb = xcd_block(blockIdx.x, gridDim.x);
+    const long long zc = lb / ncb;
+    const long long c = (lb - zc * ncb) * PJ_NT + threadIdx.x;
     if (c >= sxy) return;
     const int j = (int)(c / d.nx), i = (int)(c - (long long)j * d.nx);
     const int k0 = (int)zc * PJ_RZ, k1 = min(d.nz, k0 + PJ_RZ);
@@ -85,8 +87,10 @@ __global__ __launch_bounds__(PJ_NT) void divergence_kernel(ProjDesc d) {
 __global__ __launch_bounds__(PJ_NT) void gradient_update_kernel(ProjDesc d) {
     const long long sxy = (long long)d.nx * d.ny;
     const long long ncb = (sxy + PJ_NT - 1) / PJ_NT;
-    const long long zc = blockIdx.x / ncb;
-    const long long c = (blockIdx.x - zc * ncb) * PJ_NT + threadIdx.x;
+    // neighbouring rows on one XCD (they read each other's y neighbours)
+    const long long lb = xcd_block(blockIdx.x, gridDim.x);
+    const long long zc = lb / ncb;
+    const long long c = (lb - zc * ncb) * PJ_NT + threadIdx.x;
     if (c >= sxy) return;
     const int j = (int)(c / d.nx), i = (int)(c - (long long)j * d.nx);
     const int k0 = (int)zc * PJ_RZ, k1 = min(d.nz, k0 + PJ_RZ);
