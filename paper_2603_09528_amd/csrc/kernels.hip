@@ -531,12 +531,28 @@ int residual_blocks(const StencilDesc& st) {
 // the four x / y neighbours (cache hits), with the x / y coefficients of its
 // column held in registers.  A missing neighbour (a wall) gets coefficient 0
 // and offset 0, so the stencil needs no branches.
-__device__ __forceinline__ void residual_block(const StencilDesc& st, long long lb, double* red) {
+__device__ __forceinline__ void residual_block(const StencilDesc& st, long long lb, double* red, double* zco) {
     const int nx = st.nx, ny = st.ny, nz = st.nz;
     const long long sxy = (long long)nx * ny;
     const long long ncb = (sxy + RES_NT - 1) / RES_NT;
     const long long zc = lb / ncb, cbk = lb - zc * ncb;
     const long long c = cbk * RES_NT + threadIdx.x;  // column i + nx j
+    // the z coefficients of the block's planes, staged in LDS once (read
+    // inside the march, where a memory load per plane would wait each step)
+    {
+        const int k0 = (int)zc * RES_RZ;
+        for (int t = threadIdx.x; t < 3 * RES_RZ; t += RES_NT) {
+            const int q = t / RES_RZ, k = k0 + t % RES_RZ;
+            double v = 0.0;
+            if (k < nz) {
+                if (q == 0) v = (k > 0 || st.perz) ? st.az[k] : 0.0;
+                else if (q == 1) v = st.bz[k];
+                else v = (k < nz - 1 || st.perz) ? st.cz[k] : 0.0;
+            }
+            zco[t] = v;
+        }
+        __syncthreads();
+    }
     double sr = 0.0, sf = 0.0;
     if (c < sxy) {
         const int j = (int)(c / nx), i = (int)(c - (long long)j * nx);
@@ -562,9 +578,8 @@ __device__ __forceinline__ void residual_block(const StencilDesc& st, long long 
             double xp = 0.0;
             if (k + 1 < nz) xp = x[idx + sxy];
             else if (st.perz) xp = x[c];
-            const double azk = (k > 0 || st.perz) ? st.az[k] : 0.0;
-            const double czk = (k < nz - 1 || st.perz) ? st.cz[k] : 0.0;
-            double lap = (bxy + st.bz[k]) * xc + azk * xm + czk * xp;
+            const double azk = zco[k - k0], czk = zco[2 * RES_RZ + k - k0];
+            double lap = (bxy + zco[RES_RZ + k - k0]) * xc + azk * xm + czk * xp;
             lap += axm * x[idx + oxm] + axp * x[idx + oxp] + aym * x[idx + oym] + ayp * x[idx + oyp];
             const double ax = st.helmholtz ? xc - st.alpha * lap : lap;
             const double fv = st.f[idx] - (k == nz - 1 ? fshift : 0.0);
@@ -585,14 +600,16 @@ __device__ __forceinline__ void residual_block(const StencilDesc& st, long long 
 
 __global__ __launch_bounds__(RES_NT) void residual_kernel(StencilDesc st) {
     __shared__ double red[2 * RES_NT / 64];
+    __shared__ double zco[3 * RES_RZ];
     // consecutive logical blocks (neighbouring rows of one z chunk, whose y
     // neighbours they read) share one XCD's L2
-    residual_block(st, xcd_block(blockIdx.x, gridDim.x), red);
+    residual_block(st, xcd_block(blockIdx.x, gridDim.x), red, zco);
 }
 
 __global__ __launch_bounds__(RES_NT) void residual_multi_kernel(const StencilDesc* __restrict__ work, int nwork,
                                                                 long long total) {
     __shared__ double red[2 * RES_NT / 64];
+    __shared__ double zco[3 * RES_RZ];
     for (long long blk = blockIdx.x; blk < total; blk += gridDim.x) {
         int lo = 0, hi = nwork - 1;
         while (lo < hi) {
@@ -602,7 +619,7 @@ __global__ __launch_bounds__(RES_NT) void residual_multi_kernel(const StencilDes
         }
         const StencilDesc st = work[lo];
         const long long lb = blk - st.block_begin;
-        residual_block(st, lb, red);
+        residual_block(st, lb, red, zco);
         __syncthreads();
     }
 }
