@@ -209,7 +209,11 @@ struct StencilDesc {
     const double* wsum;
     double wscale;
     long long block_begin;  // multi-problem
+    // two columns per thread (set from residual_pairs_ok; 0 gives the
+    // larger block count, which sizes the partial sums)
+    int pair;
 };
+bool residual_pairs_ok(const StencilDesc& st);
 int residual_blocks(const StencilDesc& st);
 hipError_t launch_residual(const StencilDesc& st, hipStream_t s);
 hipError_t launch_residual_multi(const StencilDesc* d_work, int nwork, long long total_blocks, hipStream_t s);

@@ -521,7 +521,8 @@ constexpr int RES_RZ = 32;  // z planes per thread
 
 // Blocks: 256 consecutive (i, j) columns times one chunk of RES_RZ planes.
 int residual_blocks(const StencilDesc& st) {
-    const long long ncb = ((long long)st.nx * st.ny + RES_NT - 1) / RES_NT;
+    const int bc = st.pair ? 2 * RES_NT : RES_NT;
+    const long long ncb = ((long long)st.nx * st.ny + bc - 1) / bc;
     const long long nzc = (st.nz + RES_RZ - 1) / RES_RZ;
     return (int)(ncb * nzc);
 }
@@ -598,12 +599,128 @@ __device__ __forceinline__ void residual_block(const StencilDesc& st, long long 
     }
 }
 
+// Paired form (even nx, 16-byte aligned x and f, planes under 2 GB): each
+// thread owns two neighbouring columns of one row, so its plane reads are
+// 16-byte loads and a wave covers 128 columns.  The x neighbours inside the
+// wave come from the neighbouring lanes' registers (the current plane's x is
+// already held for the z stencil); only the lanes at a wave's ends or a row's
+// ends load them.  Per plane a wave then issues four full-width loads (x one
+// plane up, f, and the two y neighbours) instead of six half-width ones per
+// 64 columns: the scalar march is bound by that load issue rate, not by HBM.
+// Loads go through per-plane buffer descriptors (uniform) with 32-bit
+// per-thread offsets.  Every lane runs the march (lanes past the last column
+// work on the last pair and store nothing), so the cross-lane reads always
+// find their source lane active.
+typedef unsigned int res_u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 res_ld2(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ double res_ld1(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+
+__device__ __forceinline__ void residual_pair_block(const StencilDesc& st, long long lb, double* red, double* zco) {
+    const int nx = st.nx, ny = st.ny, nz = st.nz;
+    const long long sxy = (long long)nx * ny;
+    constexpr int BC = 2 * RES_NT;  // columns per block
+    const long long ncb = (sxy + BC - 1) / BC;
+    const long long zc = lb / ncb, cbk = lb - zc * ncb;
+    const int k0 = (int)zc * RES_RZ, k1 = min(nz, k0 + RES_RZ);
+    {
+        for (int t = threadIdx.x; t < 3 * RES_RZ; t += RES_NT) {
+            const int q = t / RES_RZ, k = k0 + t % RES_RZ;
+            double v = 0.0;
+            if (k < nz) {
+                if (q == 0) v = (k > 0 || st.perz) ? st.az[k] : 0.0;
+                else if (q == 1) v = st.bz[k];
+                else v = (k < nz - 1 || st.perz) ? st.cz[k] : 0.0;
+            }
+            zco[t] = v;
+        }
+        __syncthreads();
+    }
+    const long long c_raw = cbk * BC + 2 * (long long)threadIdx.x;
+    const bool live = c_raw < sxy;
+    const int c = (int)(live ? c_raw : sxy - 2);  // column of the pair's first element (sxy < 2^28 here)
+    const int j = c / nx, i0 = c - j * nx, i1 = i0 + 1;
+    const int lane = threadIdx.x & 63;
+    // x neighbours outside the pair: from the neighbouring lane, or loaded at
+    // a wave end or a row end (the wrap of a periodic row; a wall has
+    // coefficient 0 and re-reads the own column)
+    const double axm0 = i0 > 0 ? st.ax[i0] : (st.perx ? st.ax[0] : 0.0);
+    const double axp0 = st.cx[i0];
+    const double axm1 = st.ax[i1];
+    const double axp1 = i1 < nx - 1 ? st.cx[i1] : (st.perx ? st.cx[nx - 1] : 0.0);
+    const bool loadL = lane == 0 || i0 == 0, loadR = lane == 63 || i1 == nx - 1 || c_raw + 2 >= sxy;
+    const int colL = i0 > 0 ? c - 1 : (st.perx ? c + nx - 1 : c);
+    const int colR = i1 < nx - 1 ? c + 2 : (st.perx ? c + 2 - nx : c + 1);
+    int cym = c, cyp = c;
+    double aym = 0.0, ayp = 0.0;
+    if (j > 0) { cym = c - nx; aym = st.ay[j]; } else if (st.pery) { cym = c + (ny - 1) * nx; aym = st.ay[0]; }
+    if (j < ny - 1) { cyp = c + nx; ayp = st.cy[j]; } else if (st.pery) { cyp = c - (ny - 1) * nx; ayp = st.cy[ny - 1]; }
+    const double bxy0 = st.bx[i0] + st.by[j], bxy1 = st.bx[i1] + st.by[j];
+    const double fshift = (st.wsum && k1 == nz) ? *st.wsum * st.wscale : 0.0;
+    const int pbytes = (int)(sxy * 8);
+    auto rsrc = [&](const void* base, int bytes) {
+        return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, 0x00020000);
+    };
+    const unsigned oc = (unsigned)c * 8u, ocym = (unsigned)cym * 8u, ocyp = (unsigned)cyp * 8u;
+    const unsigned oL = (unsigned)colL * 8u, oR = (unsigned)colR * 8u;
+    // z window: the pair below k0 (or its periodic image, or 0) and at k0
+    double2 xm = make_double2(0.0, 0.0);
+    if (k0 > 0) xm = res_ld2(rsrc(st.x + (long long)(k0 - 1) * sxy, pbytes), oc);
+    else if (st.perz) xm = res_ld2(rsrc(st.x + (long long)(nz - 1) * sxy, pbytes), oc);
+    double2 xc = res_ld2(rsrc(st.x + (long long)k0 * sxy, pbytes), oc);
+    double sr = 0.0, sf = 0.0;
+    for (int k = k0; k < k1; ++k) {
+        const double* xk = st.x + (long long)k * sxy;
+        const __amdgpu_buffer_rsrc_t rx = rsrc(xk, pbytes);
+        const double2 xq = res_ld2(rsrc(k + 1 < nz ? xk + sxy : st.x, pbytes), oc);
+        const double2 fv = res_ld2(rsrc(st.f + (long long)k * sxy, pbytes), oc);
+        const double2 ym = res_ld2(rx, ocym), yp = res_ld2(rx, ocyp);
+        double xl = __shfl_up(xc.y, 1, 64), xr = __shfl_down(xc.x, 1, 64);
+        if (loadL) xl = res_ld1(rx, oL);
+        if (loadR) xr = res_ld1(rx, oR);
+        const double2 xp = (k + 1 < nz || st.perz) ? xq : make_double2(0.0, 0.0);
+        const double azk = zco[k - k0], bzk = zco[RES_RZ + k - k0], czk = zco[2 * RES_RZ + k - k0];
+        double lap0 = (bxy0 + bzk) * xc.x + azk * xm.x + czk * xp.x;
+        lap0 += axm0 * xl + axp0 * xc.y + aym * ym.x + ayp * yp.x;
+        double lap1 = (bxy1 + bzk) * xc.y + azk * xm.y + czk * xp.y;
+        lap1 += axm1 * xc.x + axp1 * xr + aym * ym.y + ayp * yp.y;
+        const double ax0 = st.helmholtz ? xc.x - st.alpha * lap0 : lap0;
+        const double ax1 = st.helmholtz ? xc.y - st.alpha * lap1 : lap1;
+        const double sh = k == nz - 1 ? fshift : 0.0;
+        const double f0 = fv.x - sh, f1 = fv.y - sh;
+        const double r0 = f0 - ax0, r1 = f1 - ax1;
+        if (live) {
+            const float2 rv = make_float2((float)r0, (float)r1);
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(res_u32x2, rv),
+                                                  rsrc(st.r + (long long)k * sxy, pbytes / 2), (int)(oc / 2u), 0, 0);
+            sr += r0 * r0 + r1 * r1;
+            sf += f0 * f0 + f1 * f1;
+        }
+        xm = xc;
+        xc = xp;
+    }
+    block_sum2<RES_NT>(sr, sf, red);
+    if (threadIdx.x == 0) {
+        st.partials[2 * lb] = sr;
+        st.partials[2 * lb + 1] = sf;
+    }
+}
+
 __global__ __launch_bounds__(RES_NT) void residual_kernel(StencilDesc st) {
     __shared__ double red[2 * RES_NT / 64];
     __shared__ double zco[3 * RES_RZ];
     // consecutive logical blocks (neighbouring rows of one z chunk, whose y
     // neighbours they read) share one XCD's L2
     residual_block(st, xcd_block(blockIdx.x, gridDim.x), red, zco);
+}
+
+__global__ __launch_bounds__(RES_NT) void residual_pair_kernel(StencilDesc st) {
+    __shared__ double red[2 * RES_NT / 64];
+    __shared__ double zco[3 * RES_RZ];
+    residual_pair_block(st, xcd_block(blockIdx.x, gridDim.x), red, zco);
 }
 
 __global__ __launch_bounds__(RES_NT) void residual_multi_kernel(const StencilDesc* __restrict__ work, int nwork,
@@ -619,15 +736,23 @@ __global__ __launch_bounds__(RES_NT) void residual_multi_kernel(const StencilDes
         }
         const StencilDesc st = work[lo];
         const long long lb = blk - st.block_begin;
-        residual_block(st, lb, red, zco);
+        if (st.pair) residual_pair_block(st, lb, red, zco);
+        else residual_block(st, lb, red, zco);
         __syncthreads();
     }
+}
+
+bool residual_pairs_ok(const StencilDesc& st) {
+    const long long sxy = (long long)st.nx * st.ny;
+    return st.nx % 2 == 0 && sxy >= 2 && sxy * 8 < (1LL << 31) && ((uintptr_t)st.x % 16) == 0 &&
+           ((uintptr_t)st.f % 16) == 0 && ((uintptr_t)st.r % 8) == 0;
 }
 
 hipError_t launch_residual(const StencilDesc& st, hipStream_t s) {
     const int nb = residual_blocks(st);
     if (nb <= 0) return hipSuccess;
-    TPT_KLAUNCH(residual_kernel, dim3(nb), dim3(RES_NT), 0, s, st);
+    if (st.pair) TPT_KLAUNCH(residual_pair_kernel, dim3(nb), dim3(RES_NT), 0, s, st);
+    else TPT_KLAUNCH(residual_kernel, dim3(nb), dim3(RES_NT), 0, s, st);
     return hipGetLastError();
 }
 

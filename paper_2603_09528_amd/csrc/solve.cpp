@@ -283,6 +283,7 @@ StencilDesc plan_stencil(const tpt_plan_s* p, const double* x, const double* f, 
         st.wsum = stats + SS_WF;
         st.wscale = p->last_area_inv;
     }
+    st.pair = residual_pairs_ok(st) ? 1 : 0;
     return st;
 }
 
@@ -472,6 +473,7 @@ Ws carve(const tpt_plan_s* p, void* ws) {
 
 long long plan_residual_blocks(const tpt_plan_s* p) {
     StencilDesc st = plan_stencil(p, nullptr, nullptr, nullptr, nullptr, nullptr);
+    st.pair = 0;  // the larger count: the paired form may not apply to the caller's buffers
     return residual_blocks(st);
 }
 
