@@ -27,6 +27,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 
 // 1/d from the hardware reciprocal and two Newton steps (about 1 ulp): the
 // Thomas recurrence is a chain of dependent operations, so a short chain is
@@ -90,6 +91,17 @@ __device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float(
 __device__ __forceinline__ void split_bf16(float x, uint16_t& hi, uint16_t& lo) {
     hi = bf16_rne(x);
     lo = bf16_rne(x - bf16_to_f(hi));
+}
+// The same split of two values at once by the hardware's packed conversion
+// (round to nearest even, as bf16_rne for every finite value; a NaN or an
+// infinity gives a NaN lo either way): element 0 in the low half of each word.
+typedef float tpt_f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 tpt_bf16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void split_bf16x2(float a, float b, uint32_t& hi, uint32_t& lo) {
+    const tpt_f32x2 v = {a, b};
+    hi = __builtin_bit_cast(uint32_t, __builtin_convertvector(v, tpt_bf16x2));
+    const tpt_f32x2 r = {a - __uint_as_float(hi << 16), b - __uint_as_float(hi & 0xffff0000u)};
+    lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, tpt_bf16x2));
 }
 
 // Blocks of one launch are dealt round-robin to the 8 XCDs, each with its own

@@ -863,14 +863,15 @@ __device__ __forceinline__ void gemm_tile_b(const GemmDesc& g, long long lb, uin
                 row = 2 * (c % (BN / 2)) + (t & 1);
                 kc = c / (BN / 2);
             }
-            u16x8 h, lo;
+            u32x4_t hw, lw;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                uint16_t hh, ll;
-                split_bf16(rd[t][e], hh, ll);
-                h[e] = hh;
-                lo[e] = ll;
+            for (int e = 0; e < 4; ++e) {
+                uint32_t hh, ll;
+                split_bf16x2(rd[t][2 * e], rd[t][2 * e + 1], hh, ll);
+                hw[e] = hh;
+                lw[e] = ll;
             }
+            const u16x8 h = __builtin_bit_cast(u16x8, hw), lo = __builtin_bit_cast(u16x8, lw);
             *(u16x8*)((BNK ? ah : bh) + row * P + kc * 8) = h;
             *(u16x8*)((BNK ? al : bl) + row * P + kc * 8) = lo;
         }
