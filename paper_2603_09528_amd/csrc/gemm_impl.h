@@ -694,8 +694,8 @@ __device__ __forceinline__ void gemm_worklist_f(const GemmDesc* __restrict__ wor
 // Bs[n][k]) so each fragment is one 16-byte LDS read.  The basis operand
 // arrives pre-split (bf16 planes); the data operand is split on the fly.
 // ---------------------------------------------------------------------------
-template <int BM, int BN> struct SmemB {
-    static constexpr int BK = 32;
+template <int BM, int BN, int BK_ = 32> struct SmemB {
+    static constexpr int BK = BK_;
     static constexpr int P = BK + 8;  // row stride in bf16 (16-byte padding)
     static constexpr int A_ELEMS = BM * P;
     static constexpr int B_ELEMS = BN * P;
@@ -719,10 +719,10 @@ __device__ __forceinline__ void load8_planes(const uint16_t* __restrict__ ph, co
     }
 }
 
-template <typename TD, typename TC, int EPI, int BM, int BN, bool BNK>
+template <typename TD, typename TC, int EPI, int BM, int BN, bool BNK, int BK_ = 32>
 __device__ __forceinline__ void gemm_tile_b(const GemmDesc& g, long long lb, uint16_t* smem, double* red) {
     typedef TileCfg<BM, BN> C;
-    typedef SmemB<BM, BN> S;
+    typedef SmemB<BM, BN, BK_> S;
     constexpr int BK = S::BK;
     constexpr int NT = C::NT;
     constexpr int P = S::P;
@@ -892,18 +892,23 @@ __device__ __forceinline__ void gemm_tile_b(const GemmDesc& g, long long lb, uin
         const uint16_t* al = sm_lo;
         const uint16_t* bh = ah + S::A_ELEMS;
         const uint16_t* bl = al + S::A_ELEMS;
+        // one MFMA K of 32 per sub-step; a 64-deep tile runs two, in the
+        // order two 32-deep tiles would, so every accumulator sees the same
+        // sequence of products (not unrolled: one set of fragments live)
+#pragma unroll 1
+        for (int kk = 0; kk < BK / 32; ++kk) {
         bf16x8 fah[C::MI], fal[C::MI], fbh[C::NI], fbl[C::NI];
 #pragma unroll
         for (int i = 0; i < C::MI; ++i) {
             const int row = wm * C::WM + i * 16 + lr;
-            fah[i] = __builtin_bit_cast(bf16x8, *(const u16x8*)(ah + row * P + lg * 8));
-            fal[i] = __builtin_bit_cast(bf16x8, *(const u16x8*)(al + row * P + lg * 8));
+            fah[i] = __builtin_bit_cast(bf16x8, *(const u16x8*)(ah + row * P + kk * 32 + lg * 8));
+            fal[i] = __builtin_bit_cast(bf16x8, *(const u16x8*)(al + row * P + kk * 32 + lg * 8));
         }
 #pragma unroll
         for (int j = 0; j < C::NI; ++j) {
             const int row = wn * C::WN + j * 16 + lr;
-            fbh[j] = __builtin_bit_cast(bf16x8, *(const u16x8*)(bh + row * P + lg * 8));
-            fbl[j] = __builtin_bit_cast(bf16x8, *(const u16x8*)(bl + row * P + lg * 8));
+            fbh[j] = __builtin_bit_cast(bf16x8, *(const u16x8*)(bh + row * P + kk * 32 + lg * 8));
+            fbl[j] = __builtin_bit_cast(bf16x8, *(const u16x8*)(bl + row * P + kk * 32 + lg * 8));
         }
         // each product over every accumulator in turn: an accumulator's
         // three MFMAs (small products first) are MI x NI instructions apart
@@ -923,6 +928,7 @@ __device__ __forceinline__ void gemm_tile_b(const GemmDesc& g, long long lb, uin
 #pragma unroll
             for (int j = 0; j < C::NI; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fah[i], fbh[j], acc[i][j], 0, 0, 0);
+        }
     }
     };
     if (full) kloop(std::true_type{});
@@ -959,7 +965,8 @@ __device__ __forceinline__ void gemm_tile_b(const GemmDesc& g, long long lb, uin
 // ---------------------------------------------------------------------------
 // PREC: GP_F64 / GP_F32 / GP_BF16X3; TA: data type of the x-pass A (or of A
 // for a plain GEMM), TB: data type of the y-pass B, TC output type.
-// DEEP = 1: K tile of 32 with a single LDS buffer (FP64/FP32 only).
+// DEEP = 1: a deep K tile in a single LDS buffer (32 for FP64/FP32, 64 for
+// BF16X3).
 // Threads of the plain tile kernels: DEEP 2 splits the tile over waves of
 // 64 x 32 (FP64 / FP32 only).
 template <int BM, int BN, int DEEP>
@@ -971,10 +978,12 @@ template <int PREC, typename TA, typename TB, typename TC, int EPI, int BM, int 
 struct GemmKernel {
     static __device__ __forceinline__ void tile(const GemmDesc& g, long long lb) {
         if constexpr (PREC == GP_BF16X3) {
-            __shared__ __attribute__((aligned(16))) uint16_t smem[SmemB<BM, BN>::TOTAL];
+            // DEEP 1: a 64-deep K tile (two MFMA K steps per LDS fill)
+            constexpr int BKb = DEEP == 1 ? 64 : 32;
+            __shared__ __attribute__((aligned(16))) uint16_t smem[SmemB<BM, BN, BKb>::TOTAL];
             __shared__ double red[2 * TileCfg<BM, BN>::NT / 64];
-            if constexpr (BNK) gemm_tile_b<TA, TC, EPI, BM, BN, true>(g, lb, smem, red);
-            else gemm_tile_b<TB, TC, EPI, BM, BN, false>(g, lb, smem, red);
+            if constexpr (BNK) gemm_tile_b<TA, TC, EPI, BM, BN, true, BKb>(g, lb, smem, red);
+            else gemm_tile_b<TB, TC, EPI, BM, BN, false, BKb>(g, lb, smem, red);
         } else {
             typedef typename std::conditional<PREC == GP_F64, double, float>::type T;
             // DEEP 1: 32-deep K tile, single buffer; DEEP 2: waves of 64 x 32
@@ -1083,8 +1092,7 @@ hipError_t launch_gemm_typed(const GemmDesc& g, const GemmDesc* d_work, int nwor
         case TV_64x64: TPT_LAUNCH(64, 64, 0); break;
         case TV_32x64: TPT_LAUNCH(32, 64, 0); break;
         case TV_128x128_K32:
-            if constexpr (PREC == GP_BF16X3) return hipErrorInvalidValue;
-            else TPT_LAUNCH(128, 128, 1);
+            TPT_LAUNCH(128, 128, 1);
             break;
         case TV_128x128_W8:
             if constexpr (PREC == GP_BF16X3) return hipErrorInvalidValue;

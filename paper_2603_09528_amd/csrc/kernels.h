@@ -26,8 +26,8 @@ enum Epilogue {
 };
 
 // Tile shapes (BM x BN) compiled for every precision; the autotuner picks.
-// TV_128x128_K32: 128 x 128 with a 32-deep K tile in a single LDS buffer
-// (FP64 and FP32 only).
+// TV_128x128_K32: 128 x 128 with a deep K tile in a single LDS buffer (32
+// deep for FP64 and FP32, 64 deep for BF16X3).
 // TV_128x128_P: the 128 x 128 tile in a persistent grid that loads the next
 // tile's first K tile during the current one (FP64 / FP32, interior tiles only).
 // TV_128x128_P8: the same with eight waves of 64 x 32 instead of four of
