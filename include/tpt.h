@@ -217,6 +217,16 @@ int tpt_solve(tpt_plan plan, const double *rhs, double *out, void *workspace,
 /* Info of the plan's last solve (call after synchronising its stream). */
 int tpt_solve_info(tpt_plan plan, tpt_info *info);
 
+/* Residual of the plan's operator, r = f - A x: A the 7-point Kronecker sum
+ * of §2.2.2 with the plan's boundary rows (L for Poisson, I - alpha L_I for
+ * Helmholtz, L_I holding only the implicit directions), evaluated in FP64
+ * and stored in FP32 — the residual the mixed-precision refinement forms
+ * (§4.1 checks an FP64 solve's residual at round-off).  x, f: nrhs device
+ * arrays of Nx*Ny*Nz doubles each (x fastest, the solve's layout); r: the
+ * same count of floats, caller-owned.  Enqueued on stream; allocates
+ * nothing.  TPT_ERR_INVALID for a NULL or host-only plan or a NULL array. */
+int tpt_residual(tpt_plan plan, const double *x, const double *f, float *r, void *stream);
+
 /* tpt_solve for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
  * workspace is a static device array of tpt_static_workspace_capacity()

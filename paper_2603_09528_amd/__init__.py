@@ -93,6 +93,7 @@ def lib():
             "tpt_solve": (i, [vp, vp, vp, vp, sz, vp]),
             "tpt_solve_info": (i, [vp, ctypes.POINTER(Info)]),
             "tpt_solve_noalloc": (i, [vp, vp, vp, vp]),
+            "tpt_residual": (i, [vp, vp, vp, vp, vp]),
             "tpt_static_workspace_capacity": (sz, []),
             "tpt_divergence": (i, [vp, vp, vp, vp, vp, vp]),
             "tpt_gradient_update": (i, [vp, vp, vp, vp, vp, vp]),
@@ -130,7 +131,7 @@ def lib():
 
 EXPORTED = ("tpt_plan_desc_init", "tpt_plan_create", "tpt_plan_destroy", "tpt_plan_shape",
             "tpt_plan_workspace_bytes", "tpt_plan_eigen", "tpt_plan_operator", "tpt_plan_transforms", "tpt_plan_fused", "tpt_solve",
-            "tpt_solve_info", "tpt_solve_noalloc", "tpt_static_workspace_capacity", "tpt_divergence", "tpt_gradient_update",
+            "tpt_solve_info", "tpt_solve_noalloc", "tpt_residual", "tpt_static_workspace_capacity", "tpt_divergence", "tpt_gradient_update",
             "tpt_project_workspace_bytes", "tpt_project", "tpt_batch_create", "tpt_batch_destroy", "tpt_batch_workspace_bytes",
             "tpt_batch_solve", "tpt_batch_info", "tpt_autotune", "tpt_autotune_save", "tpt_autotune_load",
             "tpt_server_create", "tpt_server_submit", "tpt_server_poll", "tpt_server_drain",
@@ -311,6 +312,20 @@ class Plan:
         inf = Info()
         _check(lib().tpt_solve_info(self._h, ctypes.byref(inf)))
         return inf
+
+    def residual(self, x, f, r=None, stream=None):
+        """r = f - A x of the plan's operator in FP64, stored as float32
+        (see tpt_residual); x, f float64 CUDA tensors of self.shape."""
+        import torch
+        _require_f64_cuda(x, self.shape, "x")
+        _require_f64_cuda(f, self.shape, "f")
+        if r is None:
+            r = torch.empty(x.shape, dtype=torch.float32, device=x.device)
+        if not isinstance(r, torch.Tensor) or r.dtype != torch.float32 or r.device != x.device \
+                or not r.is_contiguous() or r.numel() != x.numel():
+            raise ValueError("r must be a contiguous float32 tensor on x's device with x's size")
+        _check(lib().tpt_residual(self._h, _ptr(x), _ptr(f), _ptr(r), _stream(stream)))
+        return r
 
     # ---- projection step (pressure plans: cell-centred, periodic / Neumann) ----
     def velocity_shapes(self):

@@ -202,7 +202,7 @@ struct StencilDesc {
     const double* x;
     const double* f;
     float* r;
-    double* partials;
+    double* partials;  // 2 doubles per block (sums of r^2 and f^2), or null
     // singular problems: f on the last z plane is read as f - S * wscale, with
     // S = *wsum = sum dV f (the right-hand-side check) and wscale = 1 / (the
     // area sum dV of that plane), so that sum dV r = 0 (null = no change)

@@ -593,7 +593,7 @@ __device__ __forceinline__ void residual_block(const StencilDesc& st, long long 
         }
     }
     block_sum2<RES_NT>(sr, sf, red);
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && st.partials) {
         st.partials[2 * lb] = sr;
         st.partials[2 * lb + 1] = sf;
     }
@@ -703,7 +703,7 @@ __device__ __forceinline__ void residual_pair_block(const StencilDesc& st, long 
         xc = xp;
     }
     block_sum2<RES_NT>(sr, sf, red);
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && st.partials) {
         st.partials[2 * lb] = sr;
         st.partials[2 * lb + 1] = sf;
     }

@@ -263,8 +263,11 @@ StencilDesc plan_stencil(const tpt_plan_s* p, const double* x, const double* f, 
     st.nx = p->N[0];
     st.ny = p->N[1];
     st.nz = p->N[2];
-    st.ax = p->buf.ax; st.bx = p->buf.bx; st.cx = p->buf.cx;
-    st.ay = p->buf.ay; st.by = p->buf.by; st.cy = p->buf.cy;
+    // an explicit direction (implicit options yz, z) is not part of the
+    // operator: zero coefficients
+    const double* zx = p->buf.zeros;
+    st.ax = p->tx ? p->buf.ax : zx; st.bx = p->tx ? p->buf.bx : zx; st.cx = p->tx ? p->buf.cx : zx;
+    st.ay = p->ty ? p->buf.ay : zx; st.by = p->ty ? p->buf.by : zx; st.cy = p->ty ? p->buf.cy : zx;
     st.az = p->buf.az; st.bz = p->buf.bz; st.cz = p->buf.cz;
     st.perx = p->op[0].periodic ? 1 : 0;
     st.pery = p->op[1].periodic ? 1 : 0;
@@ -697,6 +700,21 @@ int tpt_solve(tpt_plan plan, const double* rhs, double* out, void* workspace, si
     int cur = 0;
     if (hipGetDevice(&cur) == hipSuccess && cur != plan->device) TPT_HIP(hipSetDevice(plan->device));
     return solve_one(plan, rhs, out, workspace, workspace_bytes, (hipStream_t)stream);
+}
+
+int tpt_residual(tpt_plan plan, const double* x, const double* f, float* r, void* stream) {
+    if (!plan) return fail(TPT_ERR_INVALID, "NULL plan");
+    if (plan->host_only) return fail(TPT_ERR_INVALID, "host-only plan has no device operator");
+    if (!x || !f || !r) return fail(TPT_ERR_INVALID, "NULL array");
+    int cur = 0;
+    if (hipGetDevice(&cur) == hipSuccess && cur != plan->device) TPT_HIP(hipSetDevice(plan->device));
+    for (int q = 0; q < plan->desc.nrhs; ++q) {
+        const size_t o = (size_t)q * plan->dof;
+        StencilDesc st = plan_stencil(plan, x + o, f + o, r + o, nullptr, nullptr);
+        hipError_t e = launch_residual(st, (hipStream_t)stream);
+        if (e != hipSuccess) return fail(TPT_ERR_HIP, std::string("residual launch: ") + hipGetErrorString(e));
+    }
+    return TPT_OK;
 }
 
 int tpt_solve_info(tpt_plan plan, tpt_info* info) {
