@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--variants-n", type=int, default=1024,
                     help="cells per direction of the FF/FG/GF/GG comparison (0 disables it)")
     ap.add_argument("--variants-steps", type=int, default=3)
+    ap.add_argument("--slab-steps", type=int, default=5,
+                    help="timed solves of the 1024x1024x128 z slab, the per-GPU share of a 1024^3 grid "
+                         "on 8 GPUs (0 disables it)")
     ap.add_argument("--stretch-steps", type=int, default=20,
                     help="timed solves per stretching parameter of the beta comparison (0 disables it)")
     ap.add_argument("--preheat", type=float, default=0.15,
@@ -428,6 +431,41 @@ def run_stretching(args, T, W):
     return res
 
 
+def run_slab(args, T, W):
+    """The kernels at one GPU's share of a sharded grid: the 1024^3 uniform
+    Poisson problem (periodic x, Neumann y and z) cut into 8 z slabs of
+    1024x1024x128, one per GPU.  Each slab's x and y transforms are local;
+    its Thomas lines are the local part of the lines that cross the slabs.
+    FP64, x by FFT and y by GEMM (FG) and both by GEMM (GG)."""
+    import torch
+    prob = W.make_problem((1024, 1024, 128), (0.0, 0.0, 0.0), (W.PP, W.NN, W.NN), name="slab1024x1024x128")
+    f = torch.from_numpy(W.rhs(prob, 9)).to("cuda")
+    out = torch.empty_like(f)
+    res = {"workload": "1024x1024x128 z slab of the 1024^3 uniform Poisson problem (periodic x, Neumann y, z), "
+                       "FP64: one GPU's share on 8 GPUs", "dof": prob.dof}
+    for name, dx in (("FG", False), ("GG", True)):
+        plan = T.Plan.from_problem(prob, dense_x=dx, dense_y=True)
+        T.autotune([plan])
+        ws = plan.workspace()
+        preheat(lambda: plan.solve(f, out, ws), args.preheat)
+        T.timing_collect()
+        T.timing_enable(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.slab_steps):
+            plan.solve(f, out, ws)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.slab_steps
+        T.timing_enable(False)
+        kern = T.timing_collect()
+        res[name] = {"ms_per_solve": ms, "gdofs": prob.dof / (ms * 1e-3) / 1e9, "transforms": plan.transforms,
+                     "kernels_ms_per_solve": {k: v[0] / args.slab_steps for k, v in kern.items()}}
+        log(f"slab {name}: {ms:.2f} ms/solve, {res[name]['gdofs']:.2f} GDOF/s, transforms {plan.transforms}")
+        del plan, ws
+        torch.cuda.empty_cache()
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -656,9 +694,14 @@ def main():
     if args.stretch_steps > 0:
         stretching = run_stretching(args, T, W)
 
+    slab = None
+    if args.slab_steps > 0:
+        slab = run_slab(args, T, W)
+
     if not results:
         print(json.dumps({"sections_only": True, "serving": serving, "helmholtz_1024x768x512_3rhs": helm,
-                          "batch64": batch, "transform_variants": variants, "stretching": stretching}))
+                          "batch64": batch, "transform_variants": variants, "stretching": stretching,
+                          "slab": slab}))
         return
 
     # ---- headline: fastest mode that meets its bar against the oracle ----------
@@ -729,6 +772,7 @@ def main():
         "batch64": batch,
         "transform_variants": variants,
         "stretching": stretching,
+        "slab_1024x1024x128": slab,
         "gemm_tiles": tiles,
     }
     print(json.dumps(line))
