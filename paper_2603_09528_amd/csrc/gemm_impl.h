@@ -112,15 +112,16 @@ __device__ __forceinline__ void gemm_tile_f(const GemmDesc& g, long long lb, TM*
 
     // fixed per-thread load geometry: A slot t covers row tid/BK + t*(NT/BK), column tid%BK
     const int arow = tid / BK, acol = tid % BK;
-    // interior tiles (whole tile inside M x N, K a multiple of BK) load without predicates
-    const bool full = mrem >= BM && nrem >= BN && (K % BK) == 0;
+    // interior tiles (whole tile inside M x N) load without predicates; a K
+    // that is not a multiple of BK takes the guarded loads in its last K step
+    const bool full = mrem >= BM && nrem >= BN;
     TM ra[LA], rb[LB];
     // FULL is a compile-time copy of `full`: the K loop is instantiated once
     // per case, so the interior loop has no divergent loads and the loads of
     // tile k+1 stay in flight while tile k is multiplied
     auto gload = [&](int k0, auto full_tag) {
         constexpr bool FULL = decltype(full_tag)::value;
-        if constexpr (FULL) {
+        if (FULL && k0 + BK <= K) {
             // offsets within the tile are small and non-negative: 32-bit
             // unsigned offsets from the block's (uniform) operand bases
 #pragma unroll
@@ -744,6 +745,9 @@ __device__ __forceinline__ void gemm_tile_b(const GemmDesc& g, long long lb, uin
     // y pass:       A = basis planes [m][k], B = data [k][n]
     const long long offA = (long long)b * g.sA + (long long)m0 * lda;
     const long long offB = BNK ? (long long)b * g.sB + (long long)n0 * ldb : (long long)b * g.sB + n0;
+    // the basis planes' rows: their own stride where given (padded to 16 bytes)
+    const int ldpl = g.ldp ? g.ldp : (BNK ? ldb : lda);
+    const long long offP = BNK ? (long long)b * g.sB + (long long)n0 * ldpl : (long long)b * g.sA + (long long)m0 * ldpl;
 
     f4 acc[C::MI][C::NI];
 #pragma unroll
@@ -762,8 +766,10 @@ __device__ __forceinline__ void gemm_tile_b(const GemmDesc& g, long long lb, uin
     const bool aligned_data = BNK ? ((lda % 8) == 0 && (offA % 8) == 0 && ((((uintptr_t)g.A) & 31) == 0))
                                   : ((ldb % 2) == 0 && (offB % 2) == 0 &&
                                      ((((uintptr_t)g.B) & (2 * sizeof(TD) - 1)) == 0));
-    const bool aligned_planes = BNK ? ((ldb % 8) == 0 && (offB % 8) == 0) : ((lda % 8) == 0 && (offA % 8) == 0);
-    const bool full = mrem >= BM && nrem >= BN && (K % BK) == 0 && aligned_data && aligned_planes;
+    const bool aligned_planes = (ldpl % 8) == 0 && (offP % 8) == 0;
+    // interior tiles load without predicates; a K that is not a multiple of
+    // BK takes the guarded loads in its last K step only
+    const bool full = mrem >= BM && nrem >= BN && aligned_data && aligned_planes;
     auto gload = [&](int k0, auto full_tag) {
         constexpr bool FULL = decltype(full_tag)::value;
         // basis planes
@@ -771,8 +777,8 @@ __device__ __forceinline__ void gemm_tile_b(const GemmDesc& g, long long lb, uin
         for (int t = 0; t < (BNK ? CB : CA); ++t) {
             const int c = tid + NT * t;
             const int row = c / (BK / 8), kc = c % (BK / 8);
-            const long long off = (BNK ? offB + (long long)row * ldb : offA + (long long)row * lda) + k0 + kc * 8;
-            if constexpr (FULL) {
+            const long long off = offP + (long long)row * ldpl + k0 + kc * 8;
+            if (FULL && k0 + BK <= K) {
                 rph[t] = *(const u16x8*)(g.basis_hi + off);
                 rpl[t] = *(const u16x8*)(g.basis_lo + off);
             } else {
@@ -788,7 +794,7 @@ __device__ __forceinline__ void gemm_tile_b(const GemmDesc& g, long long lb, uin
                 const int c = tid + NT * t;
                 const int row = c / (BK / 8), kc = c % (BK / 8);
                 const TD* pa = (const TD*)g.A + offA + (long long)row * lda + k0 + kc * 8;
-                if constexpr (FULL) {
+                if (FULL && k0 + BK <= K) {
                     if constexpr (sizeof(TD) == 4) {
                         const float4 p0 = *(const float4*)pa, p1 = *(const float4*)(pa + 4);
                         rd[t][0] = p0.x; rd[t][1] = p0.y; rd[t][2] = p0.z; rd[t][3] = p0.w;
@@ -819,7 +825,7 @@ __device__ __forceinline__ void gemm_tile_b(const GemmDesc& g, long long lb, uin
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
                     const int k = k0 + kc * 8 + e;
-                    if constexpr (FULL) {
+                    if (FULL && k0 + BK <= K) {
                         if constexpr (sizeof(TD) == 4) {
                             const float2 q = *(const float2*)(pb + (long long)k * ldb);
                             rd[2 * t][e] = q.x;

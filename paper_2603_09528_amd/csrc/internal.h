@@ -39,10 +39,11 @@ struct DirBasis {
     double* d_q = nullptr;
     float* s_qinv = nullptr;         // FP32 copies
     float* s_q = nullptr;
-    uint16_t* h_qinv = nullptr;      // bf16 hi / lo planes
-    uint16_t* l_qinv = nullptr;
+    uint16_t* h_qinv = nullptr;      // bf16 hi / lo planes, rows of ldp elements
+    uint16_t* l_qinv = nullptr;      // (n rounded up to 8: 16-byte rows, zero padded)
     uint16_t* h_q = nullptr;
     uint16_t* l_q = nullptr;
+    int ldp = 0;
     int fast_kind = -1;              // XformKind of the fast transform, -1 = none
     double2* d_twiddle = nullptr;    // e^{-2 pi i k/n}, k < n/2 (fast transform)
     double2* d_qtw = nullptr;        // e^{-i pi k/2n}, k <= n/2 (DCT, DST)

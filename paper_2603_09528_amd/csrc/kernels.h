@@ -64,6 +64,7 @@ struct GemmDesc {
     int tA, tB, tC;         // DType of A, B, C in global memory (basis planes ignore tA/tB)
     const uint16_t* basis_hi;
     const uint16_t* basis_lo;
+    int ldp;                // row stride of basis_hi / basis_lo (0: lda or ldb, as the basis operand)
     int basis_is_A;
     int epi;                // Epilogue
     double* partials;       // EPI_ACCUM_F64: 2 doubles per block

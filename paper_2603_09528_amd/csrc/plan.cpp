@@ -89,10 +89,14 @@ std::shared_ptr<DirBasis> basis_cache_get(int ncells, const double* faces, int b
         const size_t o_q = o_qinv + al(8 * nn);
         const size_t o_sqinv = o_q + al(8 * nn);
         const size_t o_sq = o_sqinv + al(4 * nn);
+        // bf16 planes: rows padded to a multiple of 8 elements (16 bytes), so
+        // the split-BF16 tiles load them as vectors whatever n is
+        const int ldp = (n + 7) / 8 * 8;
+        const size_t np = (size_t)n * ldp;
         const size_t o_hqinv = o_sq + al(4 * nn);
-        const size_t o_lqinv = o_hqinv + al(2 * nn);
-        const size_t o_hq = o_lqinv + al(2 * nn);
-        const size_t o_lq = o_hq + al(2 * nn);
+        const size_t o_lqinv = o_hqinv + al(2 * np);
+        const size_t o_hq = o_lqinv + al(2 * np);
+        const size_t o_lq = o_hq + al(2 * np);
         int fk = -1;
         if (b->eig.analytic && fft_supported(n)) {
             if (op.periodic) fk = UT_FOURIER;
@@ -100,7 +104,7 @@ std::shared_ptr<DirBasis> basis_cache_get(int ncells, const double* faces, int b
             else if (op.loc == LOC_C && op.bc_lo == BC_D && op.bc_hi == BC_D) fk = UT_DST;
         }
         const bool fft = fk >= 0;
-        const size_t o_tw = o_lq + al(2 * nn);
+        const size_t o_tw = o_lq + al(2 * np);
         const size_t o_qtw = o_tw + (fft ? al(16 * (size_t)(n / 2)) : 0);
         const size_t total = o_qtw + (fft ? al(16 * (size_t)(n / 2 + 1)) : 0);
         std::vector<char> host(total, 0);
@@ -144,13 +148,15 @@ std::shared_ptr<DirBasis> basis_cache_get(int ncells, const double* faces, int b
         for (size_t e = 0; e < nn; ++e) {
             sqinv[e] = (float)qinv[e];
             sq[e] = (float)q[e];
+            const size_t ep = e / n * ldp + e % n;  // padded position (padding stays 0)
             uint16_t h = host_bf16((float)qinv[e]);
-            hqinv[e] = h;
-            lqinv[e] = host_bf16((float)(qinv[e] - (double)host_bf16_to_f(h)));
+            hqinv[ep] = h;
+            lqinv[ep] = host_bf16((float)(qinv[e] - (double)host_bf16_to_f(h)));
             h = host_bf16((float)q[e]);
-            hq[e] = h;
-            lq[e] = host_bf16((float)(q[e] - (double)host_bf16_to_f(h)));
+            hq[ep] = h;
+            lq[ep] = host_bf16((float)(q[e] - (double)host_bf16_to_f(h)));
         }
+        b->ldp = ldp;
         void* blk = nullptr;
         if (hipMalloc(&blk, total) != hipSuccess) {
             err = "out of device memory for an eigenbasis";

@@ -150,6 +150,7 @@ GemmDesc stage_gemm(const tpt_plan_s* p, int stage, int prec, const void* in, in
     }
     g.basis_hi = bh;
     g.basis_lo = bl;
+    g.ldp = bh ? b->ldp : 0;
     g.epi = epi;
     g.partials = partials;
     g.tC = tout;
