@@ -240,8 +240,11 @@ __device__ __forceinline__ void gemm_tile_f(const GemmDesc& g, long long lb, TM*
 }
 
 // ---------------------------------------------------------------------------
-// Persistent form of the FP64/FP32 tile for problems whose tiles are all
-// interior (M, N multiples of 128, K a multiple of 16).  Each block walks
+// Persistent form of the FP64/FP32 tile.  Edge tiles (M or N not a multiple
+// of 128) read their operands through buffer resources that end at the
+// operand's last row, so rows past it read zero, and store only inside M x N;
+// a K that is not a multiple of 16 zeroes the elements past K in its last K
+// step (both operands, so that nothing else meets a zero).  Each block walks
 // tiles v = blockIdx.x, + gridDim.x, ... (numbered per XCD as in gemm_kernel)
 // and, during the last K step of a tile, already loads the first K tile of
 // its next tile, which it stores to the free LDS buffer before writing the
@@ -262,6 +265,11 @@ constexpr int BUF_RSRC_WORD3 = 0x00020000;  // raw 32-bit buffer (gfx9 family)
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, 0x7fffffff, BUF_RSRC_WORD3);
 }
+// buffer resource over [base, base + bytes), bytes clamped to the 31-bit range
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc_n(const void* base, long long bytes) {
+    const int n = bytes <= 0 ? 0 : (bytes > 0x7ffffff0LL ? 0x7ffffff0 : (int)bytes);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, n, BUF_RSRC_WORD3);
+}
 template <typename T> struct BufIO;
 template <> struct BufIO<double> {
     static __device__ __forceinline__ double ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
@@ -280,7 +288,7 @@ template <> struct BufIO<float> {
     }
 };
 
-template <typename TM, typename TA, typename TB, typename TC, int EPI, bool BNK, int WN = 64>
+template <typename TM, typename TA, typename TB, typename TC, int EPI, bool BNK, int WN = 64, bool EDGE = false>
 __device__ __forceinline__ void gemm_tiles_persist_f(const GemmDesc& g, long long ntiles, TM* smem, double* red) {
     constexpr int BM = 128, BN = 128, BK = 16;
     typedef TileCfg<BM, BN, 64, WN> C;
@@ -296,19 +304,41 @@ __device__ __forceinline__ void gemm_tiles_persist_f(const GemmDesc& g, long lon
     const int wm = w / C::WAVES_N, wn = w % C::WAVES_N;
     const int arow = tid / BK, acol = tid % BK;
     const int lda = g.lda, ldb = g.ldb, ldc = g.ldc;
-    const int nk = g.K / BK;
+    const int M = g.M, N = g.N, K = g.K;
+    // EDGE: M, N or K ragged (the launcher picks it); else every tile is
+    // interior and none of the edge handling below is compiled in
+    const int nk = EDGE ? (K + BK - 1) / BK : K / BK;
+    const bool ktail = EDGE && (K % BK) != 0;
     const long long grid = gridDim.x;
     // K-step scalar offsets (bytes) of the A and B tiles
     const unsigned kstepA = BK * (unsigned)sizeof(TA);
     const unsigned kstepB = BNK ? BK * (unsigned)sizeof(TB) : (unsigned)(BK * ldb) * (unsigned)sizeof(TB);
 
-    auto tile_ptrs = [&](long long v, const TA*& a, const TB*& bp, TC*& c) {
+    // a tile's operand and result resources: each ends where its operand's
+    // rows of this batch entry end (A: rows past M; B: rows past N (x pass)
+    // or past K (y pass); C: rows past M), so edge tiles read zeros there and
+    // nothing past them is ever touched; mrem / nrem bound the stores
+    auto tile_rsrc = [&](long long v, __amdgpu_buffer_rsrc_t& rA, __amdgpu_buffer_rsrc_t& rB,
+                         __amdgpu_buffer_rsrc_t& rC, int& mrem, int& nrem) {
         int b, tm, tn;
         decode_tile(g, xcd_block(v, ntiles), b, tm, tn);
         const int m0 = tm * BM, n0 = tn * BN;
-        a = (const TA*)g.A + (long long)b * g.sA + (long long)m0 * lda;
-        bp = BNK ? (const TB*)g.B + (long long)b * g.sB + (long long)n0 * ldb : (const TB*)g.B + (long long)b * g.sB + n0;
-        c = (TC*)g.C + (long long)b * g.sC + (long long)m0 * ldc + n0;
+        mrem = M - m0;
+        nrem = N - n0;
+        const TA* a = (const TA*)g.A + (long long)b * g.sA + (long long)m0 * lda;
+        const TB* bp = BNK ? (const TB*)g.B + (long long)b * g.sB + (long long)n0 * ldb
+                           : (const TB*)g.B + (long long)b * g.sB + n0;
+        TC* c = (TC*)g.C + (long long)b * g.sC + (long long)m0 * ldc + n0;
+        if constexpr (EDGE) {
+            rA = buf_rsrc_n(a, (long long)mrem * lda * (long long)sizeof(TA));
+            rB = BNK ? buf_rsrc_n(bp, (long long)nrem * ldb * (long long)sizeof(TB))
+                     : buf_rsrc_n(bp, ((long long)K * ldb - n0) * (long long)sizeof(TB));
+            rC = buf_rsrc_n(c, ((long long)mrem * ldc - n0) * (long long)sizeof(TC));
+        } else {
+            rA = buf_rsrc(a);
+            rB = buf_rsrc(bp);
+            rC = buf_rsrc(c);
+        }
     };
     TM ra[LA], rb[LB];
     auto gload = [&](__amdgpu_buffer_rsrc_t rA, __amdgpu_buffer_rsrc_t rB, int kt) {
@@ -326,6 +356,18 @@ __device__ __forceinline__ void gemm_tiles_persist_f(const GemmDesc& g, long lon
                 vo = (unsigned)(((e / BN) * ldb + e % BN) * (int)sizeof(TB));
             }
             rb[q] = (TM)BufIO<TB>::ld(rB, vo, kt * kstepB);
+        }
+        // the last K step of a K that is not a multiple of BK: elements past
+        // K (the next row's or slab's values) are zero in both operands
+        if (ktail && kt == nk - 1) {
+            const bool kin = kt * BK + acol < K;
+#pragma unroll
+            for (int q = 0; q < LA; ++q) ra[q] = kin ? ra[q] : (TM)0;
+#pragma unroll
+            for (int q = 0; q < LB; ++q) {
+                if constexpr (BNK) rb[q] = kin ? rb[q] : (TM)0;
+                else rb[q] = kt * BK + (tid + NT * q) / BN < K ? rb[q] : (TM)0;
+            }
         }
     };
     auto sstore = [&](int buf) {
@@ -346,11 +388,9 @@ __device__ __forceinline__ void gemm_tiles_persist_f(const GemmDesc& g, long lon
 
     long long v = blockIdx.x;
     if (v >= ntiles) return;
-    const TA* pa;
-    const TB* pb;
-    TC* pc;
-    tile_ptrs(v, pa, pb, pc);
-    __amdgpu_buffer_rsrc_t rA = buf_rsrc(pa), rB = buf_rsrc(pb), rC = buf_rsrc(pc);
+    __amdgpu_buffer_rsrc_t rA, rB, rC;
+    int mrem, nrem;
+    tile_rsrc(v, rA, rB, rC, mrem, nrem);
     gload(rA, rB, 0);
     sstore(0);
     __syncthreads();
@@ -364,14 +404,12 @@ __device__ __forceinline__ void gemm_tiles_persist_f(const GemmDesc& g, long lon
 #pragma unroll
             for (int j = 0; j < C::NI; ++j) acc[i][j] = MM::zero();
         __amdgpu_buffer_rsrc_t rAn = rA, rBn = rB, rCn = rC;
+        int mremn = mrem, nremn = nrem;
         for (int kt = 0; kt < nk; ++kt) {
             if (kt + 1 < nk) {
                 gload(rA, rB, kt + 1);
             } else if (more) {
-                tile_ptrs(v + grid, pa, pb, pc);
-                rAn = buf_rsrc(pa);
-                rBn = buf_rsrc(pb);
-                rCn = buf_rsrc(pc);
+                tile_rsrc(v + grid, rAn, rBn, rCn, mremn, nremn);
                 gload(rAn, rBn, 0);
             }
             const TM* a = As + buf * S::A_ELEMS + (wm * C::WM + lr) * S::PA + lg;
@@ -402,6 +440,9 @@ __device__ __forceinline__ void gemm_tiles_persist_f(const GemmDesc& g, long lon
             }
         }
         double se = 0.0, sx = 0.0;
+        // edge tiles store only the rows below M and the columns below N
+        const bool edge = EDGE && (mrem < BM || nrem < BN);
+        const int wrow = wm * C::WM + MM::row(lg, 0), wcol = wn * C::WN + lr;
 #pragma unroll
         for (int i = 0; i < C::MI; ++i) {
 #pragma unroll
@@ -410,6 +451,7 @@ __device__ __forceinline__ void gemm_tiles_persist_f(const GemmDesc& g, long lon
                 for (int r = 0; r < 4; ++r) {
                     const unsigned so = (unsigned)(((i * 16 + MM::row(0, r)) * ldc + j * 16) * (int)sizeof(TC));
                     const double val = (double)acc[i][j][r];
+                    if (edge && (wrow + i * 16 + MM::row(0, r) >= mrem || wcol + j * 16 >= nrem)) continue;
                     if constexpr (EPI == EPI_ACCUM_F64) {
                         const double x = BufIO<double>::ld(rC, tbase, so) + val;
                         BufIO<double>::st(x, rC, tbase, so);
@@ -434,6 +476,8 @@ __device__ __forceinline__ void gemm_tiles_persist_f(const GemmDesc& g, long lon
         rA = rAn;
         rB = rBn;
         rC = rCn;
+        mrem = mremn;
+        nrem = nremn;
     }
 }
 
@@ -464,11 +508,6 @@ template <int BM, int BN> struct WlCfg {
     static constexpr int LA = BM * BK / NT, LB = BN * BK / NT;
 };
 
-// buffer resource over [base, base + bytes), bytes clamped to the 31-bit range
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc_n(const void* base, long long bytes) {
-    const int n = bytes <= 0 ? 0 : (bytes > 0x7ffffff0LL ? 0x7ffffff0 : (int)bytes);
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, n, BUF_RSRC_WORD3);
-}
 
 // One tile of a work list: its problem's operands and its position.
 struct WlTile {
@@ -1011,14 +1050,14 @@ __global__ TPT_GEMM_ATTR void gemm_kernel(GemmDesc g) {
     GemmKernel<PREC, TA, TB, TC, EPI, BM, BN, BNK, DEEP>::tile(g, xcd_block(blockIdx.x, gridDim.x));
 }
 
-// Persistent single-problem kernel (interior tiles only, FP64 / FP32): four
+// Persistent single-problem kernel (FP64 / FP32): four
 // waves of 64 x 64 (WN = 64, 256 threads) or eight of 64 x 32 (WN = 32).
-template <int PREC, typename TA, typename TB, typename TC, int EPI, bool BNK, int WN = 64>
+template <int PREC, typename TA, typename TB, typename TC, int EPI, bool BNK, int WN = 64, bool EDGE = false>
 __global__ __launch_bounds__((TileCfg<128, 128, 64, WN>::NT)) void gemm_persist_kernel(GemmDesc g, long long ntiles) {
     typedef typename std::conditional<PREC == GP_F64, double, float>::type T;
     __shared__ __attribute__((aligned(16))) T smem[SmemF<T, 128, 128, BNK, 16, 2>::TOTAL];
     __shared__ double red[2 * (TileCfg<128, 128, 64, WN>::NT / 64)];
-    gemm_tiles_persist_f<T, TA, TB, TC, EPI, BNK, WN>(g, ntiles, smem, red);
+    gemm_tiles_persist_f<T, TA, TB, TC, EPI, BNK, WN, EDGE>(g, ntiles, smem, red);
 }
 
 template <int PREC, typename TA, typename TB, typename TC, int EPI, int BM, int BN, bool BNK, int DEEP>
@@ -1113,14 +1152,20 @@ hipError_t launch_gemm_typed(const GemmDesc& g, const GemmDesc* d_work, int nwor
                     TPT_LAUNCH(128, 128, 2);
                     break;
                 }
-                if (g.M % 128 || g.N % 128 || g.K % 16 || g.K < 16) return hipErrorInvalidValue;
+                if (g.K < 1) return hipErrorInvalidValue;
                 const long long grid = persistent_gemm_grid(blocks);
-                if (variant == TV_128x128_P)
-                    TPT_KLAUNCH((gemm_persist_kernel<PREC, TA, TB, TC, EPI, BNK, 64>), dim3((unsigned)grid),
-                                dim3(TileCfg<128, 128, 64, 64>::NT), 0, s, g, blocks);
-                else
-                    TPT_KLAUNCH((gemm_persist_kernel<PREC, TA, TB, TC, EPI, BNK, 32>), dim3((unsigned)grid),
-                                dim3(TileCfg<128, 128, 64, 32>::NT), 0, s, g, blocks);
+                const bool edge = g.M % 128 || g.N % 128 || g.K % 16;
+#define TPT_PERSIST(WN_, EDGE_)                                                                        \
+    TPT_KLAUNCH((gemm_persist_kernel<PREC, TA, TB, TC, EPI, BNK, WN_, EDGE_>), dim3((unsigned)grid), \
+                dim3(TileCfg<128, 128, 64, WN_>::NT), 0, s, g, blocks)
+                if (variant == TV_128x128_P) {
+                    if (edge) TPT_PERSIST(64, true);
+                    else TPT_PERSIST(64, false);
+                } else {
+                    if (edge) TPT_PERSIST(32, true);
+                    else TPT_PERSIST(32, false);
+                }
+#undef TPT_PERSIST
             }
             break;
         default: return hipErrorInvalidValue;

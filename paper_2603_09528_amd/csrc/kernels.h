@@ -29,7 +29,8 @@ enum Epilogue {
 // TV_128x128_K32: 128 x 128 with a deep K tile in a single LDS buffer (32
 // deep for FP64 and FP32, 64 deep for BF16X3).
 // TV_128x128_P: the 128 x 128 tile in a persistent grid that loads the next
-// tile's first K tile during the current one (FP64 / FP32, interior tiles only).
+// tile's first K tile during the current one (FP64 / FP32; edge tiles and a
+// ragged K through range-limited buffer resources and masks).
 // TV_128x128_P8: the same with eight waves of 64 x 32 instead of four of
 // 64 x 64 (half the accumulator registers per wave, twice the waves).
 // TV_128x128_W8: the plain 128 x 128 tile over eight waves of 64 x 32 (FP64 /
@@ -38,7 +39,7 @@ enum TileVariant {
     TV_128x128 = 0, TV_64x128 = 1, TV_128x64 = 2, TV_64x64 = 3, TV_32x64 = 4, TV_128x128_K32 = 5,
     TV_128x128_P = 6, TV_128x128_P8 = 7, TV_128x128_W8 = 8, TV_COUNT = 9
 };
-// the persistent tiles (interior tiles only, FP64 / FP32)
+// the persistent tiles (FP64 / FP32)
 inline bool tv_persistent(int v) { return v == TV_128x128_P || v == TV_128x128_P8; }
 // Grid of the persistent GEMM: two blocks per CU (a multiple of 8, so that a
 // block keeps its XCD), at most the tile count.

@@ -58,8 +58,8 @@ static size_t append(std::vector<char>& blob, const std::vector<T>& v) {
 
 int MultiExec::add_gemm_stage(int stage, int prec, const std::vector<GemmDesc>& gs, const std::vector<char>& use,
                               std::vector<long long>* nb) {
-    // A problem whose tiles are all interior runs the single-problem
-    // persistent tile, one launch per problem, while there are at most four
+    // A problem whose single solve runs the persistent tile runs it here too,
+    // one launch per problem, while there are at most four
     // of them (large grids: each launch fills the GPU); the other FP64 / FP32
     // problems share one work-list launch of the persistent work-list tile;
     // anything else (BF16x3, extents past the work-list kernel's 32-bit

@@ -108,9 +108,12 @@ int choose_variant(int prec, int kind, int M, int N, int K) {
         auto it = g_tune.find(tune_key(prec, kind, M, N, K));
         if (it != g_tune.end()) return it->second;
     }
-    // heuristic: the persistent 128 x 128 tile where every tile is interior
-    // (FP64 / FP32); else least padded area, then the larger tile
-    if (prec != GP_BF16X3 && M % 128 == 0 && N % 128 == 0 && K % 16 == 0 && K >= 16) return TV_128x128_P;
+    // heuristic: the persistent 128 x 128 tile (FP64 / FP32) where its edge
+    // tiles waste at most a tenth of the work; else least padded area, then
+    // the larger tile
+    if (prec != GP_BF16X3 && K >= 16 &&
+        std::ceil(M / 128.0) * std::ceil(N / 128.0) * 128.0 * 128.0 <= 1.1 * (double)M * N)
+        return TV_128x128_P;
     int best = TV_128x128;
     double best_cost = 1e300;
     for (int v = 0; v <= TV_32x64; ++v) {
@@ -297,9 +300,8 @@ int stage_variant(const tpt_plan_s* p, int stage, const GemmDesc& g, int prec) {
         const int kind = (stage == ST_XF || stage == ST_XI) ? 0 : 1;
         v = choose_variant(prec, kind, g.M, g.N, g.K);
     }
-    // the persistent tile needs interior tiles; the x-pass table entry is
-    // shared by every row count, so check this problem's own shape
-    if (tv_persistent(v) && (prec == GP_BF16X3 || g.M % 128 || g.N % 128 || g.K % 16)) v = TV_128x128;
+    // the persistent tile is FP64 / FP32 only
+    if (tv_persistent(v) && prec == GP_BF16X3) v = TV_128x128;
     return v;
 }
 
@@ -792,7 +794,7 @@ int tpt_gemm(int prec, int b_nk, int variant, int M, int N, int K, int batch, co
         g.basis_is_A = b_nk ? 0 : 1;
     }
     int v = variant >= 0 ? variant : choose_variant(gp, b_nk ? 0 : 1, M, N, K);
-    if (variant < 0 && tv_persistent(v) && (gp == GP_BF16X3 || M % 128 || N % 128 || K % 16)) v = TV_128x128;
+    if (variant < 0 && tv_persistent(v) && gp == GP_BF16X3) v = TV_128x128;
     hipError_t e;
     {
         TimedScope ts("gemm_test", s);

@@ -116,6 +116,27 @@ def test_persistent_tiles_match_oracle(tmp_path, prec):
         T.autotune_load(str(table))
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_persistent_tiles_ragged_edges_match_oracle(tmp_path, prec):
+    """The persistent tiles on a grid whose GEMM extents are all ragged (x
+    pass: 1440 x 136 x 136, y pass: 120 x 136 x 120 over 12 slabs): edge
+    tiles and the K tail in the last K step, forced through the tuning table
+    (shapes no other test uses)."""
+    T = _T()
+    p = W.make_problem((136, 120, 12), (1.5, 2.0, 1.0), (W.NN, W.DD, W.NN))
+    f = W.rhs(p, 15)
+    ref = O.solve(p, f)
+    gp = {"fp64": 0, "fp32": 1}[prec]
+    table = tmp_path / "tiles.txt"
+    for v in (6, 7):
+        table.write_text(f"{gp} 0 0 136 136 {v}\n{gp} 1 120 136 120 {v}\n")
+        T.autotune_load(str(table))
+        kw = {} if prec == "fp64" else {"precision": prec, "rtol": 1e-13, "max_refine": 12}
+        got, _ = _solve(p, f, dense_x=True, **kw)
+        err = parity_error(p, got, ref)
+        assert err <= (FP64_TOL if prec == "fp64" else MIXED_TOL), (v, err)
+
+
 def test_autotune_records_thomas_kernel(tmp_path):
     """The autotuner times the Thomas kernels on the plan's lines, records the
     fastest (table kind 2), and solves with it still match the oracle."""
