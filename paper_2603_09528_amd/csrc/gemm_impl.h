@@ -121,7 +121,7 @@ __device__ __forceinline__ void gemm_tile_f(const GemmDesc& g, long long lb, TM*
     // tile k+1 stay in flight while tile k is multiplied
     auto gload = [&](int k0, auto full_tag) {
         constexpr bool FULL = decltype(full_tag)::value;
-        if (FULL && k0 + BK <= K) {
+        if constexpr (FULL) {
             // offsets within the tile are small and non-negative: 32-bit
             // unsigned offsets from the block's (uniform) operand bases
 #pragma unroll
@@ -173,8 +173,23 @@ __device__ __forceinline__ void gemm_tile_f(const GemmDesc& g, long long lb, TM*
     };
 
     const int nk = (K + BK - 1) / BK;
-    auto kloop = [&](auto full_tag) {
-    gload(0, full_tag);
+    // loop forms: 0 guarded loads, 1 interior (no predicates), 2 interior
+    // with a ragged K, whose last K step takes the guarded loads (its own
+    // instantiation, so the interior loop keeps its single basic block)
+    const bool ktail = (K % BK) != 0;
+    auto gload_step = [&](int kt, auto mode) {
+        constexpr int MODE = decltype(mode)::value;
+        if constexpr (MODE == 0) {
+            gload(kt * BK, std::false_type{});
+        } else if constexpr (MODE == 1) {
+            gload(kt * BK, std::true_type{});
+        } else {
+            if (kt == nk - 1) gload(kt * BK, std::false_type{});
+            else gload(kt * BK, std::true_type{});
+        }
+    };
+    auto kloop = [&](auto mode) {
+    gload_step(0, mode);
     if constexpr (NBUF == 2) {
         sstore(0);
         __syncthreads();
@@ -186,7 +201,7 @@ __device__ __forceinline__ void gemm_tile_f(const GemmDesc& g, long long lb, TM*
             sstore(0);
             __syncthreads();
         }
-        if (kt + 1 < nk) gload((kt + 1) * BK, full_tag);
+        if (kt + 1 < nk) gload_step(kt + 1, mode);
         const TM* a = As + cur * S::A_ELEMS + (wm * C::WM + lr) * S::PA + lg;
         const TM* bb = Bs + cur * S::B_ELEMS;
 #pragma unroll
@@ -211,8 +226,9 @@ __device__ __forceinline__ void gemm_tile_f(const GemmDesc& g, long long lb, TM*
         if constexpr (NBUF == 2) __syncthreads();
     }
     };
-    if (full) kloop(std::true_type{});
-    else kloop(std::false_type{});
+    if (!full) kloop(std::integral_constant<int, 0>{});
+    else if (!ktail) kloop(std::integral_constant<int, 1>{});
+    else kloop(std::integral_constant<int, 2>{});
     if constexpr (NBUF == 1) __syncthreads();
 
     double se = 0.0, sx = 0.0;
@@ -817,7 +833,7 @@ __device__ __forceinline__ void gemm_tile_b(const GemmDesc& g, long long lb, uin
             const int c = tid + NT * t;
             const int row = c / (BK / 8), kc = c % (BK / 8);
             const long long off = offP + (long long)row * ldpl + k0 + kc * 8;
-            if (FULL && k0 + BK <= K) {
+            if constexpr (FULL) {
                 rph[t] = *(const u16x8*)(g.basis_hi + off);
                 rpl[t] = *(const u16x8*)(g.basis_lo + off);
             } else {
@@ -833,7 +849,7 @@ __device__ __forceinline__ void gemm_tile_b(const GemmDesc& g, long long lb, uin
                 const int c = tid + NT * t;
                 const int row = c / (BK / 8), kc = c % (BK / 8);
                 const TD* pa = (const TD*)g.A + offA + (long long)row * lda + k0 + kc * 8;
-                if (FULL && k0 + BK <= K) {
+                if constexpr (FULL) {
                     if constexpr (sizeof(TD) == 4) {
                         const float4 p0 = *(const float4*)pa, p1 = *(const float4*)(pa + 4);
                         rd[t][0] = p0.x; rd[t][1] = p0.y; rd[t][2] = p0.z; rd[t][3] = p0.w;
@@ -864,7 +880,7 @@ __device__ __forceinline__ void gemm_tile_b(const GemmDesc& g, long long lb, uin
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
                     const int k = k0 + kc * 8 + e;
-                    if (FULL && k0 + BK <= K) {
+                    if constexpr (FULL) {
                         if constexpr (sizeof(TD) == 4) {
                             const float2 q = *(const float2*)(pb + (long long)k * ldb);
                             rd[2 * t][e] = q.x;
@@ -926,13 +942,28 @@ __device__ __forceinline__ void gemm_tile_b(const GemmDesc& g, long long lb, uin
     // workgroups per CU); the next tile is prefetched into registers while
     // the current one is multiplied
     const int nk = (K + BK - 1) / BK;
-    auto kloop = [&](auto full_tag) {
-    gload(0, full_tag);
+    // loop forms: 0 guarded loads, 1 interior (no predicates), 2 interior
+    // with a ragged K, whose last K step takes the guarded loads (its own
+    // instantiation, so the interior loop keeps its single basic block)
+    const bool ktail = (K % BK) != 0;
+    auto gload_step = [&](int kt, auto mode) {
+        constexpr int MODE = decltype(mode)::value;
+        if constexpr (MODE == 0) {
+            gload(kt * BK, std::false_type{});
+        } else if constexpr (MODE == 1) {
+            gload(kt * BK, std::true_type{});
+        } else {
+            if (kt == nk - 1) gload(kt * BK, std::false_type{});
+            else gload(kt * BK, std::true_type{});
+        }
+    };
+    auto kloop = [&](auto mode) {
+    gload_step(0, mode);
     for (int kt = 0; kt < nk; ++kt) {
         if (kt > 0) __syncthreads();  // every wave is done reading the previous tile
         sstore();
         __syncthreads();
-        if (kt + 1 < nk) gload((kt + 1) * BK, full_tag);
+        if (kt + 1 < nk) gload_step(kt + 1, mode);
         const uint16_t* ah = sm_hi;
         const uint16_t* al = sm_lo;
         const uint16_t* bh = ah + S::A_ELEMS;
@@ -976,8 +1007,9 @@ __device__ __forceinline__ void gemm_tile_b(const GemmDesc& g, long long lb, uin
         }
     }
     };
-    if (full) kloop(std::true_type{});
-    else kloop(std::false_type{});
+    if (!full) kloop(std::integral_constant<int, 0>{});
+    else if (!ktail) kloop(std::integral_constant<int, 1>{});
+    else kloop(std::integral_constant<int, 2>{});
     __syncthreads();
 
     double se = 0.0, sx = 0.0;
