@@ -22,7 +22,10 @@ Plain, slow, obviously-correct FP64 implementations:
   assembled operator (bordered by the volume-weighted mean for singular
   problems), for grids of at most a few thousand unknowns;
 * ``projection`` - the staggered divergence and gradient of §2.1 and the
-  projection step u = u* - G phi with L phi = D u*.
+  projection step u = u* - G phi with L phi = D u*;
+* ``navier_stokes`` - the advection term and one Runge--Kutta substep of
+  §2.1 (Eq. rk3): predictor, Helmholtz solve per velocity component,
+  pressure Poisson solve, correction and pressure update.
 
 Every function is pinned by ``tests/test_oracle_*.py`` against values the
 paper prints, closed forms, library routines and brute force.
@@ -32,3 +35,4 @@ from .eig import eig_direction, jacobi_eigh  # noqa: F401
 from .solver import solve, thomas_lines, relative_error, gauge_normalise  # noqa: F401
 from .dense import solve_dense  # noqa: F401
 from . import projection  # noqa: F401
+from . import navier_stokes  # noqa: F401
