@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--slab-steps", type=int, default=5,
                     help="timed solves of the 1024x1024x128 z slab, the per-GPU share of a 1024^3 grid "
                          "on 8 GPUs (0 disables it)")
+    ap.add_argument("--ns-n", type=int, default=1024,
+                    help="cells per direction of the Navier-Stokes time-step comparison (0 disables it)")
+    ap.add_argument("--ns-steps", type=int, default=2, help="timed full time steps per Navier-Stokes case")
     ap.add_argument("--stretch-steps", type=int, default=20,
                     help="timed solves per stretching parameter of the beta comparison (0 disables it)")
     ap.add_argument("--preheat", type=float, default=0.15,
@@ -466,6 +469,79 @@ def run_slab(args, T, W):
     return res
 
 
+def run_ns(args, T, W):
+    """Cost of a complete Navier-Stokes time step (the three Runge-Kutta
+    substeps of Eq. rk3) against the Poisson solve alone, with the pressure
+    solved by fast transforms in x and y (FF) or by dense GEMMs (GG): the
+    n^3 grid of the transform-variant comparison (periodic x, walls in y and
+    z, uniform), FP64.  Diffusion explicit (the pressure is the only
+    elliptic solve; both variants) and implicit in x, y and z (FF, the
+    Helmholtz plans choosing their own transforms).  Velocity: seeded
+    Gaussian noise on the GPU, projected once; pressure zero; dt = 0.2 h,
+    nu = 1e-4."""
+    import torch
+    n = args.ns_n
+    prob = W.make_problem((n, n, n), (0.0, 0.0, 0.0), (W.PP, W.NN, W.NN), name=f"uniform{n}_pnn")
+    res = {"workload": f"{n}^3 incompressible Navier-Stokes time step (3 RK3 substeps), periodic x, "
+                       f"walls y and z, uniform, FP64", "cells": prob.dof,
+           "paper_gb200_GG_over_FF": {"poisson": 2.8, "ns_step": 1.8}}
+    dt, nu = 0.2 / n, 1e-4
+    gen = torch.Generator(device="cuda")
+    for name, dx, dy, imp in (("FF", False, False, "none"), ("GG", True, True, "none"), ("FF_xyz", False, False, "xyz")):
+        t0 = time.time()
+        plan = T.Plan.from_problem(prob, dense_x=dx, dense_y=dy)
+        ws = plan.workspace()
+        gen.manual_seed(31)
+        vel = [torch.randn(s_, generator=gen, dtype=torch.float64, device="cuda") for s_ in plan.velocity_shapes()]
+        phi = plan.project(*vel)
+        # the Poisson solve alone (the pressure correction of one substep)
+        rhs = plan.divergence(*vel)
+        rhs.normal_(generator=gen)
+        rhs -= rhs.mean()
+        plan.solve(rhs, phi, ws)
+        preheat(lambda: plan.solve(rhs, phi, ws), args.preheat)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(3 * args.ns_steps):
+            plan.solve(rhs, phi, ws)
+        torch.cuda.synchronize()
+        poisson_ms = (time.perf_counter() - t1) * 1e3 / (3 * args.ns_steps)
+        del rhs
+        ns = T.NavierStokes(plan, nu, dt, imp)
+        e = tuple(torch.zeros_like(a) for a in vel)
+        P = torch.zeros(plan.shape, dtype=torch.float64, device="cuda")
+        nws = ns.workspace()
+        for k in (1, 2, 3):
+            ns.substep(k, *vel, e, P, phi=phi, workspace=nws)
+        torch.cuda.synchronize()
+        log(f"ns {name}: set-up and first step {time.time() - t0:.1f}s")
+        T.timing_collect()
+        T.timing_enable(True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.ns_steps):
+            for k in (1, 2, 3):
+                ns.substep(k, *vel, e, P, phi=phi, workspace=nws)
+        torch.cuda.synchronize()
+        step_ms = (time.perf_counter() - t1) * 1e3 / args.ns_steps
+        T.timing_enable(False)
+        kern = T.timing_collect()
+        finite = bool(all(torch.isfinite(a).all().item() for a in vel))
+        div = float(plan.divergence(*vel).abs().max().item())
+        res[name] = {"implicit": imp, "transforms": plan.transforms, "ms_per_step": step_ms,
+                     "poisson_ms": poisson_ms, "pressure_share": 3 * poisson_ms / step_ms,
+                     "cells_per_s": prob.dof / (step_ms * 1e-3), "finite": finite, "max_divergence": div,
+                     "kernels_ms_per_step": {k_: v[0] / args.ns_steps for k_, v in kern.items()}}
+        log(f"ns {name}: {step_ms:.1f} ms/step, Poisson {poisson_ms:.2f} ms, pressure share "
+            f"{res[name]['pressure_share']:.2f}, max |D u| {div:.2e}")
+        del ns, e, P, nws, vel, phi, plan, ws
+        torch.cuda.empty_cache()
+    res["GG_over_FF"] = {"poisson": res["GG"]["poisson_ms"] / res["FF"]["poisson_ms"],
+                         "ns_step": res["GG"]["ms_per_step"] / res["FF"]["ms_per_step"]}
+    log(f"ns GG/FF: Poisson {res['GG_over_FF']['poisson']:.2f}x, step {res['GG_over_FF']['ns_step']:.2f}x")
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -698,10 +774,14 @@ def main():
     if args.slab_steps > 0:
         slab = run_slab(args, T, W)
 
+    ns = None
+    if args.ns_n > 0 and args.ns_steps > 0:
+        ns = run_ns(args, T, W)
+
     if not results:
         print(json.dumps({"sections_only": True, "serving": serving, "helmholtz_1024x768x512_3rhs": helm,
                           "batch64": batch, "transform_variants": variants, "stretching": stretching,
-                          "slab": slab}))
+                          "slab": slab, "navier_stokes": ns}))
         return
 
     # ---- headline: fastest mode that meets its bar against the oracle ----------
@@ -773,6 +853,7 @@ def main():
         "transform_variants": variants,
         "stretching": stretching,
         "slab_1024x1024x128": slab,
+        "navier_stokes_step": ns,
         "gemm_tiles": tiles,
     }
     print(json.dumps(line))

@@ -68,7 +68,9 @@ enum { TPT_POISSON = 0, TPT_HELMHOLTZ = 1 };
  * pipeline serves them, yz without the x transforms, z with the tridiagonal
  * solve only): (I - alpha L_I) u = f.  Poisson plans are always XYZ; YZ and
  * Z plans are FP64 only. */
-enum { TPT_IMPLICIT_XYZ = 0, TPT_IMPLICIT_YZ = 1, TPT_IMPLICIT_Z = 2 };
+enum { TPT_IMPLICIT_XYZ = 0, TPT_IMPLICIT_YZ = 1, TPT_IMPLICIT_Z = 2,
+       TPT_IMPLICIT_NONE = 3 /* L_I = 0, fully explicit diffusion: Navier-Stokes
+                                substeps only (tpt_ns_create); plans reject it */ };
 /* Arithmetic of the transforms.  FP64: everything in double precision.
  * MIXED_FP32: transforms in FP32 MFMA; MIXED_BF16X3: transforms as three
  * BF16 MFMA products (hi*hi + hi*lo + lo*hi) with FP32 accumulation.  Both
@@ -113,6 +115,7 @@ enum {
 typedef struct tpt_plan_s *tpt_plan;
 typedef struct tpt_batch_s *tpt_batch;
 typedef struct tpt_server_s *tpt_server;
+typedef struct tpt_ns_s *tpt_ns;
 
 typedef struct {
     int n[3];               /* cells per direction x, y, z (>= 2) */
@@ -270,6 +273,44 @@ int tpt_gradient_update(tpt_plan plan, const double *phi, double *u, double *v, 
 int tpt_project_workspace_bytes(tpt_plan plan, size_t *bytes);
 int tpt_project(tpt_plan plan, double *u, double *v, double *w, double *phi, void *workspace,
                 size_t workspace_bytes, void *stream);
+
+/* ---- Navier-Stokes Runge-Kutta substep (§2.1, Eq. rk3) -------------------- */
+
+/* A time-stepping context on the grid of `pressure` (a plan accepted by
+ * tpt_project: cell-centred Poisson, periodic or Neumann boundaries, where a
+ * Neumann direction is bounded by no-slip, no-penetration walls), with
+ * kinematic viscosity nu (>= 0), time step dt (> 0) and implicit directions
+ * TPT_IMPLICIT_{NONE, Z, YZ, XYZ} (L_I of §2.1; NONE = fully explicit
+ * diffusion).  For implicit diffusion (nu > 0 required) the context builds
+ * the FP64 Helmholtz plans (I - c_k L_I) of the three velocity components
+ * for the three substep coefficients c_k = gamma_k nu dt / 2 (nine plans,
+ * the eigenbases shared through the cache).  The pressure plan must outlive
+ * the context; its precision is that of the pressure solve.  A new dt needs
+ * a new context.  TPT_ERR_INVALID for a bad plan or parameter. */
+int tpt_ns_create(tpt_plan pressure, double nu, double dt, int implicit, tpt_ns *out);
+int tpt_ns_destroy(tpt_ns ns);
+/* Device workspace of tpt_ns_substep: three velocity-sized right-hand sides,
+ * one pressure-sized divergence and the largest solve workspace. */
+int tpt_ns_workspace_bytes(tpt_ns ns, size_t *bytes);
+/* Substep k (1, 2 or 3) of Eq. rk3 with alpha_k = (8/15, 5/12, 3/4),
+ * beta_k = (0, -17/60, -5/12), gamma_k = alpha_k + beta_k and
+ * c = gamma_k nu dt / 2:
+ *   E^k   = A u^k + nu L_E u^k
+ *   u**   = u^k + dt [alpha_k E^k + beta_k E^{k-1} + gamma_k (-G P + nu L_I u^k)]
+ *   (I - c L_I) u* = u** - c L_I u^k            (u* = u** when L_I = 0)
+ *   L Phi = D u* / (gamma_k dt),  u^{k+1} = u* - gamma_k dt G Phi
+ *   P^{k+1/2} = P^{k-1/2} + Phi - c L_I Phi
+ * A u = -div(u (x) u) is the symmetry-preserving second-order finite-volume
+ * advection (kinetic energy conserved for divergence-free u); L_E, L_I, G,
+ * D are the staggered operators of tpt_project and of the plans.
+ * u, v, w: device FP64 face velocities in the layouts of tpt_project, u^k in
+ * and u^{k+1} out.  eu, ev, ew: the same shapes, E^{k-1} in (not read for
+ * k = 1) and E^k out, carried by the caller from substep to substep.  p:
+ * (Nz, Ny, Nx) pressure, P^{k-1/2} in and P^{k+1/2} out.  phi: (Nz, Ny, Nx),
+ * receives Phi.  workspace: at least tpt_ns_workspace_bytes.  Stream-ordered;
+ * allocates nothing.  Info of the pressure solve: tpt_solve_info(pressure). */
+int tpt_ns_substep(tpt_ns ns, int k, double *u, double *v, double *w, double *eu, double *ev, double *ew,
+                   double *p, double *phi, void *workspace, size_t workspace_bytes, void *stream);
 
 /* ---- multi-problem batches (independent problems, uneven sizes) ---------- */
 

@@ -99,6 +99,10 @@ def lib():
             "tpt_gradient_update": (i, [vp, vp, vp, vp, vp, vp]),
             "tpt_project_workspace_bytes": (i, [vp, ctypes.POINTER(sz)]),
             "tpt_project": (i, [vp, vp, vp, vp, vp, vp, sz, vp]),
+            "tpt_ns_create": (i, [vp, d, d, i, ctypes.POINTER(vp)]),
+            "tpt_ns_destroy": (i, [vp]),
+            "tpt_ns_workspace_bytes": (i, [vp, ctypes.POINTER(sz)]),
+            "tpt_ns_substep": (i, [vp, i, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
             "tpt_batch_create": (i, [i, ctypes.POINTER(vp), ctypes.POINTER(vp)]),
             "tpt_batch_destroy": (i, [vp]),
             "tpt_batch_workspace_bytes": (i, [vp, ctypes.POINTER(sz)]),
@@ -132,7 +136,8 @@ def lib():
 EXPORTED = ("tpt_plan_desc_init", "tpt_plan_create", "tpt_plan_destroy", "tpt_plan_shape",
             "tpt_plan_workspace_bytes", "tpt_plan_eigen", "tpt_plan_operator", "tpt_plan_transforms", "tpt_plan_fused", "tpt_solve",
             "tpt_solve_info", "tpt_solve_noalloc", "tpt_residual", "tpt_static_workspace_capacity", "tpt_divergence", "tpt_gradient_update",
-            "tpt_project_workspace_bytes", "tpt_project", "tpt_batch_create", "tpt_batch_destroy", "tpt_batch_workspace_bytes",
+            "tpt_project_workspace_bytes", "tpt_project", "tpt_ns_create", "tpt_ns_destroy",
+            "tpt_ns_workspace_bytes", "tpt_ns_substep", "tpt_batch_create", "tpt_batch_destroy", "tpt_batch_workspace_bytes",
             "tpt_batch_solve", "tpt_batch_info", "tpt_autotune", "tpt_autotune_save", "tpt_autotune_load",
             "tpt_server_create", "tpt_server_submit", "tpt_server_poll", "tpt_server_drain",
             "tpt_server_destroy", "tpt_thomas", "tpt_gemm", "tpt_timing_enable", "tpt_timing_collect",
@@ -374,6 +379,70 @@ class Plan:
         h = getattr(self, "_h", None)
         if h is not None and _lib is not None:
             _lib.tpt_plan_destroy(h)
+            self._h = None
+
+
+class NavierStokes:
+    """Runge-Kutta substeps of the incompressible Navier-Stokes solver
+    (§2.1, Eq. rk3) on the grid of a pressure plan (see tpt_ns_create and
+    tpt_ns_substep): kinematic viscosity nu, time step dt, implicit
+    directions 'none', 'z', 'yz' or 'xyz'.  Velocities in the face layouts
+    of Plan.velocity_shapes(), pressure in the plan's shape."""
+
+    def __init__(self, pressure: "Plan", nu: float, dt: float, implicit: str = "xyz"):
+        imp = dict(_IMPLICIT, none=3)[implicit]
+        h = ctypes.c_void_p()
+        _check(lib().tpt_ns_create(pressure.handle, float(nu), float(dt), imp, ctypes.byref(h)))
+        self._h = h
+        self.pressure = pressure
+        self.nu, self.dt, self.implicit = float(nu), float(dt), implicit
+        self._ws = None
+        self._e = None
+
+    def workspace_bytes(self) -> int:
+        b = ctypes.c_size_t()
+        _check(lib().tpt_ns_workspace_bytes(self._h, ctypes.byref(b)))
+        return b.value
+
+    def workspace(self):
+        import torch
+        if self._ws is None:
+            self._ws = torch.empty(self.workspace_bytes(), dtype=torch.uint8, device="cuda")
+        return self._ws
+
+    def substep(self, k, u, v, w, e, p, phi=None, workspace=None, stream=None):
+        """Substep k (1, 2, 3) in place: (u, v, w) u^k -> u^{k+1}; e = (eu, ev,
+        ew) E^{k-1} -> E^k; p P^{k-1/2} -> P^{k+1/2}.  Returns phi."""
+        import torch
+        P = self.pressure
+        P._check_velocity(u, v, w)
+        for t, s_, name in zip(e, P.velocity_shapes(), ("eu", "ev", "ew")):
+            _require_f64_cuda(t, s_, name)
+        _require_f64_cuda(p, P.shape, "p")
+        if phi is None:
+            phi = torch.empty(P.shape, dtype=torch.float64, device="cuda")
+        _require_f64_cuda(phi, P.shape, "phi")
+        ws = self.workspace() if workspace is None else workspace
+        _check(lib().tpt_ns_substep(self._h, int(k), _ptr(u), _ptr(v), _ptr(w), _ptr(e[0]), _ptr(e[1]),
+                                    _ptr(e[2]), _ptr(p), _ptr(phi), _ptr(ws), ws.numel() * ws.element_size(),
+                                    _stream(stream)))
+        return phi
+
+    def step(self, u, v, w, p, phi=None, stream=None):
+        """One full time step (substeps 1, 2, 3) in place; returns the last
+        substep's phi."""
+        import torch
+        if self._e is None:
+            self._e = tuple(torch.empty(s_, dtype=torch.float64, device="cuda")
+                            for s_ in self.pressure.velocity_shapes())
+        for k in (1, 2, 3):
+            phi = self.substep(k, u, v, w, self._e, p, phi=phi, stream=stream)
+        return phi
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.tpt_ns_destroy(h)
             self._h = None
 
 

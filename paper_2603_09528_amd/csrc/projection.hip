@@ -21,26 +21,6 @@
 
 namespace tpt {
 
-struct ProjDesc {
-    int nx, ny, nz;
-    int perx, pery, perz;
-    int nux, nvy, nwz;               // face unknowns per direction
-    const double* wx;                // cell widths (control volumes)
-    const double* wy;
-    const double* wz;
-    const double* dx;                // centre distances of the faces (nux / nvy / nwz)
-    const double* dy;
-    const double* dz;
-    const double* u;
-    const double* v;
-    const double* w;
-    double* uo;
-    double* vo;
-    double* wo;
-    const double* phi;
-    double* div;
-};
-
 namespace {
 
 constexpr int PJ_NT = 256;
@@ -79,7 +59,7 @@ __global__ __launch_bounds__(PJ_NT) void divergence_kernel(ProjDesc d) {
         const double vh = yhi ? d.v[vbase + (long long)j * d.nx] : 0.0;
         const double vl = jlo >= 0 ? d.v[vbase + (long long)jlo * d.nx] : 0.0;
         const double wh = k < d.nwz ? d.w[(long long)k * sxy + c] : 0.0;
-        d.div[(long long)k * sxy + c] = (uh - ul) * rwx + (vh - vl) * rwy + (wh - wlo) / d.wz[k];
+        d.div[(long long)k * sxy + c] = ((uh - ul) * rwx + (vh - vl) * rwy + (wh - wlo) / d.wz[k]) * d.scale;
         wlo = wh;
     }
 }
@@ -98,7 +78,7 @@ __global__ __launch_bounds__(PJ_NT) void gradient_update_kernel(ProjDesc d) {
     const bool xf = i < d.nux, yf = j < d.nvy;
     const long long ox = i + 1 < d.nx ? 1 : -(long long)(d.nx - 1);
     const long long oy = j + 1 < d.ny ? (long long)d.nx : -(long long)(d.ny - 1) * d.nx;
-    const double rdx = xf ? 1.0 / d.dx[i] : 0.0, rdy = yf ? 1.0 / d.dy[j] : 0.0;
+    const double rdx = xf ? d.gscale / d.dx[i] : 0.0, rdy = yf ? d.gscale / d.dy[j] : 0.0;
     double pc = d.phi[(long long)k0 * sxy + c];
     for (int k = k0; k < k1; ++k) {
         const long long idx = (long long)k * sxy + c;
@@ -112,10 +92,12 @@ __global__ __launch_bounds__(PJ_NT) void gradient_update_kernel(ProjDesc d) {
         }
         const int kp = k + 1 < d.nz ? k + 1 : 0;
         const double pn = (k + 1 < d.nz || d.perz) ? d.phi[(long long)kp * sxy + c] : 0.0;
-        if (k < d.nwz) d.wo[idx] = d.w[idx] - (pn - pc) / d.dz[k];
+        if (k < d.nwz) d.wo[idx] = d.w[idx] - (pn - pc) * d.gscale / d.dz[k];
         pc = pn;
     }
 }
+
+}  // namespace
 
 // Descriptor of the plan's grid; TPT_OK or an error for a plan that is not
 // a cell-centred pressure problem with periodic / Neumann (wall) boundaries.
@@ -145,10 +127,10 @@ int proj_desc(const tpt_plan_s* p, ProjDesc& d) {
     d.dx = p->buf.dcx;
     d.dy = p->buf.dcy;
     d.dz = p->buf.dcz;
+    d.scale = 1.0;
+    d.gscale = 1.0;
     return TPT_OK;
 }
-
-}  // namespace
 
 hipError_t launch_divergence(const ProjDesc& d, hipStream_t s) {
     const long long nb = proj_blocks(d);

@@ -1,0 +1,147 @@
+"""Navier--Stokes Runge--Kutta substeps on the GPU (§2.1, Eq. rk3) through
+tpt_ns_substep, element by element against the oracle's substep.
+
+Both sides start from the same seeded state (a projected white-noise
+velocity, a random pressure) and run the three substeps of one time step;
+after every substep each output is compared: the velocity components u, v,
+w and the explicit terms E^k element by element against the oracle's, with
+the bound 1e-11 max|ref| (FP64 solves of relative accuracy ~1e-13 times
+the condition of the Helmholtz and Poisson operators at these sizes, and
+the advection's differences of O(|u|^2 / h) terms); the pressure P and the
+correction Phi in the gauge-normalised max norm (the pressure of a
+singular problem is fixed up to a constant).  The updated velocity must be
+discretely divergence-free."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from oracle import navier_stokes as NS
+from oracle import projection as PJ
+from tests.gpu_util import cuda, host, parity_error, say
+
+pytestmark = pytest.mark.gpu
+
+GRIDS = [
+    # pressure grids: n, beta, bc (P or N = walls per direction)
+    ((24, 20, 18), (0.0, 2.0, 1.5), (W.PP, W.NN, W.NN)),     # channel
+    ((21, 19, 17), (1.5, 2.0, 1.0), (W.NN, W.NN, W.NN)),     # cavity, odd sizes
+    ((32, 24, 20), (0.0, 0.0, 2.0), (W.PP, W.PP, W.NN)),     # x, y by fast transforms
+    ((20, 16, 18), (1.0, 0.0, 0.0), (W.NN, W.PP, W.PP)),     # periodic z (cyclic lines)
+]
+IMPLICIT = ["none", "z", "yz", "xyz"]
+TOL = 1e-11
+
+
+def _T():
+    import paper_2603_09528_amd as T
+    return T
+
+
+def _state(p, seed):
+    rng = np.random.default_rng(seed)
+    u, v, w = W.white_noise_velocity(p, seed)
+    u, v, w, _ = PJ.project(p, u, v, w)
+    return (u, v, w), rng.standard_normal(p.shape)
+
+
+def _run(g, implicit, nu=0.05, dt=2e-3, seed=21):
+    import torch
+    T = _T()
+    p = W.make_problem(*g)
+    plan = T.Plan.from_problem(p)
+    ns = T.NavierStokes(plan, nu, dt, implicit)
+    (u, v, w), P = _state(p, seed)
+    du, dv, dw, dP = cuda(u), cuda(v), cuda(w), cuda(P)
+    de = tuple(cuda(np.zeros_like(a)) for a in (u, v, w))
+    ref_vel, ref_e, ref_P = (u, v, w), (None, None, None), P
+    for k in (1, 2, 3):
+        say("ns substep", g, implicit, "k", k)
+        phi = ns.substep(k, du, dv, dw, de, dP)
+        torch.cuda.synchronize()
+        ref_vel, ref_e, ref_P, ref_phi = NS.rk3_substep(p, k, dt, nu, implicit, *ref_vel, ref_e, ref_P)
+        for name, got, ref in zip(("u", "v", "w", "eu", "ev", "ew"), (du, dv, dw) + de, ref_vel + ref_e):
+            err = np.abs(host(got) - ref).max()
+            assert err <= TOL * np.abs(ref).max(), (k, name, err / np.abs(ref).max())
+        assert parity_error(p, host(dP), ref_P) < TOL, k
+        assert parity_error(p, host(phi), ref_phi) < TOL, k
+        gu, gv, gw = host(du), host(dv), host(dw)
+        div = np.abs(PJ.divergence(p, gu, gv, gw)).max()
+        assert div <= 1e-11 * PJ.divergence_flux_bound(p, gu, gv, gw), (k, div)
+
+
+@pytest.mark.parametrize("implicit", IMPLICIT)
+@pytest.mark.parametrize("g", GRIDS, ids=lambda g: "".join(b[0] for b in g[2]) + f"-{g[0][0]}")
+def test_substeps_match_oracle(g, implicit):
+    _run(g, implicit)
+
+
+def test_substeps_match_oracle_several_tiles():
+    """A grid of several GEMM tiles per direction with ragged edges."""
+    _run(((136, 72, 40), (0.0, 2.0, 2.0), (W.PP, W.NN, W.NN)), "xyz", nu=0.01, dt=1e-3)
+
+
+def test_eigenmode_amplification_on_gpu():
+    """A discrete diffusion eigenmode (constant along the periodic x) decays
+    over one step by the Crank--Nicolson factor prod_k (1 + gamma_k z / 2) /
+    (1 - gamma_k z / 2), z = nu dt lambda (closed form, independent of the
+    oracle's arithmetic)."""
+    import torch
+    T = _T()
+    from oracle.operator import dense_1d, operator_1d
+    p = W.make_problem((16, 14, 12), (0.0, 2.0, 1.5), (W.PP, W.NN, W.NN))
+    plan = T.Plan.from_problem(p)
+    pc = NS.velocity_problem(p, 0)
+    vecs, lams = [], []
+    for d in (1, 2):
+        a, b, c, _ = operator_1d(pc.faces[d], pc.bc[d], pc.loc[d])
+        lam, vec = np.linalg.eig(dense_1d(a, b, c, False))
+        i = np.argsort(np.abs(lam.real))[1]
+        vecs.append(vec[:, i].real)
+        lams.append(lam[i].real)
+    q = np.zeros(pc.shape)
+    q[:] = (vecs[1][:, None] * vecs[0][None, :])[:, :, None]
+    nu = 0.01
+    dt = 0.4 / (nu * abs(sum(lams)))
+    z = -0.4
+    shp = W.velocity_shapes(p)
+    du, dv, dw = cuda(q), cuda(np.zeros(shp[1])), cuda(np.zeros(shp[2]))
+    dP = cuda(np.zeros(p.shape))
+    ns = T.NavierStokes(plan, nu, dt, "xyz")
+    ns.step(du, dv, dw, dP)
+    torch.cuda.synchronize()
+    R = np.prod([(1 + g * z / 2) / (1 - g * z / 2) for g in (8 / 15, 2 / 15, 1 / 3)])
+    assert np.abs(host(du) - R * q).max() < 1e-12 * np.abs(q).max()
+    assert np.abs(host(dv)).max() < 1e-13 and np.abs(host(dw)).max() < 1e-13
+
+
+def test_ns_rejections():
+    import torch
+    T = _T()
+    p = W.make_problem((12, 10, 8), (0.0, 1.0, 1.0), (W.PP, W.NN, W.NN))
+    plan = T.Plan.from_problem(p)
+    L = T.lib()
+    import ctypes
+    h = ctypes.c_void_p()
+    # implicit diffusion without viscosity, non-positive dt, unknown option
+    for nu, dt, imp in ((0.0, 1e-3, 0), (0.1, 0.0, 3), (0.1, 1e-3, 7)):
+        with pytest.raises(T.TptError) as ei:
+            T._check(L.tpt_ns_create(plan.handle, nu, dt, imp, ctypes.byref(h)))
+        assert ei.value.code == -1
+    # a Helmholtz plan is not a pressure plan
+    hp = T.Plan.from_problem(W.make_problem((12, 10, 8), (0.0, 1.0, 1.0), (W.PP, W.NN, W.NN),
+                                            kind="helmholtz", alpha=1e-3))
+    with pytest.raises(T.TptError):
+        T.NavierStokes(hp, 0.1, 1e-3, "xyz")
+    ns = T.NavierStokes(plan, 0.1, 1e-3, "none")
+    shp = plan.velocity_shapes()
+    vel = [torch.zeros(s, dtype=torch.float64, device="cuda") for s in shp]
+    e = [torch.zeros(s, dtype=torch.float64, device="cuda") for s in shp]
+    P = torch.zeros(plan.shape, dtype=torch.float64, device="cuda")
+    with pytest.raises(T.TptError) as ei:
+        ns.substep(4, *vel, e, P)
+    assert ei.value.code == -1
+    small = torch.empty(ns.workspace_bytes() - 8, dtype=torch.uint8, device="cuda")
+    with pytest.raises(T.TptError) as ei:
+        ns.substep(1, *vel, e, P, workspace=small)
+    assert ei.value.code == -7
