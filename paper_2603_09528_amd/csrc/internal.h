@@ -184,8 +184,5 @@ Ws carve(const tpt_plan_s* p, void* ws);
 int stage_variant(const tpt_plan_s* p, int stage, const GemmDesc& g, int prec);
 const char* stage_name(int stage, int prec);
 long long plan_residual_blocks(const tpt_plan_s* p);
-// Projection descriptor of a cell-centred pressure plan (periodic / Neumann
-// boundaries): sizes, widths and face spacings; TPT_OK or an error.
-int proj_desc(const tpt_plan_s* p, ProjDesc& d);
 
 }  // namespace tpt

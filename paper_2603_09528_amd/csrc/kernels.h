@@ -263,32 +263,4 @@ hipError_t launch_check_multi(const CheckDesc* d_work, int nwork, long long tota
 hipError_t launch_split_bf16(const float* x, uint16_t* hi, uint16_t* lo, long long n, hipStream_t s);
 hipError_t launch_convert_f64_f32(const double* x, float* y, long long n, hipStream_t s);
 
-// ---- projection step (staggered grid, projection.hip) ------------------------
-// Pressure-like fields (Nz, Ny, Nx); u (Nz, Ny, Nux), v (Nz, Nvy, Nx),
-// w (Nwz, Ny, Nx), with N face unknowns in a periodic direction and N - 1
-// between walls.
-struct ProjDesc {
-    int nx, ny, nz;
-    int perx, pery, perz;
-    int nux, nvy, nwz;               // face unknowns per direction
-    const double* wx;                // cell widths (control volumes)
-    const double* wy;
-    const double* wz;
-    const double* dx;                // centre distances of the faces (nux / nvy / nwz)
-    const double* dy;
-    const double* dz;
-    const double* u;
-    const double* v;
-    const double* w;
-    double* uo;
-    double* vo;
-    double* wo;
-    const double* phi;
-    double* div;
-    double scale;                    // div = scale * D(u, v, w)
-    double gscale;                   // uo = u - gscale * G phi
-};
-hipError_t launch_divergence(const ProjDesc& d, hipStream_t s);
-hipError_t launch_gradient_update(const ProjDesc& d, hipStream_t s);
-
 }  // namespace tpt

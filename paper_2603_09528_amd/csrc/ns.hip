@@ -30,8 +30,10 @@
 //
 // Memory-bound kernels.  The explicit kernel of a component reads the
 // component, the two transverse components, P and E^{k-1} and writes E^k
-// and rhs: 56 B per unknown (48 B for k = 1); neighbours are cache hits of
-// adjacent lanes and planes.  The pressure update moves 24 B per cell.
+// and rhs: 56 B per unknown (48 B for k = 1).  A thread marches one (i, j)
+// column through a chunk of z planes with the z neighbours in registers;
+// in-plane neighbours are cache hits of the adjacent lanes and rows.  The
+// pressure update moves 24 B per cell.
 #include <cmath>
 #include <new>
 #include <string>
@@ -41,6 +43,7 @@
 
 #include "host_ops.h"
 #include "internal.h"
+#include "projection.h"
 
 namespace tpt {
 
@@ -77,104 +80,213 @@ struct NsPressDesc {
 namespace {
 
 constexpr int NS_NT = 256;
+constexpr int NS_RZ = 32;   // z planes one thread marches through
 
-// Advection flux difference of component C across the two faces of its
-// control volume normal to direction E (E != C): the mass flux is the
-// cell-width weighted mean of component E's face velocities in cells m and
-// m + 1 along C; the transported value the mean of the two unknowns of C.
-template <int C, int E>
-__device__ __forceinline__ double ns_transverse(const NsDesc& d, const int* idx, double q0, double qm, double qp,
-                                                double hC) {
-    constexpr int F = 3 - C - E;
-    const int ext0 = E == 0 ? d.nf[0] : d.N[0];
-    const int ext1 = E == 1 ? d.nf[1] : d.N[1];
-    const long long s[3] = {1, ext0, (long long)ext0 * ext1};
-    const int m = idx[C], j = idx[E];
-    const int m1 = m + 1 < d.N[C] ? m + 1 : 0;
-    const double w0 = d.w[C][m], w1 = d.w[C][m1];
-    const double* Qe = d.q[E];
-    const long long base = (long long)idx[F] * s[F];
-    const long long o0 = base + (long long)m * s[C], o1 = base + (long long)m1 * s[C];
-    double ft = 0.0, fb = 0.0;
-    if (j < d.nf[E]) ft = 0.5 * (w0 * Qe[o0 + j * s[E]] + w1 * Qe[o1 + j * s[E]]);
-    const int jb = j > 0 ? j - 1 : (d.per[E] ? d.nf[E] - 1 : -1);
-    if (jb >= 0) fb = 0.5 * (w0 * Qe[o0 + jb * s[E]] + w1 * Qe[o1 + jb * s[E]]);
-    return -(ft * (0.5 * (q0 + qp)) - fb * (0.5 * (q0 + qm))) / (hC * d.w[E][j]);
+// Column blocks of a plane of ncol columns times chunks of NS_RZ planes.
+inline long long ns_blocks(long long ncol, int nplanes) {
+    return ((ncol + NS_NT - 1) / NS_NT) * ((nplanes + NS_RZ - 1) / NS_RZ);
 }
 
+// Offsets of the two neighbours along an in-plane direction (wrapped if
+// periodic); hm / hp are false where the neighbour is a wall.
+struct Nb {
+    long long m, p;
+    bool hm, hp;
+};
+__device__ __forceinline__ Nb ns_nb(int pos, int n, long long stride, int periodic) {
+    Nb b;
+    b.hm = pos > 0 || periodic;
+    b.hp = pos < n - 1 || periodic;
+    b.m = pos > 0 ? -stride : (long long)(n - 1) * stride;
+    b.p = pos < n - 1 ? stride : -(long long)(n - 1) * stride;
+    return b;
+}
+
+// Explicit terms and right-hand side of u (C = 0) or v (C = 1).  A thread
+// owns one (i, j) column of the component and marches it up NS_RZ planes,
+// carrying the z neighbours of the component and the z-face mass flux below
+// the current plane in registers; in-plane neighbours are cache hits of the
+// adjacent lanes and rows (neighbouring rows run on one XCD).
 template <int C>
-__global__ __launch_bounds__(NS_NT) void ns_explicit_kernel(NsDesc d) {
-    int ext[3];
-#pragma unroll
-    for (int e = 0; e < 3; ++e) ext[e] = e == C ? d.nf[e] : d.N[e];
-    const unsigned total = (unsigned)ext[0] * (unsigned)ext[1] * (unsigned)ext[2];
-    const unsigned o = (unsigned)xcd_block(blockIdx.x, gridDim.x) * NS_NT + threadIdx.x;
-    if (o >= total) return;
-    const unsigned row = o / (unsigned)ext[0];
-    int idx[3];
-    idx[0] = (int)(o - row * (unsigned)ext[0]);
-    idx[2] = (int)(row / (unsigned)ext[1]);
-    idx[1] = (int)(row - (unsigned)idx[2] * (unsigned)ext[1]);
-    const unsigned str[3] = {1u, (unsigned)ext[0], (unsigned)ext[0] * (unsigned)ext[1]};
-    const double* Q = d.q[C];
-    const double q0 = Q[o];
-    double qm[3], qp[3], le = 0.0, li = 0.0;
-#pragma unroll
-    for (int e = 0; e < 3; ++e) {
-        const int p = idx[e], n = ext[e];
-        qm[e] = p > 0 ? Q[o - str[e]] : (d.per[e] ? Q[o + (unsigned)(n - 1) * str[e]] : 0.0);
-        qp[e] = p < n - 1 ? Q[o + str[e]] : (d.per[e] ? Q[o - (unsigned)(n - 1) * str[e]] : 0.0);
-        const double lap = d.cb[e][p] * q0 + d.ca[e][p] * qm[e] + d.cc[e][p] * qp[e];
-        if (d.impl[e]) li += lap;
-        else le += lap;
-    }
+__global__ __launch_bounds__(NS_NT) void ns_explicit_xy_kernel(NsDesc d) {
+    constexpr int T = 1 - C;                        // the other in-plane direction
+    const int ext[2] = {C == 0 ? d.nf[0] : d.N[0], C == 1 ? d.nf[1] : d.N[1]};
+    const int nz = d.N[2];
+    const long long sxy = (long long)ext[0] * ext[1];
+    const long long ncb = (sxy + NS_NT - 1) / NS_NT;
+    const long long lb = xcd_block(blockIdx.x, gridDim.x);
+    const long long zc = lb / ncb;
+    const long long col = (lb - zc * ncb) * NS_NT + threadIdx.x;
+    if (col >= sxy) return;
+    const int j = (int)(col / ext[0]), i = (int)(col - (long long)j * ext[0]);
+    const int idx[2] = {i, j};
+    const int k0 = (int)zc * NS_RZ, k1 = min(nz, k0 + NS_RZ);
+    const Nb nb[2] = {ns_nb(i, ext[0], 1, d.per[0]), ns_nb(j, ext[1], ext[0], d.per[1])};
+    const double ax = d.ca[0][i], bx = d.cb[0][i], cx = d.cc[0][i];
+    const double ay = d.ca[1][j], by = d.cb[1][j], cy = d.cc[1][j];
     const int m = idx[C];
-    const double hC = d.h[C][m];
-    // along C: fluxes through the cell centres on both sides of face m
-    const double ul = 0.5 * (qm[C] + q0), uh = 0.5 * (q0 + qp[C]);
-    double adv = -(uh * uh - ul * ul) / hC;
-    constexpr int E1 = C == 0 ? 1 : 0, E2 = C == 2 ? 1 : 2;
-    adv += ns_transverse<C, E1>(d, idx, q0, qm[E1], qp[E1], hC);
-    adv += ns_transverse<C, E2>(d, idx, q0, qm[E2], qp[E2], hC);
-    // pressure gradient on the face between cells m and m + 1
-    const long long sp[3] = {1, d.N[0], (long long)d.N[0] * d.N[1]};
-    long long pb = 0;
-#pragma unroll
-    for (int e = 0; e < 3; ++e)
-        if (e != C) pb += (long long)idx[e] * sp[e];
     const int m1 = m + 1 < d.N[C] ? m + 1 : 0;
-    const double gp = (d.P[pb + (long long)m1 * sp[C]] - d.P[pb + (long long)m * sp[C]]) / hC;
-    const double ek = adv + d.nu * le;
-    double r = q0 + d.dt * (d.alpha * ek - d.gamma * gp) + d.cn * li;
-    if (d.use_prev) r += d.dt * d.beta * d.e[o];
-    d.e[o] = ek;
-    d.rhs[o] = r;
-}
-
-__global__ __launch_bounds__(NS_NT) void ns_pressure_kernel(NsPressDesc d) {
-    const unsigned total = (unsigned)d.N[0] * (unsigned)d.N[1] * (unsigned)d.N[2];
-    const unsigned o = (unsigned)xcd_block(blockIdx.x, gridDim.x) * NS_NT + threadIdx.x;
-    if (o >= total) return;
-    const unsigned row = o / (unsigned)d.N[0];
-    int idx[3];
-    idx[0] = (int)(o - row * (unsigned)d.N[0]);
-    idx[2] = (int)(row / (unsigned)d.N[1]);
-    idx[1] = (int)(row - (unsigned)idx[2] * (unsigned)d.N[1]);
-    const unsigned str[3] = {1u, (unsigned)d.N[0], (unsigned)d.N[0] * (unsigned)d.N[1]};
-    const double f0 = d.phi[o];
-    double li = 0.0;
-#pragma unroll
-    for (int e = 0; e < 3; ++e) {
-        if (!d.impl[e]) continue;
-        const int p = idx[e], n = d.N[e];
-        const double fm = p > 0 ? d.phi[o - str[e]] : (d.per[e] ? d.phi[o + (unsigned)(n - 1) * str[e]] : 0.0);
-        const double fp = p < n - 1 ? d.phi[o + str[e]] : (d.per[e] ? d.phi[o - (unsigned)(n - 1) * str[e]] : 0.0);
-        li += d.b[e][p] * f0 + d.a[e][p] * fm + d.c[e][p] * fp;
+    const double hC = d.h[C][m], w0 = d.w[C][m], w1 = d.w[C][m1];
+    const double wT = d.w[T][idx[T]];
+    // component T: cells along C, faces along T (plane tx0 x tx1)
+    const int tx0 = T == 0 ? d.nf[0] : d.N[0];
+    const long long tsxy = (long long)tx0 * (T == 1 ? d.nf[1] : d.N[1]);
+    const long long tst[2] = {1, tx0};
+    const int jT = idx[T];
+    const bool tt = jT < d.nf[T];
+    const int jb = jT > 0 ? jT - 1 : (d.per[T] ? d.nf[T] - 1 : -1);
+    const long long to0 = (long long)m * tst[C], to1 = (long long)m1 * tst[C];
+    const long long tjt = (long long)jT * tst[T], tjb = (long long)(jb > 0 ? jb : 0) * tst[T];
+    // w and P: planes of N0 x N1 cells
+    const long long psxy = (long long)d.N[0] * d.N[1];
+    const long long pst[2] = {1, d.N[0]};
+    const long long po0 = (long long)m * pst[C] + (long long)idx[T] * pst[T];
+    const long long po1 = (long long)m1 * pst[C] + (long long)idx[T] * pst[T];
+    const double* Q = d.q[C];
+    const double* Qt = d.q[T];
+    const double* Qw = d.q[2];
+    double q0 = Q[(long long)k0 * sxy + col];
+    double qzm = k0 > 0 ? Q[(long long)(k0 - 1) * sxy + col] : (d.per[2] ? Q[(long long)(nz - 1) * sxy + col] : 0.0);
+    const int kb = k0 > 0 ? k0 - 1 : (d.per[2] ? d.nf[2] - 1 : -1);
+    double fzb = kb >= 0 ? 0.5 * (w0 * Qw[(long long)kb * psxy + po0] + w1 * Qw[(long long)kb * psxy + po1]) : 0.0;
+    for (int k = k0; k < k1; ++k) {
+        const long long o = (long long)k * sxy + col;
+        const double qzp = k + 1 < nz ? Q[o + sxy] : (d.per[2] ? Q[col] : 0.0);
+        const double qxm = nb[0].hm ? Q[o + nb[0].m] : 0.0, qxp = nb[0].hp ? Q[o + nb[0].p] : 0.0;
+        const double qym = nb[1].hm ? Q[o + nb[1].m] : 0.0, qyp = nb[1].hp ? Q[o + nb[1].p] : 0.0;
+        const double lx = bx * q0 + ax * qxm + cx * qxp;
+        const double ly = by * q0 + ay * qym + cy * qyp;
+        const double lz = d.cb[2][k] * q0 + d.ca[2][k] * qzm + d.cc[2][k] * qzp;
+        const double li = (d.impl[0] ? lx : 0.0) + (d.impl[1] ? ly : 0.0) + (d.impl[2] ? lz : 0.0);
+        const double le = (d.impl[0] ? 0.0 : lx) + (d.impl[1] ? 0.0 : ly) + (d.impl[2] ? 0.0 : lz);
+        const double qcm = C == 0 ? qxm : qym, qcp = C == 0 ? qxp : qyp;
+        const double qtm = C == 0 ? qym : qxm, qtp = C == 0 ? qyp : qxp;
+        // along C: fluxes through the cell centres on both sides of face m
+        const double ul = 0.5 * (qcm + q0), uh = 0.5 * (q0 + qcp);
+        double adv = -(uh * uh - ul * ul) / hC;
+        // across T: component T's face velocities, width-weighted over cells m, m1
+        const long long tk = (long long)k * tsxy;
+        const double ft = tt ? 0.5 * (w0 * Qt[tk + to0 + tjt] + w1 * Qt[tk + to1 + tjt]) : 0.0;
+        const double fb = jb >= 0 ? 0.5 * (w0 * Qt[tk + to0 + tjb] + w1 * Qt[tk + to1 + tjb]) : 0.0;
+        adv -= (ft * (0.5 * (q0 + qtp)) - fb * (0.5 * (q0 + qtm))) / (hC * wT);
+        // across z: w on the face above plane k (the one below is carried)
+        const long long pk = (long long)k * psxy;
+        const double fzt = k < d.nf[2] ? 0.5 * (w0 * Qw[pk + po0] + w1 * Qw[pk + po1]) : 0.0;
+        adv -= (fzt * (0.5 * (q0 + qzp)) - fzb * (0.5 * (q0 + qzm))) / (hC * d.w[2][k]);
+        const double gp = (d.P[pk + po1] - d.P[pk + po0]) / hC;
+        const double ek = adv + d.nu * le;
+        double r = q0 + d.dt * (d.alpha * ek - d.gamma * gp) + d.cn * li;
+        if (d.use_prev) r += d.dt * d.beta * d.e[o];
+        d.e[o] = ek;
+        d.rhs[o] = r;
+        fzb = fzt;
+        qzm = q0;
+        q0 = qzp;
     }
-    d.P[o] = d.P[o] + f0 - d.cn * li;
 }
 
-inline unsigned ns_blocks(long long n) { return (unsigned)((n + NS_NT - 1) / NS_NT); }
+// Explicit terms and right-hand side of w (faces along z): a thread owns an
+// (i, j) column of cells and marches the z faces; the transverse velocities
+// and the pressure of the cell above face k are carried to face k + 1.
+__global__ __launch_bounds__(NS_NT) void ns_explicit_z_kernel(NsDesc d) {
+    const int nx = d.N[0], ny = d.N[1], nz = d.N[2], nzf = d.nf[2];
+    const long long sxy = (long long)nx * ny;
+    const long long ncb = (sxy + NS_NT - 1) / NS_NT;
+    const long long lb = xcd_block(blockIdx.x, gridDim.x);
+    const long long zc = lb / ncb;
+    const long long col = (lb - zc * ncb) * NS_NT + threadIdx.x;
+    if (col >= sxy) return;
+    const int j = (int)(col / nx), i = (int)(col - (long long)j * nx);
+    const int k0 = (int)zc * NS_RZ, k1 = min(nzf, k0 + NS_RZ);
+    const Nb nbx = ns_nb(i, nx, 1, d.per[0]), nby = ns_nb(j, ny, nx, d.per[1]);
+    const double ax = d.ca[0][i], bx = d.cb[0][i], cx = d.cc[0][i];
+    const double ay = d.ca[1][j], by = d.cb[1][j], cy = d.cc[1][j];
+    const double wx = d.w[0][i], wy = d.w[1][j];
+    // u: planes of nf0 x ny, x faces i (above) and i - 1 (below)
+    const long long usxy = (long long)d.nf[0] * ny;
+    const bool ut = i < d.nf[0];
+    const int ib = i > 0 ? i - 1 : (d.per[0] ? d.nf[0] - 1 : -1);
+    const long long uot = (long long)j * d.nf[0] + i, uob = (long long)j * d.nf[0] + (ib > 0 ? ib : 0);
+    // v: planes of nx x nf1, y faces j and j - 1
+    const long long vsxy = (long long)nx * d.nf[1];
+    const bool vt = j < d.nf[1];
+    const int jbv = j > 0 ? j - 1 : (d.per[1] ? d.nf[1] - 1 : -1);
+    const long long vot = (long long)j * nx + i, vob = (long long)(jbv > 0 ? jbv : 0) * nx + i;
+    const double* Q = d.q[2];
+    const double* U = d.q[0];
+    const double* V = d.q[1];
+    auto cell = [&](int m, double& ut_, double& ub_, double& vt_, double& vb_, double& p_) {
+        ut_ = ut ? U[(long long)m * usxy + uot] : 0.0;
+        ub_ = ib >= 0 ? U[(long long)m * usxy + uob] : 0.0;
+        vt_ = vt ? V[(long long)m * vsxy + vot] : 0.0;
+        vb_ = jbv >= 0 ? V[(long long)m * vsxy + vob] : 0.0;
+        p_ = d.P[(long long)m * sxy + col];
+    };
+    double ut0, ub0, vt0, vb0, p0;
+    cell(k0, ut0, ub0, vt0, vb0, p0);
+    double q0 = Q[(long long)k0 * sxy + col];
+    double qzm = k0 > 0 ? Q[(long long)(k0 - 1) * sxy + col] : (d.per[2] ? Q[(long long)(nzf - 1) * sxy + col] : 0.0);
+    for (int k = k0; k < k1; ++k) {
+        const long long o = (long long)k * sxy + col;
+        const int m1 = k + 1 < nz ? k + 1 : 0;
+        double ut1, ub1, vt1, vb1, p1;
+        cell(m1, ut1, ub1, vt1, vb1, p1);
+        const double qzp = k + 1 < nzf ? Q[o + sxy] : (d.per[2] ? Q[col] : 0.0);
+        const double qxm = nbx.hm ? Q[o + nbx.m] : 0.0, qxp = nbx.hp ? Q[o + nbx.p] : 0.0;
+        const double qym = nby.hm ? Q[o + nby.m] : 0.0, qyp = nby.hp ? Q[o + nby.p] : 0.0;
+        const double lx = bx * q0 + ax * qxm + cx * qxp;
+        const double ly = by * q0 + ay * qym + cy * qyp;
+        const double lz = d.cb[2][k] * q0 + d.ca[2][k] * qzm + d.cc[2][k] * qzp;
+        const double li = (d.impl[0] ? lx : 0.0) + (d.impl[1] ? ly : 0.0) + (d.impl[2] ? lz : 0.0);
+        const double le = (d.impl[0] ? 0.0 : lx) + (d.impl[1] ? 0.0 : ly) + (d.impl[2] ? 0.0 : lz);
+        const double hz = d.h[2][k], w0 = d.w[2][k], w1 = d.w[2][m1];
+        const double ul = 0.5 * (qzm + q0), uh = 0.5 * (q0 + qzp);
+        double adv = -(uh * uh - ul * ul) / hz;
+        const double fxt = 0.5 * (w0 * ut0 + w1 * ut1), fxb = 0.5 * (w0 * ub0 + w1 * ub1);
+        adv -= (fxt * (0.5 * (q0 + qxp)) - fxb * (0.5 * (q0 + qxm))) / (hz * wx);
+        const double fyt = 0.5 * (w0 * vt0 + w1 * vt1), fyb = 0.5 * (w0 * vb0 + w1 * vb1);
+        adv -= (fyt * (0.5 * (q0 + qyp)) - fyb * (0.5 * (q0 + qym))) / (hz * wy);
+        const double gp = (p1 - p0) / hz;
+        const double ek = adv + d.nu * le;
+        double r = q0 + d.dt * (d.alpha * ek - d.gamma * gp) + d.cn * li;
+        if (d.use_prev) r += d.dt * d.beta * d.e[o];
+        d.e[o] = ek;
+        d.rhs[o] = r;
+        ut0 = ut1; ub0 = ub1; vt0 = vt1; vb0 = vb1; p0 = p1;
+        qzm = q0;
+        q0 = qzp;
+    }
+}
+
+// P += Phi - c L_I Phi, marching z with the z neighbours in registers.
+__global__ __launch_bounds__(NS_NT) void ns_pressure_kernel(NsPressDesc d) {
+    const int nx = d.N[0], ny = d.N[1], nz = d.N[2];
+    const long long sxy = (long long)nx * ny;
+    const long long ncb = (sxy + NS_NT - 1) / NS_NT;
+    const long long lb = xcd_block(blockIdx.x, gridDim.x);
+    const long long zc = lb / ncb;
+    const long long col = (lb - zc * ncb) * NS_NT + threadIdx.x;
+    if (col >= sxy) return;
+    const int j = (int)(col / nx), i = (int)(col - (long long)j * nx);
+    const int k0 = (int)zc * NS_RZ, k1 = min(nz, k0 + NS_RZ);
+    const Nb nbx = ns_nb(i, nx, 1, d.per[0]), nby = ns_nb(j, ny, nx, d.per[1]);
+    const double ax = d.a[0][i], bx = d.b[0][i], cx = d.c[0][i];
+    const double ay = d.a[1][j], by = d.b[1][j], cy = d.c[1][j];
+    const double* F = d.phi;
+    double f0 = F[(long long)k0 * sxy + col];
+    double fzm = k0 > 0 ? F[(long long)(k0 - 1) * sxy + col] : (d.per[2] ? F[(long long)(nz - 1) * sxy + col] : 0.0);
+    for (int k = k0; k < k1; ++k) {
+        const long long o = (long long)k * sxy + col;
+        const double fzp = k + 1 < nz ? F[o + sxy] : (d.per[2] ? F[col] : 0.0);
+        double li = 0.0;
+        if (d.impl[0]) li += bx * f0 + ax * (nbx.hm ? F[o + nbx.m] : 0.0) + cx * (nbx.hp ? F[o + nbx.p] : 0.0);
+        if (d.impl[1]) li += by * f0 + ay * (nby.hm ? F[o + nby.m] : 0.0) + cy * (nby.hp ? F[o + nby.p] : 0.0);
+        if (d.impl[2]) li += d.b[2][k] * f0 + d.a[2][k] * fzm + d.c[2][k] * fzp;
+        d.P[o] = d.P[o] + f0 - d.cn * li;
+        fzm = f0;
+        f0 = fzp;
+    }
+}
 
 constexpr double kAlpha[3] = {8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0};
 constexpr double kBeta[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
@@ -183,18 +295,24 @@ inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 }  // namespace
 
-hipError_t launch_ns_explicit(int comp, const NsDesc& d, long long n, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    const unsigned nb = ns_blocks(n);
-    if (comp == 0) TPT_KLAUNCH(ns_explicit_kernel<0>, dim3(nb), dim3(NS_NT), 0, s, d);
-    else if (comp == 1) TPT_KLAUNCH(ns_explicit_kernel<1>, dim3(nb), dim3(NS_NT), 0, s, d);
-    else TPT_KLAUNCH(ns_explicit_kernel<2>, dim3(nb), dim3(NS_NT), 0, s, d);
+hipError_t launch_ns_explicit(int comp, const NsDesc& d, hipStream_t s) {
+    const long long ncol = comp == 0 ? (long long)d.nf[0] * d.N[1]
+                         : comp == 1 ? (long long)d.N[0] * d.nf[1] : (long long)d.N[0] * d.N[1];
+    const int planes = comp == 2 ? d.nf[2] : d.N[2];
+    const long long nb = ns_blocks(ncol, planes);
+    if (nb <= 0) return hipSuccess;
+    if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
+    if (comp == 0) TPT_KLAUNCH(ns_explicit_xy_kernel<0>, dim3((unsigned)nb), dim3(NS_NT), 0, s, d);
+    else if (comp == 1) TPT_KLAUNCH(ns_explicit_xy_kernel<1>, dim3((unsigned)nb), dim3(NS_NT), 0, s, d);
+    else TPT_KLAUNCH(ns_explicit_z_kernel, dim3((unsigned)nb), dim3(NS_NT), 0, s, d);
     return hipGetLastError();
 }
 
-hipError_t launch_ns_pressure(const NsPressDesc& d, long long n, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    TPT_KLAUNCH(ns_pressure_kernel, dim3(ns_blocks(n)), dim3(NS_NT), 0, s, d);
+hipError_t launch_ns_pressure(const NsPressDesc& d, hipStream_t s) {
+    const long long nb = ns_blocks((long long)d.N[0] * d.N[1], d.N[2]);
+    if (nb <= 0) return hipSuccess;
+    if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
+    TPT_KLAUNCH(ns_pressure_kernel, dim3((unsigned)nb), dim3(NS_NT), 0, s, d);
     return hipGetLastError();
 }
 
@@ -406,7 +524,7 @@ int tpt_ns_substep(tpt_ns ns, int k, double* u, double* v, double* w, double* eu
         d.cn = cn;
         d.use_prev = k > 1 ? 1 : 0;
         TimedScope ts(names[c], s);
-        hipError_t e = launch_ns_explicit(c, d, ns->count[c], s);
+        hipError_t e = launch_ns_explicit(c, d, s);
         if (e != hipSuccess) return fail(TPT_ERR_HIP, std::string("NS explicit launch: ") + hipGetErrorString(e));
     }
     // implicit diffusion: (I - c L_I) u* = rhs, u* into the velocity arrays
@@ -458,7 +576,7 @@ int tpt_ns_substep(tpt_ns ns, int k, double* u, double* v, double* w, double* eu
     q.P = p;
     q.cn = cn;
     TimedScope ts("ns_pressure_update", s);
-    hipError_t e = launch_ns_pressure(q, pp->dof, s);
+    hipError_t e = launch_ns_pressure(q, s);
     if (e != hipSuccess) return fail(TPT_ERR_HIP, std::string("NS pressure launch: ") + hipGetErrorString(e));
     return TPT_OK;
 }

@@ -18,6 +18,7 @@
 #include "device_common.h"
 
 #include "internal.h"
+#include "projection.h"
 
 namespace tpt {
 
