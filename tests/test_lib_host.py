@@ -193,3 +193,26 @@ def test_analytic_cosine_sine_bases_large_n(bc):
         c = np.where(k == n, np.sqrt(1.0 / n), np.sqrt(2.0 / n))
         ref = c * np.sin(np.pi * ((k * (2 * i + 1)) % (4 * n)) / (2 * n))
     assert np.abs(Qt - ref).max() <= 4e-16
+
+
+def test_navier_stokes_context_rejects_bad_arguments():
+    """tpt_ns_create's host checks (no GPU needed): NULL arguments, a
+    host-only plan, and the parameters are rejected before any device work."""
+    import ctypes
+    T = pytest.importorskip("paper_2603_09528_amd")
+    L = T.lib()
+    p = W.make_problem((8, 6, 6), (0.0, 1.0, 1.0), (W.PP, W.NN, W.NN))
+    plan = T.Plan.from_problem(p, host_only=True)
+    h = ctypes.c_void_p()
+    with pytest.raises(T.TptError) as ei:
+        T._check(L.tpt_ns_create(None, 0.1, 1e-3, 0, ctypes.byref(h)))
+    assert ei.value.code == -1
+    with pytest.raises(T.TptError) as ei:
+        T._check(L.tpt_ns_create(plan.handle, 0.1, 1e-3, 0, ctypes.byref(h)))
+    assert ei.value.code == -1 and "host-only" in str(ei.value)
+    with pytest.raises(T.TptError) as ei:
+        T._check(L.tpt_ns_substep(None, 1, *([None] * 8), None, 0, None))
+    assert ei.value.code == -1
+    b = ctypes.c_size_t()
+    with pytest.raises(T.TptError):
+        T._check(L.tpt_ns_workspace_bytes(None, ctypes.byref(b)))
