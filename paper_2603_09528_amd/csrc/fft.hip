@@ -277,13 +277,20 @@ __device__ __forceinline__ void ut_forward_body(const FftDesc& d, long long blk,
         // c, so its x weights are loaded once; the block's lines lie in one
         // rhs, so the (j, k) of line l follow from those of its first line.
         double cs = 0.0, ca = 0.0, cbad = 0.0;
-        double cwx0 = 0.0, cwx1 = 0.0;
+        double cwx0 = 0.0, cwx1 = 0.0, cwx2 = 0.0, cwx3 = 0.0;
         unsigned crr0 = 0;
         const bool cfix = (g.nt & (M - 1)) == 0;
+        // M = 2 nt (N = 1024): item u sits at pair position c + (u & 1) nt,
+        // so the two weight pairs are loaded once as well
+        const bool chalf = !cfix && 2 * g.nt == M;
         if (d.cpart) {
             const int c = (int)threadIdx.x & (M - 1);
             cwx0 = d.cvx[2 * c];
             cwx1 = d.cvx[2 * c + 1];
+            if (chalf) {
+                cwx2 = d.cvx[2 * (c + g.nt)];
+                cwx3 = d.cvx[2 * (c + g.nt) + 1];
+            }
             crr0 = (unsigned)g.line0 % d.crows;
         }
         for (int base = 0; base < total; base += UL * g.nt) {
@@ -313,7 +320,9 @@ __device__ __forceinline__ void ut_forward_body(const FftDesc& d, long long blk,
                 const int l = idx >> g.mlog, c = idx & (M - 1);
                 if (d.cpart) {
                     // items past the last line hold zeros (finite, weight 0)
-                    const double wx0 = cfix ? cwx0 : d.cvx[2 * c], wx1 = cfix ? cwx1 : d.cvx[2 * c + 1];
+                    const bool odd = (u & 1) != 0;
+                    const double wx0 = cfix ? cwx0 : chalf ? (odd ? cwx2 : cwx0) : d.cvx[2 * c];
+                    const double wx1 = cfix ? cwx1 : chalf ? (odd ? cwx3 : cwx1) : d.cvx[2 * c + 1];
                     const bool f0 = __builtin_isfinite(v[u].x), f1 = __builtin_isfinite(v[u].y);
                     const double x0 = f0 ? v[u].x : 0.0, x1 = f1 ? v[u].y : 0.0;
                     cs += wyz[u] * (wx0 * x0 + wx1 * x1);
