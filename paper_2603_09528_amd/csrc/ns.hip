@@ -34,7 +34,9 @@
 // column through a chunk of z planes with the z neighbours in registers;
 // in-plane neighbours are cache hits of the adjacent lanes and rows.  The
 // pressure update moves 24 B per cell.
+#include <algorithm>
 #include <cmath>
+#include <memory>
 #include <new>
 #include <string>
 #include <vector>
