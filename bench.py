@@ -537,12 +537,13 @@ def run_ns(args, T, W):
         div = float(plan.divergence(*vel).abs().max().item())
         # memory roofline of the substep's own kernels: algorithmic bytes per
         # launch (explicit terms: 56 B per unknown, 48 B at the first substep,
-        # so 53.3 B on average over a step; divergence 32 B, gradient update
-        # 56 B, pressure update 24 B per cell) over their event-timed duration
+        # so 53.3 B on average over a step; divergence 32 B; gradient update
+        # with the pressure update in its pass 72 B per cell) over their
+        # event-timed duration
         nu_ = [int(np.prod(s_)) for s_ in plan.velocity_shapes()]
         per_step = {"ns_explicit_u": nu_[0] * 160.0, "ns_explicit_v": nu_[1] * 160.0,
                     "ns_explicit_w": nu_[2] * 160.0, "divergence": prob.dof * 96.0,
-                    "gradient_update": prob.dof * 168.0, "ns_pressure_update": prob.dof * 72.0}
+                    "gradient_update": prob.dof * 216.0}
         roof = {}
         for k_, b in per_step.items():
             if k_ in kern and kern[k_][0] > 0:

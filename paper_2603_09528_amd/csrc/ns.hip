@@ -33,7 +33,8 @@
 // and rhs: 56 B per unknown (48 B for k = 1).  A thread marches one (i, j)
 // column through a chunk of z planes with the z neighbours in registers;
 // in-plane neighbours are cache hits of the adjacent lanes and rows.  The
-// pressure update moves 24 B per cell.
+// pressure update rides in the gradient update's pass (which reads Phi
+// anyway): 16 B per cell more there, P read and written.
 #include <algorithm>
 #include <cmath>
 #include <memory>
@@ -65,18 +66,6 @@ struct NsDesc {
     double* rhs;                // Helmholtz right-hand side (u* for L_I = 0)
     double dt, nu, alpha, beta, gamma, cn;
     int use_prev;
-};
-
-struct NsPressDesc {
-    int N[3];
-    int per[3];
-    int impl[3];
-    const double* a[3];         // pressure operator's 1-D coefficients
-    const double* b[3];
-    const double* c[3];
-    const double* phi;
-    double* P;
-    double cn;
 };
 
 namespace {
@@ -260,36 +249,6 @@ __global__ __launch_bounds__(NS_NT) void ns_explicit_z_kernel(NsDesc d) {
     }
 }
 
-// P += Phi - c L_I Phi, marching z with the z neighbours in registers.
-__global__ __launch_bounds__(NS_NT) void ns_pressure_kernel(NsPressDesc d) {
-    const int nx = d.N[0], ny = d.N[1], nz = d.N[2];
-    const long long sxy = (long long)nx * ny;
-    const long long ncb = (sxy + NS_NT - 1) / NS_NT;
-    const long long lb = xcd_block(blockIdx.x, gridDim.x);
-    const long long zc = lb / ncb;
-    const long long col = (lb - zc * ncb) * NS_NT + threadIdx.x;
-    if (col >= sxy) return;
-    const int j = (int)(col / nx), i = (int)(col - (long long)j * nx);
-    const int k0 = (int)zc * NS_RZ, k1 = min(nz, k0 + NS_RZ);
-    const Nb nbx = ns_nb(i, nx, 1, d.per[0]), nby = ns_nb(j, ny, nx, d.per[1]);
-    const double ax = d.a[0][i], bx = d.b[0][i], cx = d.c[0][i];
-    const double ay = d.a[1][j], by = d.b[1][j], cy = d.c[1][j];
-    const double* F = d.phi;
-    double f0 = F[(long long)k0 * sxy + col];
-    double fzm = k0 > 0 ? F[(long long)(k0 - 1) * sxy + col] : (d.per[2] ? F[(long long)(nz - 1) * sxy + col] : 0.0);
-    for (int k = k0; k < k1; ++k) {
-        const long long o = (long long)k * sxy + col;
-        const double fzp = k + 1 < nz ? F[o + sxy] : (d.per[2] ? F[col] : 0.0);
-        double li = 0.0;
-        if (d.impl[0]) li += bx * f0 + ax * (nbx.hm ? F[o + nbx.m] : 0.0) + cx * (nbx.hp ? F[o + nbx.p] : 0.0);
-        if (d.impl[1]) li += by * f0 + ay * (nby.hm ? F[o + nby.m] : 0.0) + cy * (nby.hp ? F[o + nby.p] : 0.0);
-        if (d.impl[2]) li += d.b[2][k] * f0 + d.a[2][k] * fzm + d.c[2][k] * fzp;
-        d.P[o] = d.P[o] + f0 - d.cn * li;
-        fzm = f0;
-        f0 = fzp;
-    }
-}
-
 constexpr double kAlpha[3] = {8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0};
 constexpr double kBeta[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
 
@@ -307,14 +266,6 @@ hipError_t launch_ns_explicit(int comp, const NsDesc& d, hipStream_t s) {
     if (comp == 0) TPT_KLAUNCH(ns_explicit_xy_kernel<0>, dim3((unsigned)nb), dim3(NS_NT), 0, s, d);
     else if (comp == 1) TPT_KLAUNCH(ns_explicit_xy_kernel<1>, dim3((unsigned)nb), dim3(NS_NT), 0, s, d);
     else TPT_KLAUNCH(ns_explicit_z_kernel, dim3((unsigned)nb), dim3(NS_NT), 0, s, d);
-    return hipGetLastError();
-}
-
-hipError_t launch_ns_pressure(const NsPressDesc& d, hipStream_t s) {
-    const long long nb = ns_blocks((long long)d.N[0] * d.N[1], d.N[2]);
-    if (nb <= 0) return hipSuccess;
-    if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
-    TPT_KLAUNCH(ns_pressure_kernel, dim3((unsigned)nb), dim3(NS_NT), 0, s, d);
     return hipGetLastError();
 }
 
@@ -556,30 +507,22 @@ int tpt_ns_substep(tpt_ns ns, int k, double* u, double* v, double* w, double* eu
         if (e != hipSuccess) return fail(TPT_ERR_HIP, std::string("divergence launch: ") + hipGetErrorString(e));
     }
     if ((rc = solve_one(ns->pressure, div, phi, sws, sws_bytes, s))) return rc;
-    {
-        TimedScope ts("gradient_update", s);
-        hipError_t e = launch_gradient_update(pd, s);
-        if (e != hipSuccess) return fail(TPT_ERR_HIP, std::string("gradient update launch: ") + hipGetErrorString(e));
-    }
+    // u = u* - gamma dt G Phi and, in the same pass,
     // P^{k+1/2} = P^{k-1/2} + Phi - c L_I Phi
-    NsPressDesc q{};
+    pd.P = p;
+    pd.pcn = cn;
     const double* pa[3] = {pp->buf.ax, pp->buf.ay, pp->buf.az};
     const double* pb[3] = {pp->buf.bx, pp->buf.by, pp->buf.bz};
     const double* pc[3] = {pp->buf.cx, pp->buf.cy, pp->buf.cz};
     for (int e = 0; e < 3; ++e) {
-        q.N[e] = ns->N[e];
-        q.per[e] = ns->per[e];
-        q.impl[e] = ns->impl[e];
-        q.a[e] = pa[e];
-        q.b[e] = pb[e];
-        q.c[e] = pc[e];
+        pd.pimpl[e] = ns->impl[e];
+        pd.pca[e] = pa[e];
+        pd.pcb[e] = pb[e];
+        pd.pcc[e] = pc[e];
     }
-    q.phi = phi;
-    q.P = p;
-    q.cn = cn;
-    TimedScope ts("ns_pressure_update", s);
-    hipError_t e = launch_ns_pressure(q, s);
-    if (e != hipSuccess) return fail(TPT_ERR_HIP, std::string("NS pressure launch: ") + hipGetErrorString(e));
+    TimedScope ts("gradient_update", s);
+    hipError_t e = launch_gradient_update(pd, s);
+    if (e != hipSuccess) return fail(TPT_ERR_HIP, std::string("gradient update launch: ") + hipGetErrorString(e));
     return TPT_OK;
 }
 

@@ -29,6 +29,15 @@ struct ProjDesc {
     double* div;
     double scale;                    // div = scale * D(u, v, w)
     double gscale;                   // uo = u - gscale * G phi
+    // optional pressure update in the same pass (Navier-Stokes substep):
+    // P += phi - pcn L_I phi, L_I the pressure operator's 1-D rows (pca, pcb,
+    // pcc) in the directions marked in pimpl; null P: no update
+    double* P;
+    double pcn;
+    int pimpl[3];
+    const double* pca[3];
+    const double* pcb[3];
+    const double* pcc[3];
 };
 hipError_t launch_divergence(const ProjDesc& d, hipStream_t s);
 hipError_t launch_gradient_update(const ProjDesc& d, hipStream_t s);

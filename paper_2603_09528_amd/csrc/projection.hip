@@ -81,6 +81,14 @@ __global__ __launch_bounds__(PJ_NT) void gradient_update_kernel(ProjDesc d) {
     const long long oy = j + 1 < d.ny ? (long long)d.nx : -(long long)(d.ny - 1) * d.nx;
     const double rdx = xf ? d.gscale / d.dx[i] : 0.0, rdy = yf ? d.gscale / d.dy[j] : 0.0;
     double pc = d.phi[(long long)k0 * sxy + c];
+    // pressure update: phi below plane k (zero below a wall, where the
+    // Neumann row has no coupling) and the lower x / y neighbours (wrapped;
+    // at a wall their coefficient is zero)
+    const bool pup = d.P != nullptr;
+    double pm = 0.0;
+    if (pup && (k0 > 0 || d.perz)) pm = d.phi[(long long)(k0 > 0 ? k0 - 1 : d.nz - 1) * sxy + c];
+    const long long oxm = i > 0 ? -1 : (long long)(d.nx - 1);
+    const long long oym = j > 0 ? -(long long)d.nx : (long long)(d.ny - 1) * d.nx;
     for (int k = k0; k < k1; ++k) {
         const long long idx = (long long)k * sxy + c;
         if (xf) {
@@ -94,6 +102,16 @@ __global__ __launch_bounds__(PJ_NT) void gradient_update_kernel(ProjDesc d) {
         const int kp = k + 1 < d.nz ? k + 1 : 0;
         const double pn = (k + 1 < d.nz || d.perz) ? d.phi[(long long)kp * sxy + c] : 0.0;
         if (k < d.nwz) d.wo[idx] = d.w[idx] - (pn - pc) * d.gscale / d.dz[k];
+        if (pup) {
+            double li = 0.0;
+            if (d.pimpl[0]) li += d.pcb[0][i] * pc + d.pca[0][i] * (i > 0 || d.perx ? d.phi[idx + oxm] : 0.0)
+                                  + d.pcc[0][i] * (i + 1 < d.nx || d.perx ? d.phi[idx + ox] : 0.0);
+            if (d.pimpl[1]) li += d.pcb[1][j] * pc + d.pca[1][j] * (j > 0 || d.pery ? d.phi[idx + oym] : 0.0)
+                                  + d.pcc[1][j] * (j + 1 < d.ny || d.pery ? d.phi[idx + oy] : 0.0);
+            if (d.pimpl[2]) li += d.pcb[2][k] * pc + d.pca[2][k] * pm + d.pcc[2][k] * pn;
+            d.P[idx] = d.P[idx] + pc - d.pcn * li;
+        }
+        pm = pc;
         pc = pn;
     }
 }
@@ -130,6 +148,7 @@ int proj_desc(const tpt_plan_s* p, ProjDesc& d) {
     d.dz = p->buf.dcz;
     d.scale = 1.0;
     d.gscale = 1.0;
+    d.P = nullptr;
     return TPT_OK;
 }
 
