@@ -85,6 +85,9 @@ def preheat(run, seconds):
     return calls
 
 
+LAT_SAMPLES = 200  # solves timed one by one for the p50 / p99 latency
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -655,7 +658,6 @@ def main():
         for _ in range(args.warmup):
             plan.solve(f, out, ws)
         torch.cuda.synchronize()
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
         # throughput: the timed solves back to back, issued from the host
         torch.cuda.synchronize()
         t_start = time.perf_counter()
@@ -688,11 +690,14 @@ def main():
             log(f"{mode}: graph capture failed ({e})")
         # latency: the same solves one at a time between events (an event
         # record between solves costs about 10 us of idle GPU, so these are
-        # kept out of the throughput pass)
-        for k in range(args.steps):
-            evs[k][0].record(stream)
+        # kept out of the throughput pass); at least LAT_SAMPLES of them, so
+        # that the 99th percentile is not just the largest of a few
+        lev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(max(LAT_SAMPLES, args.steps))]
+        for a, b in lev:
+            a.record(stream)
             plan.solve(f, out, ws)
-            evs[k][1].record(stream)
+            b.record(stream)
         torch.cuda.synchronize()
         # per-kernel durations from a second pass of the same solves (the
         # events bracketing each kernel stay out of the timed pass above)
@@ -703,7 +708,7 @@ def main():
         torch.cuda.synchronize()
         T.timing_enable(False)
         kern = T.timing_collect()
-        lat = np.array([a.elapsed_time(b) for a, b in evs])
+        lat = np.array([a.elapsed_time(b) for a, b in lev])
         ms_stream = wall * 1e3 / args.steps
         launch = "graph" if gms is not None and gms < ms_stream else "stream"
         ms = gms if launch == "graph" else ms_stream
